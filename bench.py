@@ -1,0 +1,173 @@
+"""Throughput of the pair-galaxy cross-correlation hot path on one MI355X.
+
+One step = the whole path over one synthetic catalogue: pair catalogue
+(validation, cell list, pair search with integer keys, bucketing), galaxy
+field and spectrum, every pair field's correlation with the galaxy field,
+bin sums and the finalisation (xi_gg, xi_pg, xi_dp, b_pg, Q_eff).
+Default workload: the 512^3 production case (L = 1000 Mpc/h, ~9.2e5 clustered
+galaxies, 200 (s, |mu|) pair fields, 20 log r-bins over 10-80 Mpc/h).
+
+Prints ONE JSON line.  `value` = pair fields per second over the timed steps.
+`roofline` is for the kernel with the largest share of the timed region:
+algorithmic bytes per launch / mean launch time, both measured in this run
+with HIP events on the launch stream.  `cpu_baseline` times the FP64 CPU
+oracle on a bounded sample of the same workload on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wl, cat, n_fields_sample=2):
+    """Oracle timed on a bounded sample: the pair search and galaxy side in
+    full, plus `n_fields_sample` pair fields; extrapolated to all fields."""
+    import numpy as np
+    from oracle.pairs import pairs_for
+    from oracle.pipeline import galaxy_side, pair_field_xi
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except Exception:
+        cores = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    pairs = pairs_for(cat, wl)
+    t1 = time.perf_counter()
+    gal = galaxy_side(cat, wl)
+    t2 = time.perf_counter()
+    counts = pairs["counts"]
+    # the most populated fields (the cost of a field grows with its pairs only
+    # through the mass assignment; the transforms dominate)
+    fields = list(np.argsort(counts)[::-1][:n_fields_sample])
+    for f in fields:
+        pair_field_xi(pairs, int(f), gal, wl)
+    t3 = time.perf_counter()
+    per_field = (t3 - t2) / n_fields_sample
+    total = (t1 - t0) + (t2 - t1) + wl.n_fields * per_field
+    return {
+        "value": wl.n_fields / total,
+        "unit": "pair fields/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"pair search + galaxy field in full ({t1 - t0:.1f} s + {t2 - t1:.1f} s) and "
+                   f"{n_fields_sample} of {wl.n_fields} pair fields ({per_field:.1f} s each), "
+                   f"extrapolated to all fields; FP64 numpy/scipy.fft with {cores} workers"),
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="cfg1")
+    ap.add_argument("--batch", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernels", action="store_true", help="print the per-kernel table to stderr")
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {a.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    from paper_1705_03464_amd import Plan, load_library
+    from synth import get_config
+
+    load_library()
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    wl = get_config(a.config)
+    cat = wl.catalog()
+    _log(f"[bench] {wl.name}: n_gal={cat.n} N={wl.N} fields={wl.n_fields} bins={wl.n_out}")
+    dev = torch.device("cuda", 0)
+    x = torch.as_tensor(cat.x, dtype=torch.float64, device=dev)
+    y = torch.as_tensor(cat.y, dtype=torch.float64, device=dev)
+    z = torch.as_tensor(cat.z, dtype=torch.float64, device=dev)
+    w = None
+    if cat.w is not None:
+        w = torch.as_tensor(cat.w, dtype=torch.float32, device=dev)
+    plan = Plan.from_workload(wl, precision="fp32", batch=a.batch)
+
+    def step():
+        plan.pairs_build(x, y, z)
+        return plan.forward(w)
+
+    for i in range(a.warmup):
+        step()
+        torch.cuda.synchronize()
+        _log(f"[bench] warmup {i + 1}/{a.warmup} done")
+    plan.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        out = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = plan.profile_read()
+    plan.profile(False)
+    _log(f"[bench] timed {a.steps} steps: {(t1 - t0) * 1e3 / a.steps:.2f} ms/step, "
+         f"n_pairs={plan.n_pairs}")
+    ms_step = (t1 - t0) * 1e3 / a.steps
+    value = wl.n_fields * a.steps / (t1 - t0)
+
+    total_kernel_ms = sum(p[2] for p in prof)
+    if a.kernels:
+        for name, n, ms, by in prof:
+            _log(f"  {name:16s} launches {n:5d}  {ms / max(n, 1):8.3f} ms/launch  "
+                 f"{by / max(n, 1) / 1e9:8.3f} GB/launch  {by / (ms * 1e-3) / 1e9 if ms > 0 else 0:8.1f} GB/s"
+                 f"  share {ms / (ms_step * a.steps):.3f}")
+    dom = max(prof, key=lambda p: p[2])
+    name, n, ms, by = dom
+    achieved = (by / n) / (ms / n * 1e-3) / 1e9
+    roofline = {
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+        "bytes_per_launch": by / n, "ms_per_launch": ms / n,
+        "kernel_share_of_step": round(ms / (ms_step * a.steps), 3),
+    }
+    finite = np.isfinite(out["xi_pg"].cpu().numpy())
+    rec = {
+        "metric": "pair-field xi_pg cross-correlations/s at 512^3 (forward), % HBM peak",
+        "value": round(value, 2),
+        "unit": "pair fields/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": wl.description,
+            "name": wl.name, "N": wl.N, "L": wl.L, "n_gal": cat.n, "n_pairs": plan.n_pairs,
+            "pair_fields": wl.n_fields, "out_bins": wl.n_out, "finite_rows": int(finite.any(1).sum()),
+            "step": "pairs_build + forward", "parallelism": "single GPU",
+        },
+        "roofline": roofline,
+    }
+    if not a.no_cpu_baseline:
+        _log("[bench] timing the CPU oracle on a bounded sample ...")
+        rec["cpu_baseline"] = cpu_baseline(wl, cat)
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

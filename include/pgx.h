@@ -1,0 +1,176 @@
+/*
+ * pgx.h - pair-galaxy cross-correlation on one AMD Instinct MI355X (gfx950).
+ *
+ * Computes, for a periodic box of galaxies, the estimator of Yuan, Eisenstein
+ * & Garrison (2017), "Using galaxy pairs to investigate the three-point
+ * correlation function in the squeezed limit":
+ *   - close galaxy pairs binned by separation (s, |mu|) or (r_p, |pi|), each
+ *     bin a "pair field" of pair midpoints (Implementation section, pair
+ *     catalogue; Methodology, equation delta_pi_x);
+ *   - each pair field's cross-correlation with the galaxy field on an N^3
+ *     grid, averaged over lattice-vector bins: xi_pg(f, b); the galaxy
+ *     auto-correlation xi_gg(b) (Methodology, equation bpg_initial with the
+ *     weight W taken as the normalised indicator of one separation bin);
+ *   - xi(d_p) of each pair bin from weighted pair counts (2PCF section,
+ *     equation 2PCF_d_collapsed), b_pg = xi_pg / xi_gg (Introduction, eq. 1)
+ *     and Q_eff (Methodology, equations Qeff and Qeff_notsq).
+ *
+ * Conventions
+ *   - Lengths in the caller's unit (Mpc/h).  Line of sight = z axis.
+ *   - Grid node (a, b, c) sits at (a, b, c) * L / N; cloud-in-cell assignment.
+ *   - Pair (i, j), i < j by catalogue index, has d = x_j - x_i folded once
+ *     into [-L/2, L/2); position x_i + d/2 wrapped into [0, L); weight w_i w_j.
+ *   - Bins are half-open [e_k, e_{k+1}) and decided on squares against e*e in
+ *     FP64; the top |mu| edge is closed.  Field index f = b1 * n_p2 + b2,
+ *     output bin index b = o1 * n_o2 + o2 (n_o2 = 1 for shells).
+ *   - Arrays marked "device" are HIP device memory owned by the caller; the
+ *     library never frees them.  The plan owns its own device work memory
+ *     (grown on demand, released by pgx_plan_destroy).
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Calls enqueue work
+ *     on it; calls that return host values synchronise it (stated below).
+ *   - Every call returns a pgx_status; no exception or abort crosses the ABI.
+ *     On a non-OK status pgx_last_error() describes the failure (per thread).
+ *   - A plan is not thread-safe: use one plan per host thread and stream.
+ */
+#ifndef PGX_H
+#define PGX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pgx_plan pgx_plan;
+
+typedef enum {
+  PGX_OK = 0,
+  PGX_EINVAL = 1,   /* invalid argument or input data */
+  PGX_ENOSPACE = 2, /* device memory exhausted */
+  PGX_EHIP = 3,     /* HIP runtime error */
+  PGX_ENOTSUP = 4,  /* unsupported size (N not a power of two in [64, 1024], too many pairs) */
+  PGX_ESTATE = 5    /* call out of order (e.g. forward before pgx_pairs_build) */
+} pgx_status;
+
+typedef enum { PGX_PAIR_S_MU = 0, PGX_PAIR_RP_PI = 1 } pgx_pair_mode;
+typedef enum { PGX_OUT_SHELL = 0, PGX_OUT_R_MU = 1, PGX_OUT_RP_PI = 2 } pgx_out_mode;
+typedef enum { PGX_FP64_PLAIN = 0, PGX_FP32_BATCHED = 1 } pgx_precision;
+typedef enum { PGX_QEFF_NOTSQ = 0, PGX_QEFF_SQUEEZED = 1, PGX_QEFF_CONST_XIW = 2 } pgx_qeff_mode;
+
+/*
+ * Plan parameters.  Edge arrays are HOST arrays of n+1 strictly ascending
+ * values, copied at plan creation.
+ *   pair_mode S_MU : p1 = s edges (> 0 at the top), p2 = |mu| edges in [0, 1].
+ *   pair_mode RP_PI: p1 = r_p edges, p2 = |pi| edges (>= 0), pair_dmax = sphere
+ *                    radius (pairs kept iff |d| < pair_dmax).
+ *   out_mode SHELL : o1 = r edges (o2 ignored); R_MU: o1 = r, o2 = |mu| in
+ *                    [0, 1]; RP_PI: o1 = r_p, o2 = |pi|.
+ *   Requirements: the maximum pair separation < L/3 (cell list with at least
+ *   3 cells per side); the largest output edge < L/2; N a power of two in
+ *   [64, 1024]; n_fields * N^2 < 2^31.
+ *   precision FP64_PLAIN: one field at a time in FP64 (transforms, sums).
+ *             FP32_BATCHED: fields paired into complex grids, FP32 transforms
+ *             and products, FP64 bin sums, normalisations and ratios.
+ *   qeff_mode NOTSQ (default, equation Qeff_notsq with xi(d_w) := xi_gg(b)),
+ *             SQUEEZED (equation Qeff), CONST_XIW (Qeff_notsq with xi(d_w) =
+ *             xi_w_const, the paper's weighting-function table value).
+ *   batch: field pairs per batch on the batched path (0 = automatic).
+ */
+typedef struct {
+  double L;
+  int32_t N;
+  int32_t precision;
+  int32_t pair_mode;
+  int32_t n_p1;
+  const double* p1_edges;
+  int32_t n_p2;
+  const double* p2_edges;
+  double pair_dmax;
+  int32_t out_mode;
+  int32_t n_o1;
+  const double* o1_edges;
+  int32_t n_o2;
+  const double* o2_edges;
+  int32_t qeff_mode;
+  double xi_w_const;
+  int32_t batch;
+} pgx_params;
+
+/* Create a plan.  Validates the parameters (PGX_EINVAL / PGX_ENOTSUP) and
+ * builds the host-side bin tables; touches no device.  Device tables and
+ * work memory are created on the current HIP device at the first
+ * pgx_pairs_build, and the plan stays bound to that device. */
+pgx_status pgx_plan_create(const pgx_params* params, pgx_plan** out);
+
+/* Release the plan and all device memory it owns.  NULL is accepted. */
+pgx_status pgx_plan_destroy(pgx_plan* plan);
+
+/* Sizes: number of pair fields F, output bins R, and the half-widths of the
+ * lattice window holding every output bin (window[3], in grid cells). */
+pgx_status pgx_plan_info(const pgx_plan* plan, int32_t* n_fields, int32_t* n_out,
+                         int32_t* window);
+
+/* Exact lattice-vector count n_b of every output bin (HOST array [R]). */
+pgx_status pgx_out_counts(const pgx_plan* plan, int64_t* n_b);
+
+/* Volume of every pair bin (HOST array [F]) used by xi(d_p): the exact
+ * (s, |mu|) shell-sector volume, or the (r_p, |pi|) annulus-slab volume cut by
+ * the sphere |d| < pair_dmax, both signs of mu or pi included. */
+pgx_status pgx_field_volumes(const pgx_plan* plan, double* vol);
+
+/*
+ * Pair catalogue (steps: validate, cell list, close-pair search with integer
+ * keys, bucketing by field and grid line) and the galaxy point set.
+ *   x, y, z: device FP64 [n_gal] positions in [0, L).
+ *   n_pairs: HOST out, total number of pairs (this call synchronises stream).
+ *   counts:  device int64 [F] out (nullable), pairs per field.
+ * Positions are not referenced after the call returns.  Errors: EINVAL for
+ * non-finite or out-of-box positions, n_gal < 0 or >= 2^31; ENOTSUP when the
+ * pair count reaches 2^31.
+ */
+pgx_status pgx_pairs_build(pgx_plan* plan, const double* x, const double* y, const double* z,
+                           int64_t n_gal, void* stream, int64_t* n_pairs, int64_t* counts);
+
+/* Copy the bucketed pair list to device arrays [n_pairs]: field index, and the
+ * catalogue indices i < j.  Order: by field, then by grid line of the
+ * midpoint's lower CIC corner, then by search order (deterministic). */
+pgx_status pgx_pairs_export(pgx_plan* plan, int32_t* field, int32_t* i, int32_t* j, void* stream);
+
+/*
+ * Forward estimator for the catalogue of the last pgx_pairs_build.
+ *   w: device FP32 [n_gal] galaxy weights (>= 0, finite) or NULL for unit
+ *      weights.  Pair weights are w_i w_j.
+ *   Outputs (device FP64, each nullable except xi_pg): wsum [F] (sum of pair
+ *   weights per field), xi_gg [R], xi_pg [F][R], xi_dp [F], b_pg [F][R],
+ *   q_eff [F][R].  Empty pair fields give NaN rows of xi_pg, b_pg, q_eff.
+ *   The call keeps what pgx_backward needs inside the plan.  Errors: ESTATE
+ *   before pgx_pairs_build.
+ */
+pgx_status pgx_forward(pgx_plan* plan, const float* w, void* stream, double* wsum, double* xi_gg,
+                       double* xi_pg, double* xi_dp, double* b_pg, double* q_eff);
+
+/*
+ * Kernel timing.  pgx_profile(plan, 1) clears the counters and starts
+ * recording a pair of HIP events on the launch stream around every launch of
+ * the transform-pass kernels (the events bracket exactly one kernel each);
+ * pgx_profile(plan, 0) stops.  pgx_profile_read returns, for entry k (one per
+ * kernel kind, in order of first launch): its name (owned by the plan, valid
+ * until the next pgx_profile call), the number of launches, the summed
+ * event-measured time in ms, and the summed algorithmic bytes of those
+ * launches (the bytes each launch has to read and write: its input lines,
+ * the galaxy spectrum where it is read, its output lines).  It synchronises
+ * the recorded events.  EINVAL when k is out of range.
+ */
+pgx_status pgx_profile(pgx_plan* plan, int32_t enable);
+pgx_status pgx_profile_read(pgx_plan* plan, int32_t k, const char** name, int64_t* launches,
+                            double* ms, double* bytes);
+
+/* Message for the last non-OK status returned on this thread. */
+const char* pgx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PGX_H */

@@ -1,0 +1,237 @@
+// C-ABI of the pair-galaxy correlation library: plan creation and validation,
+// output-bin tables, pair-bin volumes, and dispatch to the engines.
+#include <memory>
+#include <string>
+
+#include "pgx_engine.hpp"
+
+namespace pgx {
+EngineBase* make_engine_f32(const PlanCfg& c);
+EngineBase* make_engine_f64(const PlanCfg& c);
+}  // namespace pgx
+
+struct pgx_plan {
+  pgx::PlanCfg cfg;
+  std::unique_ptr<pgx::EngineBase> eng;  // created on first device use
+  pgx::EngineBase& engine() {
+    if (!eng) {
+      pgx::EngineBase* e = cfg.precision == PGX_FP32_BATCHED ? pgx::make_engine_f32(cfg)
+                                                             : pgx::make_engine_f64(cfg);
+      PGX_REQUIRE(e != nullptr, PGX_ENOTSUP, "unsupported grid size");
+      eng.reset(e);
+    }
+    return *eng;
+  }
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+pgx_status fail(pgx_status code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+template <typename F> pgx_status guarded(F&& f) {
+  try {
+    f();
+    return PGX_OK;
+  } catch (const pgx::Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(PGX_ENOSPACE, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(PGX_EHIP, e.what());
+  } catch (...) {
+    return fail(PGX_EHIP, "unknown error");
+  }
+}
+
+std::vector<double> edges(const double* p, int n, const char* name) {
+  PGX_REQUIRE(n >= 1 && p != nullptr, PGX_EINVAL, std::string(name) + ": need n >= 1 and edges");
+  std::vector<double> v(p, p + n + 1);
+  for (int i = 0; i <= n; ++i)
+    PGX_REQUIRE(std::isfinite(v[i]), PGX_EINVAL, std::string(name) + ": non-finite edge");
+  for (int i = 0; i < n; ++i)
+    PGX_REQUIRE(v[i] < v[i + 1], PGX_EINVAL, std::string(name) + ": edges must be strictly ascending");
+  return v;
+}
+
+void build_cfg(const pgx_params* p, pgx::PlanCfg& c) {
+  PGX_REQUIRE(p != nullptr, PGX_EINVAL, "params is NULL");
+  PGX_REQUIRE(std::isfinite(p->L) && p->L > 0, PGX_EINVAL, "L must be finite and > 0");
+  const int N = p->N;
+  PGX_REQUIRE(N >= 64 && N <= 1024 && (N & (N - 1)) == 0, PGX_ENOTSUP,
+              "N must be a power of two in [64, 1024]");
+  PGX_REQUIRE(p->precision == PGX_FP64_PLAIN || p->precision == PGX_FP32_BATCHED, PGX_EINVAL,
+              "unknown precision");
+  PGX_REQUIRE(p->pair_mode == PGX_PAIR_S_MU || p->pair_mode == PGX_PAIR_RP_PI, PGX_EINVAL,
+              "unknown pair_mode");
+  PGX_REQUIRE(p->out_mode >= PGX_OUT_SHELL && p->out_mode <= PGX_OUT_RP_PI, PGX_EINVAL,
+              "unknown out_mode");
+  PGX_REQUIRE(p->qeff_mode >= PGX_QEFF_NOTSQ && p->qeff_mode <= PGX_QEFF_CONST_XIW, PGX_EINVAL,
+              "unknown qeff_mode");
+  c.L = p->L;
+  c.N = N;
+  c.precision = p->precision;
+  c.pair_mode = p->pair_mode;
+  c.out_mode = p->out_mode;
+  c.qeff_mode = p->qeff_mode;
+  c.xi_w_const = p->xi_w_const;
+  c.batch = p->batch;
+  c.pair_dmax = p->pair_dmax;
+  c.p1 = edges(p->p1_edges, p->n_p1, "p1_edges");
+  c.p2 = edges(p->p2_edges, p->n_p2, "p2_edges");
+  c.o1 = edges(p->o1_edges, p->n_o1, "o1_edges");
+  if (c.out_mode != PGX_OUT_SHELL) c.o2 = edges(p->o2_edges, p->n_o2, "o2_edges");
+  PGX_REQUIRE(c.p1[0] >= 0, PGX_EINVAL, "p1_edges must be >= 0");
+  PGX_REQUIRE(c.p2[0] >= 0, PGX_EINVAL, "p2_edges must be >= 0");
+  PGX_REQUIRE(c.o1[0] >= 0, PGX_EINVAL, "o1_edges must be >= 0");
+  if (c.pair_mode == PGX_PAIR_S_MU) {
+    PGX_REQUIRE(c.p2.back() <= 1.0, PGX_EINVAL, "|mu| edges must lie in [0, 1]");
+    c.smax = c.p1.back();
+  } else {
+    PGX_REQUIRE(std::isfinite(c.pair_dmax) && c.pair_dmax > 0, PGX_EINVAL, "pair_dmax must be > 0");
+    c.smax = std::min(c.pair_dmax, std::hypot(c.p1.back(), c.p2.back()));
+  }
+  PGX_REQUIRE(c.smax > 0 && c.smax < c.L / 3.0, PGX_EINVAL,
+              "maximum pair separation must be in (0, L/3)");
+  if (c.out_mode == PGX_OUT_R_MU) {
+    PGX_REQUIRE(c.o2[0] >= 0 && c.o2.back() <= 1.0, PGX_EINVAL, "output |mu| edges must lie in [0, 1]");
+  } else if (c.out_mode == PGX_OUT_RP_PI) {
+    PGX_REQUIRE(c.o2[0] >= 0, PGX_EINVAL, "output |pi| edges must be >= 0");
+  }
+  const double delta = c.L / N;
+  double top1 = c.o1.back();
+  double topz = c.out_mode == PGX_OUT_RP_PI ? c.o2.back() : top1;
+  PGX_REQUIRE(top1 < c.L / 2 && topz < c.L / 2, PGX_EINVAL, "output bins must stay below L/2");
+  const int w1 = (int)std::floor(top1 / delta), wz = (int)std::floor(topz / delta);
+  PGX_REQUIRE(w1 <= N / 2 - 1 && wz <= N / 2 - 1, PGX_EINVAL, "output window reaches N/2");
+  c.pw[0] = w1;
+  c.pw[1] = w1;
+  c.pw[2] = wz;
+  const int n_p1 = (int)c.p1.size() - 1, n_p2 = (int)c.p2.size() - 1;
+  c.F = n_p1 * n_p2;
+  c.n_fp = (c.F + 1) / 2;
+  const int n_o2 = c.out_mode == PGX_OUT_SHELL ? 1 : (int)c.o2.size() - 1;
+  c.R = ((int)c.o1.size() - 1) * n_o2;
+  PGX_REQUIRE(c.R <= pgx::kRMax, PGX_ENOTSUP, "too many output bins");
+  PGX_REQUIRE((int64_t)c.F * N * N + 1 < (int64_t)INT32_MAX, PGX_ENOTSUP, "n_fields * N^2 too large");
+  // bin tables
+  pgx::HostBins& hb = c.bins;
+  hb.mode = c.out_mode;
+  hb.n2 = n_o2;
+  if (c.out_mode == PGX_OUT_RP_PI) {
+    hb.lut1 = pgx::bin_lut(c.o1, delta, (int64_t)2 * w1 * w1 + 1);
+    hb.lut2 = pgx::bin_lut(c.o2, delta, (int64_t)wz * wz + 1);
+  } else {
+    hb.lut1 = pgx::bin_lut(c.o1, delta, (int64_t)3 * w1 * w1 + 1);
+    if (c.out_mode == PGX_OUT_R_MU) {
+      hb.mu2.resize(c.o2.size());
+      for (size_t i = 0; i < c.o2.size(); ++i) hb.mu2[i] = c.o2[i] * c.o2[i];
+    }
+  }
+  c.nb.assign(c.R, 0);
+  for (int k = -wz; k <= wz; ++k)
+    for (int j = -w1; j <= w1; ++j)
+      for (int i = -w1; i <= w1; ++i) {
+        const int b = hb.classify(i, j, k);
+        if (b >= 0) c.nb[b] += 1;
+      }
+  // pair-bin volumes
+  c.vol.clear();
+  for (int a = 0; a < n_p1; ++a)
+    for (int b = 0; b < n_p2; ++b)
+      c.vol.push_back(c.pair_mode == PGX_PAIR_S_MU
+                          ? pgx::vol_s_mu(c.p1[a], c.p1[a + 1], c.p2[b], c.p2[b + 1])
+                          : pgx::vol_rp_pi(c.p1[a], c.p1[a + 1], c.p2[b], c.p2[b + 1], c.pair_dmax));
+}
+
+}  // namespace
+
+extern "C" {
+
+pgx_status pgx_plan_create(const pgx_params* params, pgx_plan** out) {
+  if (!out) return fail(PGX_EINVAL, "out is NULL");
+  *out = nullptr;
+  return guarded([&] {
+    std::unique_ptr<pgx_plan> p(new pgx_plan());
+    build_cfg(params, p->cfg);
+    *out = p.release();
+  });
+}
+
+pgx_status pgx_plan_destroy(pgx_plan* plan) {
+  return guarded([&] { delete plan; });
+}
+
+pgx_status pgx_plan_info(const pgx_plan* plan, int32_t* n_fields, int32_t* n_out, int32_t* window) {
+  if (!plan) return fail(PGX_EINVAL, "plan is NULL");
+  if (n_fields) *n_fields = plan->cfg.F;
+  if (n_out) *n_out = plan->cfg.R;
+  if (window)
+    for (int i = 0; i < 3; ++i) window[i] = plan->cfg.pw[i];
+  return PGX_OK;
+}
+
+pgx_status pgx_out_counts(const pgx_plan* plan, int64_t* n_b) {
+  if (!plan || !n_b) return fail(PGX_EINVAL, "NULL argument");
+  for (int b = 0; b < plan->cfg.R; ++b) n_b[b] = plan->cfg.nb[b];
+  return PGX_OK;
+}
+
+pgx_status pgx_field_volumes(const pgx_plan* plan, double* vol) {
+  if (!plan || !vol) return fail(PGX_EINVAL, "NULL argument");
+  for (int f = 0; f < plan->cfg.F; ++f) vol[f] = plan->cfg.vol[f];
+  return PGX_OK;
+}
+
+pgx_status pgx_pairs_build(pgx_plan* plan, const double* x, const double* y, const double* z,
+                           int64_t n_gal, void* stream, int64_t* n_pairs, int64_t* counts) {
+  if (!plan) return fail(PGX_EINVAL, "plan is NULL");
+  return guarded([&] {
+    plan->engine().pairs_build(x, y, z, n_gal, (hipStream_t)stream, n_pairs, counts);
+  });
+}
+
+pgx_status pgx_pairs_export(pgx_plan* plan, int32_t* field, int32_t* i, int32_t* j, void* stream) {
+  if (!plan) return fail(PGX_EINVAL, "plan is NULL");
+  return guarded([&] { plan->engine().pairs_export(field, i, j, (hipStream_t)stream); });
+}
+
+pgx_status pgx_forward(pgx_plan* plan, const float* w, void* stream, double* wsum, double* xi_gg,
+                       double* xi_pg, double* xi_dp, double* b_pg, double* q_eff) {
+  if (!plan) return fail(PGX_EINVAL, "plan is NULL");
+  return guarded([&] {
+    plan->engine().forward(w, (hipStream_t)stream, wsum, xi_gg, xi_pg, xi_dp, b_pg, q_eff);
+  });
+}
+
+pgx_status pgx_profile(pgx_plan* plan, int32_t enable) {
+  if (!plan) return fail(PGX_EINVAL, "plan is NULL");
+  return guarded([&] {
+    auto& pr = plan->engine().prof;
+    pr.reset();
+    pr.on = enable != 0;
+  });
+}
+
+pgx_status pgx_profile_read(pgx_plan* plan, int32_t k, const char** name, int64_t* launches,
+                            double* ms, double* bytes) {
+  if (!plan) return fail(PGX_EINVAL, "plan is NULL");
+  return guarded([&] {
+    auto& pr = plan->engine().prof;
+    pr.collect();
+    PGX_REQUIRE(k >= 0 && k < (int32_t)pr.cats.size(), PGX_EINVAL, "no such profile entry");
+    const auto& c = pr.cats[k];
+    if (name) *name = c.name.c_str();
+    if (launches) *launches = c.launches;
+    if (ms) *ms = c.ms;
+    if (bytes) *bytes = c.bytes;
+  });
+}
+
+const char* pgx_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

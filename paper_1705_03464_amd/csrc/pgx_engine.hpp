@@ -1,0 +1,648 @@
+// Engine: device buffers and launch sequences of one plan, templated on the
+// transform precision T and the grid side N.
+#pragma once
+#include "pgx_misc.hpp"
+#include "pgx_pairs.hpp"
+#include "pgx_prim.hpp"
+
+#include <type_traits>
+
+namespace pgx {
+
+struct PlanCfg {
+  double L = 0, pair_dmax = 0, xi_w_const = 0, smax = 0;
+  int N = 0, precision = 1, pair_mode = 0, out_mode = 0, qeff_mode = 0, batch = 0;
+  std::vector<double> p1, p2, o1, o2;
+  int F = 0, R = 0, n_fp = 0;
+  int pw[3] = {0, 0, 0};
+  HostBins bins;
+  std::vector<int64_t> nb;
+  std::vector<double> vol;
+};
+
+// Per-kernel timing with HIP events recorded on the launch stream around each
+// launch of the instrumented kernels, plus the algorithmic bytes each launch
+// must move (reads + writes of the data it is defined on).
+struct Profiler {
+  struct Cat {
+    std::string name;
+    int64_t launches = 0;
+    double bytes = 0.0, ms = 0.0;
+  };
+  bool on = false;
+  std::vector<Cat> cats;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  std::vector<hipEvent_t> pool;
+
+  int cat(const char* name) {
+    for (size_t i = 0; i < cats.size(); ++i)
+      if (cats[i].name == name) return (int)i;
+    cats.push_back(Cat{name});
+    return (int)cats.size() - 1;
+  }
+  hipEvent_t ev() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    PGX_HIP(hipEventCreate(&e));
+    return e;
+  }
+  template <typename Fn> void run(const char* name, hipStream_t s, double bytes, Fn&& launch) {
+    if (!on) {
+      launch();
+      return;
+    }
+    const int c = cat(name);
+    hipEvent_t a = ev(), b = ev();
+    PGX_HIP(hipEventRecord(a, s));
+    launch();
+    PGX_HIP(hipEventRecord(b, s));
+    pending.push_back({c, {a, b}});
+    cats[c].launches += 1;
+    cats[c].bytes += bytes;
+  }
+  void collect() {
+    for (auto& p : pending) {
+      PGX_HIP(hipEventSynchronize(p.second.second));
+      float ms = 0.f;
+      PGX_HIP(hipEventElapsedTime(&ms, p.second.first, p.second.second));
+      cats[p.first].ms += ms;
+      pool.push_back(p.second.first);
+      pool.push_back(p.second.second);
+    }
+    pending.clear();
+  }
+  void reset() {
+    collect();
+    cats.clear();
+  }
+  ~Profiler() {
+    for (auto& p : pending) {
+      (void)hipEventDestroy(p.second.first);
+      (void)hipEventDestroy(p.second.second);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+struct EngineBase {
+  virtual ~EngineBase() = default;
+  Profiler prof;
+  virtual void pairs_build(const double* x, const double* y, const double* z, int64_t n,
+                           hipStream_t s, int64_t* n_pairs, int64_t* counts) = 0;
+  virtual void pairs_export(int32_t* f, int32_t* i, int32_t* j, hipStream_t s) = 0;
+  virtual void forward(const float* w, hipStream_t s, double* wsum, double* xi_gg, double* xi_pg,
+                       double* xi_dp, double* b_pg, double* q_eff) = 0;
+  bool built = false;
+};
+
+constexpr int kRMax = 640;  // largest number of output bins handled by the bin kernels
+
+template <typename T, int N> struct Engine : EngineBase {
+  using Sh = typename DefaultShape<T, N>::type;
+  static constexpr int TPL = Sh::TPL;
+  static constexpr int W = (256 / TPL) < N ? (256 / TPL) : N;
+  static constexpr int NT = W * TPL;
+  static constexpr int64_t NN = (int64_t)N * N;
+  static constexpr int64_t NC = NN * N;
+
+  const PlanCfg& cfg;
+  int B = 1;          // field pairs per batch
+  int n_batches = 0;
+  int64_t n_gal = 0, n_pairs = 0;
+  std::vector<int64_t> batch_task_off;  // host, n_batches + 1
+  std::vector<int64_t> field_counts_h;  // host, pairs per field
+
+  // constant tables
+  DBuf tw, lut1, lut2, mu2, nbd, vold, t1, t2, slot_fa, slot_fb, slot_fp, gslot_fa, gslot_fb,
+      fidx, neg1;
+  // catalogue
+  DBuf g_key, g_ls, g_x0, g_fx, g_fy, g_fz, g_idx, g_wt, g_tasks;
+  DBuf p_key, p_ls, p_i, p_j, p_x0, p_fx, p_fy, p_fz, p_wt;
+  DBuf lflag, pflag, tasks;
+  // scratch for the build
+  DBuf s_tmp, s_k0, s_k1, s_v0, s_v1, s_cnt, s_off, s_px, s_py, s_pz, s_cell, s_cs, s_hist, s_err,
+      s_i, s_j, s_x0, s_fx, s_fy, s_fz, s_pos;
+  // forward work
+  DBuf X, P1, P2, Fg, part, S, Sgg, wsum_d, wg_d, outs;
+
+  explicit Engine(const PlanCfg& c) : cfg(c) {
+    static_assert(N % W == 0, "tile width must divide N");
+    std::vector<C<T>> h(N);
+    for (int k = 0; k < N; ++k) {
+      const double a = -2.0 * kPi * (double)k / (double)N;
+      h[k] = C<T>{(T)std::cos(a), (T)std::sin(a)};
+    }
+    upload(tw, h);
+    upload(lut1, cfg.bins.lut1);
+    upload(lut2, cfg.bins.lut2.empty() ? std::vector<int16_t>{-1} : cfg.bins.lut2);
+    upload(mu2, cfg.bins.mu2.empty() ? std::vector<double>{0.0} : cfg.bins.mu2);
+    std::vector<double> nbv(cfg.nb.begin(), cfg.nb.end());
+    upload(nbd, nbv);
+    upload(vold, cfg.vol);
+    std::vector<double> a1(cfg.p1.size()), a2(cfg.p2.size());
+    for (size_t i = 0; i < a1.size(); ++i) a1[i] = cfg.p1[i] * cfg.p1[i];
+    for (size_t i = 0; i < a2.size(); ++i) a2[i] = cfg.p2[i] * cfg.p2[i];
+    upload(t1, a1);
+    upload(t2, a2);
+    const int nfp = cfg.n_fp;
+    int b = cfg.batch;
+    if (b <= 0) b = N >= 512 ? 8 : (N >= 256 ? 16 : 32);
+    B = std::max(1, std::min(b, nfp));
+    n_batches = (nfp + B - 1) / B;
+    std::vector<int32_t> fa((size_t)n_batches * B, -1), fb((size_t)n_batches * B, -1),
+        fp((size_t)n_batches * B, 0);
+    for (int k = 0; k < nfp; ++k) {
+      fa[k] = 2 * k;
+      fb[k] = 2 * k + 1 < cfg.F ? 2 * k + 1 : -1;
+      fp[k] = k;
+    }
+    upload(slot_fa, fa);
+    upload(slot_fb, fb);
+    upload(slot_fp, fp);
+    upload(gslot_fa, std::vector<int32_t>{0});
+    upload(gslot_fb, std::vector<int32_t>{-1});
+    upload(neg1, std::vector<int32_t>{-1});
+    std::vector<int32_t> fi(std::max(cfg.F, 1));
+    for (int f = 0; f < (int)fi.size(); ++f) fi[f] = f;
+    upload(fidx, fi);
+    std::vector<int32_t> gt(NN);
+    for (int64_t l = 0; l < NN; ++l) gt[l] = (int32_t)l;
+    upload(g_tasks, gt);
+    PGX_HIP(hipDeviceSynchronize());
+  }
+
+  template <typename V> static void upload(DBuf& d, const std::vector<V>& h) {
+    d.ensure(h.size() * sizeof(V));
+    if (!h.empty()) PGX_HIP(hipMemcpy(d.p, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice));
+  }
+
+  BinMap binmap() const {
+    BinMap bm;
+    bm.mode = cfg.out_mode;
+    bm.n2 = cfg.out_mode == 0 ? 1 : (int)cfg.o2.size() - 1;
+    bm.lut1 = lut1.as<int16_t>();
+    bm.lut1_n = (int)cfg.bins.lut1.size();
+    bm.lut2 = lut2.as<int16_t>();
+    bm.lut2_n = (int)cfg.bins.lut2.size();
+    bm.mu2 = mu2.as<double>();
+    return bm;
+  }
+
+  // ------------------------------------------------------------------------
+  // pair catalogue
+  // ------------------------------------------------------------------------
+  void pairs_build(const double* x, const double* y, const double* z, int64_t n, hipStream_t s,
+                   int64_t* n_pairs_out, int64_t* counts) override {
+    PGX_REQUIRE(n >= 0 && n < INT32_MAX, PGX_EINVAL, "n_gal must be in [0, 2^31)");
+    PGX_REQUIRE(n == 0 || (x && y && z), PGX_EINVAL, "positions must not be NULL");
+    built = false;
+    n_gal = n;
+    const int F = cfg.F;
+    // validate
+    int* err = s_err.get<int>(1);
+    k_fill_i32(err, 1, s);
+    if (n > 0) {
+      k_validate<<<grid_for(n), 256, 0, s>>>(x, y, z, nullptr, n, cfg.L, err);
+      launch_check("validate");
+    }
+    int herr = 0;
+    PGX_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
+    PGX_HIP(hipStreamSynchronize(s));
+    PGX_REQUIRE(!(herr & 1), PGX_EINVAL, "non-finite galaxy position");
+    PGX_REQUIRE(!(herr & 2), PGX_EINVAL, "galaxy position outside [0, L)");
+
+    // cell list: side >= maximum pair separation
+    int nc = (int)std::floor(cfg.L / (cfg.smax * (1.0 + 1e-12)));
+    PGX_REQUIRE(nc >= 3, PGX_EINVAL, "maximum pair separation must be < L/3");
+    const double side = cfg.L / nc;
+    const int64_t ncell = (int64_t)nc * nc * nc;
+    int32_t* ck = s_k0.get<int32_t>(n);
+    int32_t* ci = s_v0.get<int32_t>(n);
+    int32_t* cks = s_k1.get<int32_t>(n);
+    int32_t* perm = s_v1.get<int32_t>(n);
+    if (n > 0) {
+      k_cell_keys<<<grid_for(n), 256, 0, s>>>(x, y, z, n, side, nc, ck, ci);
+      launch_check("cell_keys");
+    }
+    sort_pairs_i32(ck, cks, ci, perm, n, bits_for(ncell), s, s_tmp);
+    int32_t* hist = s_hist.get<int32_t>(ncell + 1);
+    int32_t* cstart = s_cs.get<int32_t>(ncell + 1);
+    counts_to_starts(cks, n, ncell, hist, cstart, s);
+    double* px = s_px.get<double>(n);
+    double* py = s_py.get<double>(n);
+    double* pz = s_pz.get<double>(n);
+    if (n > 0) {
+      k_gather_pos<<<grid_for(n), 256, 0, s>>>(perm, x, y, z, n, px, py, pz);
+      launch_check("gather_pos");
+    }
+    PairCfg pc;
+    pc.L = cfg.L;
+    pc.halfL = cfg.L * 0.5;
+    pc.gscale = (double)N / cfg.L;
+    pc.side = side;
+    pc.nc = nc;
+    pc.N = N;
+    pc.mode = cfg.pair_mode;
+    pc.n1 = (int)cfg.p1.size() - 1;
+    pc.n2 = (int)cfg.p2.size() - 1;
+    pc.t1 = t1.as<double>();
+    pc.t2 = t2.as<double>();
+    pc.dmax2 = cfg.pair_dmax * cfg.pair_dmax;
+    int64_t* cnt = s_cnt.get<int64_t>(n + 1);
+    int64_t* off = s_off.get<int64_t>(n + 1);
+    int64_t P = 0;
+    if (n > 0) {
+      k_pairs<false, T><<<grid_for(n), 256, 0, s>>>(pc, px, py, pz, perm, cks, cstart, n, cnt,
+                                                    nullptr, nullptr, nullptr, nullptr, nullptr,
+                                                    nullptr, nullptr);
+      launch_check("pair_count");
+      exscan_i64(cnt, off, n, s, s_tmp);
+      int64_t last[2] = {0, 0};
+      PGX_HIP(hipMemcpyAsync(&last[0], off + n - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      PGX_HIP(hipMemcpyAsync(&last[1], cnt + n - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      PGX_HIP(hipStreamSynchronize(s));
+      P = last[0] + last[1];
+    }
+    PGX_REQUIRE(P < (int64_t)INT32_MAX, PGX_ENOTSUP, "pair count reaches 2^31");
+    n_pairs = P;
+    int32_t* uk = s_k0.get<int32_t>(P);
+    int32_t* ui = s_i.get<int32_t>(P);
+    int32_t* uj = s_j.get<int32_t>(P);
+    int32_t* ux0 = s_x0.get<int32_t>(P);
+    T* ufx = s_fx.get<T>(P);
+    T* ufy = s_fy.get<T>(P);
+    T* ufz = s_fz.get<T>(P);
+    if (P > 0) {
+      k_pairs<true, T><<<grid_for(n), 256, 0, s>>>(pc, px, py, pz, perm, cks, cstart, n, off, uk,
+                                                   ui, uj, ux0, ufx, ufy, ufz);
+      launch_check("pair_emit");
+    }
+    // bucket by (field, line)
+    int32_t* iota = s_v0.get<int32_t>(P);
+    if (P > 0) {
+      k_iota<<<grid_for(P), 256, 0, s>>>(iota, P);
+      launch_check("iota");
+    }
+    int32_t* sk = p_key.get<int32_t>(P);
+    int32_t* pp = s_v1.get<int32_t>(P);
+    const int64_t nkeys = (int64_t)F * NN;
+    sort_pairs_i32(uk, sk, iota, pp, P, bits_for(nkeys), s, s_tmp);
+    gather(pp, ui, p_i.get<int32_t>(P), P, s);
+    gather(pp, uj, p_j.get<int32_t>(P), P, s);
+    gather(pp, ux0, p_x0.get<int32_t>(P), P, s);
+    gather(pp, ufx, p_fx.get<T>(P), P, s);
+    gather(pp, ufy, p_fy.get<T>(P), P, s);
+    gather(pp, ufz, p_fz.get<T>(P), P, s);
+    p_wt.get<T>(P);
+    int32_t* pls = p_ls.get<int32_t>(nkeys + 1);
+    counts_to_starts(sk, P, nkeys, s_hist.get<int32_t>(nkeys + 1), pls, s);
+    {
+      int64_t* cdev = s_cnt.get<int64_t>(std::max<int64_t>(n + 1, F));
+      k_field_counts<<<grid_for(F), 256, 0, s>>>(pls, NN, F, cdev);
+      launch_check("field_counts");
+      field_counts_h.assign(F, 0);
+      PGX_HIP(hipMemcpyAsync(field_counts_h.data(), cdev, F * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      if (counts)
+        PGX_HIP(hipMemcpyAsync(counts, cdev, F * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    }
+    // galaxy point set
+    int32_t* gk = s_k0.get<int32_t>(n);
+    int32_t* gi = s_v0.get<int32_t>(n);
+    int32_t* gx0 = s_x0.get<int32_t>(n);
+    T* gfx = s_fx.get<T>(n);
+    T* gfy = s_fy.get<T>(n);
+    T* gfz = s_fz.get<T>(n);
+    if (n > 0) {
+      k_gal_points<T><<<grid_for(n), 256, 0, s>>>(x, y, z, n, (double)N / cfg.L, N, gk, gi, gx0,
+                                                  gfx, gfy, gfz);
+      launch_check("gal_points");
+    }
+    int32_t* gks = g_key.get<int32_t>(n);
+    int32_t* gp = s_v1.get<int32_t>(n);
+    sort_pairs_i32(gk, gks, gi, gp, n, bits_for(NN), s, s_tmp);
+    // gp is the sorted catalogue index
+    PGX_HIP(hipMemcpyAsync(g_idx.get<int32_t>(n), gp, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    gather(gp, gx0, g_x0.get<int32_t>(n), n, s);
+    gather(gp, gfx, g_fx.get<T>(n), n, s);
+    gather(gp, gfy, g_fy.get<T>(n), n, s);
+    gather(gp, gfz, g_fz.get<T>(n), n, s);
+    g_wt.get<T>(n);
+    counts_to_starts(gks, n, NN, s_hist.get<int32_t>(NN + 1), g_ls.get<int32_t>(NN + 1), s);
+
+    // non-empty lines of every field pair and the x-pass task lists
+    if constexpr (std::is_same<T, float>::value) {
+      const int64_t nfl = (int64_t)cfg.n_fp * NN;
+      // one extra zero entry so the exclusive scan over nfl + 1 entries yields the total
+      uint8_t* lf = lflag.get<uint8_t>(nfl + 1);
+      k_fill_u8(lf, nfl + 1, s);
+      if (P > 0) {
+        k_mark_lines<<<grid_for(P), 256, 0, s>>>(sk, P, N, lf);
+        launch_check("mark_lines");
+      }
+      uint8_t* pf = pflag.get<uint8_t>((int64_t)cfg.n_fp * N);
+      k_plane_flags<<<grid_for((int64_t)cfg.n_fp * N), 256, 0, s>>>(lf, N, (int64_t)cfg.n_fp * N, pf);
+      launch_check("plane_flags");
+      int32_t* pos = s_pos.get<int32_t>(nfl + 1);
+      exscan_u8_i32(lf, pos, nfl + 1, s, s_tmp);  // entry nfl is the total
+      std::vector<int32_t> hpos(n_batches + 1);
+      for (int k = 0; k <= n_batches; ++k) {
+        const int64_t e = std::min<int64_t>((int64_t)k * B, cfg.n_fp) * NN;
+        PGX_HIP(hipMemcpyAsync(&hpos[k], pos + e, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      }
+      PGX_HIP(hipStreamSynchronize(s));
+      batch_task_off.assign(hpos.begin(), hpos.end());
+      int32_t* tk = tasks.get<int32_t>(std::max<int64_t>(hpos[n_batches], 1));
+      k_emit_tasks<<<grid_for(nfl), 256, 0, s>>>(lf, pos, nfl, N, B, tk);
+      launch_check("emit_tasks");
+    }
+    PGX_HIP(hipStreamSynchronize(s));
+    if (n_pairs_out) *n_pairs_out = P;
+    built = true;
+  }
+
+  // pairs in the fields of batch k (host copy taken at build time)
+  int64_t batch_points(int k) const {
+    if (field_counts_h.empty()) return 0;
+    int64_t n = 0;
+    for (int f = 2 * k * B; f < std::min(2 * (k + 1) * B, cfg.F); ++f) n += field_counts_h[f];
+    return n;
+  }
+
+  static int bits_for(int64_t nkeys) {
+    int b = 1;
+    while (b < 31 && ((int64_t)1 << b) < nkeys) ++b;
+    return b;
+  }
+
+  template <typename V> void gather(const int32_t* perm, const V* src, V* dst, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    k_gather<V><<<grid_for(n), 256, 0, s>>>(perm, src, n, dst);
+    launch_check("gather");
+  }
+
+  void k_fill_i32(int32_t* p, int64_t n, hipStream_t s) {
+    k_fill_value<int32_t><<<grid_for(n), 256, 0, s>>>(p, n, 0);
+    launch_check("fill");
+  }
+  void k_fill_u8(uint8_t* p, int64_t n, hipStream_t s) {
+    k_fill_value<uint8_t><<<std::min(grid_for(n), 65536), 256, 0, s>>>(p, n, 0);
+    launch_check("fill");
+  }
+
+  // starts[k] = first index of sorted keys with key >= k, for k in [0, nkeys]
+  void counts_to_starts(const int32_t* sorted, int64_t n, int64_t nkeys, int32_t* hist,
+                        int32_t* starts, hipStream_t s) {
+    k_fill_value<int32_t><<<std::min(grid_for(nkeys + 1), 65536), 256, 0, s>>>(hist, nkeys + 1, 0);
+    launch_check("fill");
+    if (n > 0) {
+      k_histogram<<<grid_for(n), 256, 0, s>>>(sorted, n, hist);
+      launch_check("histogram");
+    }
+    exscan_i32(hist, starts, nkeys + 1, s, s_tmp);
+  }
+
+  void pairs_export(int32_t* f, int32_t* i, int32_t* j, hipStream_t s) override {
+    PGX_REQUIRE(built, PGX_ESTATE, "pgx_pairs_build has not been called");
+    if (n_pairs == 0) return;
+    k_export_pairs<<<grid_for(n_pairs), 256, 0, s>>>(p_key.as<int32_t>(), p_i.as<int32_t>(),
+                                                     p_j.as<int32_t>(), n_pairs, NN, f, i, j);
+    launch_check("export");
+  }
+
+  // ------------------------------------------------------------------------
+  // forward
+  // ------------------------------------------------------------------------
+  void weights(const float* w, hipStream_t s) {
+    const int F = cfg.F;
+    if (n_pairs > 0) {
+      k_pair_weights<T><<<grid_for(n_pairs), 256, 0, s>>>(p_i.as<int32_t>(), p_j.as<int32_t>(), w,
+                                                          n_pairs, p_wt.as<T>());
+      launch_check("pair_weights");
+    }
+    if (n_gal > 0) {
+      k_gather_weights<T><<<grid_for(n_gal), 256, 0, s>>>(g_idx.as<int32_t>(), w, n_gal, g_wt.as<T>());
+      launch_check("gal_weights");
+    }
+    k_field_wsum<<<F, 256, 0, s>>>(p_ls.as<int32_t>(), NN, p_i.as<int32_t>(), p_j.as<int32_t>(), w,
+                                   wsum_d.get<double>(F));
+    launch_check("field_wsum");
+    k_weight_total<<<1, 256, 0, s>>>(w, n_gal, wg_d.get<double>(1));
+    launch_check("weight_total");
+  }
+
+  PointSet<T> gal_set() const {
+    return PointSet<T>{g_ls.as<int32_t>(), g_x0.as<int32_t>(), g_fx.as<T>(), g_fy.as<T>(),
+                       g_fz.as<T>(), g_wt.as<T>()};
+  }
+  PointSet<T> pair_set() const {
+    return PointSet<T>{p_ls.as<int32_t>(), p_x0.as<int32_t>(), p_fx.as<T>(), p_fy.as<T>(),
+                       p_fz.as<T>(), p_wt.as<T>()};
+  }
+
+  void finalize(hipStream_t s, double* xi_gg, double* xi_pg, double* xi_dp, double* b_pg,
+                double* q_eff, double* wsum) {
+    const int F = cfg.F, R = cfg.R;
+    // outputs not requested go to plan scratch
+    double* base = outs.get<double>(3 * (int64_t)F * R + F + R + 8);
+    FinalizeArgs a;
+    a.F = F;
+    a.R = R;
+    a.qmode = cfg.qeff_mode;
+    a.L = cfg.L;
+    a.xi_w_const = cfg.xi_w_const;
+    a.S = S.as<double>();
+    a.Sgg = Sgg.as<double>();
+    a.nb = nbd.as<double>();
+    a.vol = vold.as<double>();
+    a.wsum = wsum_d.as<double>();
+    a.wg = wg_d.as<double>();
+    a.xi_gg = xi_gg ? xi_gg : base;
+    a.xi_pg = xi_pg;
+    a.xi_dp = xi_dp ? xi_dp : base + R;
+    a.b_pg = b_pg ? b_pg : base + R + F;
+    a.q_eff = q_eff ? q_eff : base + R + F + (int64_t)F * R;
+    k_finalize<<<grid_for((int64_t)F * R + F + R), 256, 0, s>>>(a);
+    launch_check("finalize");
+    if (wsum) PGX_HIP(hipMemcpyAsync(wsum, wsum_d.p, F * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+
+  void forward(const float* w, hipStream_t s, double* wsum, double* xi_gg, double* xi_pg,
+               double* xi_dp, double* b_pg, double* q_eff) override {
+    PGX_REQUIRE(built, PGX_ESTATE, "pgx_pairs_build has not been called");
+    PGX_REQUIRE(xi_pg != nullptr, PGX_EINVAL, "xi_pg must not be NULL");
+    if (w && n_gal > 0) {
+      int* err = s_err.get<int>(1);
+      k_fill_i32(err, 1, s);
+      k_validate_w<<<grid_for(n_gal), 256, 0, s>>>(w, n_gal, err);
+      launch_check("validate_w");
+      int herr = 0;
+      PGX_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
+      PGX_HIP(hipStreamSynchronize(s));
+      PGX_REQUIRE(!herr, PGX_EINVAL, "weights must be finite and >= 0");
+    }
+    S.get<double>((int64_t)cfg.F * cfg.R);
+    Sgg.get<double>(cfg.R);
+    weights(w, s);
+    if constexpr (std::is_same<T, float>::value)
+      forward_batched(s);
+    else
+      forward_plain(s);
+    finalize(s, xi_gg, xi_pg, xi_dp, b_pg, q_eff, wsum);
+  }
+
+  int pwx() const { return cfg.pw[0]; }
+  int pwy() const { return cfg.pw[1]; }
+  int pwz() const { return cfg.pw[2]; }
+
+  void forward_batched(hipStream_t s) {
+    const int R = cfg.R;
+    const int ny = win_len(pwy()), nz = win_len(pwz());
+    const int nblkE = (ny * nz + W - 1) / W;
+    const int64_t p1_slot = (int64_t)nz * NN;
+    const int64_t p2_slot = (int64_t)nz * ny * N;
+    C<T>* x = X.get<C<T>>((int64_t)B * NC);
+    C<T>* p1 = P1.get<C<T>>((int64_t)B * p1_slot);
+    C<T>* p2 = P2.get<C<T>>((int64_t)B * p2_slot);
+    C<T>* fg = Fg.get<C<T>>(NC);
+    double* pt = part.get<double>((int64_t)B * nblkE * 2 * R);
+    const C<T>* twp = tw.as<C<T>>();
+    BinMap bm = binmap();
+    // ---- galaxy field: spectrum (DC removed) and auto-correlation
+    const double cb = (double)sizeof(C<T>);
+    prof.run("gal_xscatter", s, (double)n_gal * (4 + 4 * sizeof(T)) + (double)NC * cb, [&] {
+      k_xscatter<T, Sh, W><<<(int)(NN / W), NT, 0, s>>>(g_tasks.as<int32_t>(), (int)NN, gal_set(),
+                                                         gslot_fa.as<int32_t>(),
+                                                         gslot_fb.as<int32_t>(), x, twp);
+      launch_check("xscatter(gal)");
+    });
+    prof.run("gal_ypass", s, 2.0 * NC * cb, [&] {
+      k_strided<T, Sh, W, -1, false, false><<<dim3(N / W, N, 1), NT, 0, s>>>(
+          x, x, 0, 0, NN, NN, N, N, 0, nullptr, nullptr, 0, nullptr, twp);
+      launch_check("ypass(gal)");
+    });
+    prof.run("gal_zpass", s, 2.0 * NC * cb + (double)p1_slot * cb, [&] {
+      k_zcross<T, Sh, W, true><<<dim3(N / W, N, 1), NT, 0, s>>>(x, 0, nullptr, nullptr, 1, nullptr,
+                                                                 fg, p1, 0, pwz(), twp);
+      launch_check("zcross(gal)");
+    });
+    prof.run("gal_yinv", s, (double)(p1_slot + p2_slot) * cb, [&] {
+      k_strided<T, Sh, W, 1, false, true><<<dim3(N / W, nz, 1), NT, 0, s>>>(
+          p1, p2, p1_slot, p2_slot, NN, (int64_t)ny * N, N, N, pwy(), nullptr, nullptr, 0, nullptr,
+          twp);
+      launch_check("yinv(gal)");
+    });
+    prof.run("gal_xinv_bins", s, (double)p2_slot * cb, [&] {
+      k_xinv_bins<T, Sh, W, kRMax><<<dim3(nblkE, 1, 1), NT, 0, s>>>(p2, p2_slot, pwx(), pwy(),
+                                                                     pwz(), bm, R, pt, twp);
+      launch_check("xinv_bins(gal)");
+    });
+    k_reduce_bins<<<dim3(grid_for(2 * R), 1), 256, 0, s>>>(pt, nblkE, R, gslot_fa.as<int32_t>(),
+                                                           gslot_fb.as<int32_t>(), Sgg.as<double>());
+    launch_check("reduce(gal)");
+    // ---- pair fields, B field pairs per batch
+    for (int k = 0; k < n_batches; ++k) {
+      const int nb = std::min(B, cfg.n_fp - k * B);
+      const int64_t t0 = batch_task_off[k], nt = batch_task_off[k + 1] - t0;
+      const int32_t* fa = slot_fa.as<int32_t>() + (int64_t)k * B;
+      const int32_t* fb = slot_fb.as<int32_t>() + (int64_t)k * B;
+      const int32_t* fp = slot_fp.as<int32_t>() + (int64_t)k * B;
+      const double pts = (double)batch_points(k) * (4 + 4 * sizeof(T));
+      if (nt > 0) {
+        prof.run("xscatter", s, pts + (double)nt * N * cb, [&] {
+          k_xscatter<T, Sh, W><<<(int)((nt + W - 1) / W), NT, 0, s>>>(
+              tasks.as<int32_t>() + t0, (int)nt, pair_set(), fa, fb, x, twp);
+          launch_check("xscatter");
+        });
+      }
+      prof.run("ypass", s, (double)nt * N * cb + (double)nb * NC * cb, [&] {
+        k_strided<T, Sh, W, -1, true, false><<<dim3(N / W, N, nb), NT, 0, s>>>(
+            x, x, NC, NC, NN, NN, N, N, 0, lflag.as<uint8_t>(), pflag.as<uint8_t>(), NN, fp, twp);
+        launch_check("ypass");
+      });
+      prof.run("zpass_cross", s, (double)(nb + 1) * NC * cb + (double)nb * p1_slot * cb, [&] {
+        k_zcross<T, Sh, W, false><<<dim3(N / W, N, 1), NT, 0, s>>>(
+            x, NC, pflag.as<uint8_t>(), fp, nb, fg, nullptr, p1, p1_slot, pwz(), twp);
+        launch_check("zcross");
+      });
+      prof.run("yinv", s, (double)nb * (p1_slot + p2_slot) * cb, [&] {
+        k_strided<T, Sh, W, 1, false, true><<<dim3(N / W, nz, nb), NT, 0, s>>>(
+            p1, p2, p1_slot, p2_slot, NN, (int64_t)ny * N, N, N, pwy(), nullptr, nullptr, 0,
+            nullptr, twp);
+        launch_check("yinv");
+      });
+      prof.run("xinv_bins", s, (double)nb * p2_slot * cb, [&] {
+        k_xinv_bins<T, Sh, W, kRMax><<<dim3(nblkE, 1, nb), NT, 0, s>>>(p2, p2_slot, pwx(), pwy(),
+                                                                        pwz(), bm, R, pt, twp);
+        launch_check("xinv_bins");
+      });
+      k_reduce_bins<<<dim3(grid_for(2 * R), nb), 256, 0, s>>>(pt, nblkE, R, fa, fb, S.as<double>());
+      launch_check("reduce");
+    }
+  }
+
+  // one field at a time, full transforms, global-atomic scatter, FP64 or FP32
+  void scatter_plain(const PointSet<T>& ps, const int32_t* key, const int32_t* ls, int64_t k0,
+                     int64_t k1, C<T>* grid, hipStream_t s) {
+    k_fill_zero<T><<<4096, 256, 0, s>>>(grid, NC);
+    launch_check("fill_zero");
+    k_scatter_atomic<T><<<2048, 256, 0, s>>>(ls, k0, k1, key, ps, N, grid);
+    launch_check("scatter_atomic");
+  }
+
+  void fft3(C<T>* g, int dir, hipStream_t s) {
+    const C<T>* twp = tw.as<C<T>>();
+    if (dir < 0) {
+      k_xdense<T, Sh, W, -1><<<(int)(NN / W), NT, 0, s>>>(g, twp);
+      k_strided<T, Sh, W, -1, false, false><<<dim3(N / W, N, 1), NT, 0, s>>>(
+          g, g, 0, 0, NN, NN, N, N, 0, nullptr, nullptr, 0, nullptr, twp);
+      k_strided<T, Sh, W, -1, false, false><<<dim3(N / W, N, 1), NT, 0, s>>>(
+          g, g, 0, 0, N, N, NN, NN, 0, nullptr, nullptr, 0, nullptr, twp);
+    } else {
+      k_strided<T, Sh, W, 1, false, false><<<dim3(N / W, N, 1), NT, 0, s>>>(
+          g, g, 0, 0, N, N, NN, NN, 0, nullptr, nullptr, 0, nullptr, twp);
+      k_strided<T, Sh, W, 1, false, false><<<dim3(N / W, N, 1), NT, 0, s>>>(
+          g, g, 0, 0, NN, NN, N, N, 0, nullptr, nullptr, 0, nullptr, twp);
+      k_xdense<T, Sh, W, 1><<<(int)(NN / W), NT, 0, s>>>(g, twp);
+    }
+    launch_check("fft3");
+  }
+
+  void bins_plain(const C<T>* h, const int32_t* fa, double* out, hipStream_t s) {
+    const int R = cfg.R;
+    const int64_t cube = (int64_t)win_len(pwx()) * win_len(pwy()) * win_len(pwz());
+    const int nblk = grid_for(cube);
+    double* pt = part.get<double>((int64_t)nblk * 2 * R);
+    k_bins_dense<T, kRMax><<<nblk, 256, 0, s>>>(h, N, pwx(), pwy(), pwz(), binmap(), R, pt);
+    launch_check("bins_dense");
+    k_reduce_bins<<<dim3(grid_for(2 * R), 1), 256, 0, s>>>(pt, nblk, R, fa, neg1.as<int32_t>(), out);
+    launch_check("reduce_plain");
+  }
+
+  void forward_plain(hipStream_t s) {
+    C<T>* g = Fg.get<C<T>>(NC);
+    C<T>* h = X.get<C<T>>(NC);
+    scatter_plain(gal_set(), g_key.as<int32_t>(), g_ls.as<int32_t>(), 0, NN, g, s);
+    fft3(g, -1, s);
+    k_zero_dc<T><<<1, 64, 0, s>>>(g);
+    k_copy<T><<<4096, 256, 0, s>>>(g, h, NC);
+    k_mul_conj<T, true><<<4096, 256, 0, s>>>(h, nullptr, NC);
+    launch_check("gal_product");
+    fft3(h, 1, s);
+    bins_plain(h, gslot_fa.as<int32_t>(), Sgg.as<double>(), s);
+    for (int f = 0; f < cfg.F; ++f) {
+      scatter_plain(pair_set(), p_key.as<int32_t>(), p_ls.as<int32_t>(), (int64_t)f * NN,
+                    (int64_t)(f + 1) * NN, h, s);
+      fft3(h, -1, s);
+      k_mul_conj<T, false><<<4096, 256, 0, s>>>(h, g, NC);
+      launch_check("product");
+      fft3(h, 1, s);
+      bins_plain(h, fidx.as<int32_t>() + f, S.as<double>(), s);
+    }
+  }
+};
+
+}  // namespace pgx

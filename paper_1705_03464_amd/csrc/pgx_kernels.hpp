@@ -1,0 +1,336 @@
+// Device kernels of the forward correlation path (templated on precision and
+// line shape).  Grid layout: a field is an N^3 complex array indexed
+// [z][y][x] with x fastest.  Two real pair fields travel as the real and
+// imaginary parts of one complex field ("field pair"); by linearity the
+// correlation of the complex field with the real galaxy field carries the
+// two real correlations in its real and imaginary parts.
+#pragma once
+#include "pgx_fft.hpp"
+
+namespace pgx {
+
+// ----------------------------------------------------------------------------
+// Point sets: points sorted by (set, base line), where the base line of a point
+// is z0*N + y0 of its lower CIC corner.  line_start[set*N*N + l] is the first
+// point whose key is >= set*N*N + l (size n_sets*N*N + 1).
+// ----------------------------------------------------------------------------
+template <typename T> struct PointSet {
+  const int32_t* line_start;
+  const int32_t* x0;   // lower CIC corner along x
+  const T* fx;         // CIC fractions (u - floor(u)) per axis
+  const T* fy;
+  const T* fz;
+  const T* wt;         // point weight
+};
+
+// Number of lines along each axis of the pruned output window [-w, w].
+__host__ __device__ inline int win_len(int w) { return 2 * w + 1; }
+
+// Block size helpers
+template <typename Sh, int W> struct Blk {
+  static constexpr int threads = W * Sh::TPL;
+};
+
+__device__ __forceinline__ void block_sync() { __syncthreads(); }
+
+template <typename T, int N>
+__device__ __forceinline__ void load_twiddles(C<T>* tw_s, const C<T>* __restrict__ tw_g) {
+  for (int i = threadIdx.x; i < N; i += blockDim.x) tw_s[i] = tw_g[i];
+}
+
+// ----------------------------------------------------------------------------
+// (A) x pass with the CIC scatter fused in.  One task per non-empty line of a
+// field pair.  The line is built in LDS from the points of the four base lines
+// whose CIC footprint reaches it (LDS atomics), transformed along x and
+// written once.  task word = slot * N*N + line (line = z*N + y).
+// ----------------------------------------------------------------------------
+template <typename T, typename Sh, int W>
+static __global__ void __launch_bounds__(W * Sh::TPL)
+k_xscatter(const int32_t* __restrict__ tasks, int n_tasks, PointSet<T> ps,
+           const int32_t* __restrict__ slot_fa, const int32_t* __restrict__ slot_fb,
+           C<T>* __restrict__ out, const C<T>* __restrict__ tw_g) {
+  constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>();
+  constexpr int64_t NN = (int64_t)N * N;
+  __shared__ C<T> tw_s[N];
+  __shared__ C<T> lines[W][LL];
+  load_twiddles<T, N>(tw_s, tw_g);
+  const int t = threadIdx.x % TPL, l = threadIdx.x / TPL;
+  const int task = blockIdx.x * W + l;
+  const bool active = task < n_tasks;
+  C<T>* line = lines[l];
+#pragma unroll
+  for (int m = 0; m < E; ++m) line[lpad(t + TPL * m)] = C<T>{0, 0};
+  int slot = 0, y = 0, z = 0;
+  if (active) {
+    const int32_t word = tasks[task];
+    slot = (int)(word / NN);
+    const int li = (int)(word - (int64_t)slot * NN);
+    y = li % N;
+    z = li / N;
+  }
+  block_sync();
+  if (active) {
+    const int ym = (y - 1) & (N - 1), zm = (z - 1) & (N - 1);
+    const int fa = slot_fa[slot], fb = slot_fb[slot];
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+      const int f = part == 0 ? fa : fb;
+      if (f < 0) continue;
+      const int64_t fbase = (int64_t)f * NN;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int by = (q & 1) ? ym : y, bz = (q & 2) ? zm : z;
+        const int64_t key = fbase + (int64_t)bz * N + by;
+        const int s = ps.line_start[key], e = ps.line_start[key + 1];
+        for (int p = s + t; p < e; p += TPL) {
+          const T fy = ps.fy[p], fz = ps.fz[p], fx = ps.fx[p];
+          const T wy = (q & 1) ? fy : (T)1 - fy;
+          const T wz = (q & 2) ? fz : (T)1 - fz;
+          const T w = ps.wt[p] * wy * wz;
+          const int x0 = ps.x0[p];
+          T* a0 = part == 0 ? &line[lpad(x0)].x : &line[lpad(x0)].y;
+          T* a1 = part == 0 ? &line[lpad((x0 + 1) & (N - 1))].x : &line[lpad((x0 + 1) & (N - 1))].y;
+          atomicAdd(a0, w * ((T)1 - fx));
+          atomicAdd(a1, w * fx);
+        }
+      }
+    }
+  }
+  block_sync();
+  C<T> v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) v[m] = line[lpad(t + TPL * m)];
+  block_sync();
+  line_fft<Sh, -1>(v, t, line, tw_s, block_sync);
+  if (active) {
+    C<T>* o = out + (int64_t)slot * NN * N + ((int64_t)z * N + y) * N;
+#pragma unroll
+    for (int m = 0; m < E; ++m) o[t + TPL * m] = v[m];
+  }
+}
+
+// ----------------------------------------------------------------------------
+// (B) strided pass: lines along an axis with element stride `es` (N for y,
+// N*N for z) over tiles of W adjacent x positions.  Tile (xt, a): column base
+// a*A + xt*W.  Options:
+//   FLAGS   input element e of the line counts only when lflag[a*N + e] != 0,
+//           and the whole tile is skipped when pflag[a] == 0 (y pass on a
+//           field that was written sparsely by the x pass);
+//   PRUNE   only outputs e' with (e' + pw) mod N <= 2 pw are stored, at
+//           position (e' + pw) mod N of the output line (inverse passes).
+// Batched over blockIdx.z with per-slot strides.
+// ----------------------------------------------------------------------------
+template <typename T, typename Sh, int W, int DIR, bool FLAGS, bool PRUNE>
+static __global__ void __launch_bounds__(W * Sh::TPL)
+k_strided(const C<T>* in, C<T>* out, int64_t in_slot, int64_t out_slot,
+          int64_t in_A, int64_t out_A, int64_t in_es, int64_t out_es, int pw,
+          const uint8_t* __restrict__ lflag, const uint8_t* __restrict__ pflag,
+          int64_t flag_slot, const int32_t* __restrict__ slot_fp, const C<T>* __restrict__ tw_g) {
+  constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>();
+  __shared__ C<T> tw_s[N];
+  __shared__ C<T> lines[W][LL];
+  const int slot = blockIdx.z;
+  const int xt = blockIdx.x, a = blockIdx.y;
+  const uint8_t* lf = nullptr;
+  if constexpr (FLAGS) {
+    const int64_t fp = slot_fp[slot];
+    if (pflag[fp * N + a] == 0) return;  // whole plane empty: output stays untouched
+    lf = lflag + fp * flag_slot + (int64_t)a * N;
+  }
+  load_twiddles<T, N>(tw_s, tw_g);
+  const int c = threadIdx.x % W, t = threadIdx.x / W;
+  const C<T>* src = in + slot * in_slot + a * in_A + xt * W + c;
+  C<T> v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int e = t + TPL * m;
+    if constexpr (FLAGS) {
+      v[m] = lf[e] ? src[e * in_es] : C<T>{0, 0};
+    } else {
+      v[m] = src[e * in_es];
+    }
+  }
+  block_sync();
+  line_fft<Sh, DIR>(v, t, lines[c], tw_s, block_sync);
+  C<T>* dst = out + slot * out_slot + a * out_A + xt * W + c;
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int e = t + TPL * m;
+    if constexpr (PRUNE) {
+      const int pe = (e + pw) & (N - 1);
+      if (pe <= 2 * pw) dst[pe * out_es] = v[m];
+    } else {
+      dst[e * out_es] = v[m];
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// (C) z pass with the cross-power product fused in.  Tile (xt, ky); for each
+// slot of the batch: forward transform along z, multiply by conj(Fg), inverse
+// transform along z, store only the pruned window of z' (layout
+// [pz][ky][kx], pz = (z' + pw) mod N).  Fg is read once per tile per batch.
+// GAL mode (galaxy field): after the forward transform the k = 0 mode is set
+// to zero, the spectrum is stored to `fg_out`, and the product is |Fg|^2.
+// ----------------------------------------------------------------------------
+template <typename T, typename Sh, int W, bool GAL>
+static __global__ void __launch_bounds__(W * Sh::TPL)
+k_zcross(const C<T>* in, int64_t in_slot, const uint8_t* __restrict__ pflag,
+         const int32_t* __restrict__ slot_fp, int n_slots, const C<T>* __restrict__ fg,
+         C<T>* __restrict__ fg_out, C<T>* __restrict__ out, int64_t out_slot, int pw,
+         const C<T>* __restrict__ tw_g) {
+  constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>();
+  constexpr int64_t NN = (int64_t)N * N;
+  __shared__ C<T> tw_s[N];
+  __shared__ C<T> lines[W][LL];
+  load_twiddles<T, N>(tw_s, tw_g);
+  const int xt = blockIdx.x, ky = blockIdx.y;
+  const int c = threadIdx.x % W, t = threadIdx.x / W;
+  const int64_t col = (int64_t)ky * N + xt * W + c;
+  C<T> g[E];
+  if constexpr (!GAL) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) g[m] = fg[col + (int64_t)(t + TPL * m) * NN];
+  }
+  const int pw2 = 2 * pw + 1;
+  for (int slot = 0; slot < n_slots; ++slot) {
+    const C<T>* src = in + slot * in_slot + col;
+    const uint8_t* pf = GAL ? nullptr : pflag + (int64_t)slot_fp[slot] * N;
+    C<T> v[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int z = t + TPL * m;
+      if constexpr (GAL) {
+        v[m] = src[(int64_t)z * NN];
+      } else {
+        v[m] = pf[z] ? src[(int64_t)z * NN] : C<T>{0, 0};
+      }
+    }
+    block_sync();
+    line_fft<Sh, -1>(v, t, lines[c], tw_s, block_sync);
+    if constexpr (GAL) {
+      if (col == 0 && t == 0) v[0] = C<T>{0, 0};  // kz = 0 of the (0,0) column
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        fg_out[col + (int64_t)(t + TPL * m) * NN] = v[m];
+        v[m] = C<T>{v[m].x * v[m].x + v[m].y * v[m].y, (T)0};
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = cmulc(v[m], g[m]);
+    }
+    block_sync();
+    line_fft<Sh, 1>(v, t, lines[c], tw_s, block_sync);
+    C<T>* dst = out + slot * out_slot + col;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int pz = (t + TPL * m + pw) & (N - 1);
+      if (pz < pw2) dst[(int64_t)pz * NN] = v[m];
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Output-bin classification of a lattice offset (i', j', k') (signed).  All
+// modes depend only on |k'| and on i'^2 + j'^2 (+ k'^2), so a displacement
+// and its negative share a bin.
+// ----------------------------------------------------------------------------
+struct BinMap {
+  int mode;             // 0 shell, 1 r_mu, 2 rp_pi
+  int n2;               // number of second-axis bins (1 for shell)
+  const int16_t* lut1;  // shell/r_mu: indexed by m = i'^2+j'^2+k'^2 ; rp_pi: by i'^2+j'^2
+  int lut1_n;
+  const int16_t* lut2;  // rp_pi: indexed by k'^2
+  int lut2_n;
+  const double* mu2;    // r_mu: squared mu edges (n2 + 1)
+};
+
+__device__ __forceinline__ int classify_bin(const BinMap& bm, int i, int j, int k) {
+  const int xy = i * i + j * j, kk = k * k;
+  if (bm.mode == 2) {
+    if (xy >= bm.lut1_n || kk >= bm.lut2_n) return -1;
+    const int b1 = bm.lut1[xy], b2 = bm.lut2[kk];
+    if (b1 < 0 || b2 < 0) return -1;
+    return b1 * bm.n2 + b2;
+  }
+  const int m = xy + kk;
+  if (m >= bm.lut1_n) return -1;
+  const int b1 = bm.lut1[m];
+  if (b1 < 0) return -1;
+  if (bm.mode == 0) return b1;
+  const double md = (double)m, kd = (double)kk;
+  if (kd < bm.mu2[0] * md || kd > bm.mu2[bm.n2] * md) return -1;
+  int kb = 0;
+  for (int e = 1; e < bm.n2; ++e) kb += (kd >= bm.mu2[e] * md) ? 1 : 0;
+  return b1 * bm.n2 + kb;
+}
+
+// ----------------------------------------------------------------------------
+// (E) last inverse pass along x over the pruned window lines (pz, py), with
+// the bin reduction fused: FP64 bin sums in LDS, one partial row per block:
+// part[slot][block][2][R] (real part -> field a, imaginary -> field b).
+// ----------------------------------------------------------------------------
+template <typename T, typename Sh, int W, int RMAX>
+static __global__ void __launch_bounds__(W * Sh::TPL)
+k_xinv_bins(const C<T>* __restrict__ in, int64_t in_slot, int pwx, int pwy, int pwz, BinMap bm,
+            int R, double* __restrict__ part, const C<T>* __restrict__ tw_g) {
+  constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>();
+  __shared__ C<T> tw_s[N];
+  __shared__ C<T> lines[W][LL];
+  __shared__ double acc[2 * RMAX];
+  load_twiddles<T, N>(tw_s, tw_g);
+  for (int i = threadIdx.x; i < 2 * R; i += blockDim.x) acc[i] = 0.0;
+  const int slot = blockIdx.z;
+  const int t = threadIdx.x % TPL, l = threadIdx.x / TPL;
+  const int ny = win_len(pwy), nz = win_len(pwz);
+  const int task = blockIdx.x * W + l;
+  const bool active = task < ny * nz;
+  const int py = active ? task % ny : 0, pz = active ? task / ny : 0;
+  C<T> v[E];
+  const C<T>* src = in + slot * in_slot + (int64_t)task * N;
+#pragma unroll
+  for (int m = 0; m < E; ++m) v[m] = active ? src[t + TPL * m] : C<T>{0, 0};
+  block_sync();
+  line_fft<Sh, 1>(v, t, lines[l], tw_s, block_sync);
+  if (active) {
+    const int jj = py - pwy, kk = pz - pwz;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int px = (t + TPL * m + pwx) & (N - 1);
+      if (px <= 2 * pwx) {
+        const int b = classify_bin(bm, px - pwx, jj, kk);
+        if (b >= 0) {
+          atomicAdd(&acc[b], (double)v[m].x);
+          atomicAdd(&acc[R + b], (double)v[m].y);
+        }
+      }
+    }
+  }
+  block_sync();
+  double* dst = part + ((int64_t)slot * gridDim.x + blockIdx.x) * 2 * R;
+  for (int i = threadIdx.x; i < 2 * R; i += blockDim.x) dst[i] = acc[i];
+}
+
+// ----------------------------------------------------------------------------
+// Plain path pieces (one field per complex grid, imaginary part zero)
+// ----------------------------------------------------------------------------
+// contiguous x pass over all lines of a dense field, in place
+template <typename T, typename Sh, int W, int DIR>
+static __global__ void __launch_bounds__(W * Sh::TPL)
+k_xdense(C<T>* data, const C<T>* __restrict__ tw_g) {
+  constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>();
+  __shared__ C<T> tw_s[N];
+  __shared__ C<T> lines[W][LL];
+  load_twiddles<T, N>(tw_s, tw_g);
+  const int t = threadIdx.x % TPL, l = threadIdx.x / TPL;
+  C<T>* p = data + ((int64_t)blockIdx.x * W + l) * N;
+  C<T> v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) v[m] = p[t + TPL * m];
+  block_sync();
+  line_fft<Sh, DIR>(v, t, lines[l], tw_s, block_sync);
+#pragma unroll
+  for (int m = 0; m < E; ++m) p[t + TPL * m] = v[m];
+}
+
+}  // namespace pgx

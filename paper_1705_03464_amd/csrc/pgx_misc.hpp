@@ -1,0 +1,248 @@
+// Smaller kernels: weights, deterministic FP64 reductions, the finalisation
+// formulas, and the pieces of the plain one-field-at-a-time path.
+#pragma once
+#include "pgx_kernels.hpp"
+
+namespace pgx {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// ----------------------------------------------------------------------------
+// small utilities
+// ----------------------------------------------------------------------------
+template <typename V>
+static __global__ void k_fill_value(V* __restrict__ p, int64_t n, V v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+static __global__ void k_field_counts(const int32_t* __restrict__ line_start, int64_t nn, int F,
+                               int64_t* __restrict__ counts) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f < F) counts[f] = (int64_t)line_start[(int64_t)(f + 1) * nn] - line_start[(int64_t)f * nn];
+}
+
+static __global__ void k_export_pairs(const int32_t* __restrict__ key, const int32_t* __restrict__ pi,
+                               const int32_t* __restrict__ pj, int64_t n, int64_t nn,
+                               int32_t* __restrict__ f, int32_t* __restrict__ i, int32_t* __restrict__ j) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  if (f) f[p] = (int32_t)(key[p] / nn);
+  if (i) i[p] = pi[p];
+  if (j) j[p] = pj[p];
+}
+
+// weights must be finite and >= 0
+static __global__ void k_validate_w(const float* __restrict__ w, int64_t n, int* __restrict__ err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float v = w[i];
+  if (!isfinite(v) || v < 0.0f) atomicOr(err, 4);
+}
+
+// ----------------------------------------------------------------------------
+// weights
+// ----------------------------------------------------------------------------
+// pair weight w_i * w_j (exact in FP64 for FP32 weights), rounded to T
+template <typename T>
+static __global__ void k_pair_weights(const int32_t* __restrict__ pi, const int32_t* __restrict__ pj,
+                               const float* __restrict__ w, int64_t n, T* __restrict__ wp) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  wp[p] = w ? (T)((double)w[pi[p]] * (double)w[pj[p]]) : (T)1;
+}
+
+template <typename T>
+static __global__ void k_gather_weights(const int32_t* __restrict__ idx, const float* __restrict__ w,
+                                 int64_t n, T* __restrict__ out) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  out[p] = w ? (T)w[idx[p]] : (T)1;
+}
+
+// Deterministic block sum of a double per thread (fixed tree over 256 lanes).
+__device__ __forceinline__ double block_sum256(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// Sum of products w_i w_j in FP64 over each field's contiguous range of the
+// sorted pair list: one block (256 threads) per field, fixed partition.
+static __global__ void k_field_wsum(const int32_t* __restrict__ line_start, int64_t nn,
+                             const int32_t* __restrict__ pi, const int32_t* __restrict__ pj,
+                             const float* __restrict__ w, double* __restrict__ wsum) {
+  __shared__ double sh[256];
+  const int f = blockIdx.x;
+  const int64_t s = line_start[(int64_t)f * nn], e = line_start[(int64_t)(f + 1) * nn];
+  double acc = 0.0;
+  for (int64_t p = s + threadIdx.x; p < e; p += 256)
+    acc += w ? (double)w[pi[p]] * (double)w[pj[p]] : 1.0;
+  const double r = block_sum256(acc, sh);
+  if (threadIdx.x == 0) wsum[f] = r;
+}
+
+// Sum of galaxy weights in FP64 (single block, fixed partition).
+static __global__ void k_weight_total(const float* __restrict__ w, int64_t n, double* __restrict__ out) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) acc += w ? (double)w[i] : 1.0;
+  const double r = block_sum256(acc, sh);
+  if (threadIdx.x == 0) out[0] = r;
+}
+
+// ----------------------------------------------------------------------------
+// bin partial reduction: part[slot][nblk][2][R] -> S[f][R] for the two fields
+// of each slot (fixed order over blocks, deterministic)
+// ----------------------------------------------------------------------------
+static __global__ void k_reduce_bins(const double* __restrict__ part, int nblk, int R,
+                              const int32_t* __restrict__ slot_fa, const int32_t* __restrict__ slot_fb,
+                              double* __restrict__ S) {
+  const int slot = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;  // over 2R
+  if (i >= 2 * R) return;
+  const double* p = part + (int64_t)slot * nblk * 2 * R + i;
+  double acc = 0.0;
+  for (int b = 0; b < nblk; ++b) acc += p[(int64_t)b * 2 * R];
+  const int half = i / R, bin = i % R;
+  const int f = half == 0 ? slot_fa[slot] : slot_fb[slot];
+  if (f >= 0) S[(int64_t)f * R + bin] = acc;
+}
+
+// ----------------------------------------------------------------------------
+// finalisation (FP64)
+//   xi_gg[b] = Sgg[b] / (n_b Wg^2)
+//   xi_pg[f,b] = S[f,b] / (n_b Wsum_f Wg)
+//   xi_dp[f] = 2 Wsum_f L^3 / (Wg^2 V_f) - 1
+//   b = xi_pg / xi_gg ; Q from the not-strictly-squeezed estimator (default),
+//   the squeezed-limit estimator, or a constant xi_w.
+// ----------------------------------------------------------------------------
+struct FinalizeArgs {
+  int F, R, qmode;
+  double L, xi_w_const;
+  const double* S;
+  const double* Sgg;
+  const double* nb;      // n_b as double
+  const double* vol;     // V_f
+  const double* wsum;
+  const double* wg;      // [1]
+  double* xi_gg;
+  double* xi_pg;
+  double* xi_dp;
+  double* b_pg;
+  double* q_eff;
+};
+
+__device__ __forceinline__ double q_estimator(double b, double x, double xw, int mode) {
+  if (mode == 1) return ((1.0 + x) * b - 2.0) / (2.0 * x);
+  return ((1.0 + x) * b - 2.0 - xw / (2.0 * x)) / (2.0 * x + 1.5 * xw);
+}
+
+static __global__ void k_finalize(FinalizeArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const double wg = a.wg[0];
+  if (i < a.R) a.xi_gg[i] = a.Sgg[i] / (a.nb[i] * wg * wg);
+  if (i < a.F) a.xi_dp[i] = 2.0 * a.wsum[i] * a.L * a.L * a.L / (wg * wg * a.vol[i]) - 1.0;
+  if (i >= a.F * a.R) return;
+  const int f = i / a.R, b = i % a.R;
+  const double xgg = a.Sgg[b] / (a.nb[b] * wg * wg);
+  const double xpg = a.S[i] / (a.nb[b] * a.wsum[f] * wg);
+  const double x = 2.0 * a.wsum[f] * a.L * a.L * a.L / (wg * wg * a.vol[f]) - 1.0;
+  const double bb = xpg / xgg;
+  const double xw = a.qmode == 2 ? a.xi_w_const : xgg;
+  a.xi_pg[i] = xpg;
+  a.b_pg[i] = bb;
+  a.q_eff[i] = q_estimator(bb, x, xw, a.qmode);
+}
+
+// ----------------------------------------------------------------------------
+// plain path
+// ----------------------------------------------------------------------------
+template <typename T>
+static __global__ void k_fill_zero(C<T>* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = C<T>{0, 0};
+}
+
+// CIC scatter of the points in [s, e) with global atomics into the real part
+template <typename T>
+static __global__ void k_scatter_atomic(const int32_t* __restrict__ line_start, int64_t k0, int64_t k1,
+                                 const int32_t* __restrict__ key, PointSet<T> ps, int N,
+                                 C<T>* __restrict__ grid) {
+  const int64_t s = line_start[k0], e = line_start[k1];
+  const int64_t NN = (int64_t)N * N;
+  for (int64_t p = s + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < e;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t l = (int64_t)key[p] % NN;
+    const int y0 = (int)(l % N), z0 = (int)(l / N), x0 = ps.x0[p];
+    const T fx = ps.fx[p], fy = ps.fy[p], fz = ps.fz[p], w = ps.wt[p];
+    for (int c = 0; c < 8; ++c) {
+      const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
+      const T wx = ox ? fx : (T)1 - fx, wy = oy ? fy : (T)1 - fy, wz = oz ? fz : (T)1 - fz;
+      const int64_t idx = ((int64_t)((z0 + oz) & (N - 1)) * N + ((y0 + oy) & (N - 1))) * N +
+                          ((x0 + ox) & (N - 1));
+      atomicAdd(&grid[idx].x, w * wx * wy * wz);
+    }
+  }
+}
+
+// a[i] *= conj(b[i]); with SELF, a[i] = |a[i]|^2 after zeroing a[0] (the k = 0 mode)
+template <typename T, bool SELF>
+static __global__ void k_mul_conj(C<T>* __restrict__ a, const C<T>* __restrict__ b, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if constexpr (SELF) {
+      const C<T> v = a[i];
+      a[i] = C<T>{v.x * v.x + v.y * v.y, (T)0};
+    } else {
+      a[i] = cmulc(a[i], b[i]);
+    }
+  }
+}
+
+template <typename T>
+static __global__ void k_zero_dc(C<T>* a) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) a[0] = C<T>{0, 0};
+}
+
+// copy a full grid into another buffer
+template <typename T>
+static __global__ void k_copy(const C<T>* __restrict__ a, C<T>* __restrict__ b, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+
+// bin sums over the window cube of a full grid (real part); partials per block
+template <typename T, int RMAX>
+static __global__ void k_bins_dense(const C<T>* __restrict__ h, int N, int pwx, int pwy, int pwz,
+                             BinMap bm, int R, double* __restrict__ part) {
+  __shared__ double acc[RMAX];
+  for (int i = threadIdx.x; i < R; i += blockDim.x) acc[i] = 0.0;
+  __syncthreads();
+  const int nx = win_len(pwx), ny = win_len(pwy), nz = win_len(pwz);
+  const int64_t total = (int64_t)nx * ny * nz;
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < total) {
+    const int ix = (int)(q % nx), iy = (int)((q / nx) % ny), iz = (int)(q / ((int64_t)nx * ny));
+    const int i = ix - pwx, j = iy - pwy, k = iz - pwz;
+    const int b = classify_bin(bm, i, j, k);
+    if (b >= 0) {
+      const int64_t idx = ((int64_t)(k & (N - 1)) * N + (j & (N - 1))) * N + (i & (N - 1));
+      atomicAdd(&acc[b], (double)h[idx].x);
+    }
+  }
+  __syncthreads();
+  double* dst = part + (int64_t)blockIdx.x * 2 * R;
+  for (int i = threadIdx.x; i < 2 * R; i += blockDim.x) dst[i] = i < R ? acc[i] : 0.0;
+}
+
+}  // namespace pgx

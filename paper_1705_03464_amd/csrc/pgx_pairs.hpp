@@ -1,0 +1,251 @@
+// Close-pair search on a cell list, integer pair-bin keys and CIC point data.
+//
+// The paper keeps every pair closer than the maximum pair separation (a
+// close triplet gives three pairs) and places a pair at its midpoint
+// (Implementation section, pair catalogue; Methodology, equation
+// delta_pi_x).  Keys are decided with FP64 comparisons of squared
+// separations against squared edges, evaluated with the same operation order
+// as the reference definition and without fused multiply-add, so they are
+// reproducible bit for bit:
+//   d = x_j - x_i (i < j by catalogue index), folded once into [-L/2, L/2)
+//   xy = dx*dx + dy*dy ; zz = dz*dz ; s2 = xy + zz
+//   s/|mu| mode:  t1[b] <= s2 < t1[b+1] ;  k = largest with zz >= mu2[k]*s2,
+//                 kept iff mu2[0]*s2 <= zz <= mu2[n2]*s2 (top edge closed)
+//   r_p/|pi| mode: s2 < dmax^2 ; t1[b] <= xy < t1[b+1] ; t2[k] <= zz < t2[k+1]
+//   key = b * n2 + k
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pgx {
+
+struct PairCfg {
+  double L, halfL, gscale;  // gscale = N / L
+  double side;              // cell side (>= maximum pair separation)
+  int nc, N, mode, n1, n2;
+  const double* t1;         // squared first-axis edges (n1 + 1)
+  const double* t2;         // squared second-axis edges (mu^2 or pi^2) (n2 + 1)
+  double dmax2;
+};
+
+__device__ __forceinline__ double fold(double d, double L, double h) {
+#pragma clang fp contract(off)
+  return d >= h ? d - L : (d < -h ? d + L : d);
+}
+
+// returns key >= 0 or -1
+__device__ __forceinline__ int pair_key(const PairCfg& c, double dx, double dy, double dz) {
+#pragma clang fp contract(off)
+  const double xy = dx * dx + dy * dy;
+  const double zz = dz * dz;
+  const double s2 = xy + zz;
+  if (c.mode == 0) {
+    if (s2 < c.t1[0] || s2 >= c.t1[c.n1]) return -1;
+    if (zz < c.t2[0] * s2 || zz > c.t2[c.n2] * s2) return -1;
+    int b = 0;
+    for (int e = 1; e < c.n1; ++e) b += (s2 >= c.t1[e]) ? 1 : 0;
+    int k = 0;
+    for (int e = 1; e < c.n2; ++e) k += (zz >= c.t2[e] * s2) ? 1 : 0;
+    return b * c.n2 + k;
+  }
+  if (s2 >= c.dmax2) return -1;
+  if (xy < c.t1[0] || xy >= c.t1[c.n1]) return -1;
+  if (zz < c.t2[0] || zz >= c.t2[c.n2]) return -1;
+  int b = 0;
+  for (int e = 1; e < c.n1; ++e) b += (xy >= c.t1[e]) ? 1 : 0;
+  int k = 0;
+  for (int e = 1; e < c.n2; ++e) k += (zz >= c.t2[e]) ? 1 : 0;
+  return b * c.n2 + k;
+}
+
+// CIC data of a position u = x * (N / L): lower node and fraction
+__device__ __forceinline__ void cic_of(double x, double gscale, int N, int& i0, double& f) {
+#pragma clang fp contract(off)
+  const double u = x * gscale;
+  const double fl = floor(u);
+  f = u - fl;
+  i0 = ((int)fl) & (N - 1);
+}
+
+// validation: bit 1 non-finite position, bit 2 outside [0, L), bit 4 bad weight
+static __global__ void k_validate(const double* __restrict__ x, const double* __restrict__ y,
+                           const double* __restrict__ z, const float* __restrict__ w, int64_t n,
+                           double L, int* __restrict__ err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int e = 0;
+  const double a = x[i], b = y[i], c = z[i];
+  if (!isfinite(a) || !isfinite(b) || !isfinite(c)) e |= 1;
+  else if (a < 0.0 || a >= L || b < 0.0 || b >= L || c < 0.0 || c >= L) e |= 2;
+  if (w) {
+    const float v = w[i];
+    if (!isfinite(v) || v < 0.0f) e |= 4;
+  }
+  if (e) atomicOr(err, e);
+}
+
+static __global__ void k_cell_keys(const double* __restrict__ x, const double* __restrict__ y,
+                            const double* __restrict__ z, int64_t n, double side, int nc,
+                            int32_t* __restrict__ key, int32_t* __restrict__ idx) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int cx = min((int)(x[i] / side), nc - 1);
+  int cy = min((int)(y[i] / side), nc - 1);
+  int cz = min((int)(z[i] / side), nc - 1);
+  key[i] = (cx * nc + cy) * nc + cz;
+  idx[i] = (int32_t)i;
+}
+
+static __global__ void k_gather_pos(const int32_t* __restrict__ perm, const double* __restrict__ x,
+                             const double* __restrict__ y, const double* __restrict__ z, int64_t n,
+                             double* __restrict__ px, double* __restrict__ py, double* __restrict__ pz) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int i = perm[p];
+  px[p] = x[i];
+  py[p] = y[i];
+  pz[p] = z[i];
+}
+
+static __global__ void k_histogram(const int32_t* __restrict__ key, int64_t n, int32_t* __restrict__ h) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  atomicAdd(&h[key[p]], 1);
+}
+
+// One thread per galaxy in cell order; candidates are galaxies of the 27
+// neighbour cells with a larger cell-order index.  COUNT: cnt[p] = number of
+// kept pairs.  EMIT: pairs written at off[p] + local index.
+template <bool EMIT, typename T>
+static __global__ void k_pairs(PairCfg c, const double* __restrict__ px, const double* __restrict__ py,
+                        const double* __restrict__ pz, const int32_t* __restrict__ perm,
+                        const int32_t* __restrict__ cell_of, const int32_t* __restrict__ cell_start,
+                        int64_t n, int64_t* __restrict__ cnt_off, int32_t* __restrict__ skey,
+                        int32_t* __restrict__ oi, int32_t* __restrict__ oj, int32_t* __restrict__ ox0,
+                        T* __restrict__ ofx, T* __restrict__ ofy, T* __restrict__ ofz) {
+#pragma clang fp contract(off)
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int cell = cell_of[p];
+  const int nc = c.nc;
+  const int cx = cell / (nc * nc), cy = (cell / nc) % nc, cz = cell % nc;
+  const double ax = px[p], ay = py[p], az = pz[p];
+  const int ia = perm[p];
+  int64_t w = EMIT ? cnt_off[p] : 0;
+  const int64_t NN = (int64_t)c.N * c.N;
+  for (int o = 0; o < 27; ++o) {
+    const int nx = (cx + o / 9 - 1 + nc) % nc;
+    const int ny = (cy + (o / 3) % 3 - 1 + nc) % nc;
+    const int nz = (cz + o % 3 - 1 + nc) % nc;
+    const int nb = (nx * nc + ny) * nc + nz;
+    const int s = cell_start[nb], e = cell_start[nb + 1];
+    for (int q = s; q < e; ++q) {
+      if (q <= p) continue;
+      const int ib = perm[q];
+      const double bx = px[q], by = py[q], bz = pz[q];
+      // i < j by catalogue index, d = x_j - x_i
+      const bool fwd = ia < ib;
+      const double xi = fwd ? ax : bx, yi = fwd ? ay : by, zi = fwd ? az : bz;
+      const double dx = fold((fwd ? bx : ax) - xi, c.L, c.halfL);
+      const double dy = fold((fwd ? by : ay) - yi, c.L, c.halfL);
+      const double dz = fold((fwd ? bz : az) - zi, c.L, c.halfL);
+      const int key = pair_key(c, dx, dy, dz);
+      if (key < 0) continue;
+      if constexpr (EMIT) {
+        double mx = xi + 0.5 * dx, my = yi + 0.5 * dy, mz = zi + 0.5 * dz;
+        mx = mx >= c.L ? mx - c.L : (mx < 0.0 ? mx + c.L : mx);
+        my = my >= c.L ? my - c.L : (my < 0.0 ? my + c.L : my);
+        mz = mz >= c.L ? mz - c.L : (mz < 0.0 ? mz + c.L : mz);
+        int x0, y0, z0;
+        double fx, fy, fz;
+        cic_of(mx, c.gscale, c.N, x0, fx);
+        cic_of(my, c.gscale, c.N, y0, fy);
+        cic_of(mz, c.gscale, c.N, z0, fz);
+        skey[w] = (int32_t)((int64_t)key * NN + (int64_t)z0 * c.N + y0);
+        oi[w] = fwd ? ia : ib;
+        oj[w] = fwd ? ib : ia;
+        ox0[w] = x0;
+        ofx[w] = (T)fx;
+        ofy[w] = (T)fy;
+        ofz[w] = (T)fz;
+      }
+      ++w;
+    }
+  }
+  if constexpr (!EMIT) cnt_off[p] = w;
+}
+
+// galaxy CIC points: key = z0*N + y0
+template <typename T>
+static __global__ void k_gal_points(const double* __restrict__ x, const double* __restrict__ y,
+                             const double* __restrict__ z, int64_t n, double gscale, int N,
+                             int32_t* __restrict__ skey, int32_t* __restrict__ idx,
+                             int32_t* __restrict__ ox0, T* __restrict__ ofx, T* __restrict__ ofy,
+                             T* __restrict__ ofz) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int x0, y0, z0;
+  double fx, fy, fz;
+  cic_of(x[i], gscale, N, x0, fx);
+  cic_of(y[i], gscale, N, y0, fy);
+  cic_of(z[i], gscale, N, z0, fz);
+  skey[i] = z0 * N + y0;
+  idx[i] = (int32_t)i;
+  ox0[i] = x0;
+  ofx[i] = (T)fx;
+  ofy[i] = (T)fy;
+  ofz[i] = (T)fz;
+}
+
+template <typename V>
+static __global__ void k_gather(const int32_t* __restrict__ perm, const V* __restrict__ src, int64_t n,
+                         V* __restrict__ dst) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  dst[p] = src[perm[p]];
+}
+
+// mark the (up to) four lines a point's CIC footprint touches, for the field
+// pair of its field (fp = field / 2)
+static __global__ void k_mark_lines(const int32_t* __restrict__ skey, int64_t n, int N,
+                             uint8_t* __restrict__ flags) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int64_t NN = (int64_t)N * N;
+  const int64_t k = skey[p];
+  const int64_t f = k / NN, l = k % NN;
+  const int y0 = (int)(l % N), z0 = (int)(l / N);
+  uint8_t* fl = flags + (f >> 1) * NN;
+  for (int c = 0; c < 4; ++c) {
+    const int yy = (y0 + (c & 1)) & (N - 1), zz = (z0 + (c >> 1)) & (N - 1);
+    fl[(int64_t)zz * N + yy] = 1;
+  }
+}
+
+// plane flag = any line of the plane non-empty
+static __global__ void k_plane_flags(const uint8_t* __restrict__ flags, int N, int64_t n_planes,
+                              uint8_t* __restrict__ pflags) {
+  const int64_t pl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pl >= n_planes) return;
+  const uint8_t* f = flags + pl * N;
+  int any = 0;
+  for (int y = 0; y < N; ++y) any |= f[y];
+  pflags[pl] = (uint8_t)(any ? 1 : 0);
+}
+
+// task words for the x pass: slot * N^2 + line, slot = fp % batch
+static __global__ void k_emit_tasks(const uint8_t* __restrict__ flags, const int32_t* __restrict__ pos,
+                             int64_t total, int N, int batch, int32_t* __restrict__ tasks) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total || !flags[i]) return;
+  const int64_t NN = (int64_t)N * N;
+  const int64_t fp = i / NN, l = i % NN;
+  tasks[pos[i]] = (int32_t)((fp % batch) * NN + l);
+}
+
+static __global__ void k_iota(int32_t* __restrict__ a, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = (int32_t)i;
+}
+
+}  // namespace pgx

@@ -1,0 +1,85 @@
+"""C-ABI checks that need no GPU: exported symbols, parameter validation and
+the host-side tables (lattice counts n_b, pair-bin volumes) against the oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import bins as OB
+from oracle import finalize as OF
+from paper_1705_03464_amd import Plan, PgxError, load_library
+from paper_1705_03464_amd._lib import LIB_PATH
+from synth import CONFIGS
+from synth.configs import linbins, logbins
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pgx.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB_PATH), reason="libpgx.so not built")
+
+
+def declared_symbols():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pgx_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB_PATH)
+    syms = declared_symbols()
+    assert "pgx_forward" in syms and "pgx_pairs_build" in syms
+    for s in syms:
+        assert hasattr(lib, s), s
+
+
+@pytest.mark.parametrize("name", ["cfg0", "cfg1", "cfg2", "cfg3", "cfg4", "cfg4tiny"])
+def test_out_counts_and_volumes_match_oracle(name):
+    wl = CONFIGS[name]
+    plan = Plan.from_workload(wl)
+    table = OB.lattice_table(wl.out_mode, wl.o1_edges, wl.o2_edges, wl.L, wl.N)
+    assert np.array_equal(plan.out_counts(), table[2])
+    dmax = wl.pair_dmax if wl.pair_mode == "rp_pi" else None
+    vol = OF.field_volumes(wl.pair_mode, wl.p1_edges, wl.p2_edges, dmax)
+    assert np.allclose(plan.field_volumes(), vol, rtol=1e-12, atol=0)
+    assert plan.n_fields == wl.n_fields and plan.n_out == wl.n_out
+    assert plan.window == OB.window(wl.out_mode, wl.o1_edges, wl.o2_edges, wl.L, wl.N)
+
+
+@pytest.mark.parametrize("mode", ["shell", "r_mu", "rp_pi"])
+def test_out_counts_other_modes(mode):
+    L, N = 100.0, 64
+    o1 = logbins(5.0, 45.0, 9) if mode != "rp_pi" else linbins(0.0, 45.0, 7)
+    o2 = None if mode == "shell" else (linbins(0.0, 1.0, 5) if mode == "r_mu" else linbins(0.0, 30.0, 4))
+    plan = Plan(L, N, linbins(0.5, 10, 3), [0.0, 1.0], o1, o2, out_mode=mode)
+    assert np.array_equal(plan.out_counts(), OB.lattice_table(mode, o1, o2, L, N)[2])
+
+
+def bad(**kw):
+    base = dict(L=100.0, N=64, p1_edges=linbins(0.5, 10, 3), p2_edges=[0.0, 1.0],
+                o1_edges=logbins(10, 40, 5))
+    base.update(kw)
+    with pytest.raises(PgxError) as e:
+        Plan(**base)
+    return e.value
+
+
+def test_parameter_validation():
+    assert bad(N=96).code == 4                        # not a power of two
+    assert bad(N=2048).code == 4
+    assert bad(L=-1.0).code == 1
+    assert bad(p1_edges=[1.0, 0.5]).code == 1        # not ascending
+    assert bad(p1_edges=[0.5, 40.0]).code == 1       # s_max >= L/3
+    assert bad(o1_edges=[10.0, 50.0]).code == 1      # output reaches L/2
+    assert bad(p2_edges=[0.0, 1.5]).code == 1        # |mu| > 1
+    assert bad(pair_mode="rp_pi", pair_dmax=0.0).code == 1
+    assert bad(o1_edges=[float("nan"), 3.0]).code == 1
+    e = bad(p1_edges=[1.0, 1.0])
+    assert "ascending" in str(e)
+
+
+def test_valid_plans_touch_no_device():
+    for wl in CONFIGS.values():
+        p = Plan.from_workload(wl)
+        p.close()

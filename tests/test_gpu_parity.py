@@ -1,0 +1,263 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle on the
+same seeded catalogues.
+
+Bars: pair keys and counts bit-exact; FP32 path |dxi| <= 1e-5 max(|xi|, 1e-2)
+(1e-5 relative where |xi| > 1e-2, the same bound in absolute terms below);
+FP64 plain path 1e-9 relative with a 1e-12 floor.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.pairs import pairs_for
+from oracle.pipeline import forward as oracle_forward
+from synth import get_config
+from synth.catalog import Catalog
+from synth.configs import Workload, linbins, logbins
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1705_03464_amd import load_library
+    load_library()
+
+
+def dev(cat):
+    f = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    return f(cat.x), f(cat.y), f(cat.z)
+
+
+def run(wl, cat, precision, w=None, batch=0):
+    from paper_1705_03464_amd import Plan
+    plan = Plan.from_workload(wl, precision=precision, batch=batch)
+    P, counts = plan.pairs_build(*dev(cat))
+    wt = None if w is None else torch.as_tensor(np.asarray(w, np.float32), device="cuda")
+    out = plan.forward(wt)
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy() for k, v in out.items()}
+    return plan, P, counts.cpu().numpy(), out
+
+
+def xi_err_ok(got, exp, rel=1e-5, floor=1e-2):
+    got = np.asarray(got); exp = np.asarray(exp)
+    fin = np.isfinite(exp)
+    assert np.array_equal(fin, np.isfinite(got)), "NaN pattern differs"
+    d = np.abs(got[fin] - exp[fin])
+    bound = rel * np.maximum(np.abs(exp[fin]), floor)
+    worst = float(np.max(d / bound)) if d.size else 0.0
+    return worst
+
+
+def assert_fp32_parity(out, ref, rel=1e-5):
+    w_gg = xi_err_ok(out["xi_gg"], ref["xi_gg"], rel)
+    w_pg = xi_err_ok(out["xi_pg"], ref["xi_pg"], rel)
+    _say(f"  worst |dxi| / (1e-5 max(|xi|,1e-2)): gg {w_gg:.3f} pg {w_pg:.3f}")
+    assert w_gg <= 1.0 and w_pg <= 1.0
+    assert np.allclose(out["xi_dp"], ref["xi_dp"], rtol=1e-12, atol=1e-12)
+    assert np.allclose(out["wsum"], ref["wsum"], rtol=1e-13, atol=0)
+    # b and Q where both correlations are well above the noise bar
+    m = (np.abs(ref["xi_pg"]) > 1e-2) & (np.abs(ref["xi_gg"])[None, :] > 1e-2)
+    if m.any():
+        assert np.allclose(out["b_pg"][m], ref["b_pg"][m], rtol=3e-5)
+
+
+def assert_fp64_parity(out, ref):
+    for k in ("xi_gg", "xi_pg", "b_pg", "q_eff", "xi_dp"):
+        fin = np.isfinite(ref[k])
+        assert np.array_equal(fin, np.isfinite(out[k])), k
+        assert np.allclose(out[k][fin], ref[k][fin], rtol=1e-9, atol=1e-12), k
+
+
+def clustered_catalog(L, n_halo, n_field, seed, sat=8, spread=1.5):
+    rng = np.random.default_rng(seed)
+    c = rng.random((n_halo, 3)) * L
+    s = np.repeat(c, sat, axis=0) + rng.normal(0, spread, (n_halo * sat, 3))
+    pos = np.mod(np.concatenate([c, s, rng.random((n_field, 3)) * L]), L)
+    pos[pos >= L] = 0.0
+    n = pos.shape[0]
+    return Catalog(L, pos[:, 0].copy(), pos[:, 1].copy(), pos[:, 2].copy(), np.zeros(n),
+                   np.zeros(n, np.int8))
+
+
+# ------------------------------------------------------------------ pairs
+def test_pairs_bitexact_cfg0():
+    wl = get_config("cfg0")
+    cat = wl.catalog()
+    _say(f"pairs cfg0: n_gal={cat.n}")
+    ref = pairs_for(cat, wl)
+    plan, P, counts, _ = run(wl, cat, "fp64")
+    assert P == ref["key"].size
+    assert np.array_equal(counts, ref["counts"])
+    f, i, j = (t.cpu().numpy().astype(np.int64) for t in plan.pairs_export())
+    got = np.stack([f, i, j], 1)
+    exp = np.stack([ref["key"], ref["i"], ref["j"]], 1)
+    got = got[np.lexsort(got.T[::-1])]
+    exp = exp[np.lexsort(exp.T[::-1])]
+    assert np.array_equal(got, exp)
+
+
+def test_pairs_rp_pi_and_mu_edges():
+    L = 60.0
+    wl = Workload(name="t", L=L, N=64, precision="fp32", pair_mode="rp_pi",
+                  p1_edges=linbins(0.0, 12.0, 5), p2_edges=linbins(0.0, 12.0, 3), pair_dmax=12.0,
+                  out_mode="rp_pi", o1_edges=linbins(0.0, 25.0, 5), o2_edges=linbins(0.0, 25.0, 4),
+                  catalog_kw={})
+    cat = clustered_catalog(L, 60, 1500, seed=3)
+    # exact edge cases: on-edge separations, pairs along z, across the boundary
+    extra = np.array([[1.0, 1.0, 1.0], [3.4, 1.0, 1.0], [10.0, 10.0, 10.0], [10.0, 10.0, 14.8],
+                      [59.5, 30.0, 30.0], [0.5, 30.0, 30.0]])
+    for a, k in zip("xyz", range(3)):
+        setattr(cat, a, np.concatenate([getattr(cat, a), extra[:, k]]))
+    cat.halo_mass = np.zeros(cat.x.size); cat.kind = np.zeros(cat.x.size, np.int8)
+    ref = pairs_for(cat, wl, method="brute")
+    plan, P, counts, _ = run(wl, cat, "fp32")
+    assert np.array_equal(counts, ref["counts"])
+    f, i, j = (t.cpu().numpy().astype(np.int64) for t in plan.pairs_export())
+    got = np.stack([f, i, j], 1); exp = np.stack([ref["key"], ref["i"], ref["j"]], 1)
+    assert np.array_equal(got[np.lexsort(got.T[::-1])], exp[np.lexsort(exp.T[::-1])])
+
+
+def test_pairs_deterministic():
+    wl = get_config("cfg0")
+    cat = wl.catalog()
+    plan, P, _, _ = run(wl, cat, "fp32")
+    a = [t.cpu().numpy() for t in plan.pairs_export()]
+    plan.pairs_build(*dev(cat))
+    b = [t.cpu().numpy() for t in plan.pairs_export()]
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+
+
+# ------------------------------------------------------------------ forward, cfg0
+def test_forward_fp64_plain_cfg0():
+    wl = get_config("cfg0")
+    cat = wl.catalog()
+    _say("forward fp64 cfg0")
+    ref = oracle_forward(cat, wl)
+    _, _, counts, out = run(wl, cat, "fp64")
+    assert np.array_equal(counts, ref["counts"])
+    assert_fp64_parity(out, ref)
+
+
+def test_forward_fp32_cfg0():
+    wl = get_config("cfg0")
+    cat = wl.catalog()
+    _say("forward fp32 cfg0")
+    ref = oracle_forward(cat, wl)
+    _, _, _, out = run(wl, cat, "fp32")
+    assert_fp32_parity(out, ref)
+
+
+# ------------------------------------------------------------------ small grids, all modes
+SMALL = [
+    # (N, L, pair_mode, p1, p2, dmax, out_mode, o1, o2)
+    (64, 100.0, "s_mu", linbins(0.5, 8.0, 3), linbins(0.0, 1.0, 3), 0.0, "shell",
+     logbins(6.0, 40.0, 7), None),
+    (64, 100.0, "s_mu", logbins(0.5, 8.0, 4), linbins(0.0, 1.0, 2), 0.0, "r_mu",
+     logbins(6.0, 40.0, 5), linbins(0.0, 1.0, 4)),
+    (128, 160.0, "rp_pi", linbins(0.0, 10.0, 3), linbins(0.0, 10.0, 3), 10.0, "rp_pi",
+     linbins(0.0, 60.0, 6), linbins(0.0, 45.0, 5)),
+    (256, 300.0, "s_mu", logbins(0.5, 10.0, 7), linbins(0.0, 1.0, 1), 0.0, "shell",
+     logbins(10.0, 80.0, 20), None),
+]
+
+
+@pytest.mark.parametrize("case", range(len(SMALL)))
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_forward_small_grids(case, precision):
+    N, L, pm, p1, p2, dmax, om, o1, o2 = SMALL[case]
+    wl = Workload(name="t", L=L, N=N, precision=precision, pair_mode=pm, p1_edges=p1,
+                  p2_edges=p2, pair_dmax=dmax, out_mode=om, o1_edges=o1, o2_edges=o2,
+                  catalog_kw={})
+    cat = clustered_catalog(L, int(0.02 * L ** 2), int(0.8 * L ** 2), seed=case)
+    w = np.random.default_rng(case).uniform(0.3, 1.7, cat.n).astype(np.float32).astype(np.float64)
+    _say(f"small case {case} N={N} {pm}/{om} F={wl.n_fields} n_gal={cat.n} {precision}")
+    ref = oracle_forward(cat, wl, w=w)
+    _, _, counts, out = run(wl, cat, precision, w=w, batch=2)
+    assert np.array_equal(counts, ref["counts"])
+    if precision == "fp64":
+        assert_fp64_parity(out, ref)
+    else:
+        assert_fp32_parity(out, ref)
+
+
+def test_empty_field_gives_nan_rows():
+    L = 100.0
+    wl = Workload(name="t", L=L, N=64, precision="fp32", pair_mode="s_mu",
+                  p1_edges=np.array([0.5, 1.0, 2.0, 9.0]), p2_edges=np.array([0.0, 1.0]),
+                  out_mode="shell", o1_edges=logbins(6.0, 40.0, 4), o2_edges=None, catalog_kw={})
+    rng = np.random.default_rng(0)
+    # a sparse uniform catalogue: no pair closer than 1.0 is likely at this density
+    pos = rng.random((300, 3)) * L
+    cat = Catalog(L, pos[:, 0].copy(), pos[:, 1].copy(), pos[:, 2].copy(), np.zeros(300),
+                  np.zeros(300, np.int8))
+    ref = oracle_forward(cat, wl)
+    _, _, counts, out = run(wl, cat, "fp32")
+    assert np.array_equal(counts, ref["counts"])
+    for f in range(wl.n_fields):
+        if counts[f] == 0:
+            assert np.all(np.isnan(out["xi_pg"][f])) and np.all(np.isnan(out["b_pg"][f]))
+    assert_fp32_parity(out, ref)
+
+
+def test_no_galaxies_is_rejected_cleanly_or_empty():
+    from paper_1705_03464_amd import PgxError
+    wl = get_config("cfg0")
+    cat = wl.catalog()
+    bad = cat.subset(np.arange(50))
+    bad.x = bad.x.copy(); bad.x[3] = wl.L  # outside [0, L)
+    with pytest.raises(PgxError) as e:
+        run(wl, bad, "fp32")
+    assert e.value.code == 1
+
+
+# ------------------------------------------------------------------ full-size workloads
+def test_cfg2_full_size_sampled_fields():
+    wl = get_config("cfg2")
+    cat = wl.catalog()
+    _say(f"cfg2 n_gal={cat.n}")
+    pairs = pairs_for(cat, wl)
+    fields = [0, 41, 80, 119, 159]
+    ref = oracle_forward(cat, wl, pairs=pairs, fields=fields)
+    _, P, counts, out = run(wl, cat, "fp32")
+    assert P == pairs["key"].size
+    assert np.array_equal(counts, pairs["counts"])
+    sub = dict(ref)
+    sub["xi_pg"] = ref["xi_pg"][fields]
+    o = dict(out)
+    o["xi_pg"] = out["xi_pg"][fields]
+    o["b_pg"] = out["b_pg"][fields]
+    sub["b_pg"] = ref["b_pg"][fields]
+    assert_fp32_parity(o, sub)
+
+
+def test_cfg1_full_size_bench_configuration():
+    """The 512^3 production workload in the launch configuration the bench times:
+    all pair counts bit-exact, xi_gg and two sampled pair fields against the
+    FP64 oracle."""
+    wl = get_config("cfg1")
+    cat = wl.catalog()
+    _say(f"cfg1 n_gal={cat.n}")
+    pairs = pairs_for(cat, wl)
+    _, P, counts, out = run(wl, cat, "fp32")
+    assert P == pairs["key"].size
+    assert np.array_equal(counts, pairs["counts"])
+    fields = [13, 157]
+    ref = oracle_forward(cat, wl, pairs=pairs, fields=fields)
+    sub = dict(ref); o = dict(out)
+    for k in ("xi_pg", "b_pg"):
+        sub[k] = ref[k][fields]; o[k] = out[k][fields]
+    assert_fp32_parity(o, sub)
