@@ -76,6 +76,9 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernels", action="store_true", help="print the per-kernel table to stderr")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (torch) three times; used to "
+                         "scale the FETCH_SIZE / WRITE_SIZE counters of a profiler run")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); this build has no multi-GPU path",
@@ -87,6 +90,14 @@ def main(argv=None):
     from paper_1705_03464_amd import Plan, load_library
     from synth import get_config
 
+    if a.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": src.numel() * 4, "copies": 3}), flush=True)
+        return 0
     load_library()
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)

@@ -151,6 +151,25 @@ pgx_status pgx_forward(pgx_plan* plan, const float* w, void* stream, double* wsu
                        double* xi_pg, double* xi_dp, double* b_pg, double* q_eff);
 
 /*
+ * Adjoint of pgx_forward: gradient of a scalar loss with respect to the
+ * galaxy weights w of the last pgx_forward call.  Hand-written chain rule
+ * through the finalisation, the bin sums, the inverse and forward transforms,
+ * the cross-power product and the CIC assignment (which becomes a gather at
+ * the pair midpoints and galaxies); the paper has no gradients, its HOD
+ * derivatives are numerical (HOD dependency section).
+ *   g_b_pg, g_q_eff, g_xi_pg [F][R], g_xi_gg [R], g_xi_dp [F]: device FP64
+ *   upstream gradients dL/d(output), each nullable (= zero).  Entries of
+ *   outputs that were not finite (empty fields) are ignored.
+ *   grad_w: device FP32 [n_gal] out, dL/dw_i (unit weights when the forward
+ *   had w = NULL: the derivative at w = 1).
+ * Implemented for PGX_FP32_BATCHED plans (PGX_ENOTSUP otherwise); ESTATE
+ * without a preceding pgx_forward on the same catalogue.
+ */
+pgx_status pgx_backward(pgx_plan* plan, void* stream, const double* g_b_pg, const double* g_q_eff,
+                        const double* g_xi_pg, const double* g_xi_gg, const double* g_xi_dp,
+                        float* grad_w);
+
+/*
  * Kernel timing.  pgx_profile(plan, 1) clears the counters and starts
  * recording a pair of HIP events on the launch stream around every launch of
  * the transform-pass kernels (the events bracket exactly one kernel each);

@@ -238,13 +238,14 @@ def objective(out, g_b=None, g_q=None, g_xipg=None, g_xigg=None, g_xidp=None):
 
 
 def fd_weight_gradient(cat, wl, w, idx, h=1e-3, pairs=None, **g):
-    """Central differences dJ/dw_i for i in idx (relative step h * w_i, or h)."""
+    """Central differences dJ/dw_i for i in idx, step h * max(|w_i|, 0.1)
+    (an absolute floor so that zero weights get a usable step)."""
     w = np.asarray(w, np.float64)
     out0 = forward(cat, wl, pairs=pairs, w=w)
     pairs = out0["pairs"]
     res = []
     for i in idx:
-        step = h * max(abs(w[i]), 1e-12)
+        step = h * max(abs(w[i]), 0.1)
         wp = w.copy(); wp[i] += step
         wm = w.copy(); wm[i] -= step
         Jp = objective(forward(cat, wl, pairs=pairs, w=wp), **g)

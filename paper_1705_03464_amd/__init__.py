@@ -7,4 +7,13 @@ raises if it is missing.
 """
 from ._lib import Plan, PgxError, load_library
 
-__all__ = ["Plan", "PgxError", "load_library"]
+
+def __getattr__(name):
+    # torch-dependent helpers are imported on first use
+    if name in ("PairGalaxyXi", "pair_galaxy_xi", "hod_weights"):
+        from . import autograd
+        return getattr(autograd, name)
+    raise AttributeError(name)
+
+
+__all__ = ["Plan", "PgxError", "load_library", "PairGalaxyXi", "pair_galaxy_xi", "hod_weights"]

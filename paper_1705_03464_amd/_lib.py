@@ -57,6 +57,8 @@ _SIGS = {
     "pgx_pairs_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pgx_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pgx_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.c_void_p, C.c_void_p]),
     "pgx_profile": (C.c_int, [C.c_void_p, C.c_int32]),
     "pgx_profile_read": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_char_p),
                                    C.POINTER(C.c_int64), C.POINTER(C.c_double),
@@ -204,7 +206,29 @@ class Plan:
         _check(load_library().pgx_forward(self._h, _ptr(w), _stream(stream), _ptr(out["wsum"]),
                                           _ptr(out["xi_gg"]), _ptr(out["xi_pg"]), _ptr(out["xi_dp"]),
                                           _ptr(out["b_pg"]), _ptr(out["q_eff"])))
+        self.forward_count = getattr(self, "forward_count", 0) + 1
         return out
+
+    def backward(self, g_b_pg=None, g_q_eff=None, g_xi_pg=None, g_xi_gg=None, g_xi_dp=None,
+                 stream=None):
+        """dL/dw for the last forward, given upstream gradients of the outputs."""
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        F, R = self.n_fields, self.n_out
+
+        def prep(g, shape):
+            if g is None:
+                return None
+            g = g.to(device=dev, dtype=torch.float64).contiguous()
+            if tuple(g.shape) != shape:
+                raise ValueError(f"upstream gradient of shape {tuple(g.shape)}, expected {shape}")
+            return g
+        gs = [prep(g_b_pg, (F, R)), prep(g_q_eff, (F, R)), prep(g_xi_pg, (F, R)),
+              prep(g_xi_gg, (R,)), prep(g_xi_dp, (F,))]
+        grad = torch.empty(self.n_gal, dtype=torch.float32, device=dev)
+        _check(load_library().pgx_backward(self._h, _stream(stream), *[_ptr(g) for g in gs],
+                                           _ptr(grad)))
+        return grad
 
     def profile(self, enable: bool = True):
         """Start (clearing counters) or stop per-kernel event timing."""

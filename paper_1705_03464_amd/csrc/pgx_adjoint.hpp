@@ -1,0 +1,382 @@
+// Adjoint of the correlation path: gradients of a scalar loss with respect to
+// the per-galaxy weights.  With raw CIC densities rho_f (pair weights) and
+// rho_g (galaxy weights), g' = rho_g - W_g / N^3, Z_f = DFT(rho_f),
+// G = DFT(g') (its k = 0 mode is zero) and H_f = IDFT(Z_f conj(G)), the
+// forward computes
+//   S_fb = sum_{s in b} H_f(s),   xi_pg[f,b] = S_fb / (n_b Wsum_f W_g)
+//   Sgg_b = sum_{s in b} IDFT(|G|^2)(s),   xi_gg[b] = Sgg_b / (n_b W_g^2).
+// Given a_fb = dL/dS_fb and a_gb = dL/dSgg_b, with the symmetric kernels
+// K_f(r) = sum_b a_fb 1[r in b] and K_g likewise (real transforms K^):
+//   dL/drho_f      = IDFT(K^_f G)                       (per pair field)
+//   dL/dg'         = IDFT(sum_f K^_f Z_f) + 2 IDFT(K^_g G)
+// Two fields a, b travel in one complex grid: the transform of K_a + i K_b is
+// K^_a + i K^_b, so IDFT((K^_a + i K^_b) G) = dL/drho_a + i dL/drho_b, and
+// with A = Z conj(K^_a + i K^_b) / 2 summed over field pairs, plus K^_g G,
+// dL/dg' = 2 Re IDFT(A) (the sum over k and -k is folded into the real part).
+// Zeroing A(0) projects out the mean that g' removes from rho_g.  The CIC
+// gathers of these fields at the pair midpoints / galaxies, times the partner
+// weight, give the weight gradient; the explicit dependence of the
+// normalisations on Wsum_f and W_g is added by the finalisation adjoint.
+#pragma once
+#include "pgx_misc.hpp"
+
+namespace pgx {
+
+struct AdjointArgs {
+  int F, R, qmode;
+  double L, xi_w_const;
+  const double* S;
+  const double* Sgg;
+  const double* nb;
+  const double* vol;
+  const double* wsum;
+  const double* wg;
+  const double* g_b;     // [F][R] or null
+  const double* g_q;     // [F][R] or null
+  const double* g_xipg;  // [F][R] or null
+  const double* g_xigg;  // [R] or null
+  const double* g_xidp;  // [F] or null
+  double* apg;           // out [F][R] dL/dS_fb
+  double* agg;           // out [R]    dL/dSgg_b
+  double* gws;           // out [F]    explicit dL/dWsum_f
+  double* gwg;           // out [1]    explicit dL/dW_g
+};
+
+__device__ __forceinline__ double fin0(double v) { return isfinite(v) ? v : 0.0; }
+
+// One block of 256 threads.  Finalisation adjoint of
+//   b = xi_pg / xi_gg,  xi_dp = 2 Wsum L^3 / (Wg^2 V) - 1,
+//   Q (not strictly squeezed): ((1+x) b - 2 - xw/(2x)) / (2x + 1.5 xw), xw = xi_gg
+//   Q (squeezed): ((1+x) b - 2) / (2x);  Q (constant xi_w): xw = const.
+// Terms that are not finite (empty fields, zero xi_gg) carry no gradient.
+static __global__ void k_finalize_adjoint(AdjointArgs a) {
+  __shared__ double sh[256];
+  const int F = a.F, R = a.R;
+  const double wg = a.wg[0];
+  const double L3 = a.L * a.L * a.L;
+  // per field: dL/dS_fb, explicit dL/dWsum_f (own thread loops, no races)
+  double wg_acc = 0.0;
+  for (int f = threadIdx.x; f < F; f += 256) {
+    const double ws = a.wsum[f];
+    const bool ok = ws > 0.0;
+    const double x = 2.0 * ws * L3 / (wg * wg * a.vol[f]) - 1.0;
+    double gx = a.g_xidp ? fin0(a.g_xidp[f]) : 0.0;
+    double gws = 0.0;
+    for (int b = 0; b < R; ++b) {
+      const int i = f * R + b;
+      double gpg = 0.0;
+      if (ok) {
+        const double xg = a.Sgg[b] / (a.nb[b] * wg * wg);
+        const double xp = a.S[i] / (a.nb[b] * ws * wg);
+        const double bb = xp / xg;
+        const double gq = a.g_q ? fin0(a.g_q[i]) : 0.0;
+        double dqdb, dqdx;
+        if (a.qmode == 1) {
+          dqdb = (1.0 + x) / (2.0 * x);
+          dqdx = (2.0 - bb) / (2.0 * x * x);
+        } else {
+          const double xw = a.qmode == 2 ? a.xi_w_const : xg;
+          const double num = (1.0 + x) * bb - 2.0 - xw / (2.0 * x);
+          const double den = 2.0 * x + 1.5 * xw;
+          dqdb = (1.0 + x) / den;
+          dqdx = ((bb + xw / (2.0 * x * x)) * den - 2.0 * num) / (den * den);
+        }
+        const double gbt = (a.g_b ? fin0(a.g_b[i]) : 0.0) + fin0(gq * dqdb);
+        gpg = (a.g_xipg ? fin0(a.g_xipg[i]) : 0.0) + fin0(gbt / xg);
+        gx += fin0(gq * dqdx);
+        // xi_pg = S / (n_b Wsum Wg)
+        gws += -fin0(gpg * xp / ws);
+        wg_acc += -fin0(gpg * xp / wg);
+        a.apg[i] = gpg / (a.nb[b] * ws * wg);
+      } else {
+        a.apg[i] = 0.0;
+      }
+    }
+    if (ok) {
+      // xi_dp = 2 Wsum L^3 / (Wg^2 V) - 1
+      gws += gx * (x + 1.0) / ws;
+      wg_acc += -2.0 * gx * (x + 1.0) / wg;
+    }
+    a.gws[f] = ok ? gws : 0.0;
+  }
+  // per output bin: dL/dSgg_b
+  for (int b = threadIdx.x; b < R; b += 256) {
+    const double xg = a.Sgg[b] / (a.nb[b] * wg * wg);
+    double ggg = a.g_xigg ? fin0(a.g_xigg[b]) : 0.0;
+    for (int f = 0; f < F; ++f) {
+      const double ws = a.wsum[f];
+      if (!(ws > 0.0)) continue;
+      const int i = f * R + b;
+      const double x = 2.0 * ws * L3 / (wg * wg * a.vol[f]) - 1.0;
+      const double xp = a.S[i] / (a.nb[b] * ws * wg);
+      const double bb = xp / xg;
+      const double gq = a.g_q ? fin0(a.g_q[i]) : 0.0;
+      double dqdb = 0.0, dqdxw = 0.0;
+      if (a.qmode == 1) {
+        dqdb = (1.0 + x) / (2.0 * x);
+      } else {
+        const double xw = a.qmode == 2 ? a.xi_w_const : xg;
+        const double num = (1.0 + x) * bb - 2.0 - xw / (2.0 * x);
+        const double den = 2.0 * x + 1.5 * xw;
+        dqdb = (1.0 + x) / den;
+        if (a.qmode == 0) dqdxw = (-den / (2.0 * x) - 1.5 * num) / (den * den);
+      }
+      const double gbt = (a.g_b ? fin0(a.g_b[i]) : 0.0) + fin0(gq * dqdb);
+      ggg += fin0(-gbt * bb / xg) + fin0(gq * dqdxw);
+    }
+    // xi_gg = Sgg / (n_b Wg^2)
+    wg_acc += -2.0 * fin0(ggg * xg / wg);
+    a.agg[b] = ggg / (a.nb[b] * wg * wg);
+  }
+  const double tot = block_sum256(wg_acc, sh);
+  if (threadIdx.x == 0) a.gwg[0] = tot;
+}
+
+// ----------------------------------------------------------------------------
+// Kernel fields on the output window, transformed along x.  Task = window line
+// (pz, py) of a slot; values K_a(r) + i K_b(r) at the lattice offsets
+// r = (x' , py - pwy, pz - pwz), |x'| <= pwx; zero elsewhere on the line.
+// Output layout [slot][pz][py][kx].  fa/fb index rows of coef (F x R); a
+// negative index means no field.
+// ----------------------------------------------------------------------------
+template <typename T, typename Sh, int W>
+static __global__ void __launch_bounds__(W * Sh::TPL)
+k_kgen_x(const double* __restrict__ coef, int R, const int32_t* __restrict__ slot_fa,
+         const int32_t* __restrict__ slot_fb, int pwx, int pwy, int pwz, BinMap bm,
+         C<T>* __restrict__ out, int64_t out_slot, const C<T>* __restrict__ tw_g) {
+  constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>();
+  __shared__ C<T> tw_s[Sh::tw_entries()];
+  __shared__ C<T> lines[W][LL];
+  load_twiddles<T, Sh>(tw_s, tw_g);
+  const int slot = blockIdx.z;
+  const int t = threadIdx.x % TPL, l = threadIdx.x / TPL;
+  const int ny = win_len(pwy), nz = win_len(pwz);
+  const int task = blockIdx.x * W + l;
+  const bool active = task < ny * nz;
+  const int py = active ? task % ny : 0, pz = active ? task / ny : 0;
+  const int fa = slot_fa[slot], fb = slot_fb[slot];
+  C<T> v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    v[m] = C<T>{0, 0};
+    const int xx = t + TPL * m;
+    const int px = (xx + pwx) & (N - 1);
+    if (active && px <= 2 * pwx) {
+      const int b = classify_bin(bm, px - pwx, py - pwy, pz - pwz);
+      if (b >= 0) {
+        v[m].x = fa >= 0 ? (T)coef[(int64_t)fa * R + b] : (T)0;
+        v[m].y = fb >= 0 ? (T)coef[(int64_t)fb * R + b] : (T)0;
+      }
+    }
+  }
+  block_sync();
+  line_fft<Sh, -1>(v, t, lines[l], tw_s, block_sync);
+  if (active) {
+    C<T>* o = out + slot * out_slot + (int64_t)task * N;
+#pragma unroll
+    for (int m = 0; m < E; ++m) o[t + TPL * m] = v[m];
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Backward z pass.  Tile (xt, ky).  For each slot:
+//   Z  = forward z of the recomputed pair-field columns (x, y transformed)
+//   Kp = forward z of the kernel columns (only the window planes are present)
+//   acc += Z conj(Kp) / 2                       (galaxy-side accumulation)
+//   column <- inverse z of Kp G                (pair-side adjoint, in place)
+// then A += acc.  G is the galaxy spectrum with its k = 0 mode removed.
+// ----------------------------------------------------------------------------
+template <typename T, typename Sh, int W>
+static __global__ void __launch_bounds__(W * Sh::TPL)
+k_zback(C<T>* x, int64_t x_slot, const uint8_t* __restrict__ pflag,
+        const int32_t* __restrict__ slot_fp, int n_slots, const C<T>* __restrict__ ky_in,
+        int64_t ky_slot, int pwz, const C<T>* __restrict__ fg, C<T>* __restrict__ acc_out,
+        const C<T>* __restrict__ tw_g) {
+  constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>();
+  constexpr int64_t NN = (int64_t)N * N;
+  __shared__ C<T> tw_s[Sh::tw_entries()];
+  __shared__ C<T> lines[W][LL];
+  load_twiddles<T, Sh>(tw_s, tw_g);
+  const int xt = blockIdx.x, ky = blockIdx.y;
+  const int c = threadIdx.x % W, t = threadIdx.x / W;
+  const int64_t col = (int64_t)ky * N + xt * W + c;
+  C<T> g[E], acc[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    g[m] = fg[col + (int64_t)(t + TPL * m) * NN];
+    acc[m] = C<T>{0, 0};
+  }
+  for (int slot = 0; slot < n_slots; ++slot) {
+    C<T>* xs = x + slot * x_slot + col;
+    const uint8_t* pf = pflag + (int64_t)slot_fp[slot] * N;
+    C<T> v[E], k[E];
+    uint8_t fl[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) fl[m] = pf[t + TPL * m];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int z = t + TPL * m;
+      const C<T> a = xs[fl[m] ? (int64_t)z * NN : (int64_t)0];
+      v[m].x = fl[m] ? a.x : (T)0;
+      v[m].y = fl[m] ? a.y : (T)0;
+      const int pe = (z + pwz) & (N - 1);
+      const bool ok = pe <= 2 * pwz;
+      const C<T> b = ky_in[slot * ky_slot + col + (ok ? (int64_t)pe * NN : (int64_t)0)];
+      k[m].x = ok ? b.x : (T)0;
+      k[m].y = ok ? b.y : (T)0;
+    }
+    block_sync();
+    line_fft<Sh, -1>(v, t, lines[c], tw_s, block_sync);
+    block_sync();
+    line_fft<Sh, -1>(k, t, lines[c], tw_s, block_sync);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const C<T> zk = cmulc(v[m], k[m]);
+      acc[m].x += (T)0.5 * zk.x;
+      acc[m].y += (T)0.5 * zk.y;
+      v[m] = cmul(k[m], g[m]);
+    }
+    block_sync();
+    line_fft<Sh, 1>(v, t, lines[c], tw_s, block_sync);
+#pragma unroll
+    for (int m = 0; m < E; ++m) xs[(int64_t)(t + TPL * m) * NN] = v[m];
+  }
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    C<T>* p = acc_out + col + (int64_t)(t + TPL * m) * NN;
+    const C<T> o = *p;
+    *p = C<T>{o.x + acc[m].x, o.y + acc[m].y};
+  }
+}
+
+// Galaxy term of the accumulation: A = K^_g G, with K^_g the forward z
+// transform of the (x, y transformed) galaxy kernel column (real part).
+template <typename T, typename Sh, int W>
+static __global__ void __launch_bounds__(W * Sh::TPL)
+k_zinit(const C<T>* __restrict__ ky_in, int pwz, const C<T>* __restrict__ fg,
+        C<T>* __restrict__ acc_out, const C<T>* __restrict__ tw_g) {
+  constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>();
+  constexpr int64_t NN = (int64_t)N * N;
+  __shared__ C<T> tw_s[Sh::tw_entries()];
+  __shared__ C<T> lines[W][LL];
+  load_twiddles<T, Sh>(tw_s, tw_g);
+  const int xt = blockIdx.x, ky = blockIdx.y;
+  const int c = threadIdx.x % W, t = threadIdx.x / W;
+  const int64_t col = (int64_t)ky * N + xt * W + c;
+  C<T> k[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int z = t + TPL * m;
+    const int pe = (z + pwz) & (N - 1);
+    const bool ok = pe <= 2 * pwz;
+    const C<T> b = ky_in[col + (ok ? (int64_t)pe * NN : (int64_t)0)];
+    k[m].x = ok ? b.x : (T)0;
+    k[m].y = ok ? b.y : (T)0;
+  }
+  block_sync();
+  line_fft<Sh, -1>(k, t, lines[c], tw_s, block_sync);
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int64_t idx = col + (int64_t)(t + TPL * m) * NN;
+    const C<T> gv = fg[idx];
+    acc_out[idx] = C<T>{k[m].x * gv.x, k[m].x * gv.y};
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Inverse x pass fused with the CIC gather.  One task per non-empty line of a
+// field pair (same task words as the forward scatter).  The line is inverse
+// transformed, kept in LDS, and every point whose CIC footprint reaches the
+// line adds its share to acc[p] (real part for field a, imaginary for b):
+//   acc[p] += scale * wy * wz * ((1 - fx) line[x0] + fx line[x0 + 1]).
+// ----------------------------------------------------------------------------
+template <typename T, typename Sh, int W>
+static __global__ void __launch_bounds__(W * Sh::TPL)
+k_xgather(const int32_t* __restrict__ tasks, int n_tasks, PointSet<T> ps,
+          const int32_t* __restrict__ slot_fa, const int32_t* __restrict__ slot_fb,
+          const C<T>* __restrict__ in, T scale, float* __restrict__ acc,
+          const C<T>* __restrict__ tw_g) {
+  constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>();
+  constexpr int64_t NN = (int64_t)N * N;
+  __shared__ C<T> tw_s[Sh::tw_entries()];
+  __shared__ C<T> lines[W][LL];
+  load_twiddles<T, Sh>(tw_s, tw_g);
+  const int t = threadIdx.x % TPL, l = threadIdx.x / TPL;
+  const int task = blockIdx.x * W + l;
+  const bool active = task < n_tasks;
+  C<T>* line = lines[l];
+  int slot = 0, y = 0, z = 0;
+  if (active) {
+    const int32_t word = tasks[task];
+    slot = (int)(word / NN);
+    const int li = (int)(word - (int64_t)slot * NN);
+    y = li % N;
+    z = li / N;
+  }
+  C<T> v[E];
+  const C<T>* src = in + (int64_t)slot * NN * N + ((int64_t)z * N + y) * N;
+#pragma unroll
+  for (int m = 0; m < E; ++m) v[m] = active ? src[t + TPL * m] : C<T>{0, 0};
+  block_sync();
+  line_fft<Sh, 1>(v, t, line, tw_s, block_sync);
+  block_sync();
+#pragma unroll
+  for (int m = 0; m < E; ++m) line[lpad(t + TPL * m)] = v[m];
+  block_sync();
+  if (active) {
+    const int ym = (y - 1) & (N - 1), zm = (z - 1) & (N - 1);
+    const int fa = slot_fa[slot], fb = slot_fb[slot];
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+      const int f = part == 0 ? fa : fb;
+      if (f < 0) continue;
+      const int64_t fbase = (int64_t)f * NN;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int by = (q & 1) ? ym : y, bz = (q & 2) ? zm : z;
+        const int64_t key = fbase + (int64_t)bz * N + by;
+        const int s = ps.line_start[key], e = ps.line_start[key + 1];
+        for (int p = s + t; p < e; p += TPL) {
+          const T fy = ps.fy[p], fz = ps.fz[p], fx = ps.fx[p];
+          const T wy = (q & 1) ? fy : (T)1 - fy;
+          const T wz = (q & 2) ? fz : (T)1 - fz;
+          const int x0 = ps.x0[p];
+          const C<T> a0 = line[lpad(x0)], a1 = line[lpad((x0 + 1) & (N - 1))];
+          const T v0 = part == 0 ? a0.x : a0.y, v1 = part == 0 ? a1.x : a1.y;
+          atomicAdd(&acc[p], (float)(scale * wy * wz * (((T)1 - fx) * v0 + fx * v1)));
+        }
+      }
+    }
+  }
+}
+
+// grad[i] += w_j (acc[p] + gws[f]), grad[j] += w_i (...) for every pair
+static __global__ void k_pair_grad(const int32_t* __restrict__ pkey, const int32_t* __restrict__ pi,
+                                   const int32_t* __restrict__ pj, const float* __restrict__ acc,
+                                   int64_t n, int64_t nn, const double* __restrict__ gws,
+                                   const float* __restrict__ w, double* __restrict__ grad) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int f = (int)(pkey[p] / nn);
+  const double gval = (double)acc[p] + gws[f];
+  const int i = pi[p], j = pj[p];
+  const double wi = w ? (double)w[i] : 1.0, wj = w ? (double)w[j] : 1.0;
+  atomicAdd(&grad[i], wj * gval);
+  atomicAdd(&grad[j], wi * gval);
+}
+
+// galaxy term: grad[idx[p]] += acc[p] + gwg (each galaxy appears once)
+static __global__ void k_gal_grad(const int32_t* __restrict__ idx, const float* __restrict__ acc,
+                                  int64_t n, const double* __restrict__ gwg,
+                                  double* __restrict__ grad) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  grad[idx[p]] += (double)acc[p] + gwg[0];
+}
+
+static __global__ void k_grad_out(const double* __restrict__ g, int64_t n, float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (float)g[i];
+}
+
+}  // namespace pgx

@@ -208,6 +208,15 @@ pgx_status pgx_forward(pgx_plan* plan, const float* w, void* stream, double* wsu
   });
 }
 
+pgx_status pgx_backward(pgx_plan* plan, void* stream, const double* g_b_pg, const double* g_q_eff,
+                        const double* g_xi_pg, const double* g_xi_gg, const double* g_xi_dp,
+                        float* grad_w) {
+  if (!plan) return fail(PGX_EINVAL, "plan is NULL");
+  return guarded([&] {
+    plan->engine().backward((hipStream_t)stream, g_b_pg, g_q_eff, g_xi_pg, g_xi_gg, g_xi_dp, grad_w);
+  });
+}
+
 pgx_status pgx_profile(pgx_plan* plan, int32_t enable) {
   if (!plan) return fail(PGX_EINVAL, "plan is NULL");
   return guarded([&] {

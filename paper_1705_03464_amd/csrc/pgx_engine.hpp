@@ -1,6 +1,7 @@
 // Engine: device buffers and launch sequences of one plan, templated on the
 // transform precision T and the grid side N.
 #pragma once
+#include "pgx_adjoint.hpp"
 #include "pgx_misc.hpp"
 #include "pgx_pairs.hpp"
 #include "pgx_prim.hpp"
@@ -96,7 +97,10 @@ struct EngineBase {
   virtual void pairs_export(int32_t* f, int32_t* i, int32_t* j, hipStream_t s) = 0;
   virtual void forward(const float* w, hipStream_t s, double* wsum, double* xi_gg, double* xi_pg,
                        double* xi_dp, double* b_pg, double* q_eff) = 0;
+  virtual void backward(hipStream_t s, const double* g_b, const double* g_q, const double* g_xipg,
+                        const double* g_xigg, const double* g_xidp, float* grad_w) = 0;
   bool built = false;
+  bool forward_done = false;
 };
 
 constexpr int kRMax = 640;  // largest number of output bins handled by the bin kernels
@@ -104,8 +108,12 @@ constexpr int kRMax = 640;  // largest number of output bins handled by the bin 
 template <typename T, int N> struct Engine : EngineBase {
   using Sh = typename DefaultShape<T, N>::type;
   static constexpr int TPL = Sh::TPL;
-  static constexpr int W = (256 / TPL) < N ? (256 / TPL) : N;
+  // strided passes: tiles of W adjacent columns (W complex = 128 B per row);
+  // x-direction passes: WX whole lines per block
+  static constexpr int W = (int)(128 / sizeof(C<T>));
   static constexpr int NT = W * TPL;
+  static constexpr int WX = (256 / TPL) > 1 ? (256 / TPL) : 1;
+  static constexpr int NTX = WX * TPL;
   static constexpr int64_t NN = (int64_t)N * N;
   static constexpr int64_t NC = NN * N;
 
@@ -128,13 +136,21 @@ template <typename T, int N> struct Engine : EngineBase {
       s_i, s_j, s_x0, s_fx, s_fy, s_fz, s_pos;
   // forward work
   DBuf X, P1, P2, Fg, part, S, Sgg, wsum_d, wg_d, outs;
+  // backward work
+  DBuf KX, KY, Aacc, gbuf, gbuf_g, grad_d, apg, agg, gws, gwg, w_last;
+  bool w_given = false;
 
   explicit Engine(const PlanCfg& c) : cfg(c) {
     static_assert(N % W == 0, "tile width must divide N");
-    std::vector<C<T>> h(N);
-    for (int k = 0; k < N; ++k) {
-      const double a = -2.0 * kPi * (double)k / (double)N;
-      h[k] = C<T>{(T)std::cos(a), (T)std::sin(a)};
+    // per-stage twiddles exp(-2 pi i r k / (Ns R)) at [twoff(s) + r Ns + k], FP64 rounded to T
+    std::vector<C<T>> h(Sh::tw_entries());
+    for (int st = 1; st < Sh::stages; ++st) {
+      const int R = Sh::radix(st), Ns = Sh::ns(st);
+      for (int r = 0; r < R; ++r)
+        for (int k = 0; k < Ns; ++k) {
+          const double a = -2.0 * kPi * (double)(r * k) / (double)(Ns * R);
+          h[Sh::twoff(st) + r * Ns + k] = C<T>{(T)std::cos(a), (T)std::sin(a)};
+        }
     }
     upload(tw, h);
     upload(lut1, cfg.bins.lut1);
@@ -200,6 +216,7 @@ template <typename T, int N> struct Engine : EngineBase {
     PGX_REQUIRE(n >= 0 && n < INT32_MAX, PGX_EINVAL, "n_gal must be in [0, 2^31)");
     PGX_REQUIRE(n == 0 || (x && y && z), PGX_EINVAL, "positions must not be NULL");
     built = false;
+    forward_done = false;
     n_gal = n;
     const int F = cfg.F;
     // validate
@@ -486,12 +503,173 @@ template <typename T, int N> struct Engine : EngineBase {
     }
     S.get<double>((int64_t)cfg.F * cfg.R);
     Sgg.get<double>(cfg.R);
+    forward_done = false;
+    w_given = w != nullptr;
+    if (w && n_gal > 0)
+      PGX_HIP(hipMemcpyAsync(w_last.get<float>(n_gal), w, n_gal * sizeof(float),
+                             hipMemcpyDeviceToDevice, s));
     weights(w, s);
     if constexpr (std::is_same<T, float>::value)
       forward_batched(s);
     else
       forward_plain(s);
     finalize(s, xi_gg, xi_pg, xi_dp, b_pg, q_eff, wsum);
+    forward_done = true;
+  }
+
+  // ------------------------------------------------------------------------
+  // backward (batched FP32 path)
+  // ------------------------------------------------------------------------
+  void backward(hipStream_t s, const double* g_b, const double* g_q, const double* g_xipg,
+                const double* g_xigg, const double* g_xidp, float* grad_w) override {
+    PGX_REQUIRE(built && forward_done, PGX_ESTATE, "pgx_backward needs a preceding pgx_forward");
+    PGX_REQUIRE(grad_w != nullptr || n_gal == 0, PGX_EINVAL, "grad_w must not be NULL");
+    if constexpr (std::is_same<T, float>::value) {
+      backward_batched(s, g_b, g_q, g_xipg, g_xigg, g_xidp, grad_w);
+    } else {
+      throw Error(PGX_ENOTSUP, "the adjoint is implemented on the FP32 batched path");
+    }
+  }
+
+  void backward_batched(hipStream_t s, const double* g_b, const double* g_q, const double* g_xipg,
+                        const double* g_xigg, const double* g_xidp, float* grad_w) {
+    const int F = cfg.F, R = cfg.R;
+    const int ny = win_len(pwy()), nz = win_len(pwz());
+    const int nblkK = (ny * nz + WX - 1) / WX;
+    const int64_t kx_slot = (int64_t)nz * ny * N, ky_slot = (int64_t)nz * NN;
+    const double cb = (double)sizeof(C<T>);
+    const C<T>* twp = tw.as<C<T>>();
+    BinMap bm = binmap();
+    C<T>* kx = KX.get<C<T>>((int64_t)B * kx_slot);
+    C<T>* ky = KY.get<C<T>>((int64_t)B * ky_slot);
+    C<T>* x = X.get<C<T>>((int64_t)B * NC);
+    C<T>* A = Aacc.get<C<T>>(NC);
+    const C<T>* fg = Fg.as<C<T>>();
+    float* gb = gbuf.get<float>(std::max<int64_t>(n_pairs, 1));
+    float* gbg = gbuf_g.get<float>(std::max<int64_t>(n_gal, 1));
+    double* gd = grad_d.get<double>(std::max<int64_t>(n_gal, 1));
+    AdjointArgs aa;
+    aa.F = F;
+    aa.R = R;
+    aa.qmode = cfg.qeff_mode;
+    aa.L = cfg.L;
+    aa.xi_w_const = cfg.xi_w_const;
+    aa.S = S.as<double>();
+    aa.Sgg = Sgg.as<double>();
+    aa.nb = nbd.as<double>();
+    aa.vol = vold.as<double>();
+    aa.wsum = wsum_d.as<double>();
+    aa.wg = wg_d.as<double>();
+    aa.g_b = g_b;
+    aa.g_q = g_q;
+    aa.g_xipg = g_xipg;
+    aa.g_xigg = g_xigg;
+    aa.g_xidp = g_xidp;
+    aa.apg = apg.get<double>((int64_t)F * R);
+    aa.agg = agg.get<double>(R);
+    aa.gws = gws.get<double>(F);
+    aa.gwg = gwg.get<double>(1);
+    k_finalize_adjoint<<<1, 256, 0, s>>>(aa);
+    launch_check("finalize_adjoint");
+    k_fill_value<float><<<grid_for(std::max<int64_t>(n_pairs, 1)), 256, 0, s>>>(gb, std::max<int64_t>(n_pairs, 1), 0.f);
+    k_fill_value<float><<<grid_for(std::max<int64_t>(n_gal, 1)), 256, 0, s>>>(gbg, std::max<int64_t>(n_gal, 1), 0.f);
+    k_fill_value<double><<<grid_for(std::max<int64_t>(n_gal, 1)), 256, 0, s>>>(gd, std::max<int64_t>(n_gal, 1), 0.0);
+    launch_check("fill");
+    // galaxy kernel field -> A = K^_g G
+    prof.run("bwd_kgen", s, (double)kx_slot * cb, [&] {
+      k_kgen_x<T, Sh, WX><<<dim3(nblkK, 1, 1), NTX, 0, s>>>(aa.agg, R, gslot_fa.as<int32_t>(),
+                                                             gslot_fb.as<int32_t>(), pwx(), pwy(),
+                                                             pwz(), bm, kx, kx_slot, twp);
+      launch_check("kgen(gal)");
+    });
+    prof.run("bwd_kgen_y", s, (double)(kx_slot + ky_slot) * cb, [&] {
+      k_strided<T, Sh, W, -1, IN_WINDOW, OUT_DENSE><<<dim3(N / W, nz, 1), NT, 0, s>>>(
+          kx, ky, kx_slot, ky_slot, (int64_t)ny * N, NN, N, N, pwy(), nullptr, nullptr, 0, nullptr,
+          twp);
+      launch_check("kgen_y(gal)");
+    });
+    prof.run("bwd_zinit", s, (double)ky_slot * cb + 2.0 * NC * cb, [&] {
+      k_zinit<T, Sh, W><<<dim3(N / W, N, 1), NT, 0, s>>>(ky, pwz(), fg, A, twp);
+      launch_check("zinit");
+    });
+    for (int k = 0; k < n_batches; ++k) {
+      const int nb = std::min(B, cfg.n_fp - k * B);
+      const int64_t t0 = batch_task_off[k], nt = batch_task_off[k + 1] - t0;
+      const int32_t* fa = slot_fa.as<int32_t>() + (int64_t)k * B;
+      const int32_t* fb = slot_fb.as<int32_t>() + (int64_t)k * B;
+      const int32_t* fp = slot_fp.as<int32_t>() + (int64_t)k * B;
+      const double pts = (double)batch_points(k) * (4 + 4 * sizeof(T));
+      prof.run("bwd_kgen", s, (double)nb * kx_slot * cb, [&] {
+        k_kgen_x<T, Sh, WX><<<dim3(nblkK, 1, nb), NTX, 0, s>>>(aa.apg, R, fa, fb, pwx(), pwy(),
+                                                                pwz(), bm, kx, kx_slot, twp);
+        launch_check("kgen");
+      });
+      prof.run("bwd_kgen_y", s, (double)nb * (kx_slot + ky_slot) * cb, [&] {
+        k_strided<T, Sh, W, -1, IN_WINDOW, OUT_DENSE><<<dim3(N / W, nz, nb), NT, 0, s>>>(
+            kx, ky, kx_slot, ky_slot, (int64_t)ny * N, NN, N, N, pwy(), nullptr, nullptr, 0,
+            nullptr, twp);
+        launch_check("kgen_y");
+      });
+      if (nt > 0) {
+        prof.run("bwd_xscatter", s, pts + (double)nt * N * cb, [&] {
+          k_xscatter<T, Sh, WX><<<(int)((nt + WX - 1) / WX), NTX, 0, s>>>(
+              tasks.as<int32_t>() + t0, (int)nt, pair_set(), fa, fb, x, twp);
+          launch_check("xscatter(bwd)");
+        });
+      }
+      prof.run("bwd_ypass", s, (double)nt * N * cb + (double)nb * NC * cb, [&] {
+        k_strided<T, Sh, W, -1, IN_FLAGS, OUT_DENSE><<<dim3(N / W, N, nb), NT, 0, s>>>(
+            x, x, NC, NC, NN, NN, N, N, 0, lflag.as<uint8_t>(), pflag.as<uint8_t>(), NN, fp, twp);
+        launch_check("ypass(bwd)");
+      });
+      prof.run("bwd_zpass", s,
+               (double)nb * (2.0 * NC + ky_slot) * cb + 3.0 * NC * cb, [&] {
+        k_zback<T, Sh, W><<<dim3(N / W, N, 1), NT, 0, s>>>(x, NC, pflag.as<uint8_t>(), fp, nb, ky,
+                                                            ky_slot, pwz(), fg, A, twp);
+        launch_check("zback");
+      });
+      prof.run("bwd_yinv", s, (double)nb * NC * cb + (double)nt * N * cb, [&] {
+        k_strided<T, Sh, W, 1, IN_DENSE, OUT_FLAGS><<<dim3(N / W, N, nb), NT, 0, s>>>(
+            x, x, NC, NC, NN, NN, N, N, 0, lflag.as<uint8_t>(), pflag.as<uint8_t>(), NN, fp, twp);
+        launch_check("yinv(bwd)");
+      });
+      if (nt > 0) {
+        prof.run("bwd_xgather", s, pts + (double)nt * N * cb, [&] {
+          k_xgather<T, Sh, WX><<<(int)((nt + WX - 1) / WX), NTX, 0, s>>>(
+              tasks.as<int32_t>() + t0, (int)nt, pair_set(), fa, fb, x, (T)1, gb, twp);
+          launch_check("xgather");
+        });
+      }
+    }
+    // galaxy side: dL/drho_g = 2 Re IDFT(A) with A(0) removed
+    k_zero_dc<T><<<1, 64, 0, s>>>(A);
+    prof.run("bwd_gal_zinv", s, 2.0 * NC * cb, [&] {
+      k_strided<T, Sh, W, 1, IN_DENSE, OUT_DENSE><<<dim3(N / W, N, 1), NT, 0, s>>>(
+          A, A, 0, 0, N, N, NN, NN, 0, nullptr, nullptr, 0, nullptr, twp);
+      launch_check("gal_zinv");
+    });
+    prof.run("bwd_gal_yinv", s, 2.0 * NC * cb, [&] {
+      k_strided<T, Sh, W, 1, IN_DENSE, OUT_DENSE><<<dim3(N / W, N, 1), NT, 0, s>>>(
+          A, A, 0, 0, NN, NN, N, N, 0, nullptr, nullptr, 0, nullptr, twp);
+      launch_check("gal_yinv");
+    });
+    prof.run("bwd_gal_xgather", s, (double)NC * cb + (double)n_gal * (4 + 4 * sizeof(T)), [&] {
+      k_xgather<T, Sh, WX><<<(int)(NN / WX), NTX, 0, s>>>(g_tasks.as<int32_t>(), (int)NN, gal_set(),
+                                                           gslot_fa.as<int32_t>(),
+                                                           gslot_fb.as<int32_t>(), A, (T)2, gbg, twp);
+      launch_check("gal_xgather");
+    });
+    const float* wl = w_given ? w_last.as<float>() : nullptr;
+    if (n_pairs > 0) {
+      k_pair_grad<<<grid_for(n_pairs), 256, 0, s>>>(p_key.as<int32_t>(), p_i.as<int32_t>(),
+                                                    p_j.as<int32_t>(), gb, n_pairs, NN, aa.gws, wl, gd);
+      launch_check("pair_grad");
+    }
+    if (n_gal > 0) {
+      k_gal_grad<<<grid_for(n_gal), 256, 0, s>>>(g_idx.as<int32_t>(), gbg, n_gal, aa.gwg, gd);
+      k_grad_out<<<grid_for(n_gal), 256, 0, s>>>(gd, n_gal, grad_w);
+      launch_check("grad_out");
+    }
   }
 
   int pwx() const { return cfg.pw[0]; }
@@ -501,7 +679,7 @@ template <typename T, int N> struct Engine : EngineBase {
   void forward_batched(hipStream_t s) {
     const int R = cfg.R;
     const int ny = win_len(pwy()), nz = win_len(pwz());
-    const int nblkE = (ny * nz + W - 1) / W;
+    const int nblkE = (ny * nz + WX - 1) / WX;
     const int64_t p1_slot = (int64_t)nz * NN;
     const int64_t p2_slot = (int64_t)nz * ny * N;
     C<T>* x = X.get<C<T>>((int64_t)B * NC);
@@ -514,13 +692,13 @@ template <typename T, int N> struct Engine : EngineBase {
     // ---- galaxy field: spectrum (DC removed) and auto-correlation
     const double cb = (double)sizeof(C<T>);
     prof.run("gal_xscatter", s, (double)n_gal * (4 + 4 * sizeof(T)) + (double)NC * cb, [&] {
-      k_xscatter<T, Sh, W><<<(int)(NN / W), NT, 0, s>>>(g_tasks.as<int32_t>(), (int)NN, gal_set(),
+      k_xscatter<T, Sh, WX><<<(int)(NN / WX), NTX, 0, s>>>(g_tasks.as<int32_t>(), (int)NN, gal_set(),
                                                          gslot_fa.as<int32_t>(),
                                                          gslot_fb.as<int32_t>(), x, twp);
       launch_check("xscatter(gal)");
     });
     prof.run("gal_ypass", s, 2.0 * NC * cb, [&] {
-      k_strided<T, Sh, W, -1, false, false><<<dim3(N / W, N, 1), NT, 0, s>>>(
+      k_strided<T, Sh, W, -1, IN_DENSE, OUT_DENSE><<<dim3(N / W, N, 1), NT, 0, s>>>(
           x, x, 0, 0, NN, NN, N, N, 0, nullptr, nullptr, 0, nullptr, twp);
       launch_check("ypass(gal)");
     });
@@ -530,17 +708,17 @@ template <typename T, int N> struct Engine : EngineBase {
       launch_check("zcross(gal)");
     });
     prof.run("gal_yinv", s, (double)(p1_slot + p2_slot) * cb, [&] {
-      k_strided<T, Sh, W, 1, false, true><<<dim3(N / W, nz, 1), NT, 0, s>>>(
+      k_strided<T, Sh, W, 1, IN_DENSE, OUT_WINDOW><<<dim3(N / W, nz, 1), NT, 0, s>>>(
           p1, p2, p1_slot, p2_slot, NN, (int64_t)ny * N, N, N, pwy(), nullptr, nullptr, 0, nullptr,
           twp);
       launch_check("yinv(gal)");
     });
     prof.run("gal_xinv_bins", s, (double)p2_slot * cb, [&] {
-      k_xinv_bins<T, Sh, W, kRMax><<<dim3(nblkE, 1, 1), NT, 0, s>>>(p2, p2_slot, pwx(), pwy(),
+      k_xinv_bins<T, Sh, WX, kRMax><<<dim3(nblkE, 1, 1), NTX, 0, s>>>(p2, p2_slot, pwx(), pwy(),
                                                                      pwz(), bm, R, pt, twp);
       launch_check("xinv_bins(gal)");
     });
-    k_reduce_bins<<<dim3(grid_for(2 * R), 1), 256, 0, s>>>(pt, nblkE, R, gslot_fa.as<int32_t>(),
+    k_reduce_bins<<<dim3(2 * R, 1), 256, 0, s>>>(pt, nblkE, R, gslot_fa.as<int32_t>(),
                                                            gslot_fb.as<int32_t>(), Sgg.as<double>());
     launch_check("reduce(gal)");
     // ---- pair fields, B field pairs per batch
@@ -553,13 +731,13 @@ template <typename T, int N> struct Engine : EngineBase {
       const double pts = (double)batch_points(k) * (4 + 4 * sizeof(T));
       if (nt > 0) {
         prof.run("xscatter", s, pts + (double)nt * N * cb, [&] {
-          k_xscatter<T, Sh, W><<<(int)((nt + W - 1) / W), NT, 0, s>>>(
+          k_xscatter<T, Sh, WX><<<(int)((nt + WX - 1) / WX), NTX, 0, s>>>(
               tasks.as<int32_t>() + t0, (int)nt, pair_set(), fa, fb, x, twp);
           launch_check("xscatter");
         });
       }
       prof.run("ypass", s, (double)nt * N * cb + (double)nb * NC * cb, [&] {
-        k_strided<T, Sh, W, -1, true, false><<<dim3(N / W, N, nb), NT, 0, s>>>(
+        k_strided<T, Sh, W, -1, IN_FLAGS, OUT_DENSE><<<dim3(N / W, N, nb), NT, 0, s>>>(
             x, x, NC, NC, NN, NN, N, N, 0, lflag.as<uint8_t>(), pflag.as<uint8_t>(), NN, fp, twp);
         launch_check("ypass");
       });
@@ -569,17 +747,17 @@ template <typename T, int N> struct Engine : EngineBase {
         launch_check("zcross");
       });
       prof.run("yinv", s, (double)nb * (p1_slot + p2_slot) * cb, [&] {
-        k_strided<T, Sh, W, 1, false, true><<<dim3(N / W, nz, nb), NT, 0, s>>>(
+        k_strided<T, Sh, W, 1, IN_DENSE, OUT_WINDOW><<<dim3(N / W, nz, nb), NT, 0, s>>>(
             p1, p2, p1_slot, p2_slot, NN, (int64_t)ny * N, N, N, pwy(), nullptr, nullptr, 0,
             nullptr, twp);
         launch_check("yinv");
       });
       prof.run("xinv_bins", s, (double)nb * p2_slot * cb, [&] {
-        k_xinv_bins<T, Sh, W, kRMax><<<dim3(nblkE, 1, nb), NT, 0, s>>>(p2, p2_slot, pwx(), pwy(),
+        k_xinv_bins<T, Sh, WX, kRMax><<<dim3(nblkE, 1, nb), NTX, 0, s>>>(p2, p2_slot, pwx(), pwy(),
                                                                         pwz(), bm, R, pt, twp);
         launch_check("xinv_bins");
       });
-      k_reduce_bins<<<dim3(grid_for(2 * R), nb), 256, 0, s>>>(pt, nblkE, R, fa, fb, S.as<double>());
+      k_reduce_bins<<<dim3(2 * R, nb), 256, 0, s>>>(pt, nblkE, R, fa, fb, S.as<double>());
       launch_check("reduce");
     }
   }
@@ -596,17 +774,17 @@ template <typename T, int N> struct Engine : EngineBase {
   void fft3(C<T>* g, int dir, hipStream_t s) {
     const C<T>* twp = tw.as<C<T>>();
     if (dir < 0) {
-      k_xdense<T, Sh, W, -1><<<(int)(NN / W), NT, 0, s>>>(g, twp);
-      k_strided<T, Sh, W, -1, false, false><<<dim3(N / W, N, 1), NT, 0, s>>>(
+      k_xdense<T, Sh, WX, -1><<<(int)(NN / WX), NTX, 0, s>>>(g, twp);
+      k_strided<T, Sh, W, -1, IN_DENSE, OUT_DENSE><<<dim3(N / W, N, 1), NT, 0, s>>>(
           g, g, 0, 0, NN, NN, N, N, 0, nullptr, nullptr, 0, nullptr, twp);
-      k_strided<T, Sh, W, -1, false, false><<<dim3(N / W, N, 1), NT, 0, s>>>(
+      k_strided<T, Sh, W, -1, IN_DENSE, OUT_DENSE><<<dim3(N / W, N, 1), NT, 0, s>>>(
           g, g, 0, 0, N, N, NN, NN, 0, nullptr, nullptr, 0, nullptr, twp);
     } else {
-      k_strided<T, Sh, W, 1, false, false><<<dim3(N / W, N, 1), NT, 0, s>>>(
+      k_strided<T, Sh, W, 1, IN_DENSE, OUT_DENSE><<<dim3(N / W, N, 1), NT, 0, s>>>(
           g, g, 0, 0, N, N, NN, NN, 0, nullptr, nullptr, 0, nullptr, twp);
-      k_strided<T, Sh, W, 1, false, false><<<dim3(N / W, N, 1), NT, 0, s>>>(
+      k_strided<T, Sh, W, 1, IN_DENSE, OUT_DENSE><<<dim3(N / W, N, 1), NT, 0, s>>>(
           g, g, 0, 0, NN, NN, N, N, 0, nullptr, nullptr, 0, nullptr, twp);
-      k_xdense<T, Sh, W, 1><<<(int)(NN / W), NT, 0, s>>>(g, twp);
+      k_xdense<T, Sh, WX, 1><<<(int)(NN / WX), NTX, 0, s>>>(g, twp);
     }
     launch_check("fft3");
   }
@@ -618,7 +796,7 @@ template <typename T, int N> struct Engine : EngineBase {
     double* pt = part.get<double>((int64_t)nblk * 2 * R);
     k_bins_dense<T, kRMax><<<nblk, 256, 0, s>>>(h, N, pwx(), pwy(), pwz(), binmap(), R, pt);
     launch_check("bins_dense");
-    k_reduce_bins<<<dim3(grid_for(2 * R), 1), 256, 0, s>>>(pt, nblk, R, fa, neg1.as<int32_t>(), out);
+    k_reduce_bins<<<dim3(2 * R, 1), 256, 0, s>>>(pt, nblk, R, fa, neg1.as<int32_t>(), out);
     launch_check("reduce_plain");
   }
 

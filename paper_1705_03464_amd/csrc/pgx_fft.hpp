@@ -122,23 +122,28 @@ template <int N, int S, int R0, int R1, int R2> struct Shape {
   static constexpr int n = N, stages = S, E = R0, TPL = N / R0;
   static constexpr int radix(int s) { return s == 0 ? R0 : s == 1 ? R1 : R2; }
   static constexpr int ns(int s) { return s == 0 ? 1 : s == 1 ? R0 : R0 * R1; }
+  // twiddle tables: stage s >= 1 has Ns * R entries exp(-2 pi i r k / (Ns R)),
+  // stored at [twoff(s) + r * Ns + k] so consecutive k are consecutive entries
+  static constexpr int twoff(int s) { return s <= 1 ? 0 : R0 * R1; }
+  static constexpr int tw_entries() { return S == 2 ? N : R0 * R1 + N; }
 };
 
 template <typename T, int N> struct DefaultShape;
 template <> struct DefaultShape<float, 64> { using type = Shape<64, 2, 8, 8, 1>; };
-template <> struct DefaultShape<float, 128> { using type = Shape<128, 2, 16, 8, 1>; };
-template <> struct DefaultShape<float, 256> { using type = Shape<256, 2, 16, 16, 1>; };
-template <> struct DefaultShape<float, 512> { using type = Shape<512, 2, 32, 16, 1>; };
-template <> struct DefaultShape<float, 1024> { using type = Shape<1024, 2, 32, 32, 1>; };
+template <> struct DefaultShape<float, 128> { using type = Shape<128, 3, 8, 8, 2>; };
+template <> struct DefaultShape<float, 256> { using type = Shape<256, 3, 8, 8, 4>; };
+template <> struct DefaultShape<float, 512> { using type = Shape<512, 3, 8, 8, 8>; };
+template <> struct DefaultShape<float, 1024> { using type = Shape<1024, 3, 16, 8, 8>; };
 template <> struct DefaultShape<double, 64> { using type = Shape<64, 2, 8, 8, 1>; };
 template <> struct DefaultShape<double, 128> { using type = Shape<128, 3, 8, 8, 2>; };
 template <> struct DefaultShape<double, 256> { using type = Shape<256, 3, 8, 8, 4>; };
 template <> struct DefaultShape<double, 512> { using type = Shape<512, 3, 8, 8, 8>; };
 template <> struct DefaultShape<double, 1024> { using type = Shape<1024, 3, 16, 8, 8>; };
 
-// LDS index with one pad element per 16 (breaks power-of-two bank strides)
+// LDS index with one pad element per 16 (breaks power-of-two strides inside a
+// line); the line length is odd so lines of a tile start on different banks.
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
-template <int N> constexpr int lds_line_elems() { return N + N / 16; }
+template <int N> constexpr int lds_line_elems() { return N + N / 16 + 1; }
 
 // One Stockham stage for the butterflies owned by thread t (j = t + TPL*q).
 // `in` values are in registers (stage 0) or read from LDS (later stages).
@@ -152,10 +157,10 @@ __device__ __forceinline__ void stage_compute(C<T>* v, int t, const C<T>* __rest
     if constexpr (Ns > 1) {
       const int j = t + TPL * q;
       const int k = j % Ns;
-      constexpr int step = N / (Ns * R);
+      constexpr int off = Sh::twoff(s);
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        C<T> w = tw[r * k * step];
+        C<T> w = tw[off + r * Ns + k];
         if constexpr (DIR > 0) w.y = -w.y;
         b[r] = cmul(b[r], w);
       }
@@ -166,7 +171,7 @@ __device__ __forceinline__ void stage_compute(C<T>* v, int t, const C<T>* __rest
 
 // Full line transform.  On entry v[m] holds element t + TPL*m of the line; on
 // exit v[m] holds output element t + TPL*m.  `line` is this line's LDS buffer
-// (lds_line_elems<N>() entries); `tw` the N-entry forward twiddle table in LDS.
+// (lds_line_elems<N>() entries); `tw` the per-stage forward twiddle tables in LDS.
 // SYNC is a callable that synchronises all threads sharing `line`.
 template <typename Sh, int DIR, typename T, typename Sync>
 __device__ __forceinline__ void line_fft(C<T>* v, int t, C<T>* line, const C<T>* tw, Sync sync) {

@@ -33,9 +33,9 @@ template <typename Sh, int W> struct Blk {
 
 __device__ __forceinline__ void block_sync() { __syncthreads(); }
 
-template <typename T, int N>
+template <typename T, typename Sh>
 __device__ __forceinline__ void load_twiddles(C<T>* tw_s, const C<T>* __restrict__ tw_g) {
-  for (int i = threadIdx.x; i < N; i += blockDim.x) tw_s[i] = tw_g[i];
+  for (int i = threadIdx.x; i < Sh::tw_entries(); i += blockDim.x) tw_s[i] = tw_g[i];
 }
 
 // ----------------------------------------------------------------------------
@@ -51,9 +51,9 @@ k_xscatter(const int32_t* __restrict__ tasks, int n_tasks, PointSet<T> ps,
            C<T>* __restrict__ out, const C<T>* __restrict__ tw_g) {
   constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>();
   constexpr int64_t NN = (int64_t)N * N;
-  __shared__ C<T> tw_s[N];
+  __shared__ C<T> tw_s[Sh::tw_entries()];
   __shared__ C<T> lines[W][LL];
-  load_twiddles<T, N>(tw_s, tw_g);
+  load_twiddles<T, Sh>(tw_s, tw_g);
   const int t = threadIdx.x % TPL, l = threadIdx.x / TPL;
   const int task = blockIdx.x * W + l;
   const bool active = task < n_tasks;
@@ -112,43 +112,73 @@ k_xscatter(const int32_t* __restrict__ tasks, int n_tasks, PointSet<T> ps,
 // ----------------------------------------------------------------------------
 // (B) strided pass: lines along an axis with element stride `es` (N for y,
 // N*N for z) over tiles of W adjacent x positions.  Tile (xt, a): column base
-// a*A + xt*W.  Options:
-//   FLAGS   input element e of the line counts only when lflag[a*N + e] != 0,
-//           and the whole tile is skipped when pflag[a] == 0 (y pass on a
-//           field that was written sparsely by the x pass);
-//   PRUNE   only outputs e' with (e' + pw) mod N <= 2 pw are stored, at
-//           position (e' + pw) mod N of the output line (inverse passes).
-// Batched over blockIdx.z with per-slot strides.
+// a*A + xt*W.  Input modes:
+//   IN_DENSE   every element read;
+//   IN_FLAGS   element e counts only when lflag[a*N + e] != 0, and the whole
+//              tile is skipped when pflag[a] == 0 (a field written sparsely by
+//              the x pass; its untouched elements hold stale data);
+//   IN_WINDOW  only elements e with (e + pw) mod N <= 2 pw exist, stored at
+//              position (e + pw) mod N of a window-sized input line.
+// Output modes:
+//   OUT_DENSE  every element written;
+//   OUT_WINDOW only outputs e' with (e' + pw) mod N <= 2 pw, at position
+//              (e' + pw) mod N of a window-sized output line;
+//   OUT_FLAGS  only outputs whose line flag lflag[a*N + e'] is set (the tile is
+//              skipped when pflag[a] == 0).
+// Batched over blockIdx.z with per-slot strides; flags per field pair slot_fp.
 // ----------------------------------------------------------------------------
-template <typename T, typename Sh, int W, int DIR, bool FLAGS, bool PRUNE>
+enum { IN_DENSE = 0, IN_FLAGS = 1, IN_WINDOW = 2 };
+enum { OUT_DENSE = 0, OUT_WINDOW = 1, OUT_FLAGS = 2 };
+
+template <typename T, typename Sh, int W, int DIR, int IN, int OUT>
 static __global__ void __launch_bounds__(W * Sh::TPL)
 k_strided(const C<T>* in, C<T>* out, int64_t in_slot, int64_t out_slot,
           int64_t in_A, int64_t out_A, int64_t in_es, int64_t out_es, int pw,
           const uint8_t* __restrict__ lflag, const uint8_t* __restrict__ pflag,
           int64_t flag_slot, const int32_t* __restrict__ slot_fp, const C<T>* __restrict__ tw_g) {
   constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>();
-  __shared__ C<T> tw_s[N];
+  __shared__ C<T> tw_s[Sh::tw_entries()];
   __shared__ C<T> lines[W][LL];
   const int slot = blockIdx.z;
   const int xt = blockIdx.x, a = blockIdx.y;
   const uint8_t* lf = nullptr;
-  if constexpr (FLAGS) {
+  if constexpr (IN == IN_FLAGS || OUT == OUT_FLAGS) {
     const int64_t fp = slot_fp[slot];
-    if (pflag[fp * N + a] == 0) return;  // whole plane empty: output stays untouched
+    if (pflag[fp * N + a] == 0) return;  // whole plane empty
     lf = lflag + fp * flag_slot + (int64_t)a * N;
   }
-  load_twiddles<T, N>(tw_s, tw_g);
+  load_twiddles<T, Sh>(tw_s, tw_g);
   const int c = threadIdx.x % W, t = threadIdx.x / W;
   const C<T>* src = in + slot * in_slot + a * in_A + xt * W + c;
   C<T> v[E];
+  uint8_t fl[E];
+  if constexpr (IN == IN_FLAGS || OUT == OUT_FLAGS) {
 #pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int e = t + TPL * m;
-    if constexpr (FLAGS) {
-      v[m] = lf[e] ? src[e * in_es] : C<T>{0, 0};
-    } else {
-      v[m] = src[e * in_es];
+    for (int m = 0; m < E; ++m) fl[m] = lf[t + TPL * m];
+  }
+  if constexpr (IN == IN_FLAGS || IN == IN_WINDOW) {
+    // branch-free predicated loads: an absent element reads the tile's first
+    // input element (a valid, cached address) and is replaced by zero
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int e = t + TPL * m;
+      bool ok;
+      int64_t off;
+      if constexpr (IN == IN_FLAGS) {
+        ok = fl[m] != 0;
+        off = (int64_t)e * in_es;
+      } else {
+        const int pe = (e + pw) & (N - 1);
+        ok = pe <= 2 * pw;
+        off = (int64_t)pe * in_es;
+      }
+      const C<T> x = src[ok ? off : (int64_t)0];
+      v[m].x = ok ? x.x : (T)0;
+      v[m].y = ok ? x.y : (T)0;
     }
+  } else {
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = src[(int64_t)(t + TPL * m) * in_es];
   }
   block_sync();
   line_fft<Sh, DIR>(v, t, lines[c], tw_s, block_sync);
@@ -156,11 +186,13 @@ k_strided(const C<T>* in, C<T>* out, int64_t in_slot, int64_t out_slot,
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int e = t + TPL * m;
-    if constexpr (PRUNE) {
+    if constexpr (OUT == OUT_WINDOW) {
       const int pe = (e + pw) & (N - 1);
-      if (pe <= 2 * pw) dst[pe * out_es] = v[m];
+      if (pe <= 2 * pw) dst[(int64_t)pe * out_es] = v[m];
+    } else if constexpr (OUT == OUT_FLAGS) {
+      if (fl[m]) dst[(int64_t)e * out_es] = v[m];
     } else {
-      dst[e * out_es] = v[m];
+      dst[(int64_t)e * out_es] = v[m];
     }
   }
 }
@@ -181,9 +213,9 @@ k_zcross(const C<T>* in, int64_t in_slot, const uint8_t* __restrict__ pflag,
          const C<T>* __restrict__ tw_g) {
   constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>();
   constexpr int64_t NN = (int64_t)N * N;
-  __shared__ C<T> tw_s[N];
+  __shared__ C<T> tw_s[Sh::tw_entries()];
   __shared__ C<T> lines[W][LL];
-  load_twiddles<T, N>(tw_s, tw_g);
+  load_twiddles<T, Sh>(tw_s, tw_g);
   const int xt = blockIdx.x, ky = blockIdx.y;
   const int c = threadIdx.x % W, t = threadIdx.x / W;
   const int64_t col = (int64_t)ky * N + xt * W + c;
@@ -193,19 +225,33 @@ k_zcross(const C<T>* in, int64_t in_slot, const uint8_t* __restrict__ pflag,
     for (int m = 0; m < E; ++m) g[m] = fg[col + (int64_t)(t + TPL * m) * NN];
   }
   const int pw2 = 2 * pw + 1;
-  for (int slot = 0; slot < n_slots; ++slot) {
+  // software pipeline over the slots: the loads of slot + 1 are issued before
+  // the transforms of slot, so memory latency overlaps the arithmetic
+  auto load_slot = [&](int slot, C<T>* dst) {
     const C<T>* src = in + slot * in_slot + col;
-    const uint8_t* pf = GAL ? nullptr : pflag + (int64_t)slot_fp[slot] * N;
-    C<T> v[E];
+    if constexpr (GAL) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const int z = t + TPL * m;
-      if constexpr (GAL) {
-        v[m] = src[(int64_t)z * NN];
-      } else {
-        v[m] = pf[z] ? src[(int64_t)z * NN] : C<T>{0, 0};
+      for (int m = 0; m < E; ++m) dst[m] = src[(int64_t)(t + TPL * m) * NN];
+    } else {
+      const uint8_t* pf = pflag + (int64_t)slot_fp[slot] * N;
+      uint8_t fl[E];
+#pragma unroll
+      for (int m = 0; m < E; ++m) fl[m] = pf[t + TPL * m];
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const C<T> a = src[fl[m] ? (int64_t)(t + TPL * m) * NN : (int64_t)0];
+        dst[m].x = fl[m] ? a.x : (T)0;
+        dst[m].y = fl[m] ? a.y : (T)0;
       }
     }
+  };
+  C<T> nxt[E];
+  load_slot(0, nxt);
+  for (int slot = 0; slot < n_slots; ++slot) {
+    C<T> v[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = nxt[m];
+    if (slot + 1 < n_slots) load_slot(slot + 1, nxt);
     block_sync();
     line_fft<Sh, -1>(v, t, lines[c], tw_s, block_sync);
     if constexpr (GAL) {
@@ -275,10 +321,10 @@ static __global__ void __launch_bounds__(W * Sh::TPL)
 k_xinv_bins(const C<T>* __restrict__ in, int64_t in_slot, int pwx, int pwy, int pwz, BinMap bm,
             int R, double* __restrict__ part, const C<T>* __restrict__ tw_g) {
   constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>();
-  __shared__ C<T> tw_s[N];
+  __shared__ C<T> tw_s[Sh::tw_entries()];
   __shared__ C<T> lines[W][LL];
   __shared__ double acc[2 * RMAX];
-  load_twiddles<T, N>(tw_s, tw_g);
+  load_twiddles<T, Sh>(tw_s, tw_g);
   for (int i = threadIdx.x; i < 2 * R; i += blockDim.x) acc[i] = 0.0;
   const int slot = blockIdx.z;
   const int t = threadIdx.x % TPL, l = threadIdx.x / TPL;
@@ -319,9 +365,9 @@ template <typename T, typename Sh, int W, int DIR>
 static __global__ void __launch_bounds__(W * Sh::TPL)
 k_xdense(C<T>* data, const C<T>* __restrict__ tw_g) {
   constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>();
-  __shared__ C<T> tw_s[N];
+  __shared__ C<T> tw_s[Sh::tw_entries()];
   __shared__ C<T> lines[W][LL];
-  load_twiddles<T, N>(tw_s, tw_g);
+  load_twiddles<T, Sh>(tw_s, tw_g);
   const int t = threadIdx.x % TPL, l = threadIdx.x / TPL;
   C<T>* p = data + ((int64_t)blockIdx.x * W + l) * N;
   C<T> v[E];

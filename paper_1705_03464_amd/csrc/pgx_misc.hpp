@@ -105,15 +105,18 @@ static __global__ void k_weight_total(const float* __restrict__ w, int64_t n, do
 static __global__ void k_reduce_bins(const double* __restrict__ part, int nblk, int R,
                               const int32_t* __restrict__ slot_fa, const int32_t* __restrict__ slot_fb,
                               double* __restrict__ S) {
-  const int slot = blockIdx.y;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;  // over 2R
-  if (i >= 2 * R) return;
+  // one block per (entry i of the 2R partial row, slot); fixed partition and tree
+  __shared__ double sh[256];
+  const int slot = blockIdx.y, i = blockIdx.x;
   const double* p = part + (int64_t)slot * nblk * 2 * R + i;
   double acc = 0.0;
-  for (int b = 0; b < nblk; ++b) acc += p[(int64_t)b * 2 * R];
-  const int half = i / R, bin = i % R;
-  const int f = half == 0 ? slot_fa[slot] : slot_fb[slot];
-  if (f >= 0) S[(int64_t)f * R + bin] = acc;
+  for (int b = threadIdx.x; b < nblk; b += 256) acc += p[(int64_t)b * 2 * R];
+  const double r = block_sum256(acc, sh);
+  if (threadIdx.x == 0) {
+    const int half = i / R, bin = i % R;
+    const int f = half == 0 ? slot_fa[slot] : slot_fb[slot];
+    if (f >= 0) S[(int64_t)f * R + bin] = r;
+  }
 }
 
 // ----------------------------------------------------------------------------
