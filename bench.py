@@ -3,11 +3,15 @@
 One step = the whole path over one synthetic catalogue: pair catalogue
 (validation, cell list, pair search with integer keys, bucketing), galaxy
 field and spectrum, every pair field's correlation with the galaxy field,
-bin sums and the finalisation (xi_gg, xi_pg, xi_dp, b_pg, Q_eff).
+bin sums, the finalisation (xi_gg, xi_pg, xi_dp, b_pg, Q_eff), and (default
+--mode fwdbwd) the adjoint of a loss sum (b_pg - b_ref)^2 back to the galaxy
+weights through the torch.autograd wrapper (for the HOD workload, on to the
+HOD parameters).
 Default workload: the 512^3 production case (L = 1000 Mpc/h, ~9.2e5 clustered
 galaxies, 200 (s, |mu|) pair fields, 20 log r-bins over 10-80 Mpc/h).
 
-Prints ONE JSON line.  `value` = pair fields per second over the timed steps.
+Prints ONE JSON line.  `value` = pair fields per second over the timed steps
+(forward + adjoint by default; `forward_only` gives the forward rate).
 `roofline` is for the kernel with the largest share of the timed region:
 algorithmic bytes per launch / mean launch time, both measured in this run
 with HIP events on the launch stream.  `cpu_baseline` times the FP64 CPU
@@ -74,6 +78,7 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="cfg1")
     ap.add_argument("--batch", type=int, default=0)
+    ap.add_argument("--mode", choices=["fwd", "fwdbwd"], default="fwdbwd")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernels", action="store_true", help="print the per-kernel table to stderr")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -113,29 +118,62 @@ def main(argv=None):
     if cat.w is not None:
         w = torch.as_tensor(cat.w, dtype=torch.float32, device=dev)
     plan = Plan.from_workload(wl, precision="fp32", batch=a.batch)
+    from paper_1705_03464_amd import hod_weights, pair_galaxy_xi
+    hod = wl.weighted
+    if hod:
+        from synth.configs import HOD_FIDUCIAL
+        th0 = [HOD_FIDUCIAL[k] for k in ("logMcut", "logM1", "sigma", "alpha")]
+        hm = torch.as_tensor(cat.halo_mass, dtype=torch.float64, device=dev)
+        kind = torch.as_tensor(cat.kind.astype(np.int64), device=dev)
+    ones = torch.ones(cat.n, dtype=torch.float32, device=dev)
 
-    def step():
+    def step_fwd():
         plan.pairs_build(x, y, z)
         return plan.forward(w)
 
+    def step_fwdbwd():
+        plan.pairs_build(x, y, z)
+        if hod:
+            theta = torch.tensor(th0, dtype=torch.float64, device=dev, requires_grad=True)
+            wt = hod_weights(theta, hm, kind)
+        else:
+            theta = None
+            wt = ones.clone().requires_grad_(True)
+        out = pair_galaxy_xi(plan, wt)
+        b = out["b_pg"]
+        m = torch.isfinite(b)
+        loss = ((b[m] - 1.0) ** 2).sum()
+        loss.backward()
+        return out
+
+    def timed(fn, steps):
+        plan.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            out = fn()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = plan.profile_read()
+        plan.profile(False)
+        return out, (t1 - t0) * 1e3 / steps, prof
+
+    step = step_fwdbwd if a.mode == "fwdbwd" else step_fwd
     for i in range(a.warmup):
         step()
         torch.cuda.synchronize()
         _log(f"[bench] warmup {i + 1}/{a.warmup} done")
-    plan.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(a.steps):
-        out = step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = plan.profile_read()
-    plan.profile(False)
-    _log(f"[bench] timed {a.steps} steps: {(t1 - t0) * 1e3 / a.steps:.2f} ms/step, "
-         f"n_pairs={plan.n_pairs}")
-    ms_step = (t1 - t0) * 1e3 / a.steps
-    value = wl.n_fields * a.steps / (t1 - t0)
-
+    out, ms_step, prof = timed(step, a.steps)
+    _log(f"[bench] timed {a.steps} steps ({a.mode}): {ms_step:.2f} ms/step, n_pairs={plan.n_pairs}")
+    value = wl.n_fields / (ms_step * 1e-3)
+    fwd_only = None
+    if a.mode == "fwdbwd":
+        step_fwd()
+        torch.cuda.synchronize()
+        _, ms_f, _ = timed(step_fwd, max(1, a.steps // 2))
+        fwd_only = {"value": round(wl.n_fields / (ms_f * 1e-3), 2), "unit": "pair fields/s",
+                    "ms_per_step": round(ms_f, 3)}
+        _log(f"[bench] forward only: {ms_f:.2f} ms/step")
     total_kernel_ms = sum(p[2] for p in prof)
     if a.kernels:
         for name, n, ms, by in prof:
@@ -151,9 +189,9 @@ def main(argv=None):
         "bytes_per_launch": by / n, "ms_per_launch": ms / n,
         "kernel_share_of_step": round(ms / (ms_step * a.steps), 3),
     }
-    finite = np.isfinite(out["xi_pg"].cpu().numpy())
+    finite = np.isfinite(out["xi_pg"].detach().cpu().numpy())
     rec = {
-        "metric": "pair-field xi_pg cross-correlations/s at 512^3 (forward), % HBM peak",
+        "metric": "pair-field xi_pg cross-correlations/s at 512^3 (fwd, fwd+bwd), % HBM peak",
         "value": round(value, 2),
         "unit": "pair fields/s",
         "n_gpus": 1,
@@ -169,10 +207,14 @@ def main(argv=None):
             "workload": wl.description,
             "name": wl.name, "N": wl.N, "L": wl.L, "n_gal": cat.n, "n_pairs": plan.n_pairs,
             "pair_fields": wl.n_fields, "out_bins": wl.n_out, "finite_rows": int(finite.any(1).sum()),
-            "step": "pairs_build + forward", "parallelism": "single GPU",
+            "step": ("pairs_build + forward + adjoint (autograd)" if a.mode == "fwdbwd"
+                     else "pairs_build + forward"),
+            "hod_weights": bool(hod), "parallelism": "single GPU",
         },
         "roofline": roofline,
     }
+    if fwd_only is not None:
+        rec["forward_only"] = fwd_only
     if not a.no_cpu_baseline:
         _log("[bench] timing the CPU oracle on a bounded sample ...")
         rec["cpu_baseline"] = cpu_baseline(wl, cat)
