@@ -196,15 +196,23 @@ k_zback(C<T>* x, int64_t x_slot, const uint8_t* __restrict__ pflag,
   constexpr int64_t NN = (int64_t)N * N;
   __shared__ C<T> tw_s[Sh::tw_entries()];
   __shared__ C<T> lines[W][LL];
+  // accumulator of the galaxy-side term: in LDS when it fits beside the line
+  // buffers (each thread owns its entries; rows padded to an odd length so the
+  // W columns fall on different banks), in registers otherwise
+  constexpr bool ACC_LDS =
+      (size_t)(W * (N + 1) + W * LL + Sh::tw_entries()) * sizeof(C<T>) <= 160 * 1024;
+  __shared__ C<T> accs[ACC_LDS ? W : 1][ACC_LDS ? N + 1 : 1];
+  C<T> accr[ACC_LDS ? 1 : E];
   load_twiddles<T, Sh>(tw_s, tw_g);
   const int xt = blockIdx.x, ky = blockIdx.y;
   const int c = threadIdx.x % W, t = threadIdx.x / W;
   const int64_t col = (int64_t)ky * N + xt * W + c;
-  C<T> g[E], acc[E];
+  C<T> g[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     g[m] = fg[col + (int64_t)(t + TPL * m) * NN];
-    acc[m] = C<T>{0, 0};
+    if constexpr (ACC_LDS) accs[c][t + TPL * m] = C<T>{0, 0};
+    else accr[m] = C<T>{0, 0};
   }
   for (int slot = 0; slot < n_slots; ++slot) {
     C<T>* xs = x + slot * x_slot + col;
@@ -232,8 +240,9 @@ k_zback(C<T>* x, int64_t x_slot, const uint8_t* __restrict__ pflag,
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const C<T> zk = cmulc(v[m], k[m]);
-      acc[m].x += (T)0.5 * zk.x;
-      acc[m].y += (T)0.5 * zk.y;
+      C<T>& a = ACC_LDS ? accs[c][t + TPL * m] : accr[ACC_LDS ? 0 : m];
+      a.x += (T)0.5 * zk.x;
+      a.y += (T)0.5 * zk.y;
       v[m] = cmul(k[m], g[m]);
     }
     block_sync();
@@ -244,8 +253,8 @@ k_zback(C<T>* x, int64_t x_slot, const uint8_t* __restrict__ pflag,
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     C<T>* p = acc_out + col + (int64_t)(t + TPL * m) * NN;
-    const C<T> o = *p;
-    *p = C<T>{o.x + acc[m].x, o.y + acc[m].y};
+    const C<T> o = *p, a = ACC_LDS ? accs[c][t + TPL * m] : accr[ACC_LDS ? 0 : m];
+    *p = C<T>{o.x + a.x, o.y + a.y};
   }
 }
 

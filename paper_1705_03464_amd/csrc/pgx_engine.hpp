@@ -108,9 +108,10 @@ constexpr int kRMax = 640;  // largest number of output bins handled by the bin 
 template <typename T, int N> struct Engine : EngineBase {
   using Sh = typename DefaultShape<T, N>::type;
   static constexpr int TPL = Sh::TPL;
-  // strided passes: tiles of W adjacent columns (W complex = 128 B per row);
-  // x-direction passes: WX whole lines per block
-  static constexpr int W = (int)(128 / sizeof(C<T>));
+  // strided passes: tiles of W adjacent columns (W complex = 128 B per row;
+  // 64 B for 16-element shapes, whose 1024-thread blocks would cap registers
+  // at 128 per thread); x-direction passes: WX whole lines per block
+  static constexpr int W = Sh::E <= 8 ? (int)(128 / sizeof(C<T>)) : (int)(64 / sizeof(C<T>));
   static constexpr int NT = W * TPL;
   static constexpr int WX = (256 / TPL) > 1 ? (256 / TPL) : 1;
   static constexpr int NTX = WX * TPL;

@@ -145,11 +145,45 @@ template <> struct DefaultShape<double, 1024> { using type = Shape<1024, 3, 16, 
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 template <int N> constexpr int lds_line_elems() { return N + N / 16 + 1; }
 
+// Twiddle providers for stage s >= 1 of butterfly q (j = t + TPL*q), radix
+// index r, k = j mod Ns: exp(-2 pi i r k / (Ns R)).
+//  TwLds  reads the per-stage table from LDS on every use;
+//  TwReg  holds this thread's twiddles in registers (loaded once per kernel
+//         from the global table); k depends only on t and q, so a thread that
+//         transforms many lines reuses them.
+template <typename Sh, typename T> struct TwLds {
+  const C<T>* tw;
+  template <int s> __device__ __forceinline__ C<T> get(int q, int r, int k) const {
+    return tw[Sh::twoff(s) + r * Sh::ns(s) + k];
+  }
+};
+
+template <typename Sh, typename T> struct TwReg {
+  static constexpr int NS = Sh::stages > 1 ? Sh::stages - 1 : 1;
+  C<T> w[NS][Sh::E];
+  __device__ __forceinline__ void load(const C<T>* __restrict__ tw_g, int t) {
+    load_stage<1>(tw_g, t);
+    if constexpr (Sh::stages == 3) load_stage<2>(tw_g, t);
+  }
+  template <int s> __device__ __forceinline__ void load_stage(const C<T>* __restrict__ tw_g, int t) {
+    constexpr int R = Sh::radix(s), Ns = Sh::ns(s), Q = Sh::E / R;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int k = (t + Sh::TPL * q) % Ns;
+#pragma unroll
+      for (int r = 0; r < R; ++r) w[s - 1][q * R + r] = tw_g[Sh::twoff(s) + r * Ns + k];
+    }
+  }
+  template <int s> __device__ __forceinline__ C<T> get(int q, int r, int) const {
+    return w[s - 1][q * Sh::radix(s) + r];
+  }
+};
+
 // One Stockham stage for the butterflies owned by thread t (j = t + TPL*q).
 // `in` values are in registers (stage 0) or read from LDS (later stages).
-template <typename Sh, int s, int DIR, typename T>
-__device__ __forceinline__ void stage_compute(C<T>* v, int t, const C<T>* __restrict__ tw) {
-  constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL;
+template <typename Sh, int s, int DIR, typename T, typename TW>
+__device__ __forceinline__ void stage_compute(C<T>* v, int t, const TW& tw) {
+  constexpr int E = Sh::E, TPL = Sh::TPL;
   constexpr int R = Sh::radix(s), Ns = Sh::ns(s), Q = E / R;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
@@ -157,10 +191,9 @@ __device__ __forceinline__ void stage_compute(C<T>* v, int t, const C<T>* __rest
     if constexpr (Ns > 1) {
       const int j = t + TPL * q;
       const int k = j % Ns;
-      constexpr int off = Sh::twoff(s);
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        C<T> w = tw[off + r * Ns + k];
+        C<T> w = tw.template get<s>(q, r, k);
         if constexpr (DIR > 0) w.y = -w.y;
         b[r] = cmul(b[r], w);
       }
@@ -173,11 +206,11 @@ __device__ __forceinline__ void stage_compute(C<T>* v, int t, const C<T>* __rest
 // exit v[m] holds output element t + TPL*m.  `line` is this line's LDS buffer
 // (lds_line_elems<N>() entries); `tw` the per-stage forward twiddle tables in LDS.
 // SYNC is a callable that synchronises all threads sharing `line`.
-template <typename Sh, int DIR, typename T, typename Sync>
-__device__ __forceinline__ void line_fft(C<T>* v, int t, C<T>* line, const C<T>* tw, Sync sync) {
+template <typename Sh, int DIR, typename T, typename Sync, typename TW>
+__device__ __forceinline__ void line_fft_tw(C<T>* v, int t, C<T>* line, const TW& tw, Sync sync) {
   constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL;
   // stage 0: inputs j + r*(N/R0) with j = t  ->  v[r] already in place
-  stage_compute<Sh, 0, DIR, T>(v, t, tw);
+  stage_compute<Sh, 0, DIR, T, TW>(v, t, tw);
   if constexpr (Sh::stages == 1) return;
   // write stage-0 outputs: (j/Ns)*Ns*R + j%Ns + r*Ns with Ns = 1 -> j*R0 + r
 #pragma unroll
@@ -190,7 +223,7 @@ __device__ __forceinline__ void line_fft(C<T>* v, int t, C<T>* line, const C<T>*
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q * R + r] = line[lpad(t + TPL * q + r * (N / R))];
   }
-  stage_compute<Sh, 1, DIR, T>(v, t, tw);
+  stage_compute<Sh, 1, DIR, T, TW>(v, t, tw);
   if constexpr (Sh::stages == 3) {
     constexpr int R = Sh::radix(1), Ns = Sh::ns(1), Q = E / R;
     sync();
@@ -207,7 +240,7 @@ __device__ __forceinline__ void line_fft(C<T>* v, int t, C<T>* line, const C<T>*
     for (int q = 0; q < Q2; ++q)
 #pragma unroll
       for (int r = 0; r < R2; ++r) v[q * R2 + r] = line[lpad(t + TPL * q + r * (N / R2))];
-    stage_compute<Sh, 2, DIR, T>(v, t, tw);
+    stage_compute<Sh, 2, DIR, T, TW>(v, t, tw);
   }
   // last stage: butterfly q, output r -> element j + r*Ns = t + TPL*(q + r*Q);
   // reorder registers to v[m] <-> element t + TPL*m
@@ -223,6 +256,12 @@ __device__ __forceinline__ void line_fft(C<T>* v, int t, C<T>* line, const C<T>*
       for (int m = 0; m < E; ++m) v[m] = tmp[m];
     }
   }
+}
+
+// Line transform with the per-stage twiddle table in LDS.
+template <typename Sh, int DIR, typename T, typename Sync>
+__device__ __forceinline__ void line_fft(C<T>* v, int t, C<T>* line, const C<T>* tw, Sync sync) {
+  line_fft_tw<Sh, DIR, T>(v, t, line, TwLds<Sh, T>{tw}, sync);
 }
 
 }  // namespace pgx

@@ -7,6 +7,8 @@
 #pragma once
 #include "pgx_fft.hpp"
 
+#include <type_traits>
+
 namespace pgx {
 
 // ----------------------------------------------------------------------------
@@ -36,6 +38,30 @@ __device__ __forceinline__ void block_sync() { __syncthreads(); }
 template <typename T, typename Sh>
 __device__ __forceinline__ void load_twiddles(C<T>* tw_s, const C<T>* __restrict__ tw_g) {
   for (int i = threadIdx.x; i < Sh::tw_entries(); i += blockDim.x) tw_s[i] = tw_g[i];
+}
+
+// Twiddle source: kernels whose threads transform many lines (the z passes
+// loop over a batch) keep their stage twiddles in registers when a thread has
+// at most 8 elements; single-tile kernels and larger shapes read the LDS table
+// (one coalesced table load per block, no register pressure).
+// `fft<DIR>(v, t, line)` runs the line transform with it.
+struct TwNone {};
+template <typename Sh, typename T, bool PREFER_REG> struct TwAuto {
+  static constexpr bool REG = PREFER_REG && Sh::E <= 8;
+  typename std::conditional<REG, TwReg<Sh, T>, TwNone>::type reg;
+  C<T>* lds;
+  __device__ __forceinline__ void init(C<T>* lds_table, const C<T>* __restrict__ tw_g, int t) {
+    lds = lds_table;
+    if constexpr (REG) reg.load(tw_g, t);
+    else load_twiddles<T, Sh>(lds_table, tw_g);
+  }
+  template <int DIR> __device__ __forceinline__ void fft(C<T>* v, int t, C<T>* line) const {
+    if constexpr (REG) line_fft_tw<Sh, DIR, T>(v, t, line, reg, block_sync);
+    else line_fft<Sh, DIR, T>(v, t, line, lds, block_sync);
+  }
+};
+template <typename Sh, bool PREFER_REG> constexpr int tw_lds_entries() {
+  return (PREFER_REG && Sh::E <= 8) ? 1 : Sh::tw_entries();
 }
 
 // ----------------------------------------------------------------------------
@@ -137,7 +163,7 @@ k_strided(const C<T>* in, C<T>* out, int64_t in_slot, int64_t out_slot,
           const uint8_t* __restrict__ lflag, const uint8_t* __restrict__ pflag,
           int64_t flag_slot, const int32_t* __restrict__ slot_fp, const C<T>* __restrict__ tw_g) {
   constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>();
-  __shared__ C<T> tw_s[Sh::tw_entries()];
+  __shared__ C<T> tw_s[tw_lds_entries<Sh, false>()];
   __shared__ C<T> lines[W][LL];
   const int slot = blockIdx.z;
   const int xt = blockIdx.x, a = blockIdx.y;
@@ -147,8 +173,9 @@ k_strided(const C<T>* in, C<T>* out, int64_t in_slot, int64_t out_slot,
     if (pflag[fp * N + a] == 0) return;  // whole plane empty
     lf = lflag + fp * flag_slot + (int64_t)a * N;
   }
-  load_twiddles<T, Sh>(tw_s, tw_g);
   const int c = threadIdx.x % W, t = threadIdx.x / W;
+  TwAuto<Sh, T, false> twa;
+  twa.init(tw_s, tw_g, t);
   const C<T>* src = in + slot * in_slot + a * in_A + xt * W + c;
   C<T> v[E];
   uint8_t fl[E];
@@ -181,7 +208,7 @@ k_strided(const C<T>* in, C<T>* out, int64_t in_slot, int64_t out_slot,
     for (int m = 0; m < E; ++m) v[m] = src[(int64_t)(t + TPL * m) * in_es];
   }
   block_sync();
-  line_fft<Sh, DIR>(v, t, lines[c], tw_s, block_sync);
+  twa.template fft<DIR>(v, t, lines[c]);
   C<T>* dst = out + slot * out_slot + a * out_A + xt * W + c;
 #pragma unroll
   for (int m = 0; m < E; ++m) {
@@ -213,11 +240,12 @@ k_zcross(const C<T>* in, int64_t in_slot, const uint8_t* __restrict__ pflag,
          const C<T>* __restrict__ tw_g) {
   constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>();
   constexpr int64_t NN = (int64_t)N * N;
-  __shared__ C<T> tw_s[Sh::tw_entries()];
+  __shared__ C<T> tw_s[tw_lds_entries<Sh, true>()];
   __shared__ C<T> lines[W][LL];
-  load_twiddles<T, Sh>(tw_s, tw_g);
   const int xt = blockIdx.x, ky = blockIdx.y;
   const int c = threadIdx.x % W, t = threadIdx.x / W;
+  TwAuto<Sh, T, true> twa;
+  twa.init(tw_s, tw_g, t);
   const int64_t col = (int64_t)ky * N + xt * W + c;
   C<T> g[E];
   if constexpr (!GAL) {
@@ -225,8 +253,6 @@ k_zcross(const C<T>* in, int64_t in_slot, const uint8_t* __restrict__ pflag,
     for (int m = 0; m < E; ++m) g[m] = fg[col + (int64_t)(t + TPL * m) * NN];
   }
   const int pw2 = 2 * pw + 1;
-  // software pipeline over the slots: the loads of slot + 1 are issued before
-  // the transforms of slot, so memory latency overlaps the arithmetic
   auto load_slot = [&](int slot, C<T>* dst) {
     const C<T>* src = in + slot * in_slot + col;
     if constexpr (GAL) {
@@ -245,15 +271,11 @@ k_zcross(const C<T>* in, int64_t in_slot, const uint8_t* __restrict__ pflag,
       }
     }
   };
-  C<T> nxt[E];
-  load_slot(0, nxt);
   for (int slot = 0; slot < n_slots; ++slot) {
     C<T> v[E];
-#pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = nxt[m];
-    if (slot + 1 < n_slots) load_slot(slot + 1, nxt);
+    load_slot(slot, v);
     block_sync();
-    line_fft<Sh, -1>(v, t, lines[c], tw_s, block_sync);
+    twa.template fft<-1>(v, t, lines[c]);
     if constexpr (GAL) {
       if (col == 0 && t == 0) v[0] = C<T>{0, 0};  // kz = 0 of the (0,0) column
 #pragma unroll
@@ -266,7 +288,7 @@ k_zcross(const C<T>* in, int64_t in_slot, const uint8_t* __restrict__ pflag,
       for (int m = 0; m < E; ++m) v[m] = cmulc(v[m], g[m]);
     }
     block_sync();
-    line_fft<Sh, 1>(v, t, lines[c], tw_s, block_sync);
+    twa.template fft<1>(v, t, lines[c]);
     C<T>* dst = out + slot * out_slot + col;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
