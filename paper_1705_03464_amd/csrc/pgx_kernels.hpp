@@ -40,6 +40,35 @@ __device__ __forceinline__ void load_twiddles(C<T>* tw_s, const C<T>* __restrict
   for (int i = threadIdx.x; i < Sh::tw_entries(); i += blockDim.x) tw_s[i] = tw_g[i];
 }
 
+// ----------------------------------------------------------------------------
+// Buffer-resource access to one slot of a field (at most 2 GiB): a 32-bit
+// per-lane byte offset plus a per-element scalar offset, so the strided
+// element addresses cost no vector arithmetic.
+// ----------------------------------------------------------------------------
+typedef unsigned int pgx_v2u __attribute__((ext_vector_type(2)));
+typedef unsigned int pgx_v4u __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Buf {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ Buf(const void* base, uint32_t bytes) {
+    r = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+  }
+  __device__ __forceinline__ C<T> load(uint32_t voff, uint32_t soff) const {
+    if constexpr (sizeof(T) == 4) {
+      return __builtin_bit_cast(C<T>, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+    } else {
+      return __builtin_bit_cast(C<T>, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+    }
+  }
+  __device__ __forceinline__ void store(C<T> v, uint32_t voff, uint32_t soff) const {
+    if constexpr (sizeof(T) == 4) {
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(pgx_v2u, v), r, (int)voff, (int)soff, 0);
+    } else {
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(pgx_v4u, v), r, (int)voff, (int)soff, 0);
+    }
+  }
+};
+
 // Twiddle source: kernels whose threads transform many lines (the z passes
 // loop over a batch) keep their stage twiddles in registers when a thread has
 // at most 8 elements; single-tile kernels and larger shapes read the LDS table
@@ -176,50 +205,99 @@ k_strided(const C<T>* in, C<T>* out, int64_t in_slot, int64_t out_slot,
   const int c = threadIdx.x % W, t = threadIdx.x / W;
   TwAuto<Sh, T, false> twa;
   twa.init(tw_s, tw_g, t);
-  const C<T>* src = in + slot * in_slot + a * in_A + xt * W + c;
+  // buffer path: tile base in a scalar resource, per-lane 32-bit offset,
+  // per-element scalar offset (fields up to 2 GiB per slot)
+  constexpr bool BUF = (int64_t)N * N * N * (int64_t)sizeof(C<T>) < ((int64_t)1 << 31);
+  const C<T>* tin = in + slot * in_slot + a * in_A + xt * W;
   C<T> v[E];
   uint8_t fl[E];
   if constexpr (IN == IN_FLAGS || OUT == OUT_FLAGS) {
 #pragma unroll
     for (int m = 0; m < E; ++m) fl[m] = lf[t + TPL * m];
   }
-  if constexpr (IN == IN_FLAGS || IN == IN_WINDOW) {
-    // branch-free predicated loads: an absent element reads the tile's first
-    // input element (a valid, cached address) and is replaced by zero
+  if constexpr (BUF) {
+    const Buf<T> bi(tin, 0x7FFFFFF0u);
+    const uint32_t vo = (uint32_t)((c + (int64_t)t * in_es) * (int64_t)sizeof(C<T>));
+    const uint32_t st = (uint32_t)((int64_t)TPL * in_es * (int64_t)sizeof(C<T>));
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      const int e = t + TPL * m;
-      bool ok;
-      int64_t off;
       if constexpr (IN == IN_FLAGS) {
-        ok = fl[m] != 0;
-        off = (int64_t)e * in_es;
-      } else {
+        // absent lines read the tile's first element (valid, cached), then zero
+        const C<T> x = bi.load(fl[m] ? vo + (uint32_t)m * st : 0u, 0u);
+        v[m].x = fl[m] ? x.x : (T)0;
+        v[m].y = fl[m] ? x.y : (T)0;
+      } else if constexpr (IN == IN_WINDOW) {
+        const int e = t + TPL * m;
         const int pe = (e + pw) & (N - 1);
-        ok = pe <= 2 * pw;
-        off = (int64_t)pe * in_es;
+        const bool ok = pe <= 2 * pw;
+        const uint32_t o = (uint32_t)((c + (int64_t)pe * in_es) * (int64_t)sizeof(C<T>));
+        const C<T> x = bi.load(ok ? o : 0u, 0u);
+        v[m].x = ok ? x.x : (T)0;
+        v[m].y = ok ? x.y : (T)0;
+      } else {
+        v[m] = bi.load(vo, (uint32_t)m * st);
       }
-      const C<T> x = src[ok ? off : (int64_t)0];
-      v[m].x = ok ? x.x : (T)0;
-      v[m].y = ok ? x.y : (T)0;
     }
   } else {
+    const C<T>* src = tin + c;
+    if constexpr (IN == IN_FLAGS || IN == IN_WINDOW) {
+      // branch-free predicated loads: an absent element reads the tile's first
+      // input element (a valid, cached address) and is replaced by zero
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = src[(int64_t)(t + TPL * m) * in_es];
+      for (int m = 0; m < E; ++m) {
+        const int e = t + TPL * m;
+        bool ok;
+        int64_t off;
+        if constexpr (IN == IN_FLAGS) {
+          ok = fl[m] != 0;
+          off = (int64_t)e * in_es;
+        } else {
+          const int pe = (e + pw) & (N - 1);
+          ok = pe <= 2 * pw;
+          off = (int64_t)pe * in_es;
+        }
+        const C<T> x = src[ok ? off : (int64_t)0];
+        v[m].x = ok ? x.x : (T)0;
+        v[m].y = ok ? x.y : (T)0;
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = src[(int64_t)(t + TPL * m) * in_es];
+    }
   }
   block_sync();
   twa.template fft<DIR>(v, t, lines[c]);
-  C<T>* dst = out + slot * out_slot + a * out_A + xt * W + c;
+  C<T>* tout = out + slot * out_slot + a * out_A + xt * W;
+  if constexpr (BUF) {
+    const Buf<T> bo(tout, 0x7FFFFFF0u);
+    const uint32_t st = (uint32_t)((int64_t)TPL * out_es * (int64_t)sizeof(C<T>));
+    const uint32_t vo = (uint32_t)((c + (int64_t)t * out_es) * (int64_t)sizeof(C<T>));
 #pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int e = t + TPL * m;
-    if constexpr (OUT == OUT_WINDOW) {
-      const int pe = (e + pw) & (N - 1);
-      if (pe <= 2 * pw) dst[(int64_t)pe * out_es] = v[m];
-    } else if constexpr (OUT == OUT_FLAGS) {
-      if (fl[m]) dst[(int64_t)e * out_es] = v[m];
-    } else {
-      dst[(int64_t)e * out_es] = v[m];
+    for (int m = 0; m < E; ++m) {
+      const int e = t + TPL * m;
+      if constexpr (OUT == OUT_WINDOW) {
+        const int pe = (e + pw) & (N - 1);
+        if (pe <= 2 * pw)
+          bo.store(v[m], (uint32_t)((c + (int64_t)pe * out_es) * (int64_t)sizeof(C<T>)), 0u);
+      } else if constexpr (OUT == OUT_FLAGS) {
+        if (fl[m]) bo.store(v[m], vo, (uint32_t)m * st);
+      } else {
+        bo.store(v[m], vo, (uint32_t)m * st);
+      }
+    }
+  } else {
+    C<T>* dst = tout + c;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int e = t + TPL * m;
+      if constexpr (OUT == OUT_WINDOW) {
+        const int pe = (e + pw) & (N - 1);
+        if (pe <= 2 * pw) dst[(int64_t)pe * out_es] = v[m];
+      } else if constexpr (OUT == OUT_FLAGS) {
+        if (fl[m]) dst[(int64_t)e * out_es] = v[m];
+      } else {
+        dst[(int64_t)e * out_es] = v[m];
+      }
     }
   }
 }
@@ -247,15 +325,28 @@ k_zcross(const C<T>* in, int64_t in_slot, const uint8_t* __restrict__ pflag,
   TwAuto<Sh, T, true> twa;
   twa.init(tw_s, tw_g, t);
   const int64_t col = (int64_t)ky * N + xt * W + c;
+  // buffer path (fields up to 2 GiB per slot): tile base in a scalar resource,
+  // per-lane offset of the column, per-element scalar offset of the z plane
+  constexpr bool BUF = NN * N * (int64_t)sizeof(C<T>) < ((int64_t)1 << 31);
+  constexpr uint32_t CB = sizeof(C<T>);
+  constexpr uint32_t ZST = BUF ? (uint32_t)(TPL * NN * CB) : 0u;  // TPL planes
+  const int64_t tile = (int64_t)ky * N + xt * W;
+  const uint32_t vo = (uint32_t)((c + (int64_t)t * NN) * CB);
   C<T> g[E];
   if constexpr (!GAL) {
+    if constexpr (BUF) {
+      const Buf<T> bg(fg + tile, 0x7FFFFFF0u);
 #pragma unroll
-    for (int m = 0; m < E; ++m) g[m] = fg[col + (int64_t)(t + TPL * m) * NN];
+      for (int m = 0; m < E; ++m) g[m] = bg.load(vo, (uint32_t)m * ZST);
+    } else {
+#pragma unroll
+      for (int m = 0; m < E; ++m) g[m] = fg[col + (int64_t)(t + TPL * m) * NN];
+    }
   }
   const int pw2 = 2 * pw + 1;
   auto load_slot = [&](int slot, C<T>* dst) {
-    const C<T>* src = in + slot * in_slot + col;
     if constexpr (GAL) {
+      const C<T>* src = in + slot * in_slot + col;
 #pragma unroll
       for (int m = 0; m < E; ++m) dst[m] = src[(int64_t)(t + TPL * m) * NN];
     } else {
@@ -263,11 +354,23 @@ k_zcross(const C<T>* in, int64_t in_slot, const uint8_t* __restrict__ pflag,
       uint8_t fl[E];
 #pragma unroll
       for (int m = 0; m < E; ++m) fl[m] = pf[t + TPL * m];
+      if constexpr (BUF) {
+        // an absent plane reads the tile's first element (valid), then zero
+        const Buf<T> bi(in + slot * in_slot + tile, 0x7FFFFFF0u);
 #pragma unroll
-      for (int m = 0; m < E; ++m) {
-        const C<T> a = src[fl[m] ? (int64_t)(t + TPL * m) * NN : (int64_t)0];
-        dst[m].x = fl[m] ? a.x : (T)0;
-        dst[m].y = fl[m] ? a.y : (T)0;
+        for (int m = 0; m < E; ++m) {
+          const C<T> a = bi.load(fl[m] ? vo + (uint32_t)m * ZST : 0u, 0u);
+          dst[m].x = fl[m] ? a.x : (T)0;
+          dst[m].y = fl[m] ? a.y : (T)0;
+        }
+      } else {
+        const C<T>* src = in + slot * in_slot + col;
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+          const C<T> a = src[fl[m] ? (int64_t)(t + TPL * m) * NN : (int64_t)0];
+          dst[m].x = fl[m] ? a.x : (T)0;
+          dst[m].y = fl[m] ? a.y : (T)0;
+        }
       }
     }
   };
@@ -289,11 +392,20 @@ k_zcross(const C<T>* in, int64_t in_slot, const uint8_t* __restrict__ pflag,
     }
     block_sync();
     twa.template fft<1>(v, t, lines[c]);
-    C<T>* dst = out + slot * out_slot + col;
+    if constexpr (BUF) {
+      const Buf<T> bo(out + slot * out_slot + tile, 0x7FFFFFF0u);
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const int pz = (t + TPL * m + pw) & (N - 1);
-      if (pz < pw2) dst[(int64_t)pz * NN] = v[m];
+      for (int m = 0; m < E; ++m) {
+        const int pz = (t + TPL * m + pw) & (N - 1);
+        if (pz < pw2) bo.store(v[m], (uint32_t)((c + (int64_t)pz * NN) * CB), 0u);
+      }
+    } else {
+      C<T>* dst = out + slot * out_slot + col;
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int pz = (t + TPL * m + pw) & (N - 1);
+        if (pz < pw2) dst[(int64_t)pz * NN] = v[m];
+      }
     }
   }
 }
