@@ -128,6 +128,7 @@ def main(argv=None):
     ones = torch.ones(cat.n, dtype=torch.float32, device=dev)
 
     def step_fwd():
+        plan.keep_spectra(False)  # no adjoint follows
         plan.pairs_build(x, y, z)
         return plan.forward(w)
 

@@ -170,6 +170,19 @@ pgx_status pgx_backward(pgx_plan* plan, void* stream, const double* g_b_pg, cons
                         float* grad_w);
 
 /*
+ * Spectrum keeping for the adjoint.  With enable = 1, each later pgx_forward
+ * on an FP32 batched plan also writes every pair-field spectrum (one complex
+ * N^3 grid per two fields: n_fields/2 rounded up, 1 GiB each at N = 512) into
+ * plan-owned device memory, when the device has room for it plus 4 GiB;
+ * pgx_backward then reads them instead of recomputing the pair-field
+ * transforms.  Results are identical either way (the same kernels produce
+ * the same spectra); only time and memory differ.  When the memory is not
+ * available the forward silently recomputes as with enable = 0.  The memory
+ * is held until the plan is destroyed.  Default 0.  No device work.
+ */
+pgx_status pgx_keep_spectra(pgx_plan* plan, int32_t enable);
+
+/*
  * Kernel timing.  pgx_profile(plan, 1) clears the counters and starts
  * recording a pair of HIP events on the launch stream around every launch of
  * the transform-pass kernels (the events bracket exactly one kernel each);

@@ -59,6 +59,7 @@ _SIGS = {
                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pgx_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pgx_keep_spectra": (C.c_int, [C.c_void_p, C.c_int32]),
     "pgx_profile": (C.c_int, [C.c_void_p, C.c_int32]),
     "pgx_profile_read": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_char_p),
                                    C.POINTER(C.c_int64), C.POINTER(C.c_double),
@@ -229,6 +230,11 @@ class Plan:
         _check(load_library().pgx_backward(self._h, _stream(stream), *[_ptr(g) for g in gs],
                                            _ptr(grad)))
         return grad
+
+    def keep_spectra(self, enable: bool = True):
+        """Keep the pair-field spectra of each forward for the adjoint (memory
+        permitting); see pgx_keep_spectra."""
+        _check(load_library().pgx_keep_spectra(self._h, 1 if enable else 0))
 
     def profile(self, enable: bool = True):
         """Start (clearing counters) or stop per-kernel event timing."""

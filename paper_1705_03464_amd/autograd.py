@@ -22,6 +22,8 @@ class PairGalaxyXi(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, w: torch.Tensor, plan: Plan):
+        # a backward will follow: let the plan keep the pair-field spectra
+        plan.keep_spectra(bool(ctx.needs_input_grad[0]))
         out = plan.forward(w.detach().contiguous())
         ctx.plan = plan
         ctx.count = plan.forward_count

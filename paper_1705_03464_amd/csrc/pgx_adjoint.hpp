@@ -185,56 +185,130 @@ k_kgen_x(const double* __restrict__ coef, int R, const int32_t* __restrict__ slo
 //   acc += Z conj(Kp) / 2                       (galaxy-side accumulation)
 //   column <- inverse z of Kp G                (pair-side adjoint, in place)
 // then A += acc.  G is the galaxy spectrum with its k = 0 mode removed.
+// Slot pipeline as in k_zcross: plane masks in LDS, the next slot's columns
+// loaded into the idle register set at the top of each trip.  STORED mode
+// reads Z from the spectra the forward kept (`spec`, by field-pair index)
+// instead of transforming the recomputed columns.
 // ----------------------------------------------------------------------------
-template <typename T, typename Sh, int W>
+template <typename T, typename Sh, int W, bool STORED = false>
 static __global__ void __launch_bounds__(W * Sh::TPL)
 k_zback(C<T>* x, int64_t x_slot, const uint8_t* __restrict__ pflag,
         const int32_t* __restrict__ slot_fp, int n_slots, const C<T>* __restrict__ ky_in,
         int64_t ky_slot, int pwz, const C<T>* __restrict__ fg, C<T>* __restrict__ acc_out,
-        const C<T>* __restrict__ tw_g) {
+        const C<T>* __restrict__ tw_g, const C<T>* __restrict__ spec = nullptr) {
   constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>();
   constexpr int64_t NN = (int64_t)N * N;
+  constexpr bool PIPE = E <= 8;  // register room for a second set of columns
   __shared__ C<T> tw_s[Sh::tw_entries()];
   __shared__ C<T> lines[W][LL];
+  __shared__ uint32_t pmask[kMaxSlots][TPL];
   // accumulator of the galaxy-side term: in LDS when it fits beside the line
   // buffers (each thread owns its entries; rows padded to an odd length so the
   // W columns fall on different banks), in registers otherwise
   constexpr bool ACC_LDS =
-      (size_t)(W * (N + 1) + W * LL + Sh::tw_entries()) * sizeof(C<T>) <= 160 * 1024;
+      (size_t)(W * (N + 1) + W * LL + Sh::tw_entries()) * sizeof(C<T>) +
+          (size_t)kMaxSlots * TPL * sizeof(uint32_t) <= 160 * 1024;
   __shared__ C<T> accs[ACC_LDS ? W : 1][ACC_LDS ? N + 1 : 1];
   C<T> accr[ACC_LDS ? 1 : E];
   load_twiddles<T, Sh>(tw_s, tw_g);
   const int xt = blockIdx.x, ky = blockIdx.y;
   const int c = threadIdx.x % W, t = threadIdx.x / W;
-  const int64_t col = (int64_t)ky * N + xt * W + c;
-  C<T> g[E];
+  for (int i = threadIdx.x; i < n_slots * TPL; i += W * TPL) {
+    const int s = i / TPL, tt = i - s * TPL;
+    const uint8_t* pf = pflag + (int64_t)slot_fp[s] * N + tt;
+    uint32_t mk = 0;
+#pragma unroll
+    for (int m = 0; m < E; ++m) mk |= (uint32_t)(pf[TPL * m] != 0) << m;
+    pmask[s][tt] = mk;
+  }
 #pragma unroll
   for (int m = 0; m < E; ++m) {
-    g[m] = fg[col + (int64_t)(t + TPL * m) * NN];
     if constexpr (ACC_LDS) accs[c][t + TPL * m] = C<T>{0, 0};
     else accr[m] = C<T>{0, 0};
   }
-  for (int slot = 0; slot < n_slots; ++slot) {
-    C<T>* xs = x + slot * x_slot + col;
-    const uint8_t* pf = pflag + (int64_t)slot_fp[slot] * N;
-    C<T> v[E], k[E];
-    uint8_t fl[E];
+  block_sync();
+  const int64_t col = (int64_t)ky * N + xt * W + c;
+  // buffer path for fields up to 2 GiB per slot (see k_zcross)
+  constexpr bool BUF = NN * N * (int64_t)sizeof(C<T>) < ((int64_t)1 << 31);
+  constexpr uint32_t CB = sizeof(C<T>);
+  constexpr uint32_t ZST = BUF ? (uint32_t)(TPL * NN * CB) : 0u;  // TPL planes
+  const int64_t tile = (int64_t)ky * N + xt * W;
+  const uint32_t vo = (uint32_t)((c + (int64_t)t * NN) * CB);
+  auto load_cols = [&](int slot, bool take, C<T>* dst) {
+    if constexpr (STORED) {
+      // the stored spectrum Z of this slot's field pair (dense)
+      const C<T>* zs = spec + (int64_t)slot_fp[slot] * (NN * N);
+      if constexpr (BUF) {
+        const Buf<T> bz(zs + tile);
+        const uint32_t kill = take ? 0u : kBufOff;
 #pragma unroll
-    for (int m = 0; m < E; ++m) fl[m] = pf[t + TPL * m];
+        for (int m = 0; m < E; ++m) dst[m] = bz.load((vo + (uint32_t)m * ZST) | kill, 0u);
+      } else {
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const int z = t + TPL * m;
-      const C<T> a = xs[fl[m] ? (int64_t)z * NN : (int64_t)0];
-      v[m].x = fl[m] ? a.x : (T)0;
-      v[m].y = fl[m] ? a.y : (T)0;
-      const int pe = (z + pwz) & (N - 1);
-      const bool ok = pe <= 2 * pwz;
-      const C<T> b = ky_in[slot * ky_slot + col + (ok ? (int64_t)pe * NN : (int64_t)0)];
-      k[m].x = ok ? b.x : (T)0;
-      k[m].y = ok ? b.y : (T)0;
+        for (int m = 0; m < E; ++m) dst[m] = zs[col + (int64_t)(t + TPL * m) * NN];
+      }
+      return;
     }
-    block_sync();
-    line_fft<Sh, -1>(v, t, lines[c], tw_s, block_sync);
+    const uint32_t mk = take ? pmask[slot][t] : 0u;
+    if constexpr (BUF) {
+      const Buf<T> bi(x + slot * x_slot + tile);
+#pragma unroll
+      for (int m = 0; m < E; ++m)
+        dst[m] = bi.load((mk >> m) & 1u ? vo + (uint32_t)m * ZST : kBufOff, 0u);
+    } else {
+      // absent planes read the tile's first element (valid), zeroed when taken
+      const C<T>* src = x + slot * x_slot + col;
+#pragma unroll
+      for (int m = 0; m < E; ++m) dst[m] = src[(mk >> m) & 1u ? (int64_t)(t + TPL * m) * NN : 0];
+    }
+  };
+  auto take_cols = [&](int slot, const C<T>* cur, C<T>* v) {
+    if constexpr (BUF || STORED) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = cur[m];
+    } else {
+      const uint32_t mk = pmask[slot][t];
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const bool ok = (mk >> m) & 1u;
+        v[m].x = ok ? cur[m].x : (T)0;
+        v[m].y = ok ? cur[m].y : (T)0;
+      }
+    }
+  };
+  // kernel columns: only the window planes pe = (z + pwz) mod N <= 2 pwz
+  auto load_k = [&](int slot, C<T>* k) {
+    if constexpr (BUF) {
+      const Buf<T> bk(ky_in + slot * ky_slot + tile);
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int pe = (t + TPL * m + pwz) & (N - 1);
+        k[m] = bk.load(pe <= 2 * pwz ? (uint32_t)((c + (int64_t)pe * NN) * CB) : kBufOff, 0u);
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int pe = (t + TPL * m + pwz) & (N - 1);
+        const bool ok = pe <= 2 * pwz;
+        const C<T> b = ky_in[slot * ky_slot + col + (ok ? (int64_t)pe * NN : (int64_t)0)];
+        k[m].x = ok ? b.x : (T)0;
+        k[m].y = ok ? b.y : (T)0;
+      }
+    }
+  };
+  C<T> ca[E], cb[PIPE ? E : 1], g[E];
+  load_cols(0, true, ca);
+  // G after the first columns (see k_zcross)
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    if constexpr (BUF) g[m] = Buf<T>(fg + tile).load(vo, (uint32_t)m * ZST);
+    else g[m] = fg[col + (int64_t)(t + TPL * m) * NN];
+  }
+  auto body = [&](int slot, C<T>* v, C<T>* k) {
+    if constexpr (!STORED) {
+      block_sync();
+      line_fft<Sh, -1>(v, t, lines[c], tw_s, block_sync);
+    }
     block_sync();
     line_fft<Sh, -1>(k, t, lines[c], tw_s, block_sync);
 #pragma unroll
@@ -247,8 +321,41 @@ k_zback(C<T>* x, int64_t x_slot, const uint8_t* __restrict__ pflag,
     }
     block_sync();
     line_fft<Sh, 1>(v, t, lines[c], tw_s, block_sync);
+    if constexpr (BUF) {
+      const Buf<T> bo(x + slot * x_slot + tile);
 #pragma unroll
-    for (int m = 0; m < E; ++m) xs[(int64_t)(t + TPL * m) * NN] = v[m];
+      for (int m = 0; m < E; ++m) bo.store(v[m], vo, (uint32_t)m * ZST);
+    } else {
+      C<T>* xs = x + slot * x_slot + col;
+#pragma unroll
+      for (int m = 0; m < E; ++m) xs[(int64_t)(t + TPL * m) * NN] = v[m];
+    }
+  };
+  if constexpr (PIPE) {
+    auto trip = [&](int slot, const C<T>* cur, C<T>* nxt) {
+      const bool more = slot + 1 < n_slots;
+      C<T> k[E];
+      load_k(slot, k);
+      load_cols(more ? slot + 1 : slot, more, nxt);
+      __builtin_amdgcn_sched_barrier(0);
+      C<T> v[E];
+      take_cols(slot, cur, v);
+      body(slot, v, k);
+    };
+    int slot = 0;
+    for (; slot + 1 < n_slots; slot += 2) {
+      trip(slot, ca, cb);
+      trip(slot + 1, cb, ca);
+    }
+    if (slot < n_slots) trip(slot, ca, cb);
+  } else {
+    for (int slot = 0; slot < n_slots; ++slot) {
+      if (slot > 0) load_cols(slot, true, ca);
+      C<T> v[E], k[E];
+      load_k(slot, k);
+      take_cols(slot, ca, v);
+      body(slot, v, k);
+    }
   }
 #pragma unroll
   for (int m = 0; m < E; ++m) {

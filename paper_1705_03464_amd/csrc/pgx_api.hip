@@ -12,6 +12,7 @@ EngineBase* make_engine_f64(const PlanCfg& c);
 
 struct pgx_plan {
   pgx::PlanCfg cfg;
+  bool keep_spectra = false;
   std::unique_ptr<pgx::EngineBase> eng;  // created on first device use
   pgx::EngineBase& engine() {
     if (!eng) {
@@ -204,7 +205,9 @@ pgx_status pgx_forward(pgx_plan* plan, const float* w, void* stream, double* wsu
                        double* xi_pg, double* xi_dp, double* b_pg, double* q_eff) {
   if (!plan) return fail(PGX_EINVAL, "plan is NULL");
   return guarded([&] {
-    plan->engine().forward(w, (hipStream_t)stream, wsum, xi_gg, xi_pg, xi_dp, b_pg, q_eff);
+    auto& e = plan->engine();
+    e.keep_spectra = plan->keep_spectra;
+    e.forward(w, (hipStream_t)stream, wsum, xi_gg, xi_pg, xi_dp, b_pg, q_eff);
   });
 }
 
@@ -215,6 +218,11 @@ pgx_status pgx_backward(pgx_plan* plan, void* stream, const double* g_b_pg, cons
   return guarded([&] {
     plan->engine().backward((hipStream_t)stream, g_b_pg, g_q_eff, g_xi_pg, g_xi_gg, g_xi_dp, grad_w);
   });
+}
+
+pgx_status pgx_keep_spectra(pgx_plan* plan, int32_t enable) {
+  if (!plan) return fail(PGX_EINVAL, "plan is NULL");
+  return guarded([&] { plan->keep_spectra = enable != 0; });
 }
 
 pgx_status pgx_profile(pgx_plan* plan, int32_t enable) {

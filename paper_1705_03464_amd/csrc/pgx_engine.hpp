@@ -101,6 +101,10 @@ struct EngineBase {
                         const double* g_xigg, const double* g_xidp, float* grad_w) = 0;
   bool built = false;
   bool forward_done = false;
+  // keep each pair-field spectrum from the forward for the adjoint (when the
+  // device has room); the adjoint then skips recomputing them
+  bool keep_spectra = false;
+  bool spectra_valid = false;
 };
 
 constexpr int kRMax = 640;  // largest number of output bins handled by the bin kernels
@@ -139,7 +143,28 @@ template <typename T, int N> struct Engine : EngineBase {
   DBuf X, P1, P2, Fg, part, S, Sgg, wsum_d, wg_d, outs;
   // backward work
   DBuf KX, KY, Aacc, gbuf, gbuf_g, grad_d, apg, agg, gws, gwg, w_last;
+  DBuf SPEC;  // kept pair-field spectra, one N^3 grid per field pair
   bool w_given = false;
+
+  // room for the kept spectra: already allocated, or fits in free device
+  // memory with 4 GiB to spare
+  C<T>* spectra_store() {
+    const size_t need = (size_t)cfg.n_fp * (size_t)NC * sizeof(C<T>);
+    if (need == 0) return nullptr;
+    if (SPEC.bytes < need) {
+      size_t fr = 0, tot = 0;
+      PGX_HIP(hipMemGetInfo(&fr, &tot));
+      if (fr + SPEC.bytes < need + ((size_t)4 << 30)) return nullptr;
+      SPEC.release();
+      if (hipMalloc(&SPEC.p, need) != hipSuccess) {
+        (void)hipGetLastError();
+        SPEC.p = nullptr;
+        return nullptr;
+      }
+      SPEC.bytes = need;
+    }
+    return SPEC.as<C<T>>();
+  }
 
   explicit Engine(const PlanCfg& c) : cfg(c) {
     static_assert(N % W == 0, "tile width must divide N");
@@ -168,7 +193,7 @@ template <typename T, int N> struct Engine : EngineBase {
     const int nfp = cfg.n_fp;
     int b = cfg.batch;
     if (b <= 0) b = N >= 512 ? 8 : (N >= 256 ? 16 : 32);
-    B = std::max(1, std::min(b, nfp));
+    B = std::max(1, std::min({b, nfp, kMaxSlots}));
     n_batches = (nfp + B - 1) / B;
     std::vector<int32_t> fa((size_t)n_batches * B, -1), fb((size_t)n_batches * B, -1),
         fp((size_t)n_batches * B, 0);
@@ -505,6 +530,7 @@ template <typename T, int N> struct Engine : EngineBase {
     S.get<double>((int64_t)cfg.F * cfg.R);
     Sgg.get<double>(cfg.R);
     forward_done = false;
+    spectra_valid = false;
     w_given = w != nullptr;
     if (w && n_gal > 0)
       PGX_HIP(hipMemcpyAsync(w_last.get<float>(n_gal), w, n_gal * sizeof(float),
@@ -611,24 +637,34 @@ template <typename T, int N> struct Engine : EngineBase {
             nullptr, twp);
         launch_check("kgen_y");
       });
-      if (nt > 0) {
-        prof.run("bwd_xscatter", s, pts + (double)nt * N * cb, [&] {
-          k_xscatter<T, Sh, WX><<<(int)((nt + WX - 1) / WX), NTX, 0, s>>>(
-              tasks.as<int32_t>() + t0, (int)nt, pair_set(), fa, fb, x, twp);
-          launch_check("xscatter(bwd)");
+      if (spectra_valid) {
+        // Z from the spectra the forward kept: no scatter, y pass or forward z
+        prof.run("bwd_zpass", s,
+                 (double)nb * (2.0 * NC + ky_slot) * cb + 3.0 * NC * cb, [&] {
+          k_zback<T, Sh, W, true><<<dim3(N / W, N, 1), NT, 0, s>>>(
+              x, NC, pflag.as<uint8_t>(), fp, nb, ky, ky_slot, pwz(), fg, A, twp, SPEC.as<C<T>>());
+          launch_check("zback(kept)");
+        });
+      } else {
+        if (nt > 0) {
+          prof.run("bwd_xscatter", s, pts + (double)nt * N * cb, [&] {
+            k_xscatter<T, Sh, WX><<<(int)((nt + WX - 1) / WX), NTX, 0, s>>>(
+                tasks.as<int32_t>() + t0, (int)nt, pair_set(), fa, fb, x, twp);
+            launch_check("xscatter(bwd)");
+          });
+        }
+        prof.run("bwd_ypass", s, (double)nt * N * cb + (double)nb * NC * cb, [&] {
+          k_strided<T, Sh, W, -1, IN_FLAGS, OUT_DENSE><<<dim3(N / W, N, nb), NT, 0, s>>>(
+              x, x, NC, NC, NN, NN, N, N, 0, lflag.as<uint8_t>(), pflag.as<uint8_t>(), NN, fp, twp);
+          launch_check("ypass(bwd)");
+        });
+        prof.run("bwd_zpass", s,
+                 (double)nb * (2.0 * NC + ky_slot) * cb + 3.0 * NC * cb, [&] {
+          k_zback<T, Sh, W><<<dim3(N / W, N, 1), NT, 0, s>>>(x, NC, pflag.as<uint8_t>(), fp, nb, ky,
+                                                              ky_slot, pwz(), fg, A, twp);
+          launch_check("zback");
         });
       }
-      prof.run("bwd_ypass", s, (double)nt * N * cb + (double)nb * NC * cb, [&] {
-        k_strided<T, Sh, W, -1, IN_FLAGS, OUT_DENSE><<<dim3(N / W, N, nb), NT, 0, s>>>(
-            x, x, NC, NC, NN, NN, N, N, 0, lflag.as<uint8_t>(), pflag.as<uint8_t>(), NN, fp, twp);
-        launch_check("ypass(bwd)");
-      });
-      prof.run("bwd_zpass", s,
-               (double)nb * (2.0 * NC + ky_slot) * cb + 3.0 * NC * cb, [&] {
-        k_zback<T, Sh, W><<<dim3(N / W, N, 1), NT, 0, s>>>(x, NC, pflag.as<uint8_t>(), fp, nb, ky,
-                                                            ky_slot, pwz(), fg, A, twp);
-        launch_check("zback");
-      });
       prof.run("bwd_yinv", s, (double)nb * NC * cb + (double)nt * N * cb, [&] {
         k_strided<T, Sh, W, 1, IN_DENSE, OUT_FLAGS><<<dim3(N / W, N, nb), NT, 0, s>>>(
             x, x, NC, NC, NN, NN, N, N, 0, lflag.as<uint8_t>(), pflag.as<uint8_t>(), NN, fp, twp);
@@ -723,6 +759,7 @@ template <typename T, int N> struct Engine : EngineBase {
                                                            gslot_fb.as<int32_t>(), Sgg.as<double>());
     launch_check("reduce(gal)");
     // ---- pair fields, B field pairs per batch
+    C<T>* spec = keep_spectra ? spectra_store() : nullptr;
     for (int k = 0; k < n_batches; ++k) {
       const int nb = std::min(B, cfg.n_fp - k * B);
       const int64_t t0 = batch_task_off[k], nt = batch_task_off[k + 1] - t0;
@@ -742,9 +779,15 @@ template <typename T, int N> struct Engine : EngineBase {
             x, x, NC, NC, NN, NN, N, N, 0, lflag.as<uint8_t>(), pflag.as<uint8_t>(), NN, fp, twp);
         launch_check("ypass");
       });
-      prof.run("zpass_cross", s, (double)(nb + 1) * NC * cb + (double)nb * p1_slot * cb, [&] {
-        k_zcross<T, Sh, W, false><<<dim3(N / W, N, 1), NT, 0, s>>>(
-            x, NC, pflag.as<uint8_t>(), fp, nb, fg, nullptr, p1, p1_slot, pwz(), twp);
+      prof.run("zpass_cross", s,
+               (double)(nb + 1) * NC * cb + (double)nb * p1_slot * cb + (spec ? (double)nb * NC * cb : 0.0),
+               [&] {
+        if (spec)
+          k_zcross<T, Sh, W, false, true><<<dim3(N / W, N, 1), NT, 0, s>>>(
+              x, NC, pflag.as<uint8_t>(), fp, nb, fg, nullptr, p1, p1_slot, pwz(), twp, spec);
+        else
+          k_zcross<T, Sh, W, false><<<dim3(N / W, N, 1), NT, 0, s>>>(
+              x, NC, pflag.as<uint8_t>(), fp, nb, fg, nullptr, p1, p1_slot, pwz(), twp);
         launch_check("zcross");
       });
       prof.run("yinv", s, (double)nb * (p1_slot + p2_slot) * cb, [&] {
@@ -761,6 +804,7 @@ template <typename T, int N> struct Engine : EngineBase {
       k_reduce_bins<<<dim3(2 * R, nb), 256, 0, s>>>(pt, nblkE, R, fa, fb, S.as<double>());
       launch_check("reduce");
     }
+    spectra_valid = spec != nullptr;
   }
 
   // one field at a time, full transforms, global-atomic scatter, FP64 or FP32

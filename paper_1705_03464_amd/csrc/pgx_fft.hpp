@@ -140,10 +140,13 @@ template <> struct DefaultShape<double, 256> { using type = Shape<256, 3, 8, 8, 
 template <> struct DefaultShape<double, 512> { using type = Shape<512, 3, 8, 8, 8>; };
 template <> struct DefaultShape<double, 1024> { using type = Shape<1024, 3, 16, 8, 8>; };
 
-// LDS index with one pad element per 16 (breaks power-of-two strides inside a
-// line); the line length is odd so lines of a tile start on different banks.
-__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
-template <int N> constexpr int lds_line_elems() { return N + N / 16 + 1; }
+// LDS index with one pad element per 2^kPadShift (breaks power-of-two strides
+// inside a line); kLineExtra sets the line length modulo the bank count so
+// the lines of a tile start on different banks.
+constexpr int kPadShift = 4;
+constexpr int kLineExtra = 1;
+__device__ __forceinline__ int lpad(int i) { return i + (i >> kPadShift); }
+template <int N> constexpr int lds_line_elems() { return N + (N >> kPadShift) + kLineExtra; }
 
 // Twiddle providers for stage s >= 1 of butterfly q (j = t + TPL*q), radix
 // index r, k = j mod Ns: exp(-2 pi i r k / (Ns R)).
@@ -154,7 +157,8 @@ template <int N> constexpr int lds_line_elems() { return N + N / 16 + 1; }
 template <typename Sh, typename T> struct TwLds {
   const C<T>* tw;
   template <int s> __device__ __forceinline__ C<T> get(int q, int r, int k) const {
-    return tw[Sh::twoff(s) + r * Sh::ns(s) + k];
+    const C<T>* b = tw + k;  // thread base; the stage/radix part is an immediate offset
+    return b[Sh::twoff(s) + r * Sh::ns(s)];
   }
 };
 
@@ -202,6 +206,34 @@ __device__ __forceinline__ void stage_compute(C<T>* v, int t, const TW& tw) {
   }
 }
 
+// The exchanges address the line at lpad(B + K), B depending on the thread,
+// K a compile-time constant.  lpad(B + K) = lpad(B) + K + (K >> kPadShift)
+// whenever (B mod P) + (K mod P) < P (P = 2^kPadShift): then every access of a
+// thread is one base address plus an immediate offset.  pad_linear<Sh>()
+// checks that condition for all threads and accesses of a shape.
+template <typename Sh> constexpr bool pad_linear() {
+  constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, P = 1 << kPadShift;
+  for (int t = 0; t < TPL; ++t) {
+    for (int r = 0; r < E; ++r)  // stage-0 outputs: B = t E, K = r
+      if ((t * E) % P + r % P >= P) return false;
+    for (int s = 1; s < Sh::stages; ++s) {  // stage inputs: B = t, K = TPL q + r N / R
+      const int R = Sh::radix(s), Q = E / R;
+      for (int q = 0; q < Q; ++q)
+        for (int r = 0; r < R; ++r)
+          if (t % P + (TPL * q + r * (N / R)) % P >= P) return false;
+    }
+    if (Sh::stages == 3) {  // stage-1 outputs: B = (t/Ns) Ns R + t % Ns, K = TPL q R + r Ns
+      const int R = Sh::radix(1), Ns = Sh::ns(1), Q = E / R;
+      if (TPL % Ns != 0) return false;
+      const int B = (t / Ns) * Ns * R + t % Ns;
+      for (int q = 0; q < Q; ++q)
+        for (int r = 0; r < R; ++r)
+          if (B % P + (TPL * q * R + r * Ns) % P >= P) return false;
+    }
+  }
+  return true;
+}
+
 // Full line transform.  On entry v[m] holds element t + TPL*m of the line; on
 // exit v[m] holds output element t + TPL*m.  `line` is this line's LDS buffer
 // (lds_line_elems<N>() entries); `tw` the per-stage forward twiddle tables in LDS.
@@ -209,37 +241,64 @@ __device__ __forceinline__ void stage_compute(C<T>* v, int t, const TW& tw) {
 template <typename Sh, int DIR, typename T, typename Sync, typename TW>
 __device__ __forceinline__ void line_fft_tw(C<T>* v, int t, C<T>* line, const TW& tw, Sync sync) {
   constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL;
+  constexpr bool LIN = pad_linear<Sh>();
   // stage 0: inputs j + r*(N/R0) with j = t  ->  v[r] already in place
   stage_compute<Sh, 0, DIR, T, TW>(v, t, tw);
   if constexpr (Sh::stages == 1) return;
   // write stage-0 outputs: (j/Ns)*Ns*R + j%Ns + r*Ns with Ns = 1 -> j*R0 + r
+  {
+    C<T>* lw = line + lpad(t * E);
 #pragma unroll
-  for (int r = 0; r < E; ++r) line[lpad(t * E + r)] = v[r];
+    for (int r = 0; r < E; ++r) {
+      if constexpr (LIN) lw[r + (r >> kPadShift)] = v[r];
+      else line[lpad(t * E + r)] = v[r];
+    }
+  }
   sync();
+  C<T>* lr = line + lpad(t);  // base of every stage's inputs
   {
     constexpr int R = Sh::radix(1), Q = E / R;
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q * R + r] = line[lpad(t + TPL * q + r * (N / R))];
+      for (int r = 0; r < R; ++r) {
+        const int K = TPL * q + r * (N / R);
+        if constexpr (LIN) v[q * R + r] = lr[K + (K >> kPadShift)];
+        else v[q * R + r] = line[lpad(t + K)];
+      }
   }
   stage_compute<Sh, 1, DIR, T, TW>(v, t, tw);
   if constexpr (Sh::stages == 3) {
     constexpr int R = Sh::radix(1), Ns = Sh::ns(1), Q = E / R;
     sync();
+    if constexpr (LIN) {
+      C<T>* lm = line + lpad((t / Ns) * Ns * R + t % Ns);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int j = t + TPL * q;
-      const int base = (j / Ns) * Ns * R + (j % Ns);
+      for (int q = 0; q < Q; ++q)
 #pragma unroll
-      for (int r = 0; r < R; ++r) line[lpad(base + r * Ns)] = v[q * R + r];
+        for (int r = 0; r < R; ++r) {
+          const int K = TPL * q * R + r * Ns;
+          lm[K + (K >> kPadShift)] = v[q * R + r];
+        }
+    } else {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int j = t + TPL * q;
+        const int base = (j / Ns) * Ns * R + (j % Ns);
+#pragma unroll
+        for (int r = 0; r < R; ++r) line[lpad(base + r * Ns)] = v[q * R + r];
+      }
     }
     sync();
     constexpr int R2 = Sh::radix(2), Q2 = E / R2;
 #pragma unroll
     for (int q = 0; q < Q2; ++q)
 #pragma unroll
-      for (int r = 0; r < R2; ++r) v[q * R2 + r] = line[lpad(t + TPL * q + r * (N / R2))];
+      for (int r = 0; r < R2; ++r) {
+        const int K = TPL * q + r * (N / R2);
+        if constexpr (LIN) v[q * R2 + r] = lr[K + (K >> kPadShift)];
+        else v[q * R2 + r] = line[lpad(t + K)];
+      }
     stage_compute<Sh, 2, DIR, T, TW>(v, t, tw);
   }
   // last stage: butterfly q, output r -> element j + r*Ns = t + TPL*(q + r*Q);

@@ -43,15 +43,21 @@ __device__ __forceinline__ void load_twiddles(C<T>* tw_s, const C<T>* __restrict
 // ----------------------------------------------------------------------------
 // Buffer-resource access to one slot of a field (at most 2 GiB): a 32-bit
 // per-lane byte offset plus a per-element scalar offset, so the strided
-// element addresses cost no vector arithmetic.
+// element addresses cost no vector arithmetic.  The resource's record count
+// is kBufRecords; a lane offset at or beyond it (kBufOff) is out of range:
+// the hardware's range check returns zero for such a load and discards such
+// a store, which gives masked accesses without branches.
 // ----------------------------------------------------------------------------
+constexpr uint32_t kBufRecords = 0x7FFFFFF0u;
+constexpr uint32_t kBufOff = 0x80000000u;
 typedef unsigned int pgx_v2u __attribute__((ext_vector_type(2)));
 typedef unsigned int pgx_v4u __attribute__((ext_vector_type(4)));
 
 template <typename T> struct Buf {
   __amdgpu_buffer_rsrc_t r;
-  __device__ __forceinline__ Buf(const void* base, uint32_t bytes) {
-    r = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+  __device__ __forceinline__ Buf(const void* base) {
+    r = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)kBufRecords,
+                                          0x00020000);
   }
   __device__ __forceinline__ C<T> load(uint32_t voff, uint32_t soff) const {
     if constexpr (sizeof(T) == 4) {
@@ -68,6 +74,11 @@ template <typename T> struct Buf {
     }
   }
 };
+
+// z passes: twiddle source, and the most slots one launch may carry (their
+// plane masks are staged in LDS)
+constexpr bool kZTwReg = true;
+constexpr int kMaxSlots = 32;
 
 // Twiddle source: kernels whose threads transform many lines (the z passes
 // loop over a batch) keep their stage twiddles in registers when a thread has
@@ -216,7 +227,7 @@ k_strided(const C<T>* in, C<T>* out, int64_t in_slot, int64_t out_slot,
     for (int m = 0; m < E; ++m) fl[m] = lf[t + TPL * m];
   }
   if constexpr (BUF) {
-    const Buf<T> bi(tin, 0x7FFFFFF0u);
+    const Buf<T> bi(tin);
     const uint32_t vo = (uint32_t)((c + (int64_t)t * in_es) * (int64_t)sizeof(C<T>));
     const uint32_t st = (uint32_t)((int64_t)TPL * in_es * (int64_t)sizeof(C<T>));
 #pragma unroll
@@ -269,7 +280,7 @@ k_strided(const C<T>* in, C<T>* out, int64_t in_slot, int64_t out_slot,
   twa.template fft<DIR>(v, t, lines[c]);
   C<T>* tout = out + slot * out_slot + a * out_A + xt * W;
   if constexpr (BUF) {
-    const Buf<T> bo(tout, 0x7FFFFFF0u);
+    const Buf<T> bo(tout);
     const uint32_t st = (uint32_t)((int64_t)TPL * out_es * (int64_t)sizeof(C<T>));
     const uint32_t vo = (uint32_t)((c + (int64_t)t * out_es) * (int64_t)sizeof(C<T>));
 #pragma unroll
@@ -309,21 +320,39 @@ k_strided(const C<T>* in, C<T>* out, int64_t in_slot, int64_t out_slot,
 // [pz][ky][kx], pz = (z' + pw) mod N).  Fg is read once per tile per batch.
 // GAL mode (galaxy field): after the forward transform the k = 0 mode is set
 // to zero, the spectrum is stored to `fg_out`, and the product is |Fg|^2.
+// STORE mode also writes each pair-field spectrum (after the forward z
+// transform) to `spec` at its field-pair index, for the adjoint.
 // ----------------------------------------------------------------------------
-template <typename T, typename Sh, int W, bool GAL>
+template <typename T, typename Sh, int W, bool GAL, bool STORE = false>
 static __global__ void __launch_bounds__(W * Sh::TPL)
 k_zcross(const C<T>* in, int64_t in_slot, const uint8_t* __restrict__ pflag,
          const int32_t* __restrict__ slot_fp, int n_slots, const C<T>* __restrict__ fg,
          C<T>* __restrict__ fg_out, C<T>* __restrict__ out, int64_t out_slot, int pw,
-         const C<T>* __restrict__ tw_g) {
+         const C<T>* __restrict__ tw_g, C<T>* __restrict__ spec = nullptr) {
   constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>();
   constexpr int64_t NN = (int64_t)N * N;
-  __shared__ C<T> tw_s[tw_lds_entries<Sh, true>()];
+  // slot pipeline when a thread has room for a second set of columns
+  constexpr bool PIPE = !GAL && E <= 8;
+  __shared__ C<T> tw_s[tw_lds_entries<Sh, kZTwReg>()];
   __shared__ C<T> lines[W][LL];
+  __shared__ uint32_t pmask[GAL ? 1 : kMaxSlots][TPL];
   const int xt = blockIdx.x, ky = blockIdx.y;
   const int c = threadIdx.x % W, t = threadIdx.x / W;
-  TwAuto<Sh, T, true> twa;
+  TwAuto<Sh, T, kZTwReg> twa;
   twa.init(tw_s, tw_g, t);
+  if constexpr (!GAL) {
+    // plane masks of the batch: bit m of pmask[s][t] = plane t + TPL m of
+    // slot s holds data
+    for (int i = threadIdx.x; i < n_slots * TPL; i += W * TPL) {
+      const int s = i / TPL, tt = i - s * TPL;
+      const uint8_t* pf = pflag + (int64_t)slot_fp[s] * N + tt;
+      uint32_t mk = 0;
+#pragma unroll
+      for (int m = 0; m < E; ++m) mk |= (uint32_t)(pf[TPL * m] != 0) << m;
+      pmask[s][tt] = mk;
+    }
+    block_sync();
+  }
   const int64_t col = (int64_t)ky * N + xt * W + c;
   // buffer path (fields up to 2 GiB per slot): tile base in a scalar resource,
   // per-lane offset of the column, per-element scalar offset of the z plane
@@ -332,10 +361,50 @@ k_zcross(const C<T>* in, int64_t in_slot, const uint8_t* __restrict__ pflag,
   constexpr uint32_t ZST = BUF ? (uint32_t)(TPL * NN * CB) : 0u;  // TPL planes
   const int64_t tile = (int64_t)ky * N + xt * W;
   const uint32_t vo = (uint32_t)((c + (int64_t)t * NN) * CB);
-  C<T> g[E];
+  const int pw2 = 2 * pw + 1;
+  // columns of one slot; absent planes are zero (buffer path: out-of-range
+  // offset; pointer path: the tile's first element is read and zeroed when
+  // the columns are taken)
+  auto load_cols = [&](int slot, bool take, C<T>* dst) {
+    if constexpr (GAL) {
+      const C<T>* src = in + slot * in_slot + col;
+#pragma unroll
+      for (int m = 0; m < E; ++m) dst[m] = src[(int64_t)(t + TPL * m) * NN];
+    } else if constexpr (BUF) {
+      const uint32_t mk = take ? pmask[slot][t] : 0u;
+      const Buf<T> bi(in + slot * in_slot + tile);
+#pragma unroll
+      for (int m = 0; m < E; ++m)
+        dst[m] = bi.load((mk >> m) & 1u ? vo + (uint32_t)m * ZST : kBufOff, 0u);
+    } else {
+      const uint32_t mk = take ? pmask[slot][t] : 0u;
+      const C<T>* src = in + slot * in_slot + col;
+#pragma unroll
+      for (int m = 0; m < E; ++m) dst[m] = src[(mk >> m) & 1u ? (int64_t)(t + TPL * m) * NN : 0];
+    }
+  };
+  auto take_cols = [&](int slot, const C<T>* cur, C<T>* v) {
+    if constexpr (GAL || BUF) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = cur[m];
+    } else {
+      const uint32_t mk = pmask[slot][t];
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const bool ok = (mk >> m) & 1u;
+        v[m].x = ok ? cur[m].x : (T)0;
+        v[m].y = ok ? cur[m].y : (T)0;
+      }
+    }
+  };
+  C<T> ca[E], cb[PIPE ? E : 1], g[E];
+  load_cols(0, true, ca);
+  // G after the first columns: on entry to the loop, as on every later trip
+  // (where the previous slot's stores follow them), eight younger memory
+  // operations follow the columns, so the wait for them is the same
   if constexpr (!GAL) {
     if constexpr (BUF) {
-      const Buf<T> bg(fg + tile, 0x7FFFFFF0u);
+      const Buf<T> bg(fg + tile);
 #pragma unroll
       for (int m = 0; m < E; ++m) g[m] = bg.load(vo, (uint32_t)m * ZST);
     } else {
@@ -343,40 +412,7 @@ k_zcross(const C<T>* in, int64_t in_slot, const uint8_t* __restrict__ pflag,
       for (int m = 0; m < E; ++m) g[m] = fg[col + (int64_t)(t + TPL * m) * NN];
     }
   }
-  const int pw2 = 2 * pw + 1;
-  auto load_slot = [&](int slot, C<T>* dst) {
-    if constexpr (GAL) {
-      const C<T>* src = in + slot * in_slot + col;
-#pragma unroll
-      for (int m = 0; m < E; ++m) dst[m] = src[(int64_t)(t + TPL * m) * NN];
-    } else {
-      const uint8_t* pf = pflag + (int64_t)slot_fp[slot] * N;
-      uint8_t fl[E];
-#pragma unroll
-      for (int m = 0; m < E; ++m) fl[m] = pf[t + TPL * m];
-      if constexpr (BUF) {
-        // an absent plane reads the tile's first element (valid), then zero
-        const Buf<T> bi(in + slot * in_slot + tile, 0x7FFFFFF0u);
-#pragma unroll
-        for (int m = 0; m < E; ++m) {
-          const C<T> a = bi.load(fl[m] ? vo + (uint32_t)m * ZST : 0u, 0u);
-          dst[m].x = fl[m] ? a.x : (T)0;
-          dst[m].y = fl[m] ? a.y : (T)0;
-        }
-      } else {
-        const C<T>* src = in + slot * in_slot + col;
-#pragma unroll
-        for (int m = 0; m < E; ++m) {
-          const C<T> a = src[fl[m] ? (int64_t)(t + TPL * m) * NN : (int64_t)0];
-          dst[m].x = fl[m] ? a.x : (T)0;
-          dst[m].y = fl[m] ? a.y : (T)0;
-        }
-      }
-    }
-  };
-  for (int slot = 0; slot < n_slots; ++slot) {
-    C<T> v[E];
-    load_slot(slot, v);
+  auto body = [&](int slot, C<T>* v) {
     block_sync();
     twa.template fft<-1>(v, t, lines[c]);
     if constexpr (GAL) {
@@ -387,17 +423,31 @@ k_zcross(const C<T>* in, int64_t in_slot, const uint8_t* __restrict__ pflag,
         v[m] = C<T>{v[m].x * v[m].x + v[m].y * v[m].y, (T)0};
       }
     } else {
+      if constexpr (STORE) {
+        // keep the pair-field spectrum (field pair slot_fp[slot], dense N^3)
+        // for the adjoint
+        C<T>* sp = spec + (int64_t)slot_fp[slot] * (NN * N);
+        if constexpr (BUF) {
+          const Buf<T> bs(sp + tile);
+#pragma unroll
+          for (int m = 0; m < E; ++m) bs.store(v[m], vo, (uint32_t)m * ZST);
+        } else {
+#pragma unroll
+          for (int m = 0; m < E; ++m) sp[col + (int64_t)(t + TPL * m) * NN] = v[m];
+        }
+      }
 #pragma unroll
       for (int m = 0; m < E; ++m) v[m] = cmulc(v[m], g[m]);
     }
     block_sync();
     twa.template fft<1>(v, t, lines[c]);
     if constexpr (BUF) {
-      const Buf<T> bo(out + slot * out_slot + tile, 0x7FFFFFF0u);
+      // every lane issues its stores; those outside the window are discarded
+      const Buf<T> bo(out + slot * out_slot + tile);
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const int pz = (t + TPL * m + pw) & (N - 1);
-        if (pz < pw2) bo.store(v[m], (uint32_t)((c + (int64_t)pz * NN) * CB), 0u);
+        bo.store(v[m], pz < pw2 ? (uint32_t)((c + (int64_t)pz * NN) * CB) : kBufOff, 0u);
       }
     } else {
       C<T>* dst = out + slot * out_slot + col;
@@ -406,6 +456,36 @@ k_zcross(const C<T>* in, int64_t in_slot, const uint8_t* __restrict__ pflag,
         const int pz = (t + TPL * m + pw) & (N - 1);
         if (pz < pw2) dst[(int64_t)pz * NN] = v[m];
       }
+    }
+  };
+  if constexpr (PIPE) {
+    // the next slot's columns go into the idle register set at the top of
+    // each trip, before the current ones are waited for: they are in flight
+    // during both transforms (the last trip issues only out-of-range loads)
+    auto trip = [&](int slot, const C<T>* cur, C<T>* nxt) {
+      const bool more = slot + 1 < n_slots;
+      load_cols(more ? slot + 1 : slot, more, nxt);
+      // keep the arithmetic on the current columns (and its wait) after the
+      // loads are issued
+      __builtin_amdgcn_sched_barrier(0);
+      C<T> v[E];
+      take_cols(slot, cur, v);
+      body(slot, v);
+    };
+    // two trips per loop pass, so the register sets keep their roles across
+    // the back edge (no copies); an odd last slot runs after the loop
+    int slot = 0;
+    for (; slot + 1 < n_slots; slot += 2) {
+      trip(slot, ca, cb);
+      trip(slot + 1, cb, ca);
+    }
+    if (slot < n_slots) trip(slot, ca, cb);
+  } else {
+    for (int slot = 0; slot < n_slots; ++slot) {
+      if (slot > 0) load_cols(slot, true, ca);
+      C<T> v[E];
+      take_cols(slot, ca, v);
+      body(slot, v);
     }
   }
 }

@@ -190,3 +190,31 @@ def test_hod_theta_gradient_through_autograd():
     ref = gw_ref @ J
     _say(f"  theta grad gpu {gth} ref {ref}")
     assert np.allclose(gth, ref, rtol=2e-3, atol=1e-3 * np.abs(ref).max())
+
+
+def test_kept_spectra_gradient_matches_recompute():
+    """The adjoint from the spectra kept by the forward equals the adjoint that
+    recomputes them (same kernels, same spectra), and both meet the oracle."""
+    from paper_1705_03464_amd import Plan
+    wl = get_config("cfg4tiny")
+    cat = wl.catalog()
+    w = tiny_weights(cat)
+    g = upstream(wl.n_fields, wl.n_out, 6)
+    from oracle.pipeline import forward as ofw
+    g = mask_ill_conditioned_q(g, wl, ofw(cat, wl, w=w))
+    ref, _ = OG.weight_gradient(cat, wl, w, **g)
+    grads = []
+    for keep in (False, True):
+        plan = Plan.from_workload(wl, precision="fp32", batch=2)
+        plan.keep_spectra(keep)
+        plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
+        plan.forward(dev(w, torch.float32))
+        gw = plan.backward(g_b_pg=dev(g["g_b"]), g_q_eff=dev(g["g_q"]), g_xi_pg=dev(g["g_xipg"]),
+                           g_xi_gg=dev(g["g_xigg"]), g_xi_dp=dev(g["g_xidp"]))
+        torch.cuda.synchronize()
+        grads.append(gw.cpu().numpy().astype(np.float64))
+        plan.close()
+    d = np.linalg.norm(grads[1] - grads[0]) / np.linalg.norm(grads[0])
+    _say(f"  kept vs recomputed rel l2 {d:.2e}")
+    assert d <= 1e-6
+    assert grad_close(grads[1], ref)
