@@ -10,12 +10,20 @@ HOD parameters).
 Default workload: the 512^3 production case (L = 1000 Mpc/h, ~9.2e5 clustered
 galaxies, 200 (s, |mu|) pair fields, 20 log r-bins over 10-80 Mpc/h).
 
+Before the warm-up the plan's autotuner picks the batch schedule (unless
+--no-autotune).  The timed region replays the recorded launch graphs (unless
+--no-graphs); the same steps are then run again eagerly with HIP events
+around every pass kernel for the per-kernel table.
+
 Prints ONE JSON line.  `value` = pair fields per second over the timed steps
 (forward + adjoint by default; `forward_only` gives the forward rate).
-`roofline` is for the kernel with the largest share of the timed region:
-algorithmic bytes per launch / mean launch time, both measured in this run
-with HIP events on the launch stream.  `cpu_baseline` times the FP64 CPU
-oracle on a bounded sample of the same workload on this host.
+`hbm_floor_frac` = required bytes per field of the pruned, fused pass
+structure x fields/s / 8 TB/s.  `roofline` is for the kernel with the largest
+share of the profiled pass: algorithmic bytes per launch / mean launch time,
+both measured in this run with HIP events on the launch stream.
+`fp64_plain` times the one-field-at-a-time FP64 GPU path's forward;
+`cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
+workload on this host.
 """
 from __future__ import annotations
 
@@ -71,6 +79,16 @@ def cpu_baseline(wl, cat, n_fields_sample=2):
     }
 
 
+def floor_bytes_per_field(N, fields_per_batch, mode):
+    """Required HBM bytes per pair field of the pruned, fused pass structure:
+    one sweep S = half spectrum (complex64, N^2 (N/2+1) entries); forward
+    4.37 S + S/B, forward + adjoint 10.8 S + 4 S/B (B fields per batch)."""
+    S = N * N * (N // 2 + 1) * 8.0
+    if mode == "fwd":
+        return (4.37 + 1.0 / fields_per_batch) * S
+    return (10.8 + 4.0 / fields_per_batch) * S
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,7 +97,11 @@ def main(argv=None):
     ap.add_argument("--config", default="cfg1")
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--mode", choices=["fwd", "fwdbwd"], default="fwdbwd")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default batch schedule")
+    ap.add_argument("--no-graphs", action="store_true", help="eager launches in the timed region")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-plain", action="store_true",
+                    help="skip timing the one-field-at-a-time FP64 GPU path")
     ap.add_argument("--kernels", action="store_true", help="print the per-kernel table to stderr")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (torch) three times; used to "
@@ -118,6 +140,7 @@ def main(argv=None):
     if cat.w is not None:
         w = torch.as_tensor(cat.w, dtype=torch.float32, device=dev)
     plan = Plan.from_workload(wl, precision="fp32", batch=a.batch)
+    plan.use_graphs(not a.no_graphs)
     from paper_1705_03464_amd import hod_weights, pair_galaxy_xi
     hod = wl.weighted
     if hod:
@@ -138,7 +161,6 @@ def main(argv=None):
             theta = torch.tensor(th0, dtype=torch.float64, device=dev, requires_grad=True)
             wt = hod_weights(theta, hm, kind)
         else:
-            theta = None
             wt = ones.clone().requires_grad_(True)
         out = pair_galaxy_xi(plan, wt)
         b = out["b_pg"]
@@ -147,40 +169,57 @@ def main(argv=None):
         loss.backward()
         return out
 
-    def timed(fn, steps):
-        plan.profile(True)
+    def timed(fn, steps, profile=False):
+        if profile:
+            plan.profile(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(steps):
             out = fn()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        prof = plan.profile_read()
-        plan.profile(False)
+        prof = None
+        if profile:
+            prof = plan.profile_read()
+            plan.profile(False)
         return out, (t1 - t0) * 1e3 / steps, prof
 
+    schedule = plan.schedule() if a.no_autotune else None
+    if not a.no_autotune:
+        plan.pairs_build(x, y, z)
+        t0 = time.perf_counter()
+        schedule = plan.autotune()
+        _log(f"[bench] autotune {time.perf_counter() - t0:.1f} s: {schedule}")
     step = step_fwdbwd if a.mode == "fwdbwd" else step_fwd
     for i in range(a.warmup):
         step()
         torch.cuda.synchronize()
         _log(f"[bench] warmup {i + 1}/{a.warmup} done")
-    out, ms_step, prof = timed(step, a.steps)
-    _log(f"[bench] timed {a.steps} steps ({a.mode}): {ms_step:.2f} ms/step, n_pairs={plan.n_pairs}")
+    # timed region: the production configuration (launch graphs replayed)
+    out, ms_step, _ = timed(step, a.steps)
+    replays = plan.graph_replays()
+    _log(f"[bench] timed {a.steps} steps ({a.mode}): {ms_step:.2f} ms/step, n_pairs={plan.n_pairs}, "
+         f"graph replays (fwd, bwd) so far {replays}")
     value = wl.n_fields / (ms_step * 1e-3)
+    # the same steps again, eagerly, with HIP events around every pass kernel
+    _, ms_prof, prof = timed(step, a.steps, profile=True)
+    _log(f"[bench] profiled (eager) {a.steps} steps: {ms_prof:.2f} ms/step")
+    fpb = 2 * plan.schedule()["batch"]
     fwd_only = None
     if a.mode == "fwdbwd":
         step_fwd()
+        step_fwd()
         torch.cuda.synchronize()
-        _, ms_f, _ = timed(step_fwd, max(1, a.steps // 2))
-        fwd_only = {"value": round(wl.n_fields / (ms_f * 1e-3), 2), "unit": "pair fields/s",
-                    "ms_per_step": round(ms_f, 3)}
+        _, ms_f, _ = timed(step_fwd, max(2, a.steps))
+        v_f = wl.n_fields / (ms_f * 1e-3)
+        fwd_only = {"value": round(v_f, 2), "unit": "pair fields/s", "ms_per_step": round(ms_f, 3),
+                    "hbm_floor_frac": round(floor_bytes_per_field(wl.N, fpb, "fwd") * v_f / (HBM_PEAK_GBS * 1e9), 4)}
         _log(f"[bench] forward only: {ms_f:.2f} ms/step")
-    total_kernel_ms = sum(p[2] for p in prof)
     if a.kernels:
         for name, n, ms, by in prof:
             _log(f"  {name:16s} launches {n:5d}  {ms / max(n, 1):8.3f} ms/launch  "
                  f"{by / max(n, 1) / 1e9:8.3f} GB/launch  {by / (ms * 1e-3) / 1e9 if ms > 0 else 0:8.1f} GB/s"
-                 f"  share {ms / (ms_step * a.steps):.3f}")
+                 f"  share {ms / (ms_prof * a.steps):.3f}")
     dom = max(prof, key=lambda p: p[2])
     name, n, ms, by = dom
     achieved = (by / n) / (ms / n * 1e-3) / 1e9
@@ -188,9 +227,10 @@ def main(argv=None):
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
         "bytes_per_launch": by / n, "ms_per_launch": ms / n,
-        "kernel_share_of_step": round(ms / (ms_step * a.steps), 3),
+        "kernel_share_of_step": round(ms / (ms_prof * a.steps), 3),
     }
     finite = np.isfinite(out["xi_pg"].detach().cpu().numpy())
+    mode_key = "fwd" if a.mode == "fwd" else "fwdbwd"
     rec = {
         "metric": "pair-field xi_pg cross-correlations/s at 512^3 (fwd, fwd+bwd), % HBM peak",
         "value": round(value, 2),
@@ -211,11 +251,31 @@ def main(argv=None):
             "step": ("pairs_build + forward + adjoint (autograd)" if a.mode == "fwdbwd"
                      else "pairs_build + forward"),
             "hod_weights": bool(hod), "parallelism": "single GPU",
+            "schedule": plan.schedule(), "autotuned": not a.no_autotune,
+            "launch_graphs": not a.no_graphs,
         },
+        "hbm_floor_frac": round(floor_bytes_per_field(wl.N, fpb, mode_key) * value / (HBM_PEAK_GBS * 1e9), 4),
+        "ms_per_step_eager_profiled": round(ms_prof, 3),
         "roofline": roofline,
     }
     if fwd_only is not None:
         rec["forward_only"] = fwd_only
+    if not a.no_fp64_plain:
+        _log("[bench] timing the one-field-at-a-time FP64 GPU path (forward) ...")
+        p64 = Plan.from_workload(wl, precision="fp64")
+        p64.pairs_build(x, y, z)
+        p64.forward(w)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p64.forward(w)
+        torch.cuda.synchronize()
+        ms64 = (time.perf_counter() - t0) * 1e3
+        p64.close()
+        ms_fwd = fwd_only["ms_per_step"] if fwd_only else ms_step
+        rec["fp64_plain"] = {"ms_per_forward": round(ms64, 1),
+                             "value": round(wl.n_fields / (ms64 * 1e-3), 2), "unit": "pair fields/s",
+                             "speedup_fp32_batched_fwd": round(ms64 / ms_fwd, 2)}
+        _log(f"[bench] FP64 plain forward: {ms64:.1f} ms")
     if not a.no_cpu_baseline:
         _log("[bench] timing the CPU oracle on a bounded sample ...")
         rec["cpu_baseline"] = cpu_baseline(wl, cat)

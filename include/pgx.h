@@ -183,6 +183,50 @@ pgx_status pgx_backward(pgx_plan* plan, void* stream, const double* g_b_pg, cons
 pgx_status pgx_keep_spectra(pgx_plan* plan, int32_t enable);
 
 /*
+ * Autotuner for the FP32 batched path.  Times the forward launch sequence on
+ * the current pair catalogue (so call it after pgx_pairs_build) for candidate
+ * batch sizes (half, equal to and twice the default field pairs per launch,
+ * those whose buffers fit in free device memory) and, per pass, two kernel
+ * variants: the y passes in their default or second radix schedule (16
+ * elements per thread, fewer exchange stages), the z pass with its stage
+ * twiddles in registers or in the LDS table.  It keeps the fastest
+ * combination for later calls.  Results differ between schedules only by
+ * floating-point rounding.  It runs the forward eagerly several times
+ * (about ten forward passes' worth of device time), discards the state of
+ * the last pgx_forward (a pgx_backward must follow a new pgx_forward), clears
+ * the kernel-timing counters and invalidates the launch graphs.
+ *   schedule: host int32[4] out (nullable): field pairs per batch, forward
+ *   y-pass variant, inverse y-pass variant, z-pass variant (0 = default).
+ * Errors: ESTATE before pgx_pairs_build; ENOTSUP on FP64 plans.
+ */
+pgx_status pgx_autotune(pgx_plan* plan, void* stream, int32_t* schedule);
+/* The schedule in use: host int32[4] as filled by pgx_autotune.  Creates the
+ * device state of the plan if it does not exist yet. */
+pgx_status pgx_schedule(pgx_plan* plan, int32_t* schedule);
+/* Apply a schedule (host int32[4] as above, e.g. one found by an earlier
+ * pgx_autotune): batch size in [1, 32] (clamped to the number of field
+ * pairs), variants 0 or 1.  Same side effects as pgx_autotune apart from the
+ * timing runs.  Errors: EINVAL for values out of range, ESTATE before
+ * pgx_pairs_build, ENOTSUP on FP64 plans. */
+pgx_status pgx_set_schedule(pgx_plan* plan, void* stream, const int32_t* schedule);
+
+/*
+ * Launch graphs.  With enable = 1 (the default) the device work of
+ * pgx_forward (weights, galaxy side, every batch of pair fields) and of
+ * pgx_backward is recorded into a HIP graph the second time it runs with the
+ * same catalogue, batch schedule and optional-input pattern, and replayed on
+ * the caller's stream from then on (the caller's weights and upstream
+ * gradients are first copied into plan buffers; results are copied out).
+ * Validation and the finalisation run outside the graph.  A new
+ * pgx_pairs_build or pgx_autotune invalidates the graphs.  While kernel timing
+ * (pgx_profile) is on, the work runs eagerly.  No device work.
+ */
+pgx_status pgx_use_graphs(pgx_plan* plan, int32_t enable);
+/* Number of graph replays of the forward and adjoint bodies since the plan
+ * was created (host counters; either pointer may be NULL). */
+pgx_status pgx_graph_replays(pgx_plan* plan, int64_t* forward, int64_t* backward);
+
+/*
  * Kernel timing.  pgx_profile(plan, 1) clears the counters and starts
  * recording a pair of HIP events on the launch stream around every launch of
  * the transform-pass kernels (the events bracket exactly one kernel each);

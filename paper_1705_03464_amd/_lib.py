@@ -60,6 +60,11 @@ _SIGS = {
     "pgx_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_void_p, C.c_void_p]),
     "pgx_keep_spectra": (C.c_int, [C.c_void_p, C.c_int32]),
+    "pgx_use_graphs": (C.c_int, [C.c_void_p, C.c_int32]),
+    "pgx_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
+    "pgx_schedule": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "pgx_set_schedule": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
+    "pgx_graph_replays": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "pgx_profile": (C.c_int, [C.c_void_p, C.c_int32]),
     "pgx_profile_read": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_char_p),
                                    C.POINTER(C.c_int64), C.POINTER(C.c_double),
@@ -235,6 +240,41 @@ class Plan:
         """Keep the pair-field spectra of each forward for the adjoint (memory
         permitting); see pgx_keep_spectra."""
         _check(load_library().pgx_keep_spectra(self._h, 1 if enable else 0))
+
+    def autotune(self, stream=None) -> dict:
+        """Time candidate batch sizes and kernel variants on the current pair
+        catalogue and keep the fastest; returns the schedule (pgx_autotune)."""
+        out = (C.c_int32 * 4)()
+        _check(load_library().pgx_autotune(self._h, _stream(stream), out))
+        return self._sched(out)
+
+    def schedule(self) -> dict:
+        """The batch size and kernel variants in use."""
+        out = (C.c_int32 * 4)()
+        _check(load_library().pgx_schedule(self._h, out))
+        return self._sched(out)
+
+    def set_schedule(self, batch: int, ypass_variant: int = 0, yinv_variant: int = 0,
+                     zpass_variant: int = 0, stream=None):
+        """Apply a schedule (pgx_set_schedule)."""
+        arr = (C.c_int32 * 4)(batch, ypass_variant, yinv_variant, zpass_variant)
+        _check(load_library().pgx_set_schedule(self._h, _stream(stream), arr))
+
+    @staticmethod
+    def _sched(out) -> dict:
+        return dict(batch=int(out[0]), ypass_variant=int(out[1]), yinv_variant=int(out[2]),
+                    zpass_variant=int(out[3]))
+
+    def use_graphs(self, enable: bool = True):
+        """Record the forward / adjoint launch sequences into HIP graphs and
+        replay them (default on); see pgx_use_graphs."""
+        _check(load_library().pgx_use_graphs(self._h, 1 if enable else 0))
+
+    def graph_replays(self) -> tuple:
+        """(forward, backward) graph replay counts."""
+        f, b = C.c_int64(0), C.c_int64(0)
+        _check(load_library().pgx_graph_replays(self._h, C.byref(f), C.byref(b)))
+        return f.value, b.value
 
     def profile(self, enable: bool = True):
         """Start (clearing counters) or stop per-kernel event timing."""

@@ -13,6 +13,7 @@ EngineBase* make_engine_f64(const PlanCfg& c);
 struct pgx_plan {
   pgx::PlanCfg cfg;
   bool keep_spectra = false;
+  bool use_graphs = true;
   std::unique_ptr<pgx::EngineBase> eng;  // created on first device use
   pgx::EngineBase& engine() {
     if (!eng) {
@@ -207,6 +208,7 @@ pgx_status pgx_forward(pgx_plan* plan, const float* w, void* stream, double* wsu
   return guarded([&] {
     auto& e = plan->engine();
     e.keep_spectra = plan->keep_spectra;
+    e.use_graphs = plan->use_graphs;
     e.forward(w, (hipStream_t)stream, wsum, xi_gg, xi_pg, xi_dp, b_pg, q_eff);
   });
 }
@@ -216,13 +218,47 @@ pgx_status pgx_backward(pgx_plan* plan, void* stream, const double* g_b_pg, cons
                         float* grad_w) {
   if (!plan) return fail(PGX_EINVAL, "plan is NULL");
   return guarded([&] {
-    plan->engine().backward((hipStream_t)stream, g_b_pg, g_q_eff, g_xi_pg, g_xi_gg, g_xi_dp, grad_w);
+    auto& e = plan->engine();
+    e.use_graphs = plan->use_graphs;
+    e.backward((hipStream_t)stream, g_b_pg, g_q_eff, g_xi_pg, g_xi_gg, g_xi_dp, grad_w);
   });
 }
 
 pgx_status pgx_keep_spectra(pgx_plan* plan, int32_t enable) {
   if (!plan) return fail(PGX_EINVAL, "plan is NULL");
   return guarded([&] { plan->keep_spectra = enable != 0; });
+}
+
+pgx_status pgx_autotune(pgx_plan* plan, void* stream, int32_t* schedule) {
+  if (!plan) return fail(PGX_EINVAL, "plan is NULL");
+  return guarded([&] { plan->engine().autotune((hipStream_t)stream, schedule); });
+}
+
+pgx_status pgx_schedule(pgx_plan* plan, int32_t* schedule) {
+  if (!plan) return fail(PGX_EINVAL, "plan is NULL");
+  if (!schedule) return fail(PGX_EINVAL, "schedule is NULL");
+  return guarded([&] { plan->engine().schedule_info(schedule); });
+}
+
+pgx_status pgx_set_schedule(pgx_plan* plan, void* stream, const int32_t* schedule) {
+  if (!plan) return fail(PGX_EINVAL, "plan is NULL");
+  if (!schedule) return fail(PGX_EINVAL, "schedule is NULL");
+  return guarded([&] { plan->engine().set_schedule(schedule, (hipStream_t)stream); });
+}
+
+pgx_status pgx_use_graphs(pgx_plan* plan, int32_t enable) {
+  if (!plan) return fail(PGX_EINVAL, "plan is NULL");
+  return guarded([&] { plan->use_graphs = enable != 0; });
+}
+
+pgx_status pgx_graph_replays(pgx_plan* plan, int64_t* forward, int64_t* backward) {
+  if (!plan) return fail(PGX_EINVAL, "plan is NULL");
+  return guarded([&] {
+    const int64_t f = plan->eng ? plan->eng->gf.replays : 0;
+    const int64_t b = plan->eng ? plan->eng->gb.replays : 0;
+    if (forward) *forward = f;
+    if (backward) *backward = b;
+  });
 }
 
 pgx_status pgx_profile(pgx_plan* plan, int32_t enable) {

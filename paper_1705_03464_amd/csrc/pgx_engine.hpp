@@ -89,9 +89,86 @@ struct Profiler {
   }
 };
 
+// Captured launch sequences.  The forward and adjoint bodies are recorded
+// once into a HIP graph on a private stream and replayed on the caller's
+// stream; a body is captured on its second call with the same key (the first
+// runs eagerly and makes every allocation), and the key changes whenever
+// anything the recorded launches depend on may have changed (a new pair
+// catalogue, a different batch schedule, null-ness of optional inputs).
+struct GraphKey {
+  uint64_t gen = 0;
+  const void* p = nullptr;
+  int flags = 0;
+  bool operator==(const GraphKey& o) const { return gen == o.gen && p == o.p && flags == o.flags; }
+};
+struct Graphed {
+  hipGraphExec_t exec = nullptr;
+  GraphKey key, seen;
+  bool has_seen = false;
+  int64_t replays = 0;
+  Graphed() = default;
+  Graphed(const Graphed&) = delete;
+  Graphed& operator=(const Graphed&) = delete;
+  ~Graphed() { reset(); }
+  void reset() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    exec = nullptr;
+    has_seen = false;
+  }
+};
+
 struct EngineBase {
-  virtual ~EngineBase() = default;
+  virtual ~EngineBase() {
+    gf.reset();
+    gb.reset();
+    if (cap) (void)hipStreamDestroy(cap);
+  }
   Profiler prof;
+  bool use_graphs = true;
+  uint64_t gen = 0;  // bumped by every pair build
+  hipStream_t cap = nullptr;
+  Graphed gf, gb;
+
+  // run body(stream) eagerly, or capture it once and replay it (see Graphed)
+  template <typename Body> void graphed(Graphed& g, const GraphKey& key, hipStream_t s, Body&& body) {
+    if (!use_graphs || prof.on) {
+      body(s);
+      return;
+    }
+    if (g.exec && g.key == key) {
+      PGX_HIP(hipGraphLaunch(g.exec, s));
+      ++g.replays;
+      return;
+    }
+    if (!g.has_seen || !(g.seen == key)) {
+      g.reset();
+      body(s);
+      g.seen = key;
+      g.has_seen = true;
+      return;
+    }
+    if (!cap) PGX_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    PGX_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
+    try {
+      body(cap);
+    } catch (...) {
+      (void)hipStreamEndCapture(cap, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      throw;
+    }
+    PGX_HIP(hipStreamEndCapture(cap, &graph));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    PGX_HIP(e);
+    g.reset();
+    g.exec = exec;
+    g.key = key;
+    PGX_HIP(hipGraphLaunch(exec, s));
+    ++g.replays;
+  }
+
   virtual void pairs_build(const double* x, const double* y, const double* z, int64_t n,
                            hipStream_t s, int64_t* n_pairs, int64_t* counts) = 0;
   virtual void pairs_export(int32_t* f, int32_t* i, int32_t* j, hipStream_t s) = 0;
@@ -99,6 +176,9 @@ struct EngineBase {
                        double* xi_dp, double* b_pg, double* q_eff) = 0;
   virtual void backward(hipStream_t s, const double* g_b, const double* g_q, const double* g_xipg,
                         const double* g_xigg, const double* g_xidp, float* grad_w) = 0;
+  virtual void autotune(hipStream_t s, int32_t* out) = 0;
+  virtual void schedule_info(int32_t* out) const = 0;
+  virtual void set_schedule(const int32_t* in, hipStream_t s) = 0;
   bool built = false;
   bool forward_done = false;
   // keep each pair-field spectrum from the forward for the adjoint (when the
@@ -121,6 +201,11 @@ template <typename T, int N> struct Engine : EngineBase {
   static constexpr int NTX = WX * TPL;
   static constexpr int64_t NN = (int64_t)N * N;
   static constexpr int64_t NC = NN * N;
+  // second radix schedule of the y passes (autotuner candidate)
+  using ShA = typename AltShape<T, N>::type;
+  static constexpr int WA =
+      (int)(128 / sizeof(C<T>)) * ShA::TPL <= 1024 ? (int)(128 / sizeof(C<T>)) : 1024 / ShA::TPL;
+  static constexpr int NTA = WA * ShA::TPL;
 
   const PlanCfg& cfg;
   int B = 1;          // field pairs per batch
@@ -128,8 +213,13 @@ template <typename T, int N> struct Engine : EngineBase {
   int64_t n_gal = 0, n_pairs = 0;
   std::vector<int64_t> batch_task_off;  // host, n_batches + 1
   std::vector<int64_t> field_counts_h;  // host, pairs per field
+  std::vector<int64_t> build_print;     // schedule and buffers of the last pair build
 
+  // kernel variants picked by the autotuner (0 = default): forward y pass,
+  // inverse y pass (radix schedule), z pass (twiddle source)
+  int v_ypass = 0, v_yinv = 0, v_zpass = 0;
   // constant tables
+  DBuf tw_alt;
   DBuf tw, lut1, lut2, mu2, nbd, vold, t1, t2, slot_fa, slot_fb, slot_fp, gslot_fa, gslot_fb,
       fidx, neg1;
   // catalogue
@@ -144,6 +234,7 @@ template <typename T, int N> struct Engine : EngineBase {
   // backward work
   DBuf KX, KY, Aacc, gbuf, gbuf_g, grad_d, apg, agg, gws, gwg, w_last;
   DBuf SPEC;  // kept pair-field spectra, one N^3 grid per field pair
+  DBuf gup, gw_out;  // adjoint: copies of the upstream gradients, weight gradient
   bool w_given = false;
 
   // room for the kept spectra: already allocated, or fits in free device
@@ -167,18 +258,9 @@ template <typename T, int N> struct Engine : EngineBase {
   }
 
   explicit Engine(const PlanCfg& c) : cfg(c) {
-    static_assert(N % W == 0, "tile width must divide N");
-    // per-stage twiddles exp(-2 pi i r k / (Ns R)) at [twoff(s) + r Ns + k], FP64 rounded to T
-    std::vector<C<T>> h(Sh::tw_entries());
-    for (int st = 1; st < Sh::stages; ++st) {
-      const int R = Sh::radix(st), Ns = Sh::ns(st);
-      for (int r = 0; r < R; ++r)
-        for (int k = 0; k < Ns; ++k) {
-          const double a = -2.0 * kPi * (double)(r * k) / (double)(Ns * R);
-          h[Sh::twoff(st) + r * Ns + k] = C<T>{(T)std::cos(a), (T)std::sin(a)};
-        }
-    }
-    upload(tw, h);
+    static_assert(N % W == 0 && N % WA == 0, "tile width must divide N");
+    upload(tw, twiddles<Sh>());
+    upload(tw_alt, twiddles<ShA>());
     upload(lut1, cfg.bins.lut1);
     upload(lut2, cfg.bins.lut2.empty() ? std::vector<int16_t>{-1} : cfg.bins.lut2);
     upload(mu2, cfg.bins.mu2.empty() ? std::vector<double>{0.0} : cfg.bins.mu2);
@@ -191,12 +273,11 @@ template <typename T, int N> struct Engine : EngineBase {
     upload(t1, a1);
     upload(t2, a2);
     const int nfp = cfg.n_fp;
-    int b = cfg.batch;
-    if (b <= 0) b = N >= 512 ? 8 : (N >= 256 ? 16 : 32);
-    B = std::max(1, std::min({b, nfp, kMaxSlots}));
+    B = std::max(1, std::min({default_batch(), nfp, kMaxSlots}));
     n_batches = (nfp + B - 1) / B;
-    std::vector<int32_t> fa((size_t)n_batches * B, -1), fb((size_t)n_batches * B, -1),
-        fp((size_t)n_batches * B, 0);
+    // slot j of the launch sequence holds field pair j, whatever the batch size
+    std::vector<int32_t> fa((size_t)nfp + kMaxSlots, -1), fb((size_t)nfp + kMaxSlots, -1),
+        fp((size_t)nfp + kMaxSlots, 0);
     for (int k = 0; k < nfp; ++k) {
       fa[k] = 2 * k;
       fb[k] = 2 * k + 1 < cfg.F ? 2 * k + 1 : -1;
@@ -215,6 +296,20 @@ template <typename T, int N> struct Engine : EngineBase {
     for (int64_t l = 0; l < NN; ++l) gt[l] = (int32_t)l;
     upload(g_tasks, gt);
     PGX_HIP(hipDeviceSynchronize());
+  }
+
+  // per-stage twiddles exp(-2 pi i r k / (Ns R)) at [twoff(s) + r Ns + k], FP64 rounded to T
+  template <typename Shp> static std::vector<C<T>> twiddles() {
+    std::vector<C<T>> h(Shp::tw_entries());
+    for (int st = 1; st < Shp::stages; ++st) {
+      const int R = Shp::radix(st), Ns = Shp::ns(st);
+      for (int r = 0; r < R; ++r)
+        for (int k = 0; k < Ns; ++k) {
+          const double a = -2.0 * kPi * (double)(r * k) / (double)(Ns * R);
+          h[Shp::twoff(st) + r * Ns + k] = C<T>{(T)std::cos(a), (T)std::sin(a)};
+        }
+    }
+    return h;
   }
 
   template <typename V> static void upload(DBuf& d, const std::vector<V>& h) {
@@ -391,20 +486,152 @@ template <typename T, int N> struct Engine : EngineBase {
       launch_check("plane_flags");
       int32_t* pos = s_pos.get<int32_t>(nfl + 1);
       exscan_u8_i32(lf, pos, nfl + 1, s, s_tmp);  // entry nfl is the total
-      std::vector<int32_t> hpos(n_batches + 1);
-      for (int k = 0; k <= n_batches; ++k) {
-        const int64_t e = std::min<int64_t>((int64_t)k * B, cfg.n_fp) * NN;
-        PGX_HIP(hipMemcpyAsync(&hpos[k], pos + e, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-      }
-      PGX_HIP(hipStreamSynchronize(s));
-      batch_task_off.assign(hpos.begin(), hpos.end());
-      int32_t* tk = tasks.get<int32_t>(std::max<int64_t>(hpos[n_batches], 1));
-      k_emit_tasks<<<grid_for(nfl), 256, 0, s>>>(lf, pos, nfl, N, B, tk);
-      launch_check("emit_tasks");
+      schedule(B, s);
     }
     PGX_HIP(hipStreamSynchronize(s));
     if (n_pairs_out) *n_pairs_out = P;
+    // recorded launch sequences stay valid when the new catalogue has the
+    // same schedule (sizes, per-batch task counts, per-field counts) in the
+    // same buffers, as when the same catalogue is rebuilt
+    std::vector<int64_t> fpr = {n_gal, n_pairs, (int64_t)B};
+    fpr.insert(fpr.end(), batch_task_off.begin(), batch_task_off.end());
+    fpr.insert(fpr.end(), field_counts_h.begin(), field_counts_h.end());
+    for (const DBuf* d : {&g_key, &g_ls, &g_x0, &g_fx, &g_fy, &g_fz, &g_idx, &g_wt, &g_tasks, &p_key,
+                          &p_ls, &p_i, &p_j, &p_x0, &p_fx, &p_fy, &p_fz, &p_wt, &lflag, &pflag, &tasks})
+      fpr.push_back((int64_t)(intptr_t)d->p);
+    if (fpr != build_print) {
+      build_print = fpr;
+      ++gen;
+    }
     built = true;
+  }
+
+  int default_batch() const {
+    if (cfg.batch > 0) return cfg.batch;
+    return N >= 512 ? 8 : (N >= 256 ? 16 : 32);
+  }
+
+  // Autotuner.  For each candidate batch size (half, equal to and twice the
+  // default) it runs the forward launch sequence twice per variant set (once
+  // to settle allocations, once timed with events per kernel): all passes in
+  // their default variant, then all in the alternative one (y passes: second
+  // radix schedule; z pass: twiddles from the LDS table instead of
+  // registers).  Per pass it keeps the faster variant; the batch size with
+  // the smallest modelled total wins.  Candidates whose batch buffers do not
+  // fit in free device memory (with 4 GiB to spare) are skipped.
+  void autotune(hipStream_t s, int32_t* out) override {
+    PGX_REQUIRE(built, PGX_ESTATE, "pgx_pairs_build has not been called");
+    if constexpr (!std::is_same<T, float>::value) {
+      throw Error(PGX_ENOTSUP, "the autotuner tunes the FP32 batched path");
+    } else {
+      const int nfp = cfg.n_fp;
+      const int b0 = std::max(1, std::min({default_batch(), nfp, kMaxSlots}));
+      const int64_t slot_bytes =
+          (NC + (int64_t)win_len(pwz()) * NN + (int64_t)win_len(pwz()) * win_len(pwy()) * N) *
+          (int64_t)sizeof(C<T>);
+      size_t fr = 0, tot = 0;
+      PGX_HIP(hipMemGetInfo(&fr, &tot));
+      const double room = (double)fr + (double)(X.bytes + P1.bytes + P2.bytes) - (double)((size_t)4 << 30);
+      std::vector<int> cands;
+      for (int b : {b0 / 2, b0, 2 * b0}) {
+        const int bb = std::max(1, std::min({b, nfp, kMaxSlots}));
+        if (std::find(cands.begin(), cands.end(), bb) != cands.end()) continue;
+        if (bb != b0 && (double)bb * slot_bytes > room) continue;
+        cands.push_back(bb);
+      }
+      const bool prof_on = prof.on;
+      float* wl = w_given && n_gal > 0 ? w_last.as<float>() : nullptr;
+      double best_ms = 1e300;
+      int best[4] = {b0, 0, 0, 0};
+      for (int b : cands) {
+        schedule(b, s);
+        double t[2][3] = {{0, 0, 0}, {0, 0, 0}}, other = 0;
+        for (int v = 0; v < 2; ++v) {
+          v_ypass = v_yinv = v_zpass = v;
+          prof.reset();
+          prof.on = false;
+          weights(wl, s);
+          forward_batched(s, nullptr);
+          prof.on = true;
+          weights(wl, s);
+          forward_batched(s, nullptr);
+          prof.collect();
+          prof.on = false;
+          for (const auto& c : prof.cats) {
+            if (c.name == "ypass") t[v][0] = c.ms;
+            else if (c.name == "yinv") t[v][1] = c.ms;
+            else if (c.name == "zpass_cross") t[v][2] = c.ms;
+            else if (v == 0) other += c.ms;
+          }
+        }
+        const int vy = t[1][0] < t[0][0], vi = t[1][1] < t[0][1], vz = t[1][2] < t[0][2];
+        const double ms = other + t[vy][0] + t[vi][1] + t[vz][2];
+        if (ms < best_ms) {
+          best_ms = ms;
+          best[0] = b;
+          best[1] = vy;
+          best[2] = vi;
+          best[3] = vz;
+        }
+      }
+      prof.reset();
+      prof.on = prof_on;
+      schedule(best[0], s);
+      v_ypass = best[1];
+      v_yinv = best[2];
+      v_zpass = best[3];
+      ++gen;  // recorded launch sequences used the old schedule
+      forward_done = false;
+      spectra_valid = false;
+      schedule_info(out);
+    }
+  }
+
+  void set_schedule(const int32_t* in, hipStream_t s) override {
+    PGX_REQUIRE(built, PGX_ESTATE, "pgx_pairs_build has not been called");
+    PGX_REQUIRE(in[0] >= 1 && in[0] <= kMaxSlots, PGX_EINVAL, "batch size must be in [1, 32]");
+    for (int i = 1; i < 4; ++i) PGX_REQUIRE(in[i] == 0 || in[i] == 1, PGX_EINVAL, "variants are 0 or 1");
+    if constexpr (!std::is_same<T, float>::value) {
+      throw Error(PGX_ENOTSUP, "schedules apply to the FP32 batched path");
+    } else {
+      schedule(in[0], s);
+      v_ypass = in[1];
+      v_yinv = in[2];
+      v_zpass = in[3];
+      ++gen;
+      forward_done = false;
+      spectra_valid = false;
+    }
+  }
+
+  void schedule_info(int32_t* out) const override {
+    if (!out) return;
+    out[0] = B;
+    out[1] = v_ypass;
+    out[2] = v_yinv;
+    out[3] = v_zpass;
+  }
+
+  // Batch schedule for b field pairs per launch: per-batch task ranges and
+  // the x-pass task words (slot within the batch, line) of every non-empty
+  // line, from the line flags and their exclusive scan of the pair build.
+  void schedule(int b, hipStream_t s) {
+    const int nfp = cfg.n_fp;
+    B = std::max(1, std::min({b, nfp, kMaxSlots}));
+    n_batches = (nfp + B - 1) / B;
+    const int64_t nfl = (int64_t)nfp * NN;
+    const uint8_t* lf = lflag.as<uint8_t>();
+    const int32_t* pos = s_pos.as<int32_t>();
+    std::vector<int32_t> hpos(n_batches + 1);
+    for (int k = 0; k <= n_batches; ++k) {
+      const int64_t e = std::min<int64_t>((int64_t)k * B, nfp) * NN;
+      PGX_HIP(hipMemcpyAsync(&hpos[k], pos + e, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    }
+    PGX_HIP(hipStreamSynchronize(s));
+    batch_task_off.assign(hpos.begin(), hpos.end());
+    int32_t* tk = tasks.get<int32_t>(std::max<int64_t>(hpos[n_batches], 1));
+    k_emit_tasks<<<grid_for(nfl), 256, 0, s>>>(lf, pos, nfl, N, B, tk);
+    launch_check("emit_tasks");
   }
 
   // pairs in the fields of batch k (host copy taken at build time)
@@ -532,14 +759,23 @@ template <typename T, int N> struct Engine : EngineBase {
     forward_done = false;
     spectra_valid = false;
     w_given = w != nullptr;
-    if (w && n_gal > 0)
-      PGX_HIP(hipMemcpyAsync(w_last.get<float>(n_gal), w, n_gal * sizeof(float),
-                             hipMemcpyDeviceToDevice, s));
-    weights(w, s);
-    if constexpr (std::is_same<T, float>::value)
-      forward_batched(s);
-    else
-      forward_plain(s);
+    float* wl = w_given && n_gal > 0 ? w_last.get<float>(n_gal) : nullptr;
+    if (wl) PGX_HIP(hipMemcpyAsync(wl, w, n_gal * sizeof(float), hipMemcpyDeviceToDevice, s));
+    C<T>* spec = nullptr;
+    if constexpr (std::is_same<T, float>::value) spec = keep_spectra ? spectra_store() : nullptr;
+    // the recorded body reads the weights from the plan's copy
+    GraphKey key;
+    key.gen = gen;
+    key.p = spec;
+    key.flags = (w_given ? 1 : 0) | (n_gal > 0 ? 2 : 0);
+    graphed(gf, key, s, [&](hipStream_t st) {
+      weights(wl, st);
+      if constexpr (std::is_same<T, float>::value)
+        forward_batched(st, spec);
+      else
+        forward_plain(st);
+    });
+    spectra_valid = spec != nullptr;
     finalize(s, xi_gg, xi_pg, xi_dp, b_pg, q_eff, wsum);
     forward_done = true;
   }
@@ -552,7 +788,33 @@ template <typename T, int N> struct Engine : EngineBase {
     PGX_REQUIRE(built && forward_done, PGX_ESTATE, "pgx_backward needs a preceding pgx_forward");
     PGX_REQUIRE(grad_w != nullptr || n_gal == 0, PGX_EINVAL, "grad_w must not be NULL");
     if constexpr (std::is_same<T, float>::value) {
-      backward_batched(s, g_b, g_q, g_xipg, g_xigg, g_xidp, grad_w);
+      // the recorded body reads the upstream gradients from plan copies and
+      // writes the weight gradient to a plan buffer
+      const int F = cfg.F, R = cfg.R;
+      const double* src[5] = {g_b, g_q, g_xipg, g_xigg, g_xidp};
+      const int64_t len[5] = {(int64_t)F * R, (int64_t)F * R, (int64_t)F * R, R, F};
+      double* up = gup.get<double>(3 * (int64_t)F * R + R + F);
+      const double* cp[5];
+      int flags = (spectra_valid ? 1 : 0) | (w_given ? 2 : 0);
+      double* dst = up;
+      for (int i = 0; i < 5; ++i) {
+        cp[i] = src[i] ? dst : nullptr;
+        if (src[i]) {
+          PGX_HIP(hipMemcpyAsync(dst, src[i], len[i] * sizeof(double), hipMemcpyDeviceToDevice, s));
+          flags |= 4 << i;
+        }
+        dst += len[i];
+      }
+      float* gw = gw_out.get<float>(std::max<int64_t>(n_gal, 1));
+      GraphKey key;
+      key.gen = gen;
+      key.p = spectra_valid ? SPEC.p : nullptr;
+      key.flags = flags;
+      graphed(gb, key, s, [&](hipStream_t st) {
+        backward_batched(st, cp[0], cp[1], cp[2], cp[3], cp[4], gw);
+      });
+      if (n_gal > 0)
+        PGX_HIP(hipMemcpyAsync(grad_w, gw, n_gal * sizeof(float), hipMemcpyDeviceToDevice, s));
     } else {
       throw Error(PGX_ENOTSUP, "the adjoint is implemented on the FP32 batched path");
     }
@@ -654,8 +916,7 @@ template <typename T, int N> struct Engine : EngineBase {
           });
         }
         prof.run("bwd_ypass", s, (double)nt * N * cb + (double)nb * NC * cb, [&] {
-          k_strided<T, Sh, W, -1, IN_FLAGS, OUT_DENSE><<<dim3(N / W, N, nb), NT, 0, s>>>(
-              x, x, NC, NC, NN, NN, N, N, 0, lflag.as<uint8_t>(), pflag.as<uint8_t>(), NN, fp, twp);
+          ypass_launch(v_ypass, x, nb, fp, s);
           launch_check("ypass(bwd)");
         });
         prof.run("bwd_zpass", s,
@@ -709,12 +970,28 @@ template <typename T, int N> struct Engine : EngineBase {
     }
   }
 
+  // forward y pass over the flagged lines of a batch, in radix schedule v
+  void ypass_launch(int v, C<T>* x, int nb, const int32_t* fp, hipStream_t s) {
+    const uint8_t* lf = lflag.as<uint8_t>();
+    const uint8_t* pf = pflag.as<uint8_t>();
+    if (v == 0)
+      k_strided<T, Sh, W, -1, IN_FLAGS, OUT_DENSE><<<dim3(N / W, N, nb), NT, 0, s>>>(
+          x, x, NC, NC, NN, NN, N, N, 0, lf, pf, NN, fp, tw.as<C<T>>());
+    else
+      k_strided<T, ShA, WA, -1, IN_FLAGS, OUT_DENSE><<<dim3(N / WA, N, nb), NTA, 0, s>>>(
+          x, x, NC, NC, NN, NN, N, N, 0, lf, pf, NN, fp, tw_alt.as<C<T>>());
+  }
+
   int pwx() const { return cfg.pw[0]; }
   int pwy() const { return cfg.pw[1]; }
   int pwz() const { return cfg.pw[2]; }
 
-  void forward_batched(hipStream_t s) {
+  void forward_batched(hipStream_t s, C<T>* spec) {
     const int R = cfg.R;
+    // bin sums: allocated here too, since the autotuner runs this body
+    // without a preceding pgx_forward
+    double* Sd = S.get<double>((int64_t)cfg.F * R);
+    double* Sggd = Sgg.get<double>(R);
     const int ny = win_len(pwy()), nz = win_len(pwz());
     const int nblkE = (ny * nz + WX - 1) / WX;
     const int64_t p1_slot = (int64_t)nz * NN;
@@ -756,10 +1033,9 @@ template <typename T, int N> struct Engine : EngineBase {
       launch_check("xinv_bins(gal)");
     });
     k_reduce_bins<<<dim3(2 * R, 1), 256, 0, s>>>(pt, nblkE, R, gslot_fa.as<int32_t>(),
-                                                           gslot_fb.as<int32_t>(), Sgg.as<double>());
+                                                           gslot_fb.as<int32_t>(), Sggd);
     launch_check("reduce(gal)");
     // ---- pair fields, B field pairs per batch
-    C<T>* spec = keep_spectra ? spectra_store() : nullptr;
     for (int k = 0; k < n_batches; ++k) {
       const int nb = std::min(B, cfg.n_fp - k * B);
       const int64_t t0 = batch_task_off[k], nt = batch_task_off[k + 1] - t0;
@@ -775,25 +1051,37 @@ template <typename T, int N> struct Engine : EngineBase {
         });
       }
       prof.run("ypass", s, (double)nt * N * cb + (double)nb * NC * cb, [&] {
-        k_strided<T, Sh, W, -1, IN_FLAGS, OUT_DENSE><<<dim3(N / W, N, nb), NT, 0, s>>>(
-            x, x, NC, NC, NN, NN, N, N, 0, lflag.as<uint8_t>(), pflag.as<uint8_t>(), NN, fp, twp);
+        ypass_launch(v_ypass, x, nb, fp, s);
         launch_check("ypass");
       });
       prof.run("zpass_cross", s,
                (double)(nb + 1) * NC * cb + (double)nb * p1_slot * cb + (spec ? (double)nb * NC * cb : 0.0),
                [&] {
-        if (spec)
-          k_zcross<T, Sh, W, false, true><<<dim3(N / W, N, 1), NT, 0, s>>>(
-              x, NC, pflag.as<uint8_t>(), fp, nb, fg, nullptr, p1, p1_slot, pwz(), twp, spec);
+        const dim3 gz(N / W, N, 1);
+        const uint8_t* pf = pflag.as<uint8_t>();
+        if (spec && v_zpass == 0)
+          k_zcross<T, Sh, W, false, true, true><<<gz, NT, 0, s>>>(x, NC, pf, fp, nb, fg, nullptr, p1,
+                                                                  p1_slot, pwz(), twp, spec);
+        else if (spec)
+          k_zcross<T, Sh, W, false, true, false><<<gz, NT, 0, s>>>(x, NC, pf, fp, nb, fg, nullptr, p1,
+                                                                   p1_slot, pwz(), twp, spec);
+        else if (v_zpass == 0)
+          k_zcross<T, Sh, W, false, false, true><<<gz, NT, 0, s>>>(x, NC, pf, fp, nb, fg, nullptr, p1,
+                                                                   p1_slot, pwz(), twp);
         else
-          k_zcross<T, Sh, W, false><<<dim3(N / W, N, 1), NT, 0, s>>>(
-              x, NC, pflag.as<uint8_t>(), fp, nb, fg, nullptr, p1, p1_slot, pwz(), twp);
+          k_zcross<T, Sh, W, false, false, false><<<gz, NT, 0, s>>>(x, NC, pf, fp, nb, fg, nullptr,
+                                                                    p1, p1_slot, pwz(), twp);
         launch_check("zcross");
       });
       prof.run("yinv", s, (double)nb * (p1_slot + p2_slot) * cb, [&] {
-        k_strided<T, Sh, W, 1, IN_DENSE, OUT_WINDOW><<<dim3(N / W, nz, nb), NT, 0, s>>>(
-            p1, p2, p1_slot, p2_slot, NN, (int64_t)ny * N, N, N, pwy(), nullptr, nullptr, 0,
-            nullptr, twp);
+        if (v_yinv == 0)
+          k_strided<T, Sh, W, 1, IN_DENSE, OUT_WINDOW><<<dim3(N / W, nz, nb), NT, 0, s>>>(
+              p1, p2, p1_slot, p2_slot, NN, (int64_t)ny * N, N, N, pwy(), nullptr, nullptr, 0,
+              nullptr, twp);
+        else
+          k_strided<T, ShA, WA, 1, IN_DENSE, OUT_WINDOW><<<dim3(N / WA, nz, nb), NTA, 0, s>>>(
+              p1, p2, p1_slot, p2_slot, NN, (int64_t)ny * N, N, N, pwy(), nullptr, nullptr, 0,
+              nullptr, tw_alt.as<C<T>>());
         launch_check("yinv");
       });
       prof.run("xinv_bins", s, (double)nb * p2_slot * cb, [&] {
@@ -801,10 +1089,9 @@ template <typename T, int N> struct Engine : EngineBase {
                                                                         pwz(), bm, R, pt, twp);
         launch_check("xinv_bins");
       });
-      k_reduce_bins<<<dim3(2 * R, nb), 256, 0, s>>>(pt, nblkE, R, fa, fb, S.as<double>());
+      k_reduce_bins<<<dim3(2 * R, nb), 256, 0, s>>>(pt, nblkE, R, fa, fb, Sd);
       launch_check("reduce");
     }
-    spectra_valid = spec != nullptr;
   }
 
   // one field at a time, full transforms, global-atomic scatter, FP64 or FP32
@@ -846,6 +1133,8 @@ template <typename T, int N> struct Engine : EngineBase {
   }
 
   void forward_plain(hipStream_t s) {
+    S.get<double>((int64_t)cfg.F * cfg.R);
+    Sgg.get<double>(cfg.R);
     C<T>* g = Fg.get<C<T>>(NC);
     C<T>* h = X.get<C<T>>(NC);
     scatter_plain(gal_set(), g_key.as<int32_t>(), g_ls.as<int32_t>(), 0, NN, g, s);

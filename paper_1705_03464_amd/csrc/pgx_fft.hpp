@@ -140,6 +140,16 @@ template <> struct DefaultShape<double, 256> { using type = Shape<256, 3, 8, 8, 
 template <> struct DefaultShape<double, 512> { using type = Shape<512, 3, 8, 8, 8>; };
 template <> struct DefaultShape<double, 1024> { using type = Shape<1024, 3, 16, 8, 8>; };
 
+// Second radix schedule of the strided passes, one of the candidates the
+// plan's autotuner times: 16 elements per thread, fewer exchange stages.
+template <typename T, int N> struct AltShape;
+template <> struct AltShape<float, 64> { using type = Shape<64, 2, 16, 4, 1>; };
+template <> struct AltShape<float, 128> { using type = Shape<128, 2, 16, 8, 1>; };
+template <> struct AltShape<float, 256> { using type = Shape<256, 2, 16, 16, 1>; };
+template <> struct AltShape<float, 512> { using type = Shape<512, 3, 16, 8, 4>; };
+template <> struct AltShape<float, 1024> { using type = Shape<1024, 3, 16, 16, 4>; };
+template <int N> struct AltShape<double, N> { using type = typename DefaultShape<double, N>::type; };
+
 // LDS index with one pad element per 2^kPadShift (breaks power-of-two strides
 // inside a line); kLineExtra sets the line length modulo the bank count so
 // the lines of a tile start on different banks.

@@ -75,7 +75,8 @@ template <typename T> struct Buf {
   }
 };
 
-// z passes: twiddle source, and the most slots one launch may carry (their
+// z passes: default twiddle source (registers when they fit; the autotuner
+// also tries the LDS table), and the most slots one launch may carry (their
 // plane masks are staged in LDS)
 constexpr bool kZTwReg = true;
 constexpr int kMaxSlots = 32;
@@ -323,7 +324,7 @@ k_strided(const C<T>* in, C<T>* out, int64_t in_slot, int64_t out_slot,
 // STORE mode also writes each pair-field spectrum (after the forward z
 // transform) to `spec` at its field-pair index, for the adjoint.
 // ----------------------------------------------------------------------------
-template <typename T, typename Sh, int W, bool GAL, bool STORE = false>
+template <typename T, typename Sh, int W, bool GAL, bool STORE = false, bool TWREG = kZTwReg>
 static __global__ void __launch_bounds__(W * Sh::TPL)
 k_zcross(const C<T>* in, int64_t in_slot, const uint8_t* __restrict__ pflag,
          const int32_t* __restrict__ slot_fp, int n_slots, const C<T>* __restrict__ fg,
@@ -333,12 +334,12 @@ k_zcross(const C<T>* in, int64_t in_slot, const uint8_t* __restrict__ pflag,
   constexpr int64_t NN = (int64_t)N * N;
   // slot pipeline when a thread has room for a second set of columns
   constexpr bool PIPE = !GAL && E <= 8;
-  __shared__ C<T> tw_s[tw_lds_entries<Sh, kZTwReg>()];
+  __shared__ C<T> tw_s[tw_lds_entries<Sh, TWREG>()];
   __shared__ C<T> lines[W][LL];
   __shared__ uint32_t pmask[GAL ? 1 : kMaxSlots][TPL];
   const int xt = blockIdx.x, ky = blockIdx.y;
   const int c = threadIdx.x % W, t = threadIdx.x / W;
-  TwAuto<Sh, T, kZTwReg> twa;
+  TwAuto<Sh, T, TWREG> twa;
   twa.init(tw_s, tw_g, t);
   if constexpr (!GAL) {
     // plane masks of the batch: bit m of pmask[s][t] = plane t + TPL m of

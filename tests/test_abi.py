@@ -26,10 +26,12 @@ def declared_symbols():
     return sorted(set(re.findall(r"\b(pgx_[a-z_]+)\s*\(", src)))
 
 
-def test_keep_spectra_flag_needs_no_device():
+def test_option_flags_need_no_device():
     plan = Plan(100.0, 64, linbins(0.5, 10, 3), [0.0, 1.0], logbins(5.0, 45.0, 9))
     plan.keep_spectra(True)
     plan.keep_spectra(False)
+    plan.use_graphs(False)
+    plan.use_graphs(True)
 
 
 def test_library_exports_every_declared_symbol():

@@ -1,0 +1,142 @@
+"""Batch schedules and kernel variants: every variant the autotuner can pick
+meets the oracle on its own (forward on the small-grid cases, adjoint on the
+tiny HOD case), and the schedule the autotuner keeps gives the same results
+as the default one."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import grad as OG
+from oracle.pipeline import forward as oracle_forward
+from synth import get_config
+from synth.configs import Workload
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+from test_gpu_parity import SMALL, assert_fp32_parity, clustered_catalog  # noqa: E402
+
+# (batch, forward y variant, inverse y variant, z variant)
+SCHEDULES = [(2, 1, 1, 1), (1, 1, 0, 1), (3, 0, 1, 0)]
+
+
+def _say(m):
+    print(m, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def dev(a, dt=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+
+
+def small_case(case):
+    N, L, pm, p1, p2, dmax, om, o1, o2 = SMALL[case]
+    wl = Workload(name="t", L=L, N=N, precision="fp32", pair_mode=pm, p1_edges=p1,
+                  p2_edges=p2, pair_dmax=dmax, out_mode=om, o1_edges=o1, o2_edges=o2,
+                  catalog_kw={})
+    cat = clustered_catalog(L, int(0.02 * L ** 2), int(0.8 * L ** 2), seed=case)
+    w = np.random.default_rng(case).uniform(0.3, 1.7, cat.n).astype(np.float32).astype(np.float64)
+    return wl, cat, w
+
+
+@pytest.mark.parametrize("sched", SCHEDULES)
+@pytest.mark.parametrize("case", range(len(SMALL)))
+def test_forward_every_variant_meets_oracle(case, sched):
+    from paper_1705_03464_amd import Plan
+    wl, cat, w = small_case(case)
+    _say(f"case {case} N={wl.N} F={wl.n_fields} schedule {sched}")
+    ref = oracle_forward(cat, wl, w=w)
+    plan = Plan.from_workload(wl, precision="fp32")
+    plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
+    plan.set_schedule(*sched)
+    got = plan.schedule()
+    assert got["batch"] == min(sched[0], (wl.n_fields + 1) // 2)
+    assert (got["ypass_variant"], got["yinv_variant"], got["zpass_variant"]) == sched[1:]
+    out = {k: v.cpu().numpy() for k, v in plan.forward(dev(w, torch.float32)).items()}
+    assert_fp32_parity(out, ref)
+
+
+@pytest.mark.parametrize("sched", SCHEDULES)
+def test_adjoint_every_variant_meets_oracle(sched):
+    from paper_1705_03464_amd import Plan
+    wl = get_config("cfg4tiny")
+    cat = wl.catalog()
+    w = OG.hod_weights(cat.halo_mass, cat.kind,
+                       np.array([13.35, 13.8, 0.85, 1.0])).astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(21)
+    g_xipg = rng.normal(size=(wl.n_fields, wl.n_out))
+    g_xigg = rng.normal(size=wl.n_out)
+    ref, _ = OG.weight_gradient(cat, wl, w, g_xipg=g_xipg, g_xigg=g_xigg)
+    plan = Plan.from_workload(wl, precision="fp32")
+    plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
+    plan.set_schedule(*sched)
+    plan.forward(dev(w, torch.float32))
+    gw = plan.backward(g_xi_pg=dev(g_xipg), g_xi_gg=dev(g_xigg)).cpu().numpy().astype(np.float64)
+    l2 = np.linalg.norm(gw - ref) / np.linalg.norm(ref)
+    mx = np.max(np.abs(gw - ref)) / np.max(np.abs(ref))
+    _say(f"  schedule {sched}: grad rel l2 {l2:.2e} rel max {mx:.2e}")
+    assert l2 <= 1e-3 and mx <= 1e-3
+
+
+@pytest.mark.parametrize("name", ["cfg4tiny", "cfg2"])
+def test_autotuned_schedule_matches_default(name):
+    from paper_1705_03464_amd import Plan
+    wl = get_config(name)
+    cat = wl.catalog()
+    w = dev(np.random.default_rng(5).uniform(0.5, 1.5, cat.n), torch.float32)
+    plan = Plan.from_workload(wl, precision="fp32")
+    plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
+    default = plan.schedule()
+    ref = {k: v.cpu().numpy() for k, v in plan.forward(w).items()}
+    sched = plan.autotune()
+    _say(f"{name}: default {default} tuned {sched}")
+    assert plan.schedule() == sched
+    assert 1 <= sched["batch"] <= 2 * default["batch"]
+    out = {k: v.cpu().numpy() for k, v in plan.forward(w).items()}
+    for k in ("xi_gg", "xi_pg"):
+        fin = np.isfinite(ref[k])
+        assert np.array_equal(fin, np.isfinite(out[k]))
+        d = np.abs(out[k][fin] - ref[k][fin])
+        assert np.all(d <= 1e-5 * np.maximum(np.abs(ref[k][fin]), 1e-2)), k
+
+
+def test_schedule_rejects_bad_values():
+    from paper_1705_03464_amd import PgxError, Plan
+    wl = get_config("cfg4tiny")
+    cat = wl.catalog()
+    plan = Plan.from_workload(wl, precision="fp32")
+    with pytest.raises(PgxError):
+        plan.autotune()  # before the pair build
+    plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
+    for bad in [(0, 0, 0, 0), (33, 0, 0, 0), (2, 2, 0, 0), (2, 0, -1, 0), (2, 0, 0, 5)]:
+        with pytest.raises(PgxError):
+            plan.set_schedule(*bad)
+
+
+def test_autotune_as_first_device_work_after_pair_build():
+    """The autotuner runs the forward body before any pgx_forward has sized the
+    plan's bin-sum buffers; it must size them itself (regression test)."""
+    from paper_1705_03464_amd import Plan
+    wl = get_config("cfg2")
+    cat = wl.catalog()
+    ref_plan = Plan.from_workload(wl, precision="fp32")
+    ref_plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
+    ref = {k: v.cpu().numpy() for k, v in ref_plan.forward().items()}
+    ref_plan.close()
+    plan = Plan.from_workload(wl, precision="fp32")
+    plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
+    sched = plan.autotune()
+    _say(f"cfg2 tuned before any forward: {sched}")
+    out = {k: v.cpu().numpy() for k, v in plan.forward().items()}
+    for k in ("xi_gg", "xi_pg"):
+        fin = np.isfinite(ref[k])
+        assert np.array_equal(fin, np.isfinite(out[k]))
+        d = np.abs(out[k][fin] - ref[k][fin])
+        assert np.all(d <= 1e-5 * np.maximum(np.abs(ref[k][fin]), 1e-2)), k

@@ -280,3 +280,18 @@ def test_forward_1024_redshift_space_sampled():
     for k in ("xi_pg", "b_pg"):
         sub[k] = ref[k][fields]; o[k] = out[k][fields]
     assert_fp32_parity(o, sub)
+
+
+def test_fp64_plain_512_matches_fp32_batched():
+    """The one-field-at-a-time FP64 path at the production grid (the
+    reference leg of the benchmark) against the batched FP32 path, which the
+    test above holds to the oracle at this size."""
+    wl = get_config("cfg1")
+    cat = wl.catalog()
+    _say(f"cfg1 fp64 plain vs fp32 batched: n_gal={cat.n}")
+    _, _, _, o32 = run(wl, cat, "fp32")
+    _, _, _, o64 = run(wl, cat, "fp64")
+    for k in ("xi_gg", "xi_pg"):
+        worst = xi_err_ok(o64[k], o32[k], rel=1e-5)
+        _say(f"  {k}: worst |d| / (1e-5 max(|xi|,1e-2)) = {worst:.3f}")
+        assert worst <= 1.0
