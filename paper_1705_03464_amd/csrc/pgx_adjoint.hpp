@@ -190,6 +190,10 @@ k_kgen_x(const double* __restrict__ coef, int R, const int32_t* __restrict__ slo
 // reads Z from the spectra the forward kept (`spec`, by field-pair index)
 // instead of transforming the recomputed columns.
 // ----------------------------------------------------------------------------
+// the STORED variant keeps its galaxy-side accumulator in registers (it has
+// one transform less in flight than the recomputing variant)
+constexpr bool kZbAccRegStored = true;
+
 template <typename T, typename Sh, int W, bool STORED = false>
 static __global__ void __launch_bounds__(W * Sh::TPL)
 k_zback(C<T>* x, int64_t x_slot, const uint8_t* __restrict__ pflag,
@@ -206,8 +210,9 @@ k_zback(C<T>* x, int64_t x_slot, const uint8_t* __restrict__ pflag,
   // buffers (each thread owns its entries; rows padded to an odd length so the
   // W columns fall on different banks), in registers otherwise
   constexpr bool ACC_LDS =
+      !(STORED && kZbAccRegStored) &&
       (size_t)(W * (N + 1) + W * LL + Sh::tw_entries()) * sizeof(C<T>) +
-          (size_t)kMaxSlots * TPL * sizeof(uint32_t) <= 160 * 1024;
+              (size_t)kMaxSlots * TPL * sizeof(uint32_t) <= 160 * 1024;
   __shared__ C<T> accs[ACC_LDS ? W : 1][ACC_LDS ? N + 1 : 1];
   C<T> accr[ACC_LDS ? 1 : E];
   load_twiddles<T, Sh>(tw_s, tw_g);
