@@ -79,6 +79,34 @@ def cpu_baseline(wl, cat, n_fields_sample=2):
     }
 
 
+def sources_digest():
+    """SHA-256 over the kernel sources (file names and contents)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1705_03464_amd", "csrc")
+    for p in sorted(glob.glob(os.path.join(d, "*.hpp")) + glob.glob(os.path.join(d, "*.hip"))):
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, batch):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE, WRITE_SIZE scaled by a plain copy), or None when the
+    kernel sources or the batch size differ from the profiled run."""
+    p = os.path.join(ROOT, "profiles", "hbm_traffic_cfg1_512.txt")
+    try:
+        with open(p) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("sources_sha256") != sources_digest() or d.get("batch") != batch:
+        return None
+    return d.get("bytes_per_launch", {}).get(kernel)
+
+
 def floor_bytes_per_field(N, fields_per_batch, mode):
     """Required HBM bytes per pair field of the pruned, fused pass structure:
     one sweep S = half spectrum (complex64, N^2 (N/2+1) entries); forward
@@ -223,9 +251,10 @@ def main(argv=None):
     dom = max(prof, key=lambda p: p[2])
     name, n, ms, by = dom
     achieved = (by / n) / (ms / n * 1e-3) / 1e9
+    traffic = measured_traffic(name, plan.schedule()["batch"]) if wl.name == "cfg1" else None
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": name,
         "bytes_per_launch": by / n, "ms_per_launch": ms / n,
         "kernel_share_of_step": round(ms / (ms_prof * a.steps), 3),
     }
