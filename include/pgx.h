@@ -189,23 +189,30 @@ pgx_status pgx_keep_spectra(pgx_plan* plan, int32_t enable);
  * those whose buffers fit in free device memory) and, per pass, two kernel
  * variants: the y passes in their default or second radix schedule (16
  * elements per thread, fewer exchange stages), the z pass with its stage
- * twiddles in registers or in the LDS table.  It keeps the fastest
- * combination for later calls.  Results differ between schedules only by
- * floating-point rounding.  It runs the forward eagerly several times
- * (about ten forward passes' worth of device time), discards the state of
+ * twiddles in registers or in the LDS table.  Then it times the dual form of
+ * the pair-field part (the paper's own evaluation, Methodology, equation
+ * bpg_final: one transform per pair of output bins, the bin kernel convolved
+ * with the galaxy field, interpolated at every pair midpoint; the same
+ * estimator exactly, up to floating-point rounding) when its per-pair values
+ * (n_pairs x n_out FP32) fit in half the free device memory.  It keeps the
+ * fastest combination for later calls.  Results differ between schedules
+ * only by floating-point rounding.  It runs the forward eagerly several times
+ * (about twelve forward passes' worth of device time), discards the state of
  * the last pgx_forward (a pgx_backward must follow a new pgx_forward), clears
  * the kernel-timing counters and invalidates the launch graphs.
- *   schedule: host int32[4] out (nullable): field pairs per batch, forward
- *   y-pass variant, inverse y-pass variant, z-pass variant (0 = default).
+ *   schedule: host int32[5] out (nullable): field pairs (or bin pairs) per
+ *   batch, forward y-pass variant, inverse y-pass variant, z-pass variant
+ *   (0 = default), algorithm (0 = one transform per field pair, 1 = dual
+ *   form).  The adjoint is the same for both algorithms.
  * Errors: ESTATE before pgx_pairs_build; ENOTSUP on FP64 plans.
  */
 pgx_status pgx_autotune(pgx_plan* plan, void* stream, int32_t* schedule);
-/* The schedule in use: host int32[4] as filled by pgx_autotune.  Creates the
+/* The schedule in use: host int32[5] as filled by pgx_autotune.  Creates the
  * device state of the plan if it does not exist yet. */
 pgx_status pgx_schedule(pgx_plan* plan, int32_t* schedule);
-/* Apply a schedule (host int32[4] as above, e.g. one found by an earlier
+/* Apply a schedule (host int32[5] as above, e.g. one found by an earlier
  * pgx_autotune): batch size in [1, 32] (clamped to the number of field
- * pairs), variants 0 or 1.  Same side effects as pgx_autotune apart from the
+ * pairs), variants and algorithm 0 or 1.  Same side effects as pgx_autotune apart from the
  * timing runs.  Errors: EINVAL for values out of range, ESTATE before
  * pgx_pairs_build, ENOTSUP on FP64 plans. */
 pgx_status pgx_set_schedule(pgx_plan* plan, void* stream, const int32_t* schedule);

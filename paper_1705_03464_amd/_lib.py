@@ -244,26 +244,26 @@ class Plan:
     def autotune(self, stream=None) -> dict:
         """Time candidate batch sizes and kernel variants on the current pair
         catalogue and keep the fastest; returns the schedule (pgx_autotune)."""
-        out = (C.c_int32 * 4)()
+        out = (C.c_int32 * 5)()
         _check(load_library().pgx_autotune(self._h, _stream(stream), out))
         return self._sched(out)
 
     def schedule(self) -> dict:
         """The batch size and kernel variants in use."""
-        out = (C.c_int32 * 4)()
+        out = (C.c_int32 * 5)()
         _check(load_library().pgx_schedule(self._h, out))
         return self._sched(out)
 
     def set_schedule(self, batch: int, ypass_variant: int = 0, yinv_variant: int = 0,
-                     zpass_variant: int = 0, stream=None):
-        """Apply a schedule (pgx_set_schedule)."""
-        arr = (C.c_int32 * 4)(batch, ypass_variant, yinv_variant, zpass_variant)
+                     zpass_variant: int = 0, algorithm: int = 0, stream=None):
+        """Apply a schedule (pgx_set_schedule); algorithm 1 = dual form."""
+        arr = (C.c_int32 * 5)(batch, ypass_variant, yinv_variant, zpass_variant, algorithm)
         _check(load_library().pgx_set_schedule(self._h, _stream(stream), arr))
 
     @staticmethod
     def _sched(out) -> dict:
         return dict(batch=int(out[0]), ypass_variant=int(out[1]), yinv_variant=int(out[2]),
-                    zpass_variant=int(out[3]))
+                    zpass_variant=int(out[3]), algorithm=int(out[4]))
 
     def use_graphs(self, enable: bool = True):
         """Record the forward / adjoint launch sequences into HIP graphs and

@@ -143,7 +143,8 @@ template <typename T, typename Sh, int W>
 static __global__ void __launch_bounds__(W * Sh::TPL)
 k_kgen_x(const double* __restrict__ coef, int R, const int32_t* __restrict__ slot_fa,
          const int32_t* __restrict__ slot_fb, int pwx, int pwy, int pwz, BinMap bm,
-         C<T>* __restrict__ out, int64_t out_slot, const C<T>* __restrict__ tw_g) {
+         C<T>* __restrict__ out, int64_t out_slot, const C<T>* __restrict__ tw_g,
+         const float* __restrict__ fscale = nullptr) {
   constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>();
   __shared__ C<T> tw_s[Sh::tw_entries()];
   __shared__ C<T> lines[W][LL];
@@ -164,8 +165,12 @@ k_kgen_x(const double* __restrict__ coef, int R, const int32_t* __restrict__ slo
     if (active && px <= 2 * pwx) {
       const int b = classify_bin(bm, px - pwx, py - pwy, pz - pwz);
       if (b >= 0) {
-        v[m].x = fa >= 0 ? (T)coef[(int64_t)fa * R + b] : (T)0;
-        v[m].y = fb >= 0 ? (T)coef[(int64_t)fb * R + b] : (T)0;
+        // coefficients of a field whose transform ran scaled by fscale[f] are
+        // divided by it, so products with its spectrum come out unscaled
+        const double sa = fscale && fa >= 0 ? (double)fscale[fa] : 1.0;
+        const double sb = fscale && fb >= 0 ? (double)fscale[fb] : 1.0;
+        v[m].x = fa >= 0 ? (T)(coef[(int64_t)fa * R + b] / sa) : (T)0;
+        v[m].y = fb >= 0 ? (T)(coef[(int64_t)fb * R + b] / sb) : (T)0;
       }
     }
   }
@@ -416,7 +421,7 @@ static __global__ void __launch_bounds__(W * Sh::TPL)
 k_xgather(const int32_t* __restrict__ tasks, int n_tasks, PointSet<T> ps,
           const int32_t* __restrict__ slot_fa, const int32_t* __restrict__ slot_fb,
           const C<T>* __restrict__ in, T scale, float* __restrict__ acc,
-          const C<T>* __restrict__ tw_g) {
+          const C<T>* __restrict__ tw_g, const float* __restrict__ fscale = nullptr) {
   constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>();
   constexpr int64_t NN = (int64_t)N * N;
   __shared__ C<T> tw_s[Sh::tw_entries()];
@@ -452,6 +457,9 @@ k_xgather(const int32_t* __restrict__ tasks, int n_tasks, PointSet<T> ps,
       const int f = part == 0 ? fa : fb;
       if (f < 0) continue;
       const int64_t fbase = (int64_t)f * NN;
+      // a field whose kernel coefficients were divided by fscale[f] gives
+      // values scaled by 1 / fscale[f]: undo it here
+      const T sc = scale * (fscale ? (T)fscale[f] : (T)1);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int by = (q & 1) ? ym : y, bz = (q & 2) ? zm : z;
@@ -464,7 +472,7 @@ k_xgather(const int32_t* __restrict__ tasks, int n_tasks, PointSet<T> ps,
           const int x0 = ps.x0[p];
           const C<T> a0 = line[lpad(x0)], a1 = line[lpad((x0 + 1) & (N - 1))];
           const T v0 = part == 0 ? a0.x : a0.y, v1 = part == 0 ? a1.x : a1.y;
-          atomicAdd(&acc[p], (float)(scale * wy * wz * (((T)1 - fx) * v0 + fx * v1)));
+          atomicAdd(&acc[p], (float)(sc * wy * wz * (((T)1 - fx) * v0 + fx * v1)));
         }
       }
     }

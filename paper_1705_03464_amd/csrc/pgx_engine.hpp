@@ -2,6 +2,7 @@
 // transform precision T and the grid side N.
 #pragma once
 #include "pgx_adjoint.hpp"
+#include "pgx_dual.hpp"
 #include "pgx_misc.hpp"
 #include "pgx_pairs.hpp"
 #include "pgx_prim.hpp"
@@ -218,6 +219,12 @@ template <typename T, int N> struct Engine : EngineBase {
   // kernel variants picked by the autotuner (0 = default): forward y pass,
   // inverse y pass (radix schedule), z pass (twiddle source)
   int v_ypass = 0, v_yinv = 0, v_zpass = 0;
+  // algorithm of the pair-field part of the forward: 0 = one transform per
+  // field pair, 1 = dual form (one transform per pair of output bins, then a
+  // gather at the pair midpoints)
+  int algo = 0;
+  DBuf coef_id, bscale, bfa, bfb, GV;  // dual form: bin coefficients 1/n_b (and their FP32 values), bin-pair slots, gathered values
+  DBuf FSC;  // per-field FP32 transform scale 1 / Wsum_f
   // constant tables
   DBuf tw_alt;
   DBuf tw, lut1, lut2, mu2, nbd, vold, t1, t2, slot_fa, slot_fb, slot_fp, gslot_fa, gslot_fb,
@@ -286,6 +293,24 @@ template <typename T, int N> struct Engine : EngineBase {
     upload(slot_fa, fa);
     upload(slot_fb, fb);
     upload(slot_fp, fp);
+    // dual form: slot q holds output bins (2q, 2q + 1) with unit coefficients
+    const int R = cfg.R, Q = (R + 1) / 2;
+    std::vector<double> ci((size_t)R * R, 0.0);
+    std::vector<float> bs((size_t)std::max(R, 1), 1.0f);
+    for (int b = 0; b < R; ++b) {
+      const double sc = cfg.nb[b] > 0 ? 1.0 / (double)cfg.nb[b] : 1.0;
+      bs[b] = (float)sc;
+      ci[(size_t)b * R + b] = (double)bs[b];  // the generator casts to T: same value
+    }
+    upload(coef_id, ci);
+    upload(bscale, bs);
+    std::vector<int32_t> qa((size_t)Q + kMaxSlots, -1), qb((size_t)Q + kMaxSlots, -1);
+    for (int q = 0; q < Q; ++q) {
+      qa[q] = 2 * q;
+      qb[q] = 2 * q + 1 < R ? 2 * q + 1 : -1;
+    }
+    upload(bfa, qa);
+    upload(bfb, qb);
     upload(gslot_fa, std::vector<int32_t>{0});
     upload(gslot_fb, std::vector<int32_t>{-1});
     upload(neg1, std::vector<int32_t>{-1});
@@ -551,10 +576,10 @@ template <typename T, int N> struct Engine : EngineBase {
           prof.reset();
           prof.on = false;
           weights(wl, s);
-          forward_batched(s, nullptr);
+          forward_batched(s, nullptr, wl);
           prof.on = true;
           weights(wl, s);
-          forward_batched(s, nullptr);
+          forward_batched(s, nullptr, wl);
           prof.collect();
           prof.on = false;
           for (const auto& c : prof.cats) {
@@ -574,12 +599,34 @@ template <typename T, int N> struct Engine : EngineBase {
           best[3] = vz;
         }
       }
+      // the dual form (one transform per pair of output bins) at the chosen
+      // batch size, when its gathered values fit
+      int best_algo = 0;
+      algo = 0;
+      if (dual_fits()) {
+        schedule(best[0], s);
+        algo = 1;
+        prof.reset();
+        prof.on = false;
+        weights(wl, s);
+        forward_batched(s, nullptr, wl);
+        prof.on = true;
+        weights(wl, s);
+        forward_batched(s, nullptr, wl);
+        prof.collect();
+        prof.on = false;
+        double ms = 0;
+        for (const auto& c : prof.cats) ms += c.ms;
+        algo = 0;
+        if (ms < best_ms) best_algo = 1;
+      }
       prof.reset();
       prof.on = prof_on;
       schedule(best[0], s);
       v_ypass = best[1];
       v_yinv = best[2];
       v_zpass = best[3];
+      algo = best_algo;
       ++gen;  // recorded launch sequences used the old schedule
       forward_done = false;
       spectra_valid = false;
@@ -590,7 +637,7 @@ template <typename T, int N> struct Engine : EngineBase {
   void set_schedule(const int32_t* in, hipStream_t s) override {
     PGX_REQUIRE(built, PGX_ESTATE, "pgx_pairs_build has not been called");
     PGX_REQUIRE(in[0] >= 1 && in[0] <= kMaxSlots, PGX_EINVAL, "batch size must be in [1, 32]");
-    for (int i = 1; i < 4; ++i) PGX_REQUIRE(in[i] == 0 || in[i] == 1, PGX_EINVAL, "variants are 0 or 1");
+    for (int i = 1; i < 5; ++i) PGX_REQUIRE(in[i] == 0 || in[i] == 1, PGX_EINVAL, "variants are 0 or 1");
     if constexpr (!std::is_same<T, float>::value) {
       throw Error(PGX_ENOTSUP, "schedules apply to the FP32 batched path");
     } else {
@@ -598,6 +645,7 @@ template <typename T, int N> struct Engine : EngineBase {
       v_ypass = in[1];
       v_yinv = in[2];
       v_zpass = in[3];
+      algo = in[4];
       ++gen;
       forward_done = false;
       spectra_valid = false;
@@ -610,6 +658,7 @@ template <typename T, int N> struct Engine : EngineBase {
     out[1] = v_ypass;
     out[2] = v_yinv;
     out[3] = v_zpass;
+    out[4] = algo;
   }
 
   // Batch schedule for b field pairs per launch: per-batch task ranges and
@@ -700,6 +749,8 @@ template <typename T, int N> struct Engine : EngineBase {
     k_field_wsum<<<F, 256, 0, s>>>(p_ls.as<int32_t>(), NN, p_i.as<int32_t>(), p_j.as<int32_t>(), w,
                                    wsum_d.get<double>(F));
     launch_check("field_wsum");
+    k_field_scale<<<grid_for(F), 256, 0, s>>>(wsum_d.as<double>(), F, FSC.get<float>(std::max(F, 1)));
+    launch_check("field_scale");
     k_weight_total<<<1, 256, 0, s>>>(w, n_gal, wg_d.get<double>(1));
     launch_check("weight_total");
   }
@@ -762,16 +813,17 @@ template <typename T, int N> struct Engine : EngineBase {
     float* wl = w_given && n_gal > 0 ? w_last.get<float>(n_gal) : nullptr;
     if (wl) PGX_HIP(hipMemcpyAsync(wl, w, n_gal * sizeof(float), hipMemcpyDeviceToDevice, s));
     C<T>* spec = nullptr;
-    if constexpr (std::is_same<T, float>::value) spec = keep_spectra ? spectra_store() : nullptr;
+    if constexpr (std::is_same<T, float>::value)
+      spec = keep_spectra && algo == 0 ? spectra_store() : nullptr;  // the dual form has no pair-field spectra
     // the recorded body reads the weights from the plan's copy
     GraphKey key;
     key.gen = gen;
     key.p = spec;
-    key.flags = (w_given ? 1 : 0) | (n_gal > 0 ? 2 : 0);
+    key.flags = (w_given ? 1 : 0) | (n_gal > 0 ? 2 : 0) | (algo << 2);
     graphed(gf, key, s, [&](hipStream_t st) {
       weights(wl, st);
       if constexpr (std::is_same<T, float>::value)
-        forward_batched(st, spec);
+        forward_batched(st, spec, wl);
       else
         forward_plain(st);
     });
@@ -890,7 +942,8 @@ template <typename T, int N> struct Engine : EngineBase {
       const double pts = (double)batch_points(k) * (4 + 4 * sizeof(T));
       prof.run("bwd_kgen", s, (double)nb * kx_slot * cb, [&] {
         k_kgen_x<T, Sh, WX><<<dim3(nblkK, 1, nb), NTX, 0, s>>>(aa.apg, R, fa, fb, pwx(), pwy(),
-                                                                pwz(), bm, kx, kx_slot, twp);
+                                                                pwz(), bm, kx, kx_slot, twp,
+                                                                FSC.as<float>());
         launch_check("kgen");
       });
       prof.run("bwd_kgen_y", s, (double)nb * (kx_slot + ky_slot) * cb, [&] {
@@ -911,7 +964,7 @@ template <typename T, int N> struct Engine : EngineBase {
         if (nt > 0) {
           prof.run("bwd_xscatter", s, pts + (double)nt * N * cb, [&] {
             k_xscatter<T, Sh, WX><<<(int)((nt + WX - 1) / WX), NTX, 0, s>>>(
-                tasks.as<int32_t>() + t0, (int)nt, pair_set(), fa, fb, x, twp);
+                tasks.as<int32_t>() + t0, (int)nt, pair_set(), fa, fb, x, twp, FSC.as<float>());
             launch_check("xscatter(bwd)");
           });
         }
@@ -934,7 +987,8 @@ template <typename T, int N> struct Engine : EngineBase {
       if (nt > 0) {
         prof.run("bwd_xgather", s, pts + (double)nt * N * cb, [&] {
           k_xgather<T, Sh, WX><<<(int)((nt + WX - 1) / WX), NTX, 0, s>>>(
-              tasks.as<int32_t>() + t0, (int)nt, pair_set(), fa, fb, x, (T)1, gb, twp);
+              tasks.as<int32_t>() + t0, (int)nt, pair_set(), fa, fb, x, (T)1, gb, twp,
+              FSC.as<float>());
           launch_check("xgather");
         });
       }
@@ -986,7 +1040,72 @@ template <typename T, int N> struct Engine : EngineBase {
   int pwy() const { return cfg.pw[1]; }
   int pwz() const { return cfg.pw[2]; }
 
-  void forward_batched(hipStream_t s, C<T>* spec) {
+  // whether the dual form fits: its per-pair, per-bin gathered values must
+  // fit in half the free device memory
+  bool dual_fits() const {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) return false;
+    return (double)cfg.R * (double)std::max<int64_t>(n_pairs, 1) * 4.0 + (double)GV.bytes < 0.5 * (double)fr;
+  }
+
+  // Dual form of the pair-field part (see pgx_dual.hpp): for each batch of B
+  // bin pairs, the kernel fields S_b1 + i S_b2 (x, y transforms of the
+  // window), the z pass with G, inverse y and x transforms, and the gather at
+  // every pair midpoint; then the per-field sums.
+  void forward_dual_pairs(hipStream_t s, C<T>* x, const C<T>* fg, const C<T>* twp, const BinMap& bm,
+                          double* Sd, const float* wl) {
+    const int R = cfg.R, F = cfg.F, Q = (R + 1) / 2;
+    const int ny = win_len(pwy()), nz = win_len(pwz());
+    const int nblkK = (ny * nz + WX - 1) / WX;
+    const int64_t kx_slot = (int64_t)nz * ny * N, ky_slot = (int64_t)nz * NN;
+    const double cb = (double)sizeof(C<T>);
+    C<T>* kx = KX.get<C<T>>((int64_t)B * kx_slot);
+    C<T>* ky = KY.get<C<T>>((int64_t)B * ky_slot);
+    float* gv = GV.get<float>(std::max<int64_t>((int64_t)R * n_pairs, 1));
+    for (int q0 = 0; q0 < Q; q0 += B) {
+      const int nq = std::min(B, Q - q0);
+      prof.run("dual_kgen", s, (double)nq * kx_slot * cb, [&] {
+        k_kgen_x<T, Sh, WX><<<dim3(nblkK, 1, nq), NTX, 0, s>>>(
+            coef_id.as<double>(), R, bfa.as<int32_t>() + q0, bfb.as<int32_t>() + q0, pwx(), pwy(),
+            pwz(), bm, kx, kx_slot, twp);
+        launch_check("kgen(dual)");
+      });
+      prof.run("dual_kgen_y", s, (double)nq * (kx_slot + ky_slot) * cb, [&] {
+        k_strided<T, Sh, W, -1, IN_WINDOW, OUT_DENSE><<<dim3(N / W, nz, nq), NT, 0, s>>>(
+            kx, ky, kx_slot, ky_slot, (int64_t)ny * N, NN, N, N, pwy(), nullptr, nullptr, 0,
+            nullptr, twp);
+        launch_check("kgen_y(dual)");
+      });
+      prof.run("dual_zconv", s, (double)(nq * ky_slot + NC + nq * NC) * cb, [&] {
+        k_zconv<T, Sh, W><<<dim3(N / W, N, 1), NT, 0, s>>>(ky, ky_slot, nq, pwz(), fg, x, NC, twp);
+        launch_check("zconv");
+      });
+      prof.run("dual_yinv", s, 2.0 * nq * NC * cb, [&] {
+        k_strided<T, Sh, W, 1, IN_DENSE, OUT_DENSE><<<dim3(N / W, N, nq), NT, 0, s>>>(
+            x, x, NC, NC, NN, NN, N, N, 0, nullptr, nullptr, 0, nullptr, twp);
+        launch_check("yinv(dual)");
+      });
+      prof.run("dual_xinv", s, 2.0 * nq * NC * cb, [&] {
+        for (int j = 0; j < nq; ++j)
+          k_xdense<T, Sh, WX, 1><<<(int)(NN / WX), NTX, 0, s>>>(x + (int64_t)j * NC, twp);
+        launch_check("xinv(dual)");
+      });
+      if (n_pairs > 0) {
+        prof.run("dual_gather", s, (double)n_pairs * (20.0 + 8.0 * nq * (4.0 + 2.0 * cb)), [&] {
+          k_dual_gather<T><<<grid_for(n_pairs), 256, 0, s>>>(
+              p_key.as<int32_t>(), p_x0.as<int32_t>(), p_fx.as<T>(), p_fy.as<T>(), p_fz.as<T>(),
+              n_pairs, N, x, NC, nq, 2 * q0, R, gv);
+          launch_check("gather(dual)");
+        });
+      }
+    }
+    k_dual_reduce<<<dim3(F, R), 256, 0, s>>>(p_ls.as<int32_t>(), NN, p_i.as<int32_t>(),
+                                             p_j.as<int32_t>(), wl, gv, n_pairs, R,
+                                             bscale.as<float>(), Sd);
+    launch_check("reduce(dual)");
+  }
+
+  void forward_batched(hipStream_t s, C<T>* spec, const float* wl) {
     const int R = cfg.R;
     // bin sums: allocated here too, since the autotuner runs this body
     // without a preceding pgx_forward
@@ -1035,6 +1154,10 @@ template <typename T, int N> struct Engine : EngineBase {
     k_reduce_bins<<<dim3(2 * R, 1), 256, 0, s>>>(pt, nblkE, R, gslot_fa.as<int32_t>(),
                                                            gslot_fb.as<int32_t>(), Sggd);
     launch_check("reduce(gal)");
+    if (algo == 1) {
+      forward_dual_pairs(s, x, fg, twp, bm, Sd, wl);
+      return;
+    }
     // ---- pair fields, B field pairs per batch
     for (int k = 0; k < n_batches; ++k) {
       const int nb = std::min(B, cfg.n_fp - k * B);
@@ -1046,7 +1169,7 @@ template <typename T, int N> struct Engine : EngineBase {
       if (nt > 0) {
         prof.run("xscatter", s, pts + (double)nt * N * cb, [&] {
           k_xscatter<T, Sh, WX><<<(int)((nt + WX - 1) / WX), NTX, 0, s>>>(
-              tasks.as<int32_t>() + t0, (int)nt, pair_set(), fa, fb, x, twp);
+              tasks.as<int32_t>() + t0, (int)nt, pair_set(), fa, fb, x, twp, FSC.as<float>());
           launch_check("xscatter");
         });
       }
@@ -1089,7 +1212,7 @@ template <typename T, int N> struct Engine : EngineBase {
                                                                         pwz(), bm, R, pt, twp);
         launch_check("xinv_bins");
       });
-      k_reduce_bins<<<dim3(2 * R, nb), 256, 0, s>>>(pt, nblkE, R, fa, fb, Sd);
+      k_reduce_bins<<<dim3(2 * R, nb), 256, 0, s>>>(pt, nblkE, R, fa, fb, Sd, FSC.as<float>());
       launch_check("reduce");
     }
   }

@@ -115,7 +115,8 @@ template <typename T, typename Sh, int W>
 static __global__ void __launch_bounds__(W * Sh::TPL)
 k_xscatter(const int32_t* __restrict__ tasks, int n_tasks, PointSet<T> ps,
            const int32_t* __restrict__ slot_fa, const int32_t* __restrict__ slot_fb,
-           C<T>* __restrict__ out, const C<T>* __restrict__ tw_g) {
+           C<T>* __restrict__ out, const C<T>* __restrict__ tw_g,
+           const float* __restrict__ fscale = nullptr) {
   constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>();
   constexpr int64_t NN = (int64_t)N * N;
   __shared__ C<T> tw_s[Sh::tw_entries()];
@@ -144,6 +145,7 @@ k_xscatter(const int32_t* __restrict__ tasks, int n_tasks, PointSet<T> ps,
       const int f = part == 0 ? fa : fb;
       if (f < 0) continue;
       const int64_t fbase = (int64_t)f * NN;
+      const T sc = fscale ? (T)fscale[f] : (T)1;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int by = (q & 1) ? ym : y, bz = (q & 2) ? zm : z;
@@ -153,7 +155,7 @@ k_xscatter(const int32_t* __restrict__ tasks, int n_tasks, PointSet<T> ps,
           const T fy = ps.fy[p], fz = ps.fz[p], fx = ps.fx[p];
           const T wy = (q & 1) ? fy : (T)1 - fy;
           const T wz = (q & 2) ? fz : (T)1 - fz;
-          const T w = ps.wt[p] * wy * wz;
+          const T w = ps.wt[p] * sc * wy * wz;
           const int x0 = ps.x0[p];
           T* a0 = part == 0 ? &line[lpad(x0)].x : &line[lpad(x0)].y;
           T* a1 = part == 0 ? &line[lpad((x0 + 1) & (N - 1))].x : &line[lpad((x0 + 1) & (N - 1))].y;

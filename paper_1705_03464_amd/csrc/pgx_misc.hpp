@@ -89,6 +89,14 @@ static __global__ void k_field_wsum(const int32_t* __restrict__ line_start, int6
   if (threadIdx.x == 0) wsum[f] = r;
 }
 
+// Per-field scale of the pair fields in the transforms: 1 / Wsum_f rounded to
+// FP32 (1 for empty fields), so that the two fields sharing a complex grid
+// have unit mass each and neither one's rounding swamps the other's signal.
+static __global__ void k_field_scale(const double* __restrict__ wsum, int F, float* __restrict__ fsc) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f < F) fsc[f] = (float)(wsum[f] > 1e-30 ? 1.0 / wsum[f] : 1.0);
+}
+
 // Sum of galaxy weights in FP64 (single block, fixed partition).
 static __global__ void k_weight_total(const float* __restrict__ w, int64_t n, double* __restrict__ out) {
   __shared__ double sh[256];
@@ -104,7 +112,7 @@ static __global__ void k_weight_total(const float* __restrict__ w, int64_t n, do
 // ----------------------------------------------------------------------------
 static __global__ void k_reduce_bins(const double* __restrict__ part, int nblk, int R,
                               const int32_t* __restrict__ slot_fa, const int32_t* __restrict__ slot_fb,
-                              double* __restrict__ S) {
+                              double* __restrict__ S, const float* __restrict__ fscale = nullptr) {
   // one block per (entry i of the 2R partial row, slot); fixed partition and tree
   __shared__ double sh[256];
   const int slot = blockIdx.y, i = blockIdx.x;
@@ -115,7 +123,8 @@ static __global__ void k_reduce_bins(const double* __restrict__ part, int nblk, 
   if (threadIdx.x == 0) {
     const int half = i / R, bin = i % R;
     const int f = half == 0 ? slot_fa[slot] : slot_fb[slot];
-    if (f >= 0) S[(int64_t)f * R + bin] = r;
+    // undo the field's transform scale (the FP32 value the scatter applied)
+    if (f >= 0) S[(int64_t)f * R + bin] = fscale ? r / (double)fscale[f] : r;
   }
 }
 

@@ -17,8 +17,9 @@ torch = pytest.importorskip("torch")
 
 from test_gpu_parity import SMALL, assert_fp32_parity, clustered_catalog  # noqa: E402
 
-# (batch, forward y variant, inverse y variant, z variant)
-SCHEDULES = [(2, 1, 1, 1), (1, 1, 0, 1), (3, 0, 1, 0)]
+# (batch, forward y variant, inverse y variant, z variant, algorithm: 1 = dual form)
+SCHEDULES = [(2, 1, 1, 1, 0), (1, 1, 0, 1, 0), (3, 0, 1, 0, 0), (2, 0, 0, 0, 1), (1, 0, 0, 0, 1),
+             (5, 0, 0, 0, 1)]
 
 
 def _say(m):
@@ -58,7 +59,8 @@ def test_forward_every_variant_meets_oracle(case, sched):
     plan.set_schedule(*sched)
     got = plan.schedule()
     assert got["batch"] == min(sched[0], (wl.n_fields + 1) // 2)
-    assert (got["ypass_variant"], got["yinv_variant"], got["zpass_variant"]) == sched[1:]
+    assert (got["ypass_variant"], got["yinv_variant"], got["zpass_variant"],
+            got["algorithm"]) == sched[1:]
     out = {k: v.cpu().numpy() for k, v in plan.forward(dev(w, torch.float32)).items()}
     assert_fp32_parity(out, ref)
 
@@ -85,10 +87,67 @@ def test_adjoint_every_variant_meets_oracle(sched):
     assert l2 <= 1e-3 and mx <= 1e-3
 
 
-@pytest.mark.parametrize("name", ["cfg4tiny", "cfg2"])
-def test_autotuned_schedule_matches_default(name):
+def _worst(got, ref, rel):
+    fin = np.isfinite(ref)
+    assert np.array_equal(fin, np.isfinite(got))
+    d = np.abs(got[fin] - ref[fin])
+    return float(np.max(d / (rel * np.maximum(np.abs(ref[fin]), 1e-2))))
+
+
+@pytest.mark.parametrize("case", [0, 2])
+def test_autotuned_schedule_meets_oracle(case):
     from paper_1705_03464_amd import Plan
-    wl = get_config(name)
+    wl, cat, w = small_case(case)
+    ref = oracle_forward(cat, wl, w=w)
+    plan = Plan.from_workload(wl, precision="fp32")
+    plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
+    default = plan.schedule()
+    out0 = {k: v.cpu().numpy() for k, v in plan.forward(dev(w, torch.float32)).items()}
+    sched = plan.autotune()
+    out1 = {k: v.cpu().numpy() for k, v in plan.forward(dev(w, torch.float32)).items()}
+    _say(f"case {case}: default {default} tuned {sched}")
+    assert plan.schedule() == sched
+    for out in (out0, out1):
+        assert_fp32_parity(out, ref)
+
+
+@pytest.mark.parametrize("algo", [0, 1])
+@pytest.mark.parametrize("weights", ["unit", "random"])
+def test_fp32_floor_on_tiny_hod_subset(algo, weights):
+    """The tiny HOD subset (2 000 candidates in 40 halos of a 125 Mpc/h box,
+    64^3) is the most clustered workload: its correlations reach |xi| ~ 5, and
+    FP32 transforms then leave an absolute error of ~3e-7 on every bin (about
+    one FP32 unit of the largest values).  Bins with 1e-2 < |xi| < 3e-2 can
+    therefore miss the 1e-5 relative bar by up to ~3x; the bound checked here
+    is 1e-5 relative above |xi| = 3e-2 and 3e-7 absolute below, for both the
+    per-field transforms and the dual form."""
+    from paper_1705_03464_amd import Plan
+    wl = get_config("cfg4tiny")
+    cat = wl.catalog()
+    w = None
+    if weights == "random":
+        w = np.random.default_rng(5).uniform(0.5, 1.5, cat.n).astype(np.float32).astype(np.float64)
+    ref = oracle_forward(cat, wl, w=w)
+    plan = Plan.from_workload(wl, precision="fp32")
+    plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
+    plan.set_schedule(10, 0, 0, 0, algo)
+    out = {k: v.cpu().numpy() for k, v in
+           plan.forward(None if w is None else dev(w, torch.float32)).items()}
+    for k in ("xi_gg", "xi_pg"):
+        strict = _worst(out[k], ref[k], 1e-5)
+        floor = float(np.max(np.abs(out[k] - ref[k])[np.isfinite(ref[k])]
+                             / (1e-5 * np.maximum(np.abs(ref[k][np.isfinite(ref[k])]), 3e-2))))
+        _say(f"  {weights} algo {algo} {k}: 1e-5 max(|xi|,1e-2) ratio {strict:.2f}; "
+             f"1e-5 max(|xi|,3e-2) ratio {floor:.2f}")
+        assert floor <= 1.0, k
+
+
+def test_autotuned_schedule_matches_default_cfg2():
+    """At 256^3 (no oracle run): the tuned schedule against the default one.
+    Each meets the oracle within 1e-5 max(|xi|, 1e-2) (the variant tests on
+    the small grids), so they agree within twice that."""
+    from paper_1705_03464_amd import Plan
+    wl = get_config("cfg2")
     cat = wl.catalog()
     w = dev(np.random.default_rng(5).uniform(0.5, 1.5, cat.n), torch.float32)
     plan = Plan.from_workload(wl, precision="fp32")
@@ -96,15 +155,14 @@ def test_autotuned_schedule_matches_default(name):
     default = plan.schedule()
     ref = {k: v.cpu().numpy() for k, v in plan.forward(w).items()}
     sched = plan.autotune()
-    _say(f"{name}: default {default} tuned {sched}")
+    _say(f"cfg2: default {default} tuned {sched}")
     assert plan.schedule() == sched
     assert 1 <= sched["batch"] <= 2 * default["batch"]
     out = {k: v.cpu().numpy() for k, v in plan.forward(w).items()}
     for k in ("xi_gg", "xi_pg"):
-        fin = np.isfinite(ref[k])
-        assert np.array_equal(fin, np.isfinite(out[k]))
-        d = np.abs(out[k][fin] - ref[k][fin])
-        assert np.all(d <= 1e-5 * np.maximum(np.abs(ref[k][fin]), 1e-2)), k
+        worst = _worst(out[k], ref[k], 2e-5)
+        _say(f"  {k}: worst {worst:.3f}")
+        assert worst <= 1.0, k
 
 
 def test_schedule_rejects_bad_values():
@@ -115,7 +173,8 @@ def test_schedule_rejects_bad_values():
     with pytest.raises(PgxError):
         plan.autotune()  # before the pair build
     plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
-    for bad in [(0, 0, 0, 0), (33, 0, 0, 0), (2, 2, 0, 0), (2, 0, -1, 0), (2, 0, 0, 5)]:
+    for bad in [(0, 0, 0, 0, 0), (33, 0, 0, 0, 0), (2, 2, 0, 0, 0), (2, 0, -1, 0, 0),
+                (2, 0, 0, 5, 0), (2, 0, 0, 0, 2)]:
         with pytest.raises(PgxError):
             plan.set_schedule(*bad)
 
@@ -136,7 +195,25 @@ def test_autotune_as_first_device_work_after_pair_build():
     _say(f"cfg2 tuned before any forward: {sched}")
     out = {k: v.cpu().numpy() for k, v in plan.forward().items()}
     for k in ("xi_gg", "xi_pg"):
-        fin = np.isfinite(ref[k])
-        assert np.array_equal(fin, np.isfinite(out[k]))
-        d = np.abs(out[k][fin] - ref[k][fin])
-        assert np.all(d <= 1e-5 * np.maximum(np.abs(ref[k][fin]), 1e-2)), k
+        assert _worst(out[k], ref[k], 2e-5) <= 1.0, k
+
+
+def test_dual_form_matches_per_field_path_at_512():
+    """The dual form against the per-field transforms on the full 512^3
+    production workload (the per-field path is held to the oracle at this size
+    by the sampled-field test)."""
+    from paper_1705_03464_amd import Plan
+    wl = get_config("cfg1")
+    cat = wl.catalog()
+    _say(f"cfg1 dual vs per-field: n_gal={cat.n}")
+    outs = []
+    for algo in (0, 1):
+        plan = Plan.from_workload(wl, precision="fp32")
+        plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
+        plan.set_schedule(8, 0, 0, 0, algo)
+        outs.append({k: v.cpu().numpy() for k, v in plan.forward().items()})
+        plan.close()
+    for k in ("xi_gg", "xi_pg"):
+        worst = _worst(outs[1][k], outs[0][k], 2e-5)
+        _say(f"  {k}: worst |d| / (2e-5 max(|xi|,1e-2)) = {worst:.3f}")
+        assert worst <= 1.0, k
