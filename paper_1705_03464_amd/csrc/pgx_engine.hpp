@@ -232,6 +232,10 @@ template <typename T, int N> struct Engine : EngineBase {
   // catalogue
   DBuf g_key, g_ls, g_x0, g_fx, g_fy, g_fz, g_idx, g_wt, g_tasks;
   DBuf p_key, p_ls, p_i, p_j, p_x0, p_fx, p_fy, p_fz, p_wt;
+  // line-major copy of the pair catalogue (all fields together): line starts,
+  // CIC corner and fractions, field, field-major index, weight (adjoint of the
+  // dual form)
+  DBuf l_ls, l_x0, l_fx, l_fy, l_fz, l_f, l_p, l_wt, dcoef;
   DBuf lflag, pflag, tasks;
   // scratch for the build
   DBuf s_tmp, s_k0, s_k1, s_v0, s_v1, s_cnt, s_off, s_px, s_py, s_pz, s_cell, s_cs, s_hist, s_err,
@@ -243,6 +247,8 @@ template <typename T, int N> struct Engine : EngineBase {
   DBuf SPEC;  // kept pair-field spectra, one N^3 grid per field pair
   DBuf gup, gw_out;  // adjoint: copies of the upstream gradients, weight gradient
   bool w_given = false;
+  // the last forward ran the dual form: its gathered values are in GV
+  bool fwd_dual = false;
 
   // room for the kept spectra: already allocated, or fits in free device
   // memory with 4 GiB to spare
@@ -496,6 +502,29 @@ template <typename T, int N> struct Engine : EngineBase {
     g_wt.get<T>(n);
     counts_to_starts(gks, n, NN, s_hist.get<int32_t>(NN + 1), g_ls.get<int32_t>(NN + 1), s);
 
+    // line-major copy of the pairs (stable sort of the field-major order by
+    // base line)
+    if constexpr (std::is_same<T, float>::value) {
+      int32_t* lk = s_k0.get<int32_t>(P);
+      int32_t* lks = s_i.get<int32_t>(P);
+      int32_t* lp = l_p.get<int32_t>(P);
+      if (P > 0) {
+        k_line_of<<<grid_for(P), 256, 0, s>>>(sk, P, NN, lk);
+        launch_check("line_of");
+      }
+      sort_pairs_i32(lk, lks, iota, lp, P, bits_for(NN), s, s_tmp);
+      gather(lp, p_x0.as<int32_t>(), l_x0.get<int32_t>(P), P, s);
+      gather(lp, p_fx.as<T>(), l_fx.get<T>(P), P, s);
+      gather(lp, p_fy.as<T>(), l_fy.get<T>(P), P, s);
+      gather(lp, p_fz.as<T>(), l_fz.get<T>(P), P, s);
+      int32_t* lf = l_f.get<int32_t>(P);
+      if (P > 0) {
+        k_field_of<<<grid_for(P), 256, 0, s>>>(lp, sk, P, NN, lf);
+        launch_check("field_of");
+      }
+      l_wt.get<T>(P);
+      counts_to_starts(lks, P, NN, s_hist.get<int32_t>(NN + 1), l_ls.get<int32_t>(NN + 1), s);
+    }
     // non-empty lines of every field pair and the x-pass task lists
     if constexpr (std::is_same<T, float>::value) {
       const int64_t nfl = (int64_t)cfg.n_fp * NN;
@@ -522,7 +551,8 @@ template <typename T, int N> struct Engine : EngineBase {
     fpr.insert(fpr.end(), batch_task_off.begin(), batch_task_off.end());
     fpr.insert(fpr.end(), field_counts_h.begin(), field_counts_h.end());
     for (const DBuf* d : {&g_key, &g_ls, &g_x0, &g_fx, &g_fy, &g_fz, &g_idx, &g_wt, &g_tasks, &p_key,
-                          &p_ls, &p_i, &p_j, &p_x0, &p_fx, &p_fy, &p_fz, &p_wt, &lflag, &pflag, &tasks})
+                          &p_ls, &p_i, &p_j, &p_x0, &p_fx, &p_fy, &p_fz, &p_wt, &lflag, &pflag, &tasks, &l_ls, &l_x0, &l_fx,
+                          &l_fy, &l_fz, &l_f, &l_p, &l_wt})
       fpr.push_back((int64_t)(intptr_t)d->p);
     if (fpr != build_print) {
       build_print = fpr;
@@ -763,6 +793,10 @@ template <typename T, int N> struct Engine : EngineBase {
     return PointSet<T>{p_ls.as<int32_t>(), p_x0.as<int32_t>(), p_fx.as<T>(), p_fy.as<T>(),
                        p_fz.as<T>(), p_wt.as<T>()};
   }
+  PointSet<T> line_set() const {
+    return PointSet<T>{l_ls.as<int32_t>(), l_x0.as<int32_t>(), l_fx.as<T>(), l_fy.as<T>(),
+                       l_fz.as<T>(), l_wt.as<T>()};
+  }
 
   void finalize(hipStream_t s, double* xi_gg, double* xi_pg, double* xi_dp, double* b_pg,
                 double* q_eff, double* wsum) {
@@ -828,6 +862,7 @@ template <typename T, int N> struct Engine : EngineBase {
         forward_plain(st);
     });
     spectra_valid = spec != nullptr;
+    fwd_dual = std::is_same<T, float>::value && algo == 1;
     finalize(s, xi_gg, xi_pg, xi_dp, b_pg, q_eff, wsum);
     forward_done = true;
   }
@@ -847,7 +882,7 @@ template <typename T, int N> struct Engine : EngineBase {
       const int64_t len[5] = {(int64_t)F * R, (int64_t)F * R, (int64_t)F * R, R, F};
       double* up = gup.get<double>(3 * (int64_t)F * R + R + F);
       const double* cp[5];
-      int flags = (spectra_valid ? 1 : 0) | (w_given ? 2 : 0);
+      int flags = (spectra_valid ? 1 : 0) | (w_given ? 2 : 0) | (fwd_dual ? 256 : 0);
       double* dst = up;
       for (int i = 0; i < 5; ++i) {
         cp[i] = src[i] ? dst : nullptr;
@@ -933,64 +968,68 @@ template <typename T, int N> struct Engine : EngineBase {
       k_zinit<T, Sh, W><<<dim3(N / W, N, 1), NT, 0, s>>>(ky, pwz(), fg, A, twp);
       launch_check("zinit");
     });
-    for (int k = 0; k < n_batches; ++k) {
-      const int nb = std::min(B, cfg.n_fp - k * B);
-      const int64_t t0 = batch_task_off[k], nt = batch_task_off[k + 1] - t0;
-      const int32_t* fa = slot_fa.as<int32_t>() + (int64_t)k * B;
-      const int32_t* fb = slot_fb.as<int32_t>() + (int64_t)k * B;
-      const int32_t* fp = slot_fp.as<int32_t>() + (int64_t)k * B;
-      const double pts = (double)batch_points(k) * (4 + 4 * sizeof(T));
-      prof.run("bwd_kgen", s, (double)nb * kx_slot * cb, [&] {
-        k_kgen_x<T, Sh, WX><<<dim3(nblkK, 1, nb), NTX, 0, s>>>(aa.apg, R, fa, fb, pwx(), pwy(),
-                                                                pwz(), bm, kx, kx_slot, twp,
-                                                                FSC.as<float>());
-        launch_check("kgen");
-      });
-      prof.run("bwd_kgen_y", s, (double)nb * (kx_slot + ky_slot) * cb, [&] {
-        k_strided<T, Sh, W, -1, IN_WINDOW, OUT_DENSE><<<dim3(N / W, nz, nb), NT, 0, s>>>(
-            kx, ky, kx_slot, ky_slot, (int64_t)ny * N, NN, N, N, pwy(), nullptr, nullptr, 0,
-            nullptr, twp);
-        launch_check("kgen_y");
-      });
-      if (spectra_valid) {
-        // Z from the spectra the forward kept: no scatter, y pass or forward z
-        prof.run("bwd_zpass", s,
-                 (double)nb * (2.0 * NC + ky_slot) * cb + 3.0 * NC * cb, [&] {
-          k_zback<T, Sh, W, true><<<dim3(N / W, N, 1), NT, 0, s>>>(
-              x, NC, pflag.as<uint8_t>(), fp, nb, ky, ky_slot, pwz(), fg, A, twp, SPEC.as<C<T>>());
-          launch_check("zback(kept)");
+    if (fwd_dual) {
+      backward_dual_pairs(s, aa.apg, kx, ky, x, A, gb, twp, bm);
+    } else {
+      for (int k = 0; k < n_batches; ++k) {
+        const int nb = std::min(B, cfg.n_fp - k * B);
+        const int64_t t0 = batch_task_off[k], nt = batch_task_off[k + 1] - t0;
+        const int32_t* fa = slot_fa.as<int32_t>() + (int64_t)k * B;
+        const int32_t* fb = slot_fb.as<int32_t>() + (int64_t)k * B;
+        const int32_t* fp = slot_fp.as<int32_t>() + (int64_t)k * B;
+        const double pts = (double)batch_points(k) * (4 + 4 * sizeof(T));
+        prof.run("bwd_kgen", s, (double)nb * kx_slot * cb, [&] {
+          k_kgen_x<T, Sh, WX><<<dim3(nblkK, 1, nb), NTX, 0, s>>>(aa.apg, R, fa, fb, pwx(), pwy(),
+                                                                  pwz(), bm, kx, kx_slot, twp,
+                                                                  FSC.as<float>());
+          launch_check("kgen");
         });
-      } else {
-        if (nt > 0) {
-          prof.run("bwd_xscatter", s, pts + (double)nt * N * cb, [&] {
-            k_xscatter<T, Sh, WX><<<(int)((nt + WX - 1) / WX), NTX, 0, s>>>(
-                tasks.as<int32_t>() + t0, (int)nt, pair_set(), fa, fb, x, twp, FSC.as<float>());
-            launch_check("xscatter(bwd)");
+        prof.run("bwd_kgen_y", s, (double)nb * (kx_slot + ky_slot) * cb, [&] {
+          k_strided<T, Sh, W, -1, IN_WINDOW, OUT_DENSE><<<dim3(N / W, nz, nb), NT, 0, s>>>(
+              kx, ky, kx_slot, ky_slot, (int64_t)ny * N, NN, N, N, pwy(), nullptr, nullptr, 0,
+              nullptr, twp);
+          launch_check("kgen_y");
+        });
+        if (spectra_valid) {
+          // Z from the spectra the forward kept: no scatter, y pass or forward z
+          prof.run("bwd_zpass", s,
+                   (double)nb * (2.0 * NC + ky_slot) * cb + 3.0 * NC * cb, [&] {
+            k_zback<T, Sh, W, true><<<dim3(N / W, N, 1), NT, 0, s>>>(
+                x, NC, pflag.as<uint8_t>(), fp, nb, ky, ky_slot, pwz(), fg, A, twp, SPEC.as<C<T>>());
+            launch_check("zback(kept)");
+          });
+        } else {
+          if (nt > 0) {
+            prof.run("bwd_xscatter", s, pts + (double)nt * N * cb, [&] {
+              k_xscatter<T, Sh, WX><<<(int)((nt + WX - 1) / WX), NTX, 0, s>>>(
+                  tasks.as<int32_t>() + t0, (int)nt, pair_set(), fa, fb, x, twp, FSC.as<float>());
+              launch_check("xscatter(bwd)");
+            });
+          }
+          prof.run("bwd_ypass", s, (double)nt * N * cb + (double)nb * NC * cb, [&] {
+            ypass_launch(v_ypass, x, nb, fp, s);
+            launch_check("ypass(bwd)");
+          });
+          prof.run("bwd_zpass", s,
+                   (double)nb * (2.0 * NC + ky_slot) * cb + 3.0 * NC * cb, [&] {
+            k_zback<T, Sh, W><<<dim3(N / W, N, 1), NT, 0, s>>>(x, NC, pflag.as<uint8_t>(), fp, nb, ky,
+                                                                ky_slot, pwz(), fg, A, twp);
+            launch_check("zback");
           });
         }
-        prof.run("bwd_ypass", s, (double)nt * N * cb + (double)nb * NC * cb, [&] {
-          ypass_launch(v_ypass, x, nb, fp, s);
-          launch_check("ypass(bwd)");
+        prof.run("bwd_yinv", s, (double)nb * NC * cb + (double)nt * N * cb, [&] {
+          k_strided<T, Sh, W, 1, IN_DENSE, OUT_FLAGS><<<dim3(N / W, N, nb), NT, 0, s>>>(
+              x, x, NC, NC, NN, NN, N, N, 0, lflag.as<uint8_t>(), pflag.as<uint8_t>(), NN, fp, twp);
+          launch_check("yinv(bwd)");
         });
-        prof.run("bwd_zpass", s,
-                 (double)nb * (2.0 * NC + ky_slot) * cb + 3.0 * NC * cb, [&] {
-          k_zback<T, Sh, W><<<dim3(N / W, N, 1), NT, 0, s>>>(x, NC, pflag.as<uint8_t>(), fp, nb, ky,
-                                                              ky_slot, pwz(), fg, A, twp);
-          launch_check("zback");
-        });
-      }
-      prof.run("bwd_yinv", s, (double)nb * NC * cb + (double)nt * N * cb, [&] {
-        k_strided<T, Sh, W, 1, IN_DENSE, OUT_FLAGS><<<dim3(N / W, N, nb), NT, 0, s>>>(
-            x, x, NC, NC, NN, NN, N, N, 0, lflag.as<uint8_t>(), pflag.as<uint8_t>(), NN, fp, twp);
-        launch_check("yinv(bwd)");
-      });
-      if (nt > 0) {
-        prof.run("bwd_xgather", s, pts + (double)nt * N * cb, [&] {
-          k_xgather<T, Sh, WX><<<(int)((nt + WX - 1) / WX), NTX, 0, s>>>(
-              tasks.as<int32_t>() + t0, (int)nt, pair_set(), fa, fb, x, (T)1, gb, twp,
-              FSC.as<float>());
-          launch_check("xgather");
-        });
+        if (nt > 0) {
+          prof.run("bwd_xgather", s, pts + (double)nt * N * cb, [&] {
+            k_xgather<T, Sh, WX><<<(int)((nt + WX - 1) / WX), NTX, 0, s>>>(
+                tasks.as<int32_t>() + t0, (int)nt, pair_set(), fa, fb, x, (T)1, gb, twp,
+                FSC.as<float>());
+            launch_check("xgather");
+          });
+        }
       }
     }
     // galaxy side: dL/drho_g = 2 Re IDFT(A) with A(0) removed
@@ -1021,6 +1060,58 @@ template <typename T, int N> struct Engine : EngineBase {
       k_gal_grad<<<grid_for(n_gal), 256, 0, s>>>(g_idx.as<int32_t>(), gbg, n_gal, aa.gwg, gd);
       k_grad_out<<<grid_for(n_gal), 256, 0, s>>>(gd, n_gal, grad_w);
       launch_check("grad_out");
+    }
+  }
+
+  // Pair-field part of the adjoint after a dual-form forward (see
+  // pgx_dual.hpp): the pair side from the values the forward gathered, the
+  // galaxy side through the per-bin pair fields, accumulated into A.
+  void backward_dual_pairs(hipStream_t s, const double* apg, C<T>* kx, C<T>* ky, C<T>* x, C<T>* A,
+                           float* gb, const C<T>* twp, const BinMap& bm) {
+    const int R = cfg.R, F = cfg.F, Q = (R + 1) / 2;
+    if (n_pairs == 0) return;
+    const int ny = win_len(pwy()), nz = win_len(pwz());
+    const int nblkK = (ny * nz + WX - 1) / WX;
+    const int64_t kx_slot = (int64_t)nz * ny * N, ky_slot = (int64_t)nz * NN;
+    const double cb = (double)sizeof(C<T>);
+    float2* cf = dcoef.get<float2>((int64_t)Q * F);
+    k_dual_coef<<<grid_for((int64_t)Q * F), 256, 0, s>>>(apg, F, R, bscale.as<float>(), Q, cf);
+    launch_check("dual_coef");
+    prof.run("bwd_dual_pairs", s, (double)n_pairs * (8.0 + 4.0 * R), [&] {
+      k_dual_pair_grad<<<grid_for(n_pairs), 256, 0, s>>>(p_key.as<int32_t>(), n_pairs, NN, apg, R,
+                                                         GV.as<float>(), bscale.as<float>(), gb);
+      launch_check("dual_pair_grad");
+    });
+    gather(l_p.as<int32_t>(), p_wt.as<T>(), l_wt.as<T>(), n_pairs, s);
+    const double pts = (double)n_pairs * (12.0 + 4.0 * sizeof(T)) + (double)NN * 4.0;
+    for (int q0 = 0; q0 < Q; q0 += B) {
+      const int nq = std::min(B, Q - q0);
+      prof.run("bwd_dual_kgen", s, (double)nq * kx_slot * cb, [&] {
+        k_kgen_x<T, Sh, WX><<<dim3(nblkK, 1, nq), NTX, 0, s>>>(
+            coef_id.as<double>(), R, bfa.as<int32_t>() + q0, bfb.as<int32_t>() + q0, pwx(), pwy(),
+            pwz(), bm, kx, kx_slot, twp);
+        launch_check("kgen(dual adjoint)");
+      });
+      prof.run("bwd_dual_kgen_y", s, (double)nq * (kx_slot + ky_slot) * cb, [&] {
+        k_strided<T, Sh, W, -1, IN_WINDOW, OUT_DENSE><<<dim3(N / W, nz, nq), NT, 0, s>>>(
+            kx, ky, kx_slot, ky_slot, (int64_t)ny * N, NN, N, N, pwy(), nullptr, nullptr, 0,
+            nullptr, twp);
+        launch_check("kgen_y(dual adjoint)");
+      });
+      prof.run("bwd_dual_xscatter", s, (double)nq * ((double)NC * cb + pts), [&] {
+        k_xscatter_dual<T, Sh, WX><<<dim3((int)(NN / WX), 1, nq), NTX, 0, s>>>(
+            line_set(), l_f.as<int32_t>(), cf, F, q0, x, NC, twp);
+        launch_check("xscatter(dual adjoint)");
+      });
+      prof.run("bwd_dual_ypass", s, 2.0 * nq * NC * cb, [&] {
+        k_strided<T, Sh, W, -1, IN_DENSE, OUT_DENSE><<<dim3(N / W, N, nq), NT, 0, s>>>(
+            x, x, NC, NC, NN, NN, N, N, 0, nullptr, nullptr, 0, nullptr, twp);
+        launch_check("ypass(dual adjoint)");
+      });
+      prof.run("bwd_dual_zacc", s, (double)nq * (NC + ky_slot) * cb + 2.0 * NC * cb, [&] {
+        k_zdual_acc<T, Sh, W><<<dim3(N / W, N, 1), NT, 0, s>>>(x, NC, nq, ky, ky_slot, pwz(), A, twp);
+        launch_check("zacc(dual adjoint)");
+      });
     }
   }
 

@@ -44,24 +44,26 @@ def eager_work():
     return float(y)
 
 
-def make(wl, cat, graphs, keep=False):
+def make(wl, cat, graphs, keep=False, algo=0):
     from paper_1705_03464_amd import Plan
     plan = Plan.from_workload(wl, precision="fp32", batch=2)
     plan.use_graphs(graphs)
     plan.keep_spectra(keep)
     plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
+    plan.set_schedule(2, 0, 0, 0, algo)
     return plan
 
 
+@pytest.mark.parametrize("algo", [0, 1])
 @pytest.mark.parametrize("name", ["cfg4tiny", "cfg2"])
-def test_forward_graph_replays_match_eager(name):
+def test_forward_graph_replays_match_eager(name, algo):
     wl = get_config(name)
     cat = wl.catalog()
     _say(f"{name}: n_gal={cat.n} N={wl.N}")
     w = dev(np.random.default_rng(11).uniform(0.5, 1.5, cat.n), torch.float32)
-    pe = make(wl, cat, graphs=False)
+    pe = make(wl, cat, graphs=False, algo=algo)
     ref = {k: v.cpu().numpy() for k, v in pe.forward(w).items()}
-    pg = make(wl, cat, graphs=True)
+    pg = make(wl, cat, graphs=True, algo=algo)
     for i in range(4):
         out = {k: v.cpu().numpy() for k, v in pg.forward(w).items()}
         eager_work()
@@ -73,8 +75,8 @@ def test_forward_graph_replays_match_eager(name):
     assert pe.graph_replays() == (0, 0)
 
 
-@pytest.mark.parametrize("keep", [False, True])
-def test_adjoint_graph_replays_match_eager(keep):
+@pytest.mark.parametrize("keep,algo", [(False, 0), (True, 0), (False, 1)])
+def test_adjoint_graph_replays_match_eager(keep, algo):
     wl = get_config("cfg4tiny")
     cat = wl.catalog()
     rng = np.random.default_rng(12)
@@ -86,8 +88,8 @@ def test_adjoint_graph_replays_match_eager(keep):
         plan.forward(w)
         return plan.backward(g_xi_pg=g_xipg, g_xi_gg=g_xigg).cpu().numpy().astype(np.float64)
 
-    ref = run(make(wl, cat, graphs=False, keep=keep))
-    pg = make(wl, cat, graphs=True, keep=keep)
+    ref = run(make(wl, cat, graphs=False, keep=keep, algo=algo))
+    pg = make(wl, cat, graphs=True, keep=keep, algo=algo)
     for i in range(4):
         gw = run(pg)
         eager_work()
