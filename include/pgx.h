@@ -194,16 +194,18 @@ pgx_status pgx_keep_spectra(pgx_plan* plan, int32_t enable);
  * bpg_final: one transform per pair of output bins, the bin kernel convolved
  * with the galaxy field, interpolated at every pair midpoint; the same
  * estimator exactly, up to floating-point rounding) when its per-pair values
- * (n_pairs x n_out FP32) fit in half the free device memory.  It keeps the
- * fastest combination for later calls.  Results differ between schedules
- * only by floating-point rounding.  It runs the forward eagerly several times
- * (about twelve forward passes' worth of device time), discards the state of
+ * (n_pairs x n_out FP32) fit in half the free device memory, with its two z
+ * passes in tiles of the default width or half of it.  It keeps the fastest
+ * combination for later calls.  Results differ between schedules only by
+ * floating-point rounding.  It runs the forward eagerly several times
+ * (about sixteen forward passes' worth of device time), discards the state of
  * the last pgx_forward (a pgx_backward must follow a new pgx_forward), clears
  * the kernel-timing counters and invalidates the launch graphs.
  *   schedule: host int32[5] out (nullable): field pairs (or bin pairs) per
  *   batch, forward y-pass variant, inverse y-pass variant, z-pass variant
- *   (0 = default), algorithm (0 = one transform per field pair, 1 = dual
- *   form).  The adjoint is the same for both algorithms.
+ *   (0 = default; for the dual form: 1 = half-width z-pass tiles), algorithm
+ *   (0 = one transform per field pair, 1 = dual form).  pgx_backward runs
+ *   the adjoint of the algorithm the preceding pgx_forward used.
  * Errors: ESTATE before pgx_pairs_build; ENOTSUP on FP64 plans.
  */
 pgx_status pgx_autotune(pgx_plan* plan, void* stream, int32_t* schedule);

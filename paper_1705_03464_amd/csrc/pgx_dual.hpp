@@ -28,6 +28,8 @@
 // field: a second, line-major copy of the pair catalogue.
 #pragma once
 
+#include <climits>
+
 #include "pgx_kernels.hpp"
 
 namespace pgx {
@@ -35,7 +37,10 @@ namespace pgx {
 // z pass of the dual form.  Tile (xt, ky); for each slot (pair of bins): the
 // forward z transform of the kernel columns (only the window planes
 // pe = (z + pwz) mod N <= 2 pwz are present), times G, inverse z transform,
-// stored dense.
+// stored dense.  Slot pipeline as in the forward cross-power pass: the next
+// slot's kernel columns are loaded into the idle register set at the top of
+// each trip, so the wait for them does not include the current slot's
+// stores.
 template <typename T, typename Sh, int W>
 static __global__ void __launch_bounds__(W * Sh::TPL)
 k_zconv(const C<T>* __restrict__ ky_in, int64_t ky_slot, int n_slots, int pwz,
@@ -43,6 +48,7 @@ k_zconv(const C<T>* __restrict__ ky_in, int64_t ky_slot, int n_slots, int pwz,
         const C<T>* __restrict__ tw_g) {
   constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>();
   constexpr int64_t NN = (int64_t)N * N;
+  constexpr bool PIPE = E <= 8;
   __shared__ C<T> tw_s[tw_lds_entries<Sh, kZTwReg>()];
   __shared__ C<T> lines[W][LL];
   const int xt = blockIdx.x, ky = blockIdx.y;
@@ -55,31 +61,36 @@ k_zconv(const C<T>* __restrict__ ky_in, int64_t ky_slot, int n_slots, int pwz,
   constexpr uint32_t ZST = BUF ? (uint32_t)(TPL * NN * CB) : 0u;
   const int64_t tile = (int64_t)ky * N + xt * W;
   const uint32_t vo = (uint32_t)((c + (int64_t)t * NN) * CB);
-  C<T> g[E];
-#pragma unroll
-  for (int m = 0; m < E; ++m) {
-    if constexpr (BUF) g[m] = Buf<T>(fg + tile).load(vo, (uint32_t)m * ZST);
-    else g[m] = fg[col + (int64_t)(t + TPL * m) * NN];
-  }
-  for (int slot = 0; slot < n_slots; ++slot) {
-    C<T> v[E];
+  // kernel columns of one slot; planes outside the window, and every plane
+  // when `take` is false, are zero
+  auto load_k = [&](int slot, bool take, C<T>* k) {
     if constexpr (BUF) {
       const Buf<T> bk(ky_in + slot * ky_slot + tile);
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const int pe = (t + TPL * m + pwz) & (N - 1);
-        v[m] = bk.load(pe <= 2 * pwz ? (uint32_t)((c + (int64_t)pe * NN) * CB) : kBufOff, 0u);
+        k[m] = bk.load(take && pe <= 2 * pwz ? (uint32_t)((c + (int64_t)pe * NN) * CB) : kBufOff, 0u);
       }
     } else {
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const int pe = (t + TPL * m + pwz) & (N - 1);
-        const bool ok = pe <= 2 * pwz;
+        const bool ok = take && pe <= 2 * pwz;
         const C<T> b = ky_in[slot * ky_slot + col + (ok ? (int64_t)pe * NN : (int64_t)0)];
-        v[m].x = ok ? b.x : (T)0;
-        v[m].y = ok ? b.y : (T)0;
+        k[m].x = ok ? b.x : (T)0;
+        k[m].y = ok ? b.y : (T)0;
       }
     }
+  };
+  C<T> ka[E], kb[PIPE ? E : 1], g[E];
+  load_k(0, true, ka);
+  // G after the first columns (the same wait on entry as on later trips)
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    if constexpr (BUF) g[m] = Buf<T>(fg + tile).load(vo, (uint32_t)m * ZST);
+    else g[m] = fg[col + (int64_t)(t + TPL * m) * NN];
+  }
+  auto body = [&](int slot, C<T>* v) {
     block_sync();
     twa.template fft<-1>(v, t, lines[c]);
 #pragma unroll
@@ -94,6 +105,31 @@ k_zconv(const C<T>* __restrict__ ky_in, int64_t ky_slot, int n_slots, int pwz,
       C<T>* dst = out + slot * out_slot + col;
 #pragma unroll
       for (int m = 0; m < E; ++m) dst[(int64_t)(t + TPL * m) * NN] = v[m];
+    }
+  };
+  if constexpr (PIPE) {
+    auto trip = [&](int slot, const C<T>* cur, C<T>* nxt) {
+      const bool more = slot + 1 < n_slots;
+      load_k(more ? slot + 1 : slot, more, nxt);
+      __builtin_amdgcn_sched_barrier(0);
+      C<T> v[E];
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = cur[m];
+      body(slot, v);
+    };
+    int slot = 0;
+    for (; slot + 1 < n_slots; slot += 2) {
+      trip(slot, ka, kb);
+      trip(slot + 1, kb, ka);
+    }
+    if (slot < n_slots) trip(slot, ka, kb);
+  } else {
+    for (int slot = 0; slot < n_slots; ++slot) {
+      if (slot > 0) load_k(slot, true, ka);
+      C<T> v[E];
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = ka[m];
+      body(slot, v);
     }
   }
 }
@@ -160,11 +196,18 @@ static __global__ void k_dual_reduce(const int32_t* __restrict__ line_start, int
 // ----------------------------------------------------------------------------
 // Adjoint of the dual form
 // ----------------------------------------------------------------------------
-// line-major order of the pair catalogue: base line of each pair (sort key)
-static __global__ void k_line_of(const int32_t* __restrict__ key, int64_t P, int64_t nn,
-                                 int32_t* __restrict__ out) {
+// line-major order of the pair catalogue: sort key (base line, x0) of each
+// pair, so that within a base line the points run in x order
+static __global__ void k_line_x_key(const int32_t* __restrict__ key, const int32_t* __restrict__ x0,
+                                    int64_t P, int64_t nn, int n, int32_t* __restrict__ out) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < P) out[p] = (int32_t)(key[p] % nn);
+  if (p < P) out[p] = (int32_t)((key[p] % nn) * n + x0[p]);
+}
+// base line of a sorted (line, x0) key
+static __global__ void k_key_line(const int32_t* __restrict__ k, int64_t P, int n,
+                                  int32_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < P) out[i] = k[i] / n;
 }
 // field of each pair in line-major order (lp: line-major -> field-major index)
 static __global__ void k_field_of(const int32_t* __restrict__ lp, const int32_t* __restrict__ key,
@@ -204,16 +247,114 @@ static __global__ void k_dual_pair_grad(const int32_t* __restrict__ key, int64_t
   acc[p] = (float)s;
 }
 
-// x pass of the Pi fields with the CIC scatter fused in.  Block = W whole
-// lines (all N*N lines of every slot are written: zero lines transform to
-// zero); slot = blockIdx.z, bins (2(q0+slot), 2(q0+slot)+1).  The line is
-// built in LDS from the points of the four base lines whose CIC footprint
-// reaches it, each point weighted by its pair weight and its field's
-// coefficient pair, then transformed along x.
+// The points whose CIC footprint reaches line (y, z): those of the four base
+// lines (y, z), (y-1, z), (y, z-1), (y-1, z-1), taken as one index range
+// (range q = base line q, whose y / z weight is the upper one when bit 0 /
+// bit 1 of q is set).
+struct LineRanges {
+  int o1, o2, o3, n, d0, d1, d2, d3;
+  template <typename T>
+  __device__ __forceinline__ void init(const PointSet<T>& ps, int y, int z, int N) {
+    const int ym = (y - 1) & (N - 1), zm = (z - 1) & (N - 1);
+    const int k0 = z * N + y, k1 = z * N + ym, k2 = zm * N + y, k3 = zm * N + ym;
+    const int s0 = ps.line_start[k0], e0 = ps.line_start[k0 + 1];
+    const int s1 = ps.line_start[k1], e1 = ps.line_start[k1 + 1];
+    const int s2 = ps.line_start[k2], e2 = ps.line_start[k2 + 1];
+    const int s3 = ps.line_start[k3], e3 = ps.line_start[k3 + 1];
+    o1 = e0 - s0;
+    o2 = o1 + (e1 - s1);
+    o3 = o2 + (e2 - s2);
+    n = o3 + (e3 - s3);
+    d0 = s0;
+    d1 = s1 - o1;
+    d2 = s2 - o2;
+    d3 = s3 - o3;
+  }
+  // range and point of combined index i < n
+  __device__ __forceinline__ int range(int i) const { return (i >= o1) + (i >= o2) + (i >= o3); }
+  __device__ __forceinline__ int point(int i, int q) const {
+    return i + (q == 0 ? d0 : q == 1 ? d1 : q == 2 ? d2 : d3);
+  }
+};
+
+// CIC weights of point p on a line of its range q: the two x nodes
+// (x0, x0 + 1) get w * (1 - fx) and w * fx, w = weight * y weight * z weight.
+template <typename T>
+__device__ __forceinline__ void cic_on_line(const PointSet<T>& ps, int p, int q, T& wa, T& wb,
+                                            int& x0) {
+  const T fy = ps.fy[p], fz = ps.fz[p], fx = ps.fx[p];
+  const T wy = (q & 1) ? fy : (T)1 - fy;
+  const T wz = (q & 2) ? fz : (T)1 - fz;
+  const T w = (ps.wt ? ps.wt[p] : (T)1) * wy * wz;
+  wa = w * ((T)1 - fx);
+  wb = w * fx;
+  x0 = ps.x0[p];
+}
+
+// Segmented inclusive sums over one wavefront (64 lanes, lane = threadIdx.x
+// mod 64) whose keys ascend, so that equal keys form contiguous runs: after
+// add(v), each lane holds the sum of v over the lanes of its run up to and
+// including itself; `tail` marks the last lane of each run.  In-row steps
+// use DPP row shifts (1, 2, 4, 8 lanes within rows of 16), then the running
+// sums are carried across rows from lanes 15, 31 and 47 in turn (the usual
+// wavefront scan); every step adds only where the source lane has the same
+// key.  All 64 lanes must take part.
+struct WaveRuns {
+  uint32_t m;
+  bool tail;
+  __device__ __forceinline__ void init(int key) {
+    const int lane = (int)(threadIdx.x & 63u);
+    const int k1 = __builtin_amdgcn_update_dpp(INT_MIN, key, 0x111, 0xF, 0xF, false);
+    const int k2 = __builtin_amdgcn_update_dpp(INT_MIN, key, 0x112, 0xF, 0xF, false);
+    const int k4 = __builtin_amdgcn_update_dpp(INT_MIN, key, 0x114, 0xF, 0xF, false);
+    const int k8 = __builtin_amdgcn_update_dpp(INT_MIN, key, 0x118, 0xF, 0xF, false);
+    const int k15 = __builtin_amdgcn_readlane(key, 15);
+    const int k31 = __builtin_amdgcn_readlane(key, 31);
+    const int k47 = __builtin_amdgcn_readlane(key, 47);
+    const int row = lane >> 4;
+    m = (uint32_t)(k1 == key) | ((uint32_t)(k2 == key) << 1) | ((uint32_t)(k4 == key) << 2) |
+        ((uint32_t)(k8 == key) << 3) | ((uint32_t)(row == 1 && key == k15) << 4) |
+        ((uint32_t)(row == 2 && key == k31) << 5) | ((uint32_t)(row == 3 && key == k47) << 6);
+    const int next = __builtin_amdgcn_ds_bpermute(((lane + 1) & 63) << 2, key);
+    tail = lane == 63 || next != key;
+  }
+  __device__ __forceinline__ float add(float v) const {
+    int b = __builtin_bit_cast(int, v);
+    float s;
+    s = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, b, 0x111, 0xF, 0xF, false));
+    v += (m & 1u) ? s : 0.f;
+    b = __builtin_bit_cast(int, v);
+    s = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, b, 0x112, 0xF, 0xF, false));
+    v += (m & 2u) ? s : 0.f;
+    b = __builtin_bit_cast(int, v);
+    s = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, b, 0x114, 0xF, 0xF, false));
+    v += (m & 4u) ? s : 0.f;
+    b = __builtin_bit_cast(int, v);
+    s = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, b, 0x118, 0xF, 0xF, false));
+    v += (m & 8u) ? s : 0.f;
+    s = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 15));
+    v += (m & 16u) ? s : 0.f;
+    s = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 31));
+    v += (m & 32u) ? s : 0.f;
+    s = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 47));
+    v += (m & 64u) ? s : 0.f;
+    return v;
+  }
+};
+
+// x pass of the Pi fields with the CIC scatter fused in.  Block = W lines
+// (y, z), each for every slot of the batch in turn (bins 2(q0+slot),
+// 2(q0+slot)+1): the line is built in LDS from the points whose CIC
+// footprint reaches it, each weighted by its pair weight and its field's
+// coefficient pair, transformed along x and written.  The first point of
+// every thread (most lines have at most TPL points) stays in registers
+// across the slots, with its coefficients for the next slot loaded one slot
+// ahead; further points of crowded lines are read again per slot.  Every one
+// of the N*N lines is written (zero lines transform to zero).
 template <typename T, typename Sh, int W>
 static __global__ void __launch_bounds__(W * Sh::TPL)
 k_xscatter_dual(PointSet<T> ps, const int32_t* __restrict__ lfield, const float2* __restrict__ coef,
-                int F, int q0, C<T>* __restrict__ out, int64_t out_slot,
+                int F, int q0, int nq, C<T>* __restrict__ out, int64_t out_slot,
                 const C<T>* __restrict__ tw_g) {
   constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>();
   __shared__ C<T> tw_s[Sh::tw_entries()];
@@ -221,49 +362,105 @@ k_xscatter_dual(PointSet<T> ps, const int32_t* __restrict__ lfield, const float2
   load_twiddles<T, Sh>(tw_s, tw_g);
   const int t = threadIdx.x % TPL, l = threadIdx.x / TPL;
   const int li = blockIdx.x * W + l;  // < N*N by the grid
-  const int slot = blockIdx.z;
-  const float2* cq = coef + (int64_t)(q0 + slot) * F;
-  C<T>* line = lines[l];
-#pragma unroll
-  for (int m = 0; m < E; ++m) line[lpad(t + TPL * m)] = C<T>{0, 0};
   const int y = li % N, z = li / N;
-  block_sync();
-  const int ym = (y - 1) & (N - 1), zm = (z - 1) & (N - 1);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int by = (q & 1) ? ym : y, bz = (q & 2) ? zm : z;
-    const int key = bz * N + by;
-    const int s = ps.line_start[key], e = ps.line_start[key + 1];
-    for (int p = s + t; p < e; p += TPL) {
-      const T fy = ps.fy[p], fz = ps.fz[p], fx = ps.fx[p];
-      const T wy = (q & 1) ? fy : (T)1 - fy;
-      const T wz = (q & 2) ? fz : (T)1 - fz;
-      const T w = ps.wt[p] * wy * wz;
-      const float2 c = cq[lfield[p]];
-      const T w0 = w * ((T)1 - fx), w1 = w * fx;
-      const int x0 = ps.x0[p];
-      C<T>* a0 = &line[lpad(x0)];
-      C<T>* a1 = &line[lpad((x0 + 1) & (N - 1))];
-      atomicAdd(&a0->x, w0 * (T)c.x);
-      atomicAdd(&a0->y, w0 * (T)c.y);
-      atomicAdd(&a1->x, w1 * (T)c.x);
-      atomicAdd(&a1->y, w1 * (T)c.y);
-    }
+  C<T>* line = lines[l];
+  LineRanges lr;
+  lr.init(ps, y, z, N);
+  const bool has0 = t < lr.n;
+  T wa0 = (T)0, wb0 = (T)0;
+  int xa0 = 0, f0 = 0;
+  if (has0) {
+    const int q = lr.range(t), p = lr.point(t, q);
+    cic_on_line(ps, p, q, wa0, wb0, xa0);
+    f0 = lfield[p];
   }
-  block_sync();
-  C<T> v[E];
+  const int xb0 = (xa0 + 1) & (N - 1);
+  // one line per wavefront: contributions of points on the same x node are
+  // summed across the wavefront first (the points of a base line run in x
+  // order), and only the last lane of each run adds to LDS
+  constexpr bool RUNS = TPL == 64 && std::is_same<T, float>::value;
+  WaveRuns r0;
+  if constexpr (RUNS) r0.init(has0 ? lr.range(t) * N + xa0 : 4 * N + t);
+  float2 cn = has0 ? coef[(int64_t)q0 * F + f0] : float2{0.f, 0.f};
+  for (int slot = 0; slot < nq; ++slot) {
+    const float2 c0 = cn;
+    if (has0 && slot + 1 < nq) cn = coef[(int64_t)(q0 + slot + 1) * F + f0];
+    if (slot > 0) block_sync();  // the previous slot's transform has left the LDS line
 #pragma unroll
-  for (int m = 0; m < E; ++m) v[m] = line[lpad(t + TPL * m)];
-  block_sync();
-  line_fft<Sh, -1>(v, t, line, tw_s, block_sync);
-  C<T>* o = out + (int64_t)slot * out_slot + (int64_t)li * N;
+    for (int m = 0; m < E; ++m) line[lpad(t + TPL * m)] = C<T>{0, 0};
+    block_sync();
+    const float2* cq = coef + (int64_t)(q0 + slot) * F;
+    if constexpr (RUNS) {
+      const T ax = r0.add(wa0 * (T)c0.x), ay = r0.add(wa0 * (T)c0.y);
+      const T bx = r0.add(wb0 * (T)c0.x), by = r0.add(wb0 * (T)c0.y);
+      if (has0 && r0.tail) {
+        atomicAdd(&line[lpad(xa0)].x, ax);
+        atomicAdd(&line[lpad(xa0)].y, ay);
+        atomicAdd(&line[lpad(xb0)].x, bx);
+        atomicAdd(&line[lpad(xb0)].y, by);
+      }
+      // crowded lines: further points, a wavefront-wide pass at a time
+      for (int base = TPL; base < lr.n; base += TPL) {
+        const int i = base + t;
+        const bool act = i < lr.n;
+        T wa = (T)0, wb = (T)0;
+        int xa = 0, q = 0;
+        float2 c = float2{0.f, 0.f};
+        if (act) {
+          q = lr.range(i);
+          const int p = lr.point(i, q);
+          cic_on_line(ps, p, q, wa, wb, xa);
+          c = cq[lfield[p]];
+        }
+        WaveRuns r;
+        r.init(act ? q * N + xa : 4 * N + t);
+        const T sx = r.add(wa * (T)c.x), sy = r.add(wa * (T)c.y);
+        const T tx = r.add(wb * (T)c.x), ty = r.add(wb * (T)c.y);
+        if (act && r.tail) {
+          const int xb = (xa + 1) & (N - 1);
+          atomicAdd(&line[lpad(xa)].x, sx);
+          atomicAdd(&line[lpad(xa)].y, sy);
+          atomicAdd(&line[lpad(xb)].x, tx);
+          atomicAdd(&line[lpad(xb)].y, ty);
+        }
+      }
+    } else {
+      if (has0) {
+        atomicAdd(&line[lpad(xa0)].x, wa0 * (T)c0.x);
+        atomicAdd(&line[lpad(xa0)].y, wa0 * (T)c0.y);
+        atomicAdd(&line[lpad(xb0)].x, wb0 * (T)c0.x);
+        atomicAdd(&line[lpad(xb0)].y, wb0 * (T)c0.y);
+      }
+      for (int i = t + TPL; i < lr.n; i += TPL) {
+        const int q = lr.range(i), p = lr.point(i, q);
+        T wa, wb;
+        int xa;
+        cic_on_line(ps, p, q, wa, wb, xa);
+        const float2 c = cq[lfield[p]];
+        const int xb = (xa + 1) & (N - 1);
+        atomicAdd(&line[lpad(xa)].x, wa * (T)c.x);
+        atomicAdd(&line[lpad(xa)].y, wa * (T)c.y);
+        atomicAdd(&line[lpad(xb)].x, wb * (T)c.x);
+        atomicAdd(&line[lpad(xb)].y, wb * (T)c.y);
+      }
+    }
+    block_sync();
+    C<T> v[E];
 #pragma unroll
-  for (int m = 0; m < E; ++m) o[t + TPL * m] = v[m];
+    for (int m = 0; m < E; ++m) v[m] = line[lpad(t + TPL * m)];
+    block_sync();
+    line_fft<Sh, -1>(v, t, line, tw_s, block_sync);
+    C<T>* o = out + (int64_t)slot * out_slot + (int64_t)li * N;
+#pragma unroll
+    for (int m = 0; m < E; ++m) o[t + TPL * m] = v[m];
+  }
 }
 
 // z pass of the galaxy-side adjoint.  Tile (xt, ky); for each slot: forward z
 // transform of the Pi columns (dense) and of the kernel columns (window
-// planes only), acc += Pi^ conj(K^) / 2; then A += acc.
+// planes only), acc += Pi^ conj(K^) / 2; then A += acc.  Slot pipeline: at
+// the top of each trip the current slot's kernel columns and the next slot's
+// Pi columns are issued, so both are in flight during the transforms.
 template <typename T, typename Sh, int W>
 static __global__ void __launch_bounds__(W * Sh::TPL)
 k_zdual_acc(const C<T>* __restrict__ x, int64_t x_slot, int n_slots,
@@ -271,6 +468,7 @@ k_zdual_acc(const C<T>* __restrict__ x, int64_t x_slot, int n_slots,
             const C<T>* __restrict__ tw_g) {
   constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>();
   constexpr int64_t NN = (int64_t)N * N;
+  constexpr bool PIPE = E <= 8;
   __shared__ C<T> tw_s[tw_lds_entries<Sh, kZTwReg>()];
   __shared__ C<T> lines[W][LL];
   const int xt = blockIdx.x, ky = blockIdx.y;
@@ -283,24 +481,34 @@ k_zdual_acc(const C<T>* __restrict__ x, int64_t x_slot, int n_slots,
   constexpr uint32_t ZST = BUF ? (uint32_t)(TPL * NN * CB) : 0u;
   const int64_t tile = (int64_t)ky * N + xt * W;
   const uint32_t vo = (uint32_t)((c + (int64_t)t * NN) * CB);
-  C<T> acc[E];
-#pragma unroll
-  for (int m = 0; m < E; ++m) acc[m] = C<T>{0, 0};
-  for (int slot = 0; slot < n_slots; ++slot) {
-    C<T> v[E], k[E];
+  // Pi columns of one slot (zero when `take` is false)
+  auto load_pi = [&](int slot, bool take, C<T>* v) {
     if constexpr (BUF) {
       const Buf<T> bi(x + slot * x_slot + tile);
+      const uint32_t kill = take ? 0u : kBufOff;
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = bi.load((vo + (uint32_t)m * ZST) | kill, 0u);
+    } else {
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const C<T> b = x[slot * x_slot + col + (int64_t)(t + TPL * m) * NN];
+        v[m].x = take ? b.x : (T)0;
+        v[m].y = take ? b.y : (T)0;
+      }
+    }
+  };
+  // kernel columns: only the window planes pe = (z + pwz) mod N <= 2 pwz
+  auto load_k = [&](int slot, C<T>* k) {
+    if constexpr (BUF) {
       const Buf<T> bk(ky_in + slot * ky_slot + tile);
 #pragma unroll
       for (int m = 0; m < E; ++m) {
-        v[m] = bi.load(vo, (uint32_t)m * ZST);
         const int pe = (t + TPL * m + pwz) & (N - 1);
         k[m] = bk.load(pe <= 2 * pwz ? (uint32_t)((c + (int64_t)pe * NN) * CB) : kBufOff, 0u);
       }
     } else {
 #pragma unroll
       for (int m = 0; m < E; ++m) {
-        v[m] = x[slot * x_slot + col + (int64_t)(t + TPL * m) * NN];
         const int pe = (t + TPL * m + pwz) & (N - 1);
         const bool ok = pe <= 2 * pwz;
         const C<T> b = ky_in[slot * ky_slot + col + (ok ? (int64_t)pe * NN : (int64_t)0)];
@@ -308,6 +516,11 @@ k_zdual_acc(const C<T>* __restrict__ x, int64_t x_slot, int n_slots,
         k[m].y = ok ? b.y : (T)0;
       }
     }
+  };
+  C<T> acc[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) acc[m] = C<T>{0, 0};
+  auto body = [&](C<T>* v, C<T>* k) {
     block_sync();
     twa.template fft<-1>(v, t, lines[c]);
     block_sync();
@@ -317,6 +530,34 @@ k_zdual_acc(const C<T>* __restrict__ x, int64_t x_slot, int n_slots,
       const C<T> pk = cmulc(v[m], k[m]);
       acc[m].x += (T)0.5 * pk.x;
       acc[m].y += (T)0.5 * pk.y;
+    }
+  };
+  C<T> pa[E], pb[PIPE ? E : 1];
+  load_pi(0, true, pa);
+  if constexpr (PIPE) {
+    auto trip = [&](int slot, const C<T>* cur, C<T>* nxt) {
+      const bool more = slot + 1 < n_slots;
+      C<T> k[E];
+      load_k(slot, k);
+      load_pi(more ? slot + 1 : slot, more, nxt);
+      __builtin_amdgcn_sched_barrier(0);
+      C<T> v[E];
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = cur[m];
+      body(v, k);
+    };
+    int slot = 0;
+    for (; slot + 1 < n_slots; slot += 2) {
+      trip(slot, pa, pb);
+      trip(slot + 1, pb, pa);
+    }
+    if (slot < n_slots) trip(slot, pa, pb);
+  } else {
+    for (int slot = 0; slot < n_slots; ++slot) {
+      if (slot > 0) load_pi(slot, true, pa);
+      C<T> k[E];
+      load_k(slot, k);
+      body(pa, k);
     }
   }
 #pragma unroll

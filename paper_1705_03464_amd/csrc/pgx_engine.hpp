@@ -200,6 +200,9 @@ template <typename T, int N> struct Engine : EngineBase {
   static constexpr int NT = W * TPL;
   static constexpr int WX = (256 / TPL) > 1 ? (256 / TPL) : 1;
   static constexpr int NTX = WX * TPL;
+  // dual form, z passes: tile width of the second variant (half the columns,
+  // so that two blocks share a compute unit)
+  static constexpr int WH = W / 2 >= 4 ? W / 2 : W;
   static constexpr int64_t NN = (int64_t)N * N;
   static constexpr int64_t NC = NN * N;
   // second radix schedule of the y passes (autotuner candidate)
@@ -217,7 +220,8 @@ template <typename T, int N> struct Engine : EngineBase {
   std::vector<int64_t> build_print;     // schedule and buffers of the last pair build
 
   // kernel variants picked by the autotuner (0 = default): forward y pass,
-  // inverse y pass (radix schedule), z pass (twiddle source)
+  // inverse y pass (radix schedule), z pass (twiddle source; for the dual
+  // form: tile width)
   int v_ypass = 0, v_yinv = 0, v_zpass = 0;
   // algorithm of the pair-field part of the forward: 0 = one transform per
   // field pair, 1 = dual form (one transform per pair of output bins, then a
@@ -503,16 +507,21 @@ template <typename T, int N> struct Engine : EngineBase {
     counts_to_starts(gks, n, NN, s_hist.get<int32_t>(NN + 1), g_ls.get<int32_t>(NN + 1), s);
 
     // line-major copy of the pairs (stable sort of the field-major order by
-    // base line)
+    // base line, then x node)
     if constexpr (std::is_same<T, float>::value) {
       int32_t* lk = s_k0.get<int32_t>(P);
       int32_t* lks = s_i.get<int32_t>(P);
+      int32_t* lln = s_j.get<int32_t>(P);
       int32_t* lp = l_p.get<int32_t>(P);
       if (P > 0) {
-        k_line_of<<<grid_for(P), 256, 0, s>>>(sk, P, NN, lk);
-        launch_check("line_of");
+        k_line_x_key<<<grid_for(P), 256, 0, s>>>(sk, p_x0.as<int32_t>(), P, NN, N, lk);
+        launch_check("line_x_key");
       }
-      sort_pairs_i32(lk, lks, iota, lp, P, bits_for(NN), s, s_tmp);
+      sort_pairs_i32(lk, lks, iota, lp, P, bits_for(NN * N), s, s_tmp);
+      if (P > 0) {
+        k_key_line<<<grid_for(P), 256, 0, s>>>(lks, P, N, lln);
+        launch_check("key_line");
+      }
       gather(lp, p_x0.as<int32_t>(), l_x0.get<int32_t>(P), P, s);
       gather(lp, p_fx.as<T>(), l_fx.get<T>(P), P, s);
       gather(lp, p_fy.as<T>(), l_fy.get<T>(P), P, s);
@@ -523,7 +532,7 @@ template <typename T, int N> struct Engine : EngineBase {
         launch_check("field_of");
       }
       l_wt.get<T>(P);
-      counts_to_starts(lks, P, NN, s_hist.get<int32_t>(NN + 1), l_ls.get<int32_t>(NN + 1), s);
+      counts_to_starts(lln, P, NN, s_hist.get<int32_t>(NN + 1), l_ls.get<int32_t>(NN + 1), s);
     }
     // non-empty lines of every field pair and the x-pass task lists
     if constexpr (std::is_same<T, float>::value) {
@@ -631,31 +640,39 @@ template <typename T, int N> struct Engine : EngineBase {
       }
       // the dual form (one transform per pair of output bins) at the chosen
       // batch size, when its gathered values fit
-      int best_algo = 0;
+      // (its z-pass variant is the tile width of its z passes)
+      int best_algo = 0, best_vz_dual = 0;
       algo = 0;
       if (dual_fits()) {
         schedule(best[0], s);
         algo = 1;
-        prof.reset();
-        prof.on = false;
-        weights(wl, s);
-        forward_batched(s, nullptr, wl);
-        prof.on = true;
-        weights(wl, s);
-        forward_batched(s, nullptr, wl);
-        prof.collect();
-        prof.on = false;
-        double ms = 0;
-        for (const auto& c : prof.cats) ms += c.ms;
+        for (int v = 0; v < 2; ++v) {
+          v_zpass = v;
+          prof.reset();
+          prof.on = false;
+          weights(wl, s);
+          forward_batched(s, nullptr, wl);
+          prof.on = true;
+          weights(wl, s);
+          forward_batched(s, nullptr, wl);
+          prof.collect();
+          prof.on = false;
+          double ms = 0;
+          for (const auto& c : prof.cats) ms += c.ms;
+          if (ms < best_ms) {
+            best_ms = ms;
+            best_algo = 1;
+            best_vz_dual = v;
+          }
+        }
         algo = 0;
-        if (ms < best_ms) best_algo = 1;
       }
       prof.reset();
       prof.on = prof_on;
       schedule(best[0], s);
       v_ypass = best[1];
       v_yinv = best[2];
-      v_zpass = best[3];
+      v_zpass = best_algo == 1 ? best_vz_dual : best[3];
       algo = best_algo;
       ++gen;  // recorded launch sequences used the old schedule
       forward_done = false;
@@ -1099,8 +1116,8 @@ template <typename T, int N> struct Engine : EngineBase {
         launch_check("kgen_y(dual adjoint)");
       });
       prof.run("bwd_dual_xscatter", s, (double)nq * ((double)NC * cb + pts), [&] {
-        k_xscatter_dual<T, Sh, WX><<<dim3((int)(NN / WX), 1, nq), NTX, 0, s>>>(
-            line_set(), l_f.as<int32_t>(), cf, F, q0, x, NC, twp);
+        k_xscatter_dual<T, Sh, WX><<<(int)(NN / WX), NTX, 0, s>>>(line_set(), l_f.as<int32_t>(), cf, F,
+                                                                 q0, nq, x, NC, twp);
         launch_check("xscatter(dual adjoint)");
       });
       prof.run("bwd_dual_ypass", s, 2.0 * nq * NC * cb, [&] {
@@ -1109,7 +1126,11 @@ template <typename T, int N> struct Engine : EngineBase {
         launch_check("ypass(dual adjoint)");
       });
       prof.run("bwd_dual_zacc", s, (double)nq * (NC + ky_slot) * cb + 2.0 * NC * cb, [&] {
-        k_zdual_acc<T, Sh, W><<<dim3(N / W, N, 1), NT, 0, s>>>(x, NC, nq, ky, ky_slot, pwz(), A, twp);
+        if (v_zpass == 0)
+          k_zdual_acc<T, Sh, W><<<dim3(N / W, N, 1), NT, 0, s>>>(x, NC, nq, ky, ky_slot, pwz(), A, twp);
+        else
+          k_zdual_acc<T, Sh, WH><<<dim3(N / WH, N, 1), WH * TPL, 0, s>>>(x, NC, nq, ky, ky_slot, pwz(),
+                                                                      A, twp);
         launch_check("zacc(dual adjoint)");
       });
     }
@@ -1168,7 +1189,11 @@ template <typename T, int N> struct Engine : EngineBase {
         launch_check("kgen_y(dual)");
       });
       prof.run("dual_zconv", s, (double)(nq * ky_slot + NC + nq * NC) * cb, [&] {
-        k_zconv<T, Sh, W><<<dim3(N / W, N, 1), NT, 0, s>>>(ky, ky_slot, nq, pwz(), fg, x, NC, twp);
+        if (v_zpass == 0)
+          k_zconv<T, Sh, W><<<dim3(N / W, N, 1), NT, 0, s>>>(ky, ky_slot, nq, pwz(), fg, x, NC, twp);
+        else
+          k_zconv<T, Sh, WH><<<dim3(N / WH, N, 1), WH * TPL, 0, s>>>(ky, ky_slot, nq, pwz(), fg, x, NC,
+                                                                  twp);
         launch_check("zconv");
       });
       prof.run("dual_yinv", s, 2.0 * nq * NC * cb, [&] {
