@@ -17,10 +17,15 @@ around every pass kernel for the per-kernel table.
 
 Prints ONE JSON line.  `value` = pair fields per second over the timed steps
 (forward + adjoint by default; `forward_only` gives the forward rate).
-`hbm_floor_frac` = required bytes per field of the pruned, fused pass
-structure x fields/s / 8 TB/s.  `roofline` is for the kernel with the largest
-share of the profiled pass: algorithmic bytes per launch / mean launch time,
-both measured in this run with HIP events on the launch stream.
+`step_hbm_frac` = algorithmic bytes of every instrumented pass kernel of a
+step (the schedule in use: per-field transforms or the dual form) / step
+time / 8 TB/s.  `hbm_floor_frac` = the least bytes per field of the
+per-field pass structure (one transform chain per field pair, pruned and
+fused) x fields/s / 8 TB/s: above 1 when the dual form, which transforms one
+kernel per pair of output bins instead, beats that floor.  `roofline` is for
+the kernel with the largest share of the profiled pass: algorithmic bytes per
+launch / mean launch time, both measured in this run with HIP events on the
+launch stream.
 `fp64_plain` times the one-field-at-a-time FP64 GPU path's forward;
 `cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
 workload on this host.
@@ -248,6 +253,8 @@ def main(argv=None):
             _log(f"  {name:16s} launches {n:5d}  {ms / max(n, 1):8.3f} ms/launch  "
                  f"{by / max(n, 1) / 1e9:8.3f} GB/launch  {by / (ms * 1e-3) / 1e9 if ms > 0 else 0:8.1f} GB/s"
                  f"  share {ms / (ms_prof * a.steps):.3f}")
+    step_bytes = sum(p[3] for p in prof) / a.steps
+    step_hbm_frac = step_bytes / (ms_prof * 1e-3) / (HBM_PEAK_GBS * 1e9)
     dom = max(prof, key=lambda p: p[2])
     name, n, ms, by = dom
     achieved = (by / n) / (ms / n * 1e-3) / 1e9
@@ -283,7 +290,10 @@ def main(argv=None):
             "schedule": plan.schedule(), "autotuned": not a.no_autotune,
             "launch_graphs": not a.no_graphs,
         },
+        "step_hbm_frac": round(step_hbm_frac, 4),
+        "step_gb": round(step_bytes / 1e9, 2),
         "hbm_floor_frac": round(floor_bytes_per_field(wl.N, fpb, mode_key) * value / (HBM_PEAK_GBS * 1e9), 4),
+        "hbm_floor_basis": "per-field transforms",
         "ms_per_step_eager_profiled": round(ms_prof, 3),
         "roofline": roofline,
     }
