@@ -288,6 +288,7 @@ def main(argv=None):
                      else "pairs_build + forward"),
             "hod_weights": bool(hod), "parallelism": "single GPU",
             "schedule": plan.schedule(), "autotuned": not a.no_autotune,
+            "dual_form_check": round(plan.dual_check(), 4),
             "launch_graphs": not a.no_graphs,
         },
         "step_hbm_frac": round(step_hbm_frac, 4),

@@ -195,7 +195,9 @@ pgx_status pgx_keep_spectra(pgx_plan* plan, int32_t enable);
  * with the galaxy field, interpolated at every pair midpoint; the same
  * estimator exactly, up to floating-point rounding) when its per-pair values
  * (n_pairs x n_out FP32) fit in half the free device memory, with its two z
- * passes in tiles of the default width or half of it.  It keeps the fastest
+ * passes in tiles of the default width or half of it; the dual form is a
+ * candidate only when its xi agree with the per-field transforms' within
+ * half of 1e-5 max(|xi|, 1e-2) on every bin (pgx_dual_check).  It keeps the fastest
  * combination for later calls.  Results differ between schedules only by
  * floating-point rounding.  It runs the forward eagerly several times
  * (about sixteen forward passes' worth of device time), discards the state of
@@ -212,6 +214,16 @@ pgx_status pgx_autotune(pgx_plan* plan, void* stream, int32_t* schedule);
 /* The schedule in use: host int32[5] as filled by pgx_autotune.  Creates the
  * device state of the plan if it does not exist yet. */
 pgx_status pgx_schedule(pgx_plan* plan, int32_t* schedule);
+/* The accuracy check of the dual form in the last pgx_autotune: its largest
+ * xi disagreement with the per-field transforms on the tuned catalogue, in
+ * units of 1e-5 max(|xi|, 1e-2) over every bin of every non-empty field (the
+ * autotuner keeps the dual form only when it is at most 0.5); -1 when not
+ * measured (no autotune yet, FP64 plan, or the dual form did not fit).  The
+ * FP32 rounding of the dual form sits in the bin kernels' convolution at
+ * each pair midpoint, which the few pairs of a sparse field do not average,
+ * so on sparse catalogues it can exceed the per-field transforms' error.
+ *   disagreement: host double out.  No device work. */
+pgx_status pgx_dual_check(pgx_plan* plan, double* disagreement);
 /* Apply a schedule (host int32[5] as above, e.g. one found by an earlier
  * pgx_autotune): batch size in [1, 32] (clamped to the number of field
  * pairs), variants and algorithm 0 or 1.  Same side effects as pgx_autotune apart from the

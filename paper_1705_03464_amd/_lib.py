@@ -63,6 +63,7 @@ _SIGS = {
     "pgx_use_graphs": (C.c_int, [C.c_void_p, C.c_int32]),
     "pgx_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
     "pgx_schedule": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "pgx_dual_check": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "pgx_set_schedule": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
     "pgx_graph_replays": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "pgx_profile": (C.c_int, [C.c_void_p, C.c_int32]),
@@ -253,6 +254,14 @@ class Plan:
         out = (C.c_int32 * 5)()
         _check(load_library().pgx_schedule(self._h, out))
         return self._sched(out)
+
+    def dual_check(self) -> float:
+        """The dual form's xi disagreement with the per-field transforms in
+        the last autotune, in units of 1e-5 max(|xi|, 1e-2); -1 if not
+        measured (pgx_dual_check)."""
+        d = C.c_double()
+        _check(load_library().pgx_dual_check(self._h, C.byref(d)))
+        return d.value
 
     def set_schedule(self, batch: int, ypass_variant: int = 0, yinv_variant: int = 0,
                      zpass_variant: int = 0, algorithm: int = 0, stream=None):

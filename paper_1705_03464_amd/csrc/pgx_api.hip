@@ -240,6 +240,12 @@ pgx_status pgx_schedule(pgx_plan* plan, int32_t* schedule) {
   return guarded([&] { plan->engine().schedule_info(schedule); });
 }
 
+pgx_status pgx_dual_check(pgx_plan* plan, double* disagreement) {
+  if (!plan) return fail(PGX_EINVAL, "plan is NULL");
+  if (!disagreement) return fail(PGX_EINVAL, "disagreement is NULL");
+  return guarded([&] { *disagreement = plan->eng ? plan->eng->dual_disagreement : -1.0; });
+}
+
 pgx_status pgx_set_schedule(pgx_plan* plan, void* stream, const int32_t* schedule) {
   if (!plan) return fail(PGX_EINVAL, "plan is NULL");
   if (!schedule) return fail(PGX_EINVAL, "schedule is NULL");

@@ -51,7 +51,8 @@ k_zconv(const C<T>* __restrict__ ky_in, int64_t ky_slot, int n_slots, int pwz,
   constexpr bool PIPE = E <= 8;
   __shared__ C<T> tw_s[tw_lds_entries<Sh, kZTwReg>()];
   __shared__ C<T> lines[W][LL];
-  const int xt = blockIdx.x, ky = blockIdx.y;
+  int xt, ky;
+  xcd_tile(xt, ky);
   const int c = threadIdx.x % W, t = threadIdx.x / W;
   TwAuto<Sh, T, kZTwReg> twa;
   twa.init(tw_s, tw_g, t);
@@ -172,11 +173,11 @@ static __global__ void k_dual_gather(const int32_t* __restrict__ key, const int3
   }
 }
 
-// S[f][b] = sum over the pairs of field f of w_i w_j gv[b][p] (FP64, one
-// 256-thread block per (field, bin), fixed partition: deterministic).
+// S[f][b] = sum over the pairs of field f of (w_i w_j) gv[b][p] (FP64 pair
+// weights from k_pair_wprod; one 256-thread block per (field, bin), fixed
+// partition: deterministic).
 static __global__ void k_dual_reduce(const int32_t* __restrict__ line_start, int64_t nn,
-                                     const int32_t* __restrict__ pi, const int32_t* __restrict__ pj,
-                                     const float* __restrict__ w, const float* __restrict__ gv,
+                                     const double* __restrict__ wp, const float* __restrict__ gv,
                                      int64_t P, int R, const float* __restrict__ bscale,
                                      double* __restrict__ S) {
   __shared__ double sh[256];
@@ -184,10 +185,7 @@ static __global__ void k_dual_reduce(const int32_t* __restrict__ line_start, int
   const int64_t s = line_start[(int64_t)f * nn], e = line_start[(int64_t)(f + 1) * nn];
   const float* g = gv + (int64_t)b * P;
   double acc = 0.0;
-  for (int64_t p = s + threadIdx.x; p < e; p += 256) {
-    const double wp = w ? (double)w[pi[p]] * (double)w[pj[p]] : 1.0;
-    acc += wp * (double)g[p];
-  }
+  for (int64_t p = s + threadIdx.x; p < e; p += 256) acc += wp[p] * (double)g[p];
   const double r = block_sum256(acc, sh);
   // undo the bin's kernel scale (the FP32 value the kernel generator applied)
   if (threadIdx.x == 0) S[(int64_t)f * R + b] = r / (double)bscale[b];
@@ -471,7 +469,8 @@ k_zdual_acc(const C<T>* __restrict__ x, int64_t x_slot, int n_slots,
   constexpr bool PIPE = E <= 8;
   __shared__ C<T> tw_s[tw_lds_entries<Sh, kZTwReg>()];
   __shared__ C<T> lines[W][LL];
-  const int xt = blockIdx.x, ky = blockIdx.y;
+  int xt, ky;
+  xcd_tile(xt, ky);
   const int c = threadIdx.x % W, t = threadIdx.x / W;
   TwAuto<Sh, T, kZTwReg> twa;
   twa.init(tw_s, tw_g, t);

@@ -186,6 +186,9 @@ struct EngineBase {
   // device has room); the adjoint then skips recomputing them
   bool keep_spectra = false;
   bool spectra_valid = false;
+  // autotuner: the dual form's largest xi disagreement with the per-field
+  // transforms in units of 1e-5 max(|xi|, 1e-2) (-1 when not measured)
+  double dual_disagreement = -1.0;
 };
 
 constexpr int kRMax = 640;  // largest number of output bins handled by the bin kernels
@@ -236,6 +239,7 @@ template <typename T, int N> struct Engine : EngineBase {
   // catalogue
   DBuf g_key, g_ls, g_x0, g_fx, g_fy, g_fz, g_idx, g_wt, g_tasks;
   DBuf p_key, p_ls, p_i, p_j, p_x0, p_fx, p_fy, p_fz, p_wt;
+  DBuf p_wd, wg_part;  // FP64 pair weights of the current forward; partial weight sums
   // line-major copy of the pair catalogue (all fields together): line starts,
   // CIC corner and fractions, field, field-major index, weight (adjoint of the
   // dual form)
@@ -253,6 +257,7 @@ template <typename T, int N> struct Engine : EngineBase {
   bool w_given = false;
   // the last forward ran the dual form: its gathered values are in GV
   bool fwd_dual = false;
+  DBuf S_ref, dis_d;  // autotuner: per-field bin sums, disagreement of the dual form
 
   // room for the kept spectra: already allocated, or fits in free device
   // memory with 4 GiB to spare
@@ -276,6 +281,7 @@ template <typename T, int N> struct Engine : EngineBase {
 
   explicit Engine(const PlanCfg& c) : cfg(c) {
     static_assert(N % W == 0 && N % WA == 0, "tile width must divide N");
+    static_assert((N / W) * N % 8 == 0 && (N / WH) * N % 8 == 0, "z-pass grids are whole XCD rounds");
     upload(tw, twiddles<Sh>());
     upload(tw_alt, twiddles<ShA>());
     upload(lut1, cfg.bins.lut1);
@@ -607,6 +613,7 @@ template <typename T, int N> struct Engine : EngineBase {
       float* wl = w_given && n_gal > 0 ? w_last.as<float>() : nullptr;
       double best_ms = 1e300;
       int best[4] = {b0, 0, 0, 0};
+      algo = 0;  // the per-field trials, whatever the schedule in use
       for (int b : cands) {
         schedule(b, s);
         double t[2][3] = {{0, 0, 0}, {0, 0, 0}}, other = 0;
@@ -639,11 +646,20 @@ template <typename T, int N> struct Engine : EngineBase {
         }
       }
       // the dual form (one transform per pair of output bins) at the chosen
-      // batch size, when its gathered values fit
-      // (its z-pass variant is the tile width of its z passes)
+      // batch size, when its gathered values fit (its z-pass variant is the
+      // tile width of its z passes).  It is kept only if its xi agree with
+      // the per-field transforms' within half of 1e-5 max(|xi|, 1e-2) on
+      // every bin (so its error exceeds theirs by at most that): its FP32
+      // rounding sits in the bin kernels' convolution at each pair midpoint,
+      // which the few pairs of a sparse field do not average.
       int best_algo = 0, best_vz_dual = 0;
+      dual_disagreement = -1.0;
       algo = 0;
       if (dual_fits()) {
+        const int F = cfg.F, R = cfg.R;
+        double* sref = S_ref.get<double>((int64_t)F * R);
+        PGX_HIP(hipMemcpyAsync(sref, S.as<double>(), (size_t)F * R * sizeof(double),
+                               hipMemcpyDeviceToDevice, s));
         schedule(best[0], s);
         algo = 1;
         for (int v = 0; v < 2; ++v) {
@@ -652,6 +668,15 @@ template <typename T, int N> struct Engine : EngineBase {
           prof.on = false;
           weights(wl, s);
           forward_batched(s, nullptr, wl);
+          if (v == 0) {
+            double* r = dis_d.get<double>(1);
+            k_xi_disagreement<<<1, 256, 0, s>>>(sref, S.as<double>(), nbd.as<double>(),
+                                                wsum_d.as<double>(), wg_d.as<double>(), F, R, 1e-5, r);
+            launch_check("xi_disagreement");
+            PGX_HIP(hipMemcpyAsync(&dual_disagreement, r, sizeof(double), hipMemcpyDeviceToHost, s));
+            PGX_HIP(hipStreamSynchronize(s));
+            if (!(dual_disagreement <= 0.5)) break;
+          }
           prof.on = true;
           weights(wl, s);
           forward_batched(s, nullptr, wl);
@@ -793,12 +818,18 @@ template <typename T, int N> struct Engine : EngineBase {
       k_gather_weights<T><<<grid_for(n_gal), 256, 0, s>>>(g_idx.as<int32_t>(), w, n_gal, g_wt.as<T>());
       launch_check("gal_weights");
     }
-    k_field_wsum<<<F, 256, 0, s>>>(p_ls.as<int32_t>(), NN, p_i.as<int32_t>(), p_j.as<int32_t>(), w,
-                                   wsum_d.get<double>(F));
+    double* wp = p_wd.get<double>(std::max<int64_t>(n_pairs, 1));
+    if (n_pairs > 0) {
+      k_pair_wprod<<<grid_for(n_pairs), 256, 0, s>>>(p_i.as<int32_t>(), p_j.as<int32_t>(), w, n_pairs, wp);
+      launch_check("pair_wprod");
+    }
+    k_field_wsum<<<F, 256, 0, s>>>(p_ls.as<int32_t>(), NN, wp, wsum_d.get<double>(F));
     launch_check("field_wsum");
     k_field_scale<<<grid_for(F), 256, 0, s>>>(wsum_d.as<double>(), F, FSC.get<float>(std::max(F, 1)));
     launch_check("field_scale");
-    k_weight_total<<<1, 256, 0, s>>>(w, n_gal, wg_d.get<double>(1));
+    double* wpart = wg_part.get<double>(kWtBlocks);
+    k_weight_partial<<<kWtBlocks, 256, 0, s>>>(w, n_gal, wpart);
+    k_weight_total<<<1, 256, 0, s>>>(wpart, wg_d.get<double>(1));
     launch_check("weight_total");
   }
 
@@ -1215,9 +1246,8 @@ template <typename T, int N> struct Engine : EngineBase {
         });
       }
     }
-    k_dual_reduce<<<dim3(F, R), 256, 0, s>>>(p_ls.as<int32_t>(), NN, p_i.as<int32_t>(),
-                                             p_j.as<int32_t>(), wl, gv, n_pairs, R,
-                                             bscale.as<float>(), Sd);
+    k_dual_reduce<<<dim3(F, R), 256, 0, s>>>(p_ls.as<int32_t>(), NN, p_wd.as<double>(), gv, n_pairs,
+                                             R, bscale.as<float>(), Sd);
     launch_check("reduce(dual)");
   }
 

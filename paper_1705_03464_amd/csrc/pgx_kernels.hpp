@@ -75,6 +75,18 @@ template <typename T> struct Buf {
   }
 };
 
+// XCD-aware order of the (x tile, y) blocks of a z pass: the hardware hands
+// block b to XCD b mod 8, so XCD k gets the contiguous range of logical tiles
+// [k T/8, (k+1) T/8) (T = blocks in the grid, a multiple of 8 for every grid
+// side used), and the tiles one XCD works on at a time share rows, hence its
+// L2 and its address-translation caches.
+__device__ __forceinline__ void xcd_tile(int& xt, int& ky) {
+  const int nb = (int)(gridDim.x * gridDim.y), bid = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+  const int lt = (bid & 7) * (nb >> 3) + (bid >> 3);
+  xt = lt % (int)gridDim.x;
+  ky = lt / (int)gridDim.x;
+}
+
 // z passes: default twiddle source (registers when they fit; the autotuner
 // also tries the LDS table), and the most slots one launch may carry (their
 // plane masks are staged in LDS)

@@ -74,19 +74,47 @@ __device__ __forceinline__ double block_sum256(double v, double* sh) {
   return r;
 }
 
-// Sum of products w_i w_j in FP64 over each field's contiguous range of the
-// sorted pair list: one block (256 threads) per field, fixed partition.
+// Sum of products w_i w_j in FP64 (k_pair_wprod) over each field's contiguous
+// range of the sorted pair list: one block (256 threads) per field, fixed
+// partition.
 static __global__ void k_field_wsum(const int32_t* __restrict__ line_start, int64_t nn,
-                             const int32_t* __restrict__ pi, const int32_t* __restrict__ pj,
-                             const float* __restrict__ w, double* __restrict__ wsum) {
+                                    const double* __restrict__ wp, double* __restrict__ wsum) {
   __shared__ double sh[256];
   const int f = blockIdx.x;
   const int64_t s = line_start[(int64_t)f * nn], e = line_start[(int64_t)(f + 1) * nn];
   double acc = 0.0;
-  for (int64_t p = s + threadIdx.x; p < e; p += 256)
-    acc += w ? (double)w[pi[p]] * (double)w[pj[p]] : 1.0;
+  for (int64_t p = s + threadIdx.x; p < e; p += 256) acc += wp[p];
   const double r = block_sum256(acc, sh);
   if (threadIdx.x == 0) wsum[f] = r;
+}
+
+// Largest disagreement between two sets of bin sums of the same estimator,
+// in units of tol * max(|xi|, 1e-2) with xi = S / (n_b Wsum_f W_g) (fields
+// with Wsum_f = 0 skipped).  One block; out[0] = the largest ratio.
+static __global__ void k_xi_disagreement(const double* __restrict__ Sa, const double* __restrict__ Sb,
+                                         const double* __restrict__ nb, const double* __restrict__ wsum,
+                                         const double* __restrict__ wg, int F, int R, double tol,
+                                         double* __restrict__ out) {
+  __shared__ double sh[256];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < F * R; i += 256) {
+    const int f = i / R, b = i - f * R;
+    const double norm = nb[b] * wsum[f] * wg[0];
+    if (!(wsum[f] > 0.0) || !(norm > 0.0)) continue;
+    const double xa = Sa[i] / norm, xb = Sb[i] / norm;
+    const double r = fabs(xa - xb) / (tol * fmax(fabs(xa), 1e-2));
+    m = r > m || r != r ? r : m;
+  }
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      const double o = sh[threadIdx.x + s];
+      if (o > sh[threadIdx.x] || o != o) sh[threadIdx.x] = o;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
 }
 
 // Per-field scale of the pair fields in the transforms: 1 / Wsum_f rounded to
@@ -97,13 +125,32 @@ static __global__ void k_field_scale(const double* __restrict__ wsum, int F, flo
   if (f < F) fsc[f] = (float)(wsum[f] > 1e-30 ? 1.0 / wsum[f] : 1.0);
 }
 
-// Sum of galaxy weights in FP64 (single block, fixed partition).
-static __global__ void k_weight_total(const float* __restrict__ w, int64_t n, double* __restrict__ out) {
+// Sum of galaxy weights in FP64, deterministic: kWtBlocks blocks each sum a
+// fixed contiguous chunk (256 threads, fixed partition), then one block sums
+// the partials in order.
+constexpr int kWtBlocks = 256;
+static __global__ void k_weight_partial(const float* __restrict__ w, int64_t n, double* __restrict__ part) {
+  __shared__ double sh[256];
+  const int64_t chunk = (n + kWtBlocks - 1) / kWtBlocks;
+  const int64_t a = (int64_t)blockIdx.x * chunk, b = a + chunk < n ? a + chunk : n;
+  double acc = 0.0;
+  for (int64_t i = a + threadIdx.x; i < b; i += 256) acc += w ? (double)w[i] : 1.0;
+  const double r = block_sum256(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+static __global__ void k_weight_total(const double* __restrict__ part, double* __restrict__ out) {
   __shared__ double sh[256];
   double acc = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) acc += w ? (double)w[i] : 1.0;
+  for (int i = threadIdx.x; i < kWtBlocks; i += 256) acc += part[i];
   const double r = block_sum256(acc, sh);
   if (threadIdx.x == 0) out[0] = r;
+}
+
+// FP64 pair weights w_i w_j (1 without weights), one per pair.
+static __global__ void k_pair_wprod(const int32_t* __restrict__ pi, const int32_t* __restrict__ pj,
+                                    const float* __restrict__ w, int64_t P, double* __restrict__ out) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < P) out[p] = w ? (double)w[pi[p]] * (double)w[pj[p]] : 1.0;
 }
 
 // ----------------------------------------------------------------------------

@@ -32,6 +32,7 @@ def test_option_flags_need_no_device():
     plan.keep_spectra(False)
     plan.use_graphs(False)
     plan.use_graphs(True)
+    assert plan.dual_check() == -1.0  # no autotune has run
 
 
 def test_library_exports_every_declared_symbol():
