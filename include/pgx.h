@@ -54,7 +54,7 @@ typedef enum {
 } pgx_status;
 
 typedef enum { PGX_PAIR_S_MU = 0, PGX_PAIR_RP_PI = 1 } pgx_pair_mode;
-typedef enum { PGX_OUT_SHELL = 0, PGX_OUT_R_MU = 1, PGX_OUT_RP_PI = 2 } pgx_out_mode;
+typedef enum { PGX_OUT_SHELL = 0, PGX_OUT_R_MU = 1, PGX_OUT_RP_PI = 2, PGX_OUT_GSW = 3 } pgx_out_mode;
 typedef enum { PGX_FP64_PLAIN = 0, PGX_FP32_BATCHED = 1 } pgx_precision;
 typedef enum { PGX_QEFF_NOTSQ = 0, PGX_QEFF_SQUEEZED = 1, PGX_QEFF_CONST_XIW = 2 } pgx_qeff_mode;
 
@@ -66,8 +66,20 @@ typedef enum { PGX_QEFF_NOTSQ = 0, PGX_QEFF_SQUEEZED = 1, PGX_QEFF_CONST_XIW = 2
  *                    radius (pairs kept iff |d| < pair_dmax).
  *   out_mode SHELL : o1 = r edges (o2 ignored); R_MU: o1 = r, o2 = |mu| in
  *                    [0, 1]; RP_PI: o1 = r_p, o2 = |pi|.
+ *            GSW   : one output "bin" weighted by the paper's Gaussian-sigmoid
+ *                    weighting function (Section "weighting", equation
+ *                    weighting): with r_perp, r_par the lattice offset's
+ *                    components across and along the line of sight (z),
+ *                    W = sigmoid(w_s0 (r_perp - w_rs)) exp(-(r_perp^2 +
+ *                    r_par^2) / (2 w_sigma^2)) where r_perp >= w_rcut and
+ *                    |r| <= w_rmax, 0 elsewhere (the normalisation constant
+ *                    cancels; w_rmax cuts the Gaussian tail off the lattice
+ *                    window).  xi = sum_r W(r) C(r) / sum_r W(r), so b_pg is
+ *                    the paper's estimator (equation bpg_initial) with W.
+ *                    o1 / o2 are ignored (may be NULL).
  *   Requirements: the maximum pair separation < L/3 (cell list with at least
- *   3 cells per side); the largest output edge < L/2; N a power of two in
+ *   3 cells per side); the largest output edge (w_rmax for GSW) < L/2, with
+ *   w_sigma > 0, w_s0 > 0, 0 <= w_rcut < w_rmax; N a power of two in
  *   [64, 1024]; n_fields * N^2 < 2^31.
  *   precision FP64_PLAIN: one field at a time in FP64 (transforms, sums).
  *             FP32_BATCHED: fields paired into complex grids, FP32 transforms
@@ -95,6 +107,8 @@ typedef struct {
   int32_t qeff_mode;
   double xi_w_const;
   int32_t batch;
+  /* out_mode GSW only */
+  double w_sigma, w_rs, w_s0, w_rcut, w_rmax;
 } pgx_params;
 
 /* Create a plan.  Validates the parameters (PGX_EINVAL / PGX_ENOTSUP) and
@@ -111,8 +125,14 @@ pgx_status pgx_plan_destroy(pgx_plan* plan);
 pgx_status pgx_plan_info(const pgx_plan* plan, int32_t* n_fields, int32_t* n_out,
                          int32_t* window);
 
-/* Exact lattice-vector count n_b of every output bin (HOST array [R]). */
+/* Exact lattice-vector count n_b of every output bin (HOST array [R]); for
+ * GSW the number of lattice vectors with W > 0. */
 pgx_status pgx_out_counts(const pgx_plan* plan, int64_t* n_b);
+
+/* Normalisation of every output bin (HOST array [R]), the denominator of xi:
+ * n_b for the indicator bins, sum_r W(r) over the lattice window for GSW
+ * (FP64). */
+pgx_status pgx_out_norms(const pgx_plan* plan, double* norm);
 
 /* Volume of every pair bin (HOST array [F]) used by xi(d_p): the exact
  * (s, |mu|) shell-sector volume, or the (r_p, |pi|) annulus-slab volume cut by

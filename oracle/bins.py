@@ -10,6 +10,11 @@ against FP64 thresholds q*q, q = e/Delta:
   r_mu    shell bin on m, then |mu| = |k'|/sqrt(m) about the z line of sight:
           largest k with k'^2 >= (mu_k*mu_k)*m, top edge closed;
   rp_pi   r_p bin on i'^2 + j'^2, |pi| bin on k'^2 (both half-open).
+The paper's own W (Section "weighting", equation weighting), out_mode "gsw",
+is one weighted bin: xi = sum_r W(r) C(r) / sum_r W(r) over the lattice
+vectors with r_perp >= r_cut (squares against the FP64 threshold, as above)
+and |r| <= r_max; its parameters (sigma, r_s, s_0, r_cut, r_max) travel in
+o1_edges.
 """
 from __future__ import annotations
 
@@ -22,9 +27,28 @@ def _thresholds(edges, L, N):
     return q * q
 
 
+def gsw_weight(ip, jp, kp, params, L, N):
+    """The paper's Gaussian-sigmoid weighting function (Section "weighting",
+    equation weighting) at lattice offsets, without its normalisation
+    constant (it cancels in every ratio): a sigmoid in the distance r_perp
+    across the line of sight (x, y), centred at r_s with slope s_0, times an
+    isotropic Gaussian of width sigma in (r_perp, r_par), r_par along z.  The
+    cavity r_perp < r_cut and the cut |r| > r_max are the classification's."""
+    sigma, rs, s0 = float(params[0]), float(params[1]), float(params[2])
+    delta = L / N
+    ip = np.asarray(ip, np.float64); jp = np.asarray(jp, np.float64); kp = np.asarray(kp, np.float64)
+    rperp = delta * np.sqrt(ip * ip + jp * jp)
+    rpar = delta * np.abs(kp)
+    sig = 1.0 / (1.0 + np.exp(-s0 * (rperp - rs)))
+    return sig * np.exp(-0.5 * (rperp * rperp + rpar * rpar) / (sigma * sigma))
+
+
 def window(out_mode, o1_edges, o2_edges, L, N):
     """Half-widths (wx, wy, wz) of the lattice cube that holds every bin."""
     delta = L / N
+    if out_mode == "gsw":
+        w = int(np.floor(o1_edges[4] / delta))
+        return (w, w, w)
     if out_mode in ("shell", "r_mu"):
         w = int(np.floor(o1_edges[-1] / delta))
         return (w, w, w)
@@ -36,6 +60,11 @@ def window(out_mode, o1_edges, o2_edges, L, N):
 def classify_lattice(ip, jp, kp, out_mode, o1_edges, o2_edges, L, N):
     """Bin index (or -1) for integer lattice offsets."""
     ip = np.asarray(ip, np.int64); jp = np.asarray(jp, np.int64); kp = np.asarray(kp, np.int64)
+    if out_mode == "gsw":
+        tc, tm = _thresholds([o1_edges[3], o1_edges[4]], L, N)
+        xy = (ip * ip + jp * jp).astype(np.float64)
+        m = xy + (kp * kp).astype(np.float64)
+        return np.where((xy >= tc) & (m <= tm), 0, -1)
     t1 = _thresholds(o1_edges, L, N)
     if out_mode == "shell" or out_mode == "r_mu":
         m = ip * ip + jp * jp + kp * kp
@@ -67,6 +96,8 @@ def classify_lattice(ip, jp, kp, out_mode, o1_edges, o2_edges, L, N):
 
 
 def n_out(out_mode, o1_edges, o2_edges):
+    if out_mode == "gsw":
+        return 1
     n1 = len(o1_edges) - 1
     return n1 if out_mode == "shell" else n1 * (len(o2_edges) - 1)
 
@@ -87,11 +118,31 @@ def lattice_table(out_mode, o1_edges, o2_edges, L, N):
     return (np.mod(I, N), np.mod(J, N), np.mod(K, N)), b, counts
 
 
-def bin_average(C: np.ndarray, table, R: int) -> np.ndarray:
+def lattice_weights(out_mode, o1_edges, o2_edges, L, N, table):
+    """Weight of every entry of `table` (1 for the indicator bins, W for
+    "gsw") and the normalisation of every bin (their sums)."""
     idx, b, counts = table
-    sums = np.bincount(b, weights=C[idx], minlength=R)
+    R = counts.size
+    if out_mode != "gsw":
+        return np.ones(b.size), counts.astype(np.float64)
+    # the table holds grid indices; back to signed offsets
+    off = [np.where(a < N // 2, a, a - N) for a in idx]
+    w = gsw_weight(off[0], off[1], off[2], o1_edges, L, N)
+    return w, np.bincount(b, weights=w, minlength=R)
+
+
+def bin_average(C: np.ndarray, table, R: int, weights=None) -> np.ndarray:
+    """Per-bin average of C over the table's lattice vectors, weighted by
+    `weights` = (per-entry weights, per-bin sums) when given."""
+    idx, b, counts = table
+    if weights is None:
+        sums = np.bincount(b, weights=C[idx], minlength=R)
+        norm = counts
+    else:
+        w, norm = weights
+        sums = np.bincount(b, weights=w * C[idx], minlength=R)
     with np.errstate(invalid="ignore", divide="ignore"):
-        return sums / counts
+        return sums / norm
 
 
 def bin_counts_bruteforce(out_mode, o1_edges, o2_edges, L, N):

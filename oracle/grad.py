@@ -12,7 +12,8 @@ Chain, with c_f = N_c / Wsum_f and c_g = N_c / W_g:
   xi_pg[f,b] = (N_c n_b)^-1 sum_{r in b} sum_x d_f(x) d_g(x + r)
   xi_gg[b]   = (N_c n_b)^-1 sum_{r in b} sum_x d_g(x) d_g(x + r)
   d_f = c_f rho_f - 1,   d_g = c_g rho_g - 1
-  kappa_f(r) = sum_b gbar_pg[f,b] 1[r in b] / (N_c n_b), kappa_g likewise
+  kappa_f(r) = sum_b gbar_pg[f,b] w(r) 1[r in b] / (N_c norm_b), kappa_g likewise
+  (w = 1, norm_b = n_b for the indicator bins; W and sum W for the weighted one)
   dJ/dd_f(x) = sum_r kappa_f(r) d_g(x + r)
   dJ/dd_g(y) = sum_f sum_r kappa_f(r) d_f(y - r)
                + sum_r kappa_g(r) [d_g(y - r) + d_g(y + r)]
@@ -145,12 +146,15 @@ def finalize_adjoint(out, wl, g_b=None, g_q=None, g_xipg=None, g_xigg=None, g_xi
 # ----------------------------------------------------------------------------
 # weight gradient
 # ----------------------------------------------------------------------------
-def _kappa_grid(gbar, table, N, R):
+def _kappa_grid(gbar, table, N, R, bw):
+    """kappa(r) = dJ/dC(r) = gbar_b w(r) / (N^3 norm_b) for r in bin b (w = 1
+    and norm_b = n_b for the indicator bins)."""
     idx, b, counts = table
+    w, norm = bw
     k = np.zeros((N, N, N))
     with np.errstate(invalid="ignore", divide="ignore"):
-        per_bin = np.where(counts > 0, gbar / (N ** 3 * counts), 0.0)
-    k[idx] = per_bin[b]
+        per_bin = np.where(norm > 0, gbar / (N ** 3 * norm), 0.0)
+    k[idx] = per_bin[b] * w
     return k
 
 
@@ -188,6 +192,7 @@ def weight_gradient(cat, wl, w, g_b=None, g_q=None, g_xipg=None, g_xigg=None, g_
     pairs = out["pairs"]
     gpg, ggg, gws, gwg = finalize_adjoint(out, wl, g_b, g_q, g_xipg, g_xigg, g_xidp)
     table = _bins.lattice_table(wl.out_mode, wl.o1_edges, wl.o2_edges, L, N)
+    bw = _bins.lattice_weights(wl.out_mode, wl.o1_edges, wl.o2_edges, L, N, table)
     R = table[2].size
     Nc = N ** 3
     corr = _corr_sum if method == "fft" else _corr_sum_direct
@@ -197,7 +202,7 @@ def weight_gradient(cat, wl, w, g_b=None, g_q=None, g_xipg=None, g_xigg=None, g_
     rho_g = cic_assign(pos, w, N, L)
     dg = rho_g * (Nc / wg) - 1.0
     E = np.zeros((N, N, N))
-    kg = _kappa_grid(ggg, table, N, R)
+    kg = _kappa_grid(ggg, table, N, R, bw)
     E += conv(kg, dg) + corr(kg, dg)
     grad = np.zeros(cat.n)
     for f in range(wl.n_fields):
@@ -209,7 +214,7 @@ def weight_gradient(cat, wl, w, g_b=None, g_q=None, g_xipg=None, g_xigg=None, g_
         pw = pairs["w"][sel]
         rho_f = cic_assign(mid, pw, N, L)
         df = rho_f * (Nc / ws) - 1.0
-        kf = _kappa_grid(gpg[f], table, N, R)
+        kf = _kappa_grid(gpg[f], table, N, R, bw)
         D = corr(kf, dg)
         E += conv(kf, df)
         drho_f = D * (Nc / ws)

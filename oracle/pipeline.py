@@ -30,9 +30,10 @@ def galaxy_side(cat, wl, w=None):
     Fg = rfftn(dg)
     table = _bins.lattice_table(wl.out_mode, wl.o1_edges, wl.o2_edges, L, N)
     R = _bins.n_out(wl.out_mode, wl.o1_edges, wl.o2_edges)
+    bw = _bins.lattice_weights(wl.out_mode, wl.o1_edges, wl.o2_edges, L, N, table)
     Cgg = irfftn(Fg * np.conj(Fg), dg.shape) / dg.size
-    xi_gg = _bins.bin_average(Cgg, table, R)
-    return dict(wg=wg, dg=dg, Fg=Fg, table=table, R=R, xi_gg=xi_gg, w=w)
+    xi_gg = _bins.bin_average(Cgg, table, R, bw)
+    return dict(wg=wg, dg=dg, Fg=Fg, table=table, R=R, bw=bw, xi_gg=xi_gg, w=w)
 
 
 def pair_field_xi(pairs, f, gal, wl):
@@ -45,7 +46,7 @@ def pair_field_xi(pairs, f, gal, wl):
     rho_f = cic_assign(pairs["mid"][sel], pairs["w"][sel], N, L)
     df = overdensity(rho_f, ws)
     C = irfftn(np.conj(rfftn(df)) * gal["Fg"], df.shape) / df.size
-    return _bins.bin_average(C, gal["table"], gal["R"])
+    return _bins.bin_average(C, gal["table"], gal["R"], gal["bw"])
 
 
 def forward(cat, wl, pairs=None, fields=None, w=None):
@@ -71,4 +72,5 @@ def forward(cat, wl, pairs=None, fields=None, w=None):
     fin = finalize(gal["xi_gg"], xi_pg, pairs["wsum"], gal["wg"], wl.L, vol,
                    wl.qeff_mode, wl.xi_w_const)
     return dict(counts=pairs["counts"], wsum=pairs["wsum"], wg=gal["wg"], xi_gg=gal["xi_gg"],
-                xi_pg=xi_pg, volumes=vol, n_b=gal["table"][2], pairs=pairs, **fin)
+                xi_pg=xi_pg, volumes=vol, n_b=gal["table"][2], norm_b=gal["bw"][1], pairs=pairs,
+                **fin)

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libpgx.so")
 STATUS = {0: "PGX_OK", 1: "PGX_EINVAL", 2: "PGX_ENOSPACE", 3: "PGX_EHIP", 4: "PGX_ENOTSUP",
           5: "PGX_ESTATE"}
 PAIR_MODES = {"s_mu": 0, "rp_pi": 1}
-OUT_MODES = {"shell": 0, "r_mu": 1, "rp_pi": 2}
+OUT_MODES = {"shell": 0, "r_mu": 1, "rp_pi": 2, "gsw": 3}
 PRECISIONS = {"fp64": 0, "fp32": 1}
 QEFF_MODES = {"notsq": 0, "squeezed": 1, "const": 2}
 
@@ -40,6 +40,8 @@ class _Params(C.Structure):
         ("n_o1", C.c_int32), ("o1_edges", C.POINTER(C.c_double)),
         ("n_o2", C.c_int32), ("o2_edges", C.POINTER(C.c_double)),
         ("qeff_mode", C.c_int32), ("xi_w_const", C.c_double), ("batch", C.c_int32),
+        ("w_sigma", C.c_double), ("w_rs", C.c_double), ("w_s0", C.c_double),
+        ("w_rcut", C.c_double), ("w_rmax", C.c_double),
     ]
 
 
@@ -51,6 +53,7 @@ _SIGS = {
     "pgx_plan_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                 C.POINTER(C.c_int32)]),
     "pgx_out_counts": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    "pgx_out_norms": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "pgx_field_volumes": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "pgx_pairs_build": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                   C.c_void_p, C.POINTER(C.c_int64), C.c_void_p]),
@@ -119,7 +122,10 @@ def _edges(a) -> np.ndarray:
 
 
 class Plan:
-    """One plan of the pair-galaxy correlation (wraps pgx_plan)."""
+    """One plan of the pair-galaxy correlation (wraps pgx_plan).  With
+    out_mode "gsw" (the paper's Gaussian-sigmoid weighting function, one
+    weighted output bin) `o1_edges` carries its parameters
+    (sigma, r_s, s_0, r_cut, r_max) and `o2_edges` is ignored."""
 
     def __init__(self, L: float, N: int, p1_edges: Sequence[float], p2_edges: Sequence[float],
                  o1_edges: Sequence[float], o2_edges: Optional[Sequence[float]] = None, *,
@@ -127,14 +133,18 @@ class Plan:
                  pair_dmax: float = 0.0, qeff_mode: str = "notsq", xi_w_const: float = 0.0,
                  batch: int = 0):
         lib = load_library()
-        self._keep = [_edges(p1_edges), _edges(p2_edges), _edges(o1_edges),
+        gsw = out_mode == "gsw"
+        wpar = [float(v) for v in o1_edges] if gsw else [0.0] * 5
+        if gsw and len(wpar) != 5:
+            raise ValueError("out_mode gsw takes (sigma, r_s, s_0, r_cut, r_max)")
+        self._keep = [_edges(p1_edges), _edges(p2_edges), _edges([0.0, 1.0] if gsw else o1_edges),
                       _edges(o2_edges if o2_edges is not None else [0.0, 1.0])]
         e1, e2, e3, e4 = self._keep
         dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
         prm = _Params(float(L), int(N), PRECISIONS[precision], PAIR_MODES[pair_mode],
                       e1.size - 1, dp(e1), e2.size - 1, dp(e2), float(pair_dmax),
                       OUT_MODES[out_mode], e3.size - 1, dp(e3), e4.size - 1, dp(e4),
-                      QEFF_MODES[qeff_mode], float(xi_w_const), int(batch))
+                      QEFF_MODES[qeff_mode], float(xi_w_const), int(batch), *wpar)
         h = C.c_void_p()
         _check(lib.pgx_plan_create(C.byref(prm), C.byref(h)))
         self._h = h
@@ -168,6 +178,12 @@ class Plan:
     def out_counts(self) -> np.ndarray:
         a = np.zeros(self.n_out, np.int64)
         _check(load_library().pgx_out_counts(self._h, a.ctypes.data_as(C.POINTER(C.c_int64))))
+        return a
+
+    def out_norms(self) -> np.ndarray:
+        """Denominator of xi per output bin: n_b, or sum of W for "gsw"."""
+        a = np.zeros(self.n_out, np.float64)
+        _check(load_library().pgx_out_norms(self._h, a.ctypes.data_as(C.POINTER(C.c_double))))
         return a
 
     def field_volumes(self) -> np.ndarray:

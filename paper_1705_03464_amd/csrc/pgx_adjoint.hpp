@@ -6,7 +6,9 @@
 //   S_fb = sum_{s in b} H_f(s),   xi_pg[f,b] = S_fb / (n_b Wsum_f W_g)
 //   Sgg_b = sum_{s in b} IDFT(|G|^2)(s),   xi_gg[b] = Sgg_b / (n_b W_g^2).
 // Given a_fb = dL/dS_fb and a_gb = dL/dSgg_b, with the symmetric kernels
-// K_f(r) = sum_b a_fb 1[r in b] and K_g likewise (real transforms K^):
+// K_f(r) = sum_b a_fb w(r) 1[r in b] (w = 1 for the indicator bins, the
+// Gaussian-sigmoid weight for the weighted bin) and K_g likewise (real
+// transforms K^):
 //   dL/drho_f      = IDFT(K^_f G)                       (per pair field)
 //   dL/dg'         = IDFT(sum_f K^_f Z_f) + 2 IDFT(K^_g G)
 // Two fields a, b travel in one complex grid: the transform of K_a + i K_b is
@@ -169,8 +171,9 @@ k_kgen_x(const double* __restrict__ coef, int R, const int32_t* __restrict__ slo
         // divided by it, so products with its spectrum come out unscaled
         const double sa = fscale && fa >= 0 ? (double)fscale[fa] : 1.0;
         const double sb = fscale && fb >= 0 ? (double)fscale[fb] : 1.0;
-        v[m].x = fa >= 0 ? (T)(coef[(int64_t)fa * R + b] / sa) : (T)0;
-        v[m].y = fb >= 0 ? (T)(coef[(int64_t)fb * R + b] / sb) : (T)0;
+        const double wb = bin_weight(bm, px - pwx, py - pwy, pz - pwz);
+        v[m].x = fa >= 0 ? (T)(coef[(int64_t)fa * R + b] * wb / sa) : (T)0;
+        v[m].y = fb >= 0 ? (T)(coef[(int64_t)fb * R + b] * wb / sb) : (T)0;
       }
     }
   }

@@ -70,7 +70,7 @@ void build_cfg(const pgx_params* p, pgx::PlanCfg& c) {
               "unknown precision");
   PGX_REQUIRE(p->pair_mode == PGX_PAIR_S_MU || p->pair_mode == PGX_PAIR_RP_PI, PGX_EINVAL,
               "unknown pair_mode");
-  PGX_REQUIRE(p->out_mode >= PGX_OUT_SHELL && p->out_mode <= PGX_OUT_RP_PI, PGX_EINVAL,
+  PGX_REQUIRE(p->out_mode >= PGX_OUT_SHELL && p->out_mode <= PGX_OUT_GSW, PGX_EINVAL,
               "unknown out_mode");
   PGX_REQUIRE(p->qeff_mode >= PGX_QEFF_NOTSQ && p->qeff_mode <= PGX_QEFF_CONST_XIW, PGX_EINVAL,
               "unknown qeff_mode");
@@ -85,8 +85,17 @@ void build_cfg(const pgx_params* p, pgx::PlanCfg& c) {
   c.pair_dmax = p->pair_dmax;
   c.p1 = edges(p->p1_edges, p->n_p1, "p1_edges");
   c.p2 = edges(p->p2_edges, p->n_p2, "p2_edges");
-  c.o1 = edges(p->o1_edges, p->n_o1, "o1_edges");
-  if (c.out_mode != PGX_OUT_SHELL) c.o2 = edges(p->o2_edges, p->n_o2, "o2_edges");
+  const bool gsw = c.out_mode == PGX_OUT_GSW;
+  if (gsw) {
+    const double w[5] = {p->w_sigma, p->w_rs, p->w_s0, p->w_rcut, p->w_rmax};
+    for (double v : w) PGX_REQUIRE(std::isfinite(v), PGX_EINVAL, "weighting parameters must be finite");
+    PGX_REQUIRE(p->w_sigma > 0 && p->w_s0 > 0 && p->w_rcut >= 0 && p->w_rcut < p->w_rmax, PGX_EINVAL,
+                "weighting parameters need w_sigma > 0, w_s0 > 0, 0 <= w_rcut < w_rmax");
+    c.o1 = {p->w_rcut, p->w_rmax};  // radial extent: the window and the cut test
+  } else {
+    c.o1 = edges(p->o1_edges, p->n_o1, "o1_edges");
+    if (c.out_mode != PGX_OUT_SHELL) c.o2 = edges(p->o2_edges, p->n_o2, "o2_edges");
+  }
   PGX_REQUIRE(c.p1[0] >= 0, PGX_EINVAL, "p1_edges must be >= 0");
   PGX_REQUIRE(c.p2[0] >= 0, PGX_EINVAL, "p2_edges must be >= 0");
   PGX_REQUIRE(c.o1[0] >= 0, PGX_EINVAL, "o1_edges must be >= 0");
@@ -116,7 +125,7 @@ void build_cfg(const pgx_params* p, pgx::PlanCfg& c) {
   const int n_p1 = (int)c.p1.size() - 1, n_p2 = (int)c.p2.size() - 1;
   c.F = n_p1 * n_p2;
   c.n_fp = (c.F + 1) / 2;
-  const int n_o2 = c.out_mode == PGX_OUT_SHELL ? 1 : (int)c.o2.size() - 1;
+  const int n_o2 = (c.out_mode == PGX_OUT_SHELL || gsw) ? 1 : (int)c.o2.size() - 1;
   c.R = ((int)c.o1.size() - 1) * n_o2;
   PGX_REQUIRE(c.R <= pgx::kRMax, PGX_ENOTSUP, "too many output bins");
   PGX_REQUIRE((int64_t)c.F * N * N + 1 < (int64_t)INT32_MAX, PGX_ENOTSUP, "n_fields * N^2 too large");
@@ -124,7 +133,15 @@ void build_cfg(const pgx_params* p, pgx::PlanCfg& c) {
   pgx::HostBins& hb = c.bins;
   hb.mode = c.out_mode;
   hb.n2 = n_o2;
-  if (c.out_mode == PGX_OUT_RP_PI) {
+  if (gsw) {
+    hb.g[0] = delta;
+    hb.g[1] = p->w_s0;
+    hb.g[2] = p->w_rs;
+    hb.g[3] = 1.0 / (2.0 * p->w_sigma * p->w_sigma);
+    const double qc = p->w_rcut / delta, qm = p->w_rmax / delta;
+    hb.rcut2 = qc * qc;
+    hb.rmax2 = qm * qm;
+  } else if (c.out_mode == PGX_OUT_RP_PI) {
     hb.lut1 = pgx::bin_lut(c.o1, delta, (int64_t)2 * w1 * w1 + 1);
     hb.lut2 = pgx::bin_lut(c.o2, delta, (int64_t)wz * wz + 1);
   } else {
@@ -135,11 +152,15 @@ void build_cfg(const pgx_params* p, pgx::PlanCfg& c) {
     }
   }
   c.nb.assign(c.R, 0);
+  c.nbw.assign(c.R, 0.0);
   for (int k = -wz; k <= wz; ++k)
     for (int j = -w1; j <= w1; ++j)
       for (int i = -w1; i <= w1; ++i) {
         const int b = hb.classify(i, j, k);
-        if (b >= 0) c.nb[b] += 1;
+        if (b >= 0) {
+          c.nb[b] += 1;
+          c.nbw[b] += hb.weight(i, j, k);
+        }
       }
   // pair-bin volumes
   c.vol.clear();
@@ -180,6 +201,12 @@ pgx_status pgx_plan_info(const pgx_plan* plan, int32_t* n_fields, int32_t* n_out
 pgx_status pgx_out_counts(const pgx_plan* plan, int64_t* n_b) {
   if (!plan || !n_b) return fail(PGX_EINVAL, "NULL argument");
   for (int b = 0; b < plan->cfg.R; ++b) n_b[b] = plan->cfg.nb[b];
+  return PGX_OK;
+}
+
+pgx_status pgx_out_norms(const pgx_plan* plan, double* norm) {
+  if (!plan || !norm) return fail(PGX_EINVAL, "NULL argument");
+  for (int b = 0; b < plan->cfg.R; ++b) norm[b] = plan->cfg.nbw[b];
   return PGX_OK;
 }
 

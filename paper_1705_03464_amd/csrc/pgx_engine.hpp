@@ -18,7 +18,8 @@ struct PlanCfg {
   int F = 0, R = 0, n_fp = 0;
   int pw[3] = {0, 0, 0};
   HostBins bins;
-  std::vector<int64_t> nb;
+  std::vector<int64_t> nb;   // lattice vectors per output bin (weight > 0)
+  std::vector<double> nbw;   // normalisation per output bin: n_b, or sum of weights
   std::vector<double> vol;
 };
 
@@ -230,7 +231,7 @@ template <typename T, int N> struct Engine : EngineBase {
   // field pair, 1 = dual form (one transform per pair of output bins, then a
   // gather at the pair midpoints)
   int algo = 0;
-  DBuf coef_id, bscale, bfa, bfb, GV;  // dual form: bin coefficients 1/n_b (and their FP32 values), bin-pair slots, gathered values
+  DBuf coef_id, bscale, bfa, bfb, GV;  // dual form: bin coefficients 1/norm_b (and their FP32 values), bin-pair slots, gathered values
   DBuf FSC;  // per-field FP32 transform scale 1 / Wsum_f
   // constant tables
   DBuf tw_alt;
@@ -284,11 +285,10 @@ template <typename T, int N> struct Engine : EngineBase {
     static_assert((N / W) * N % 8 == 0 && (N / WH) * N % 8 == 0, "z-pass grids are whole XCD rounds");
     upload(tw, twiddles<Sh>());
     upload(tw_alt, twiddles<ShA>());
-    upload(lut1, cfg.bins.lut1);
+    upload(lut1, cfg.bins.lut1.empty() ? std::vector<int16_t>{-1} : cfg.bins.lut1);
     upload(lut2, cfg.bins.lut2.empty() ? std::vector<int16_t>{-1} : cfg.bins.lut2);
     upload(mu2, cfg.bins.mu2.empty() ? std::vector<double>{0.0} : cfg.bins.mu2);
-    std::vector<double> nbv(cfg.nb.begin(), cfg.nb.end());
-    upload(nbd, nbv);
+    upload(nbd, cfg.nbw);
     upload(vold, cfg.vol);
     std::vector<double> a1(cfg.p1.size()), a2(cfg.p2.size());
     for (size_t i = 0; i < a1.size(); ++i) a1[i] = cfg.p1[i] * cfg.p1[i];
@@ -314,7 +314,7 @@ template <typename T, int N> struct Engine : EngineBase {
     std::vector<double> ci((size_t)R * R, 0.0);
     std::vector<float> bs((size_t)std::max(R, 1), 1.0f);
     for (int b = 0; b < R; ++b) {
-      const double sc = cfg.nb[b] > 0 ? 1.0 / (double)cfg.nb[b] : 1.0;
+      const double sc = cfg.nbw[b] > 0 ? 1.0 / cfg.nbw[b] : 1.0;
       bs[b] = (float)sc;
       ci[(size_t)b * R + b] = (double)bs[b];  // the generator casts to T: same value
     }
@@ -367,6 +367,9 @@ template <typename T, int N> struct Engine : EngineBase {
     bm.lut2 = lut2.as<int16_t>();
     bm.lut2_n = (int)cfg.bins.lut2.size();
     bm.mu2 = mu2.as<double>();
+    for (int i = 0; i < 4; ++i) bm.g[i] = cfg.bins.g[i];
+    bm.rcut2 = cfg.bins.rcut2;
+    bm.rmax2 = cfg.bins.rmax2;
     return bm;
   }
 

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/pgx.h"
+#include "pgx_weight.hpp"
 
 namespace pgx {
 
@@ -96,8 +97,13 @@ struct HostBins {
   int mode, n2;
   std::vector<int16_t> lut1, lut2;
   std::vector<double> mu2;
+  // GSW: gsw_value parameters and the cuts r_perp >= r_cut, |r| <= r_max as
+  // squared lattice lengths (r / cell)^2
+  double g[4] = {1.0, 0.0, 0.0, 0.0};
+  double rcut2 = 0.0, rmax2 = 0.0;
   int classify(int i, int j, int k) const {
     const int xy = i * i + j * j, kk = k * k;
+    if (mode == 3) return ((double)xy >= rcut2 && (double)(xy + kk) <= rmax2) ? 0 : -1;
     if (mode == 2) {
       if (xy >= (int)lut1.size() || kk >= (int)lut2.size()) return -1;
       const int b1 = lut1[xy], b2 = lut2[kk];
@@ -114,6 +120,10 @@ struct HostBins {
     int kb = 0;
     for (int e = 1; e < n2; ++e) kb += (kd >= mu2[e] * md) ? 1 : 0;
     return b1 * n2 + kb;
+  }
+  // weight of a classified offset: 1 for the indicator bins
+  double weight(int i, int j, int k) const {
+    return mode == 3 ? gsw_value(i * i + j * j, k * k, g) : 1.0;
   }
 };
 

@@ -6,6 +6,7 @@
 // two real correlations in its real and imaginary parts.
 #pragma once
 #include "pgx_fft.hpp"
+#include "pgx_weight.hpp"
 
 #include <type_traits>
 
@@ -511,17 +512,20 @@ k_zcross(const C<T>* in, int64_t in_slot, const uint8_t* __restrict__ pflag,
 // and its negative share a bin.
 // ----------------------------------------------------------------------------
 struct BinMap {
-  int mode;             // 0 shell, 1 r_mu, 2 rp_pi
+  int mode;             // 0 shell, 1 r_mu, 2 rp_pi, 3 Gaussian-sigmoid weight
   int n2;               // number of second-axis bins (1 for shell)
   const int16_t* lut1;  // shell/r_mu: indexed by m = i'^2+j'^2+k'^2 ; rp_pi: by i'^2+j'^2
   int lut1_n;
   const int16_t* lut2;  // rp_pi: indexed by k'^2
   int lut2_n;
   const double* mu2;    // r_mu: squared mu edges (n2 + 1)
+  double g[4];          // Gaussian-sigmoid: gsw_value parameters
+  double rcut2, rmax2;  // Gaussian-sigmoid: cuts as squared lattice lengths
 };
 
 __device__ __forceinline__ int classify_bin(const BinMap& bm, int i, int j, int k) {
   const int xy = i * i + j * j, kk = k * k;
+  if (bm.mode == 3) return ((double)xy >= bm.rcut2 && (double)(xy + kk) <= bm.rmax2) ? 0 : -1;
   if (bm.mode == 2) {
     if (xy >= bm.lut1_n || kk >= bm.lut2_n) return -1;
     const int b1 = bm.lut1[xy], b2 = bm.lut2[kk];
@@ -538,6 +542,12 @@ __device__ __forceinline__ int classify_bin(const BinMap& bm, int i, int j, int 
   int kb = 0;
   for (int e = 1; e < bm.n2; ++e) kb += (kd >= bm.mu2[e] * md) ? 1 : 0;
   return b1 * bm.n2 + kb;
+}
+
+// weight of an offset classified into a bin: 1 for the indicator bins, the
+// Gaussian-sigmoid value in mode 3
+__device__ __forceinline__ double bin_weight(const BinMap& bm, int i, int j, int k) {
+  return bm.mode == 3 ? gsw_value(i * i + j * j, k * k, bm.g) : 1.0;
 }
 
 // ----------------------------------------------------------------------------
@@ -575,8 +585,9 @@ k_xinv_bins(const C<T>* __restrict__ in, int64_t in_slot, int pwx, int pwy, int 
       if (px <= 2 * pwx) {
         const int b = classify_bin(bm, px - pwx, jj, kk);
         if (b >= 0) {
-          atomicAdd(&acc[b], (double)v[m].x);
-          atomicAdd(&acc[R + b], (double)v[m].y);
+          const double wb = bin_weight(bm, px - pwx, jj, kk);
+          atomicAdd(&acc[b], wb * (double)v[m].x);
+          atomicAdd(&acc[R + b], wb * (double)v[m].y);
         }
       }
     }

@@ -296,7 +296,7 @@ static __global__ void k_bins_dense(const C<T>* __restrict__ h, int N, int pwx, 
     const int b = classify_bin(bm, i, j, k);
     if (b >= 0) {
       const int64_t idx = ((int64_t)(k & (N - 1)) * N + (j & (N - 1))) * N + (i & (N - 1));
-      atomicAdd(&acc[b], (double)h[idx].x);
+      atomicAdd(&acc[b], bin_weight(bm, i, j, k) * (double)h[idx].x);
     }
   }
   __syncthreads();

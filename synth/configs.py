@@ -5,7 +5,9 @@ Sizes follow the five benchmark workloads of this project (plain FP64 at
 weighted 512^3 HOD-fit case) plus a tiny 64^3 case for brute-force gradient
 checks.  Pair modes: "s_mu" (separation s, |mu| = |d_z|/s w.r.t. the z line of
 sight) and "rp_pi" (r_p, |pi| = |d_z| inside a sphere |d| < dmax).  Output
-modes: "shell", "r_mu", "rp_pi".
+modes: "shell", "r_mu", "rp_pi", and "gsw" (the paper's Gaussian-sigmoid
+weighting function as one weighted output bin; o1_edges then holds its
+parameters sigma, r_s, s_0, r_cut and the cut radius r_max).
 """
 from __future__ import annotations
 
@@ -51,6 +53,8 @@ class Workload:
 
     @property
     def n_out(self) -> int:
+        if self.out_mode == "gsw":
+            return 1
         n2 = 1 if self.o2_edges is None else len(self.o2_edges) - 1
         return (len(self.o1_edges) - 1) * n2
 
@@ -62,6 +66,16 @@ class Workload:
 
 
 _AH_Z05 = flat_lcdm_aH(0.5, 0.31)
+
+# The paper's weighting-function table: (sigma, r_s, s_0, r_cut) and xi(d_w)
+# for maximum pair separations 10 and 30 Mpc/h; the cut radius of the lattice
+# window is 5 sigma (the Gaussian is down to 4e-6 there).
+GSW_DP10 = dict(sigma=30.0, rs=20.0, s0=0.8, rcut=10.0, xi_dw=0.362)
+GSW_DP30 = dict(sigma=50.0, rs=35.0, s0=0.5, rcut=20.0, xi_dw=0.104)
+
+
+def gsw_params(t, rmax_sigmas=5.0):
+    return np.array([t["sigma"], t["rs"], t["s0"], t["rcut"], rmax_sigmas * t["sigma"]])
 
 _CFG1_CAT = dict(n_halos=40000, mass_dist="powerlaw", m_lo=1e13, m_hi=2e15, slope=1.9,
                  placement="sp", sat_mode="poisson", n_field=800000)
@@ -99,6 +113,14 @@ CONFIGS = {
         catalog_kw=dict(_CFG1_CAT, sat_mode="candidates", n_candidates=49, n_field=0),
         weighted=True, seed=1004,
         description="weighted HOD candidates, L=1000, 512^3, 20 s-bins x 20 r-bins, fwd+bwd"),
+    "cfg1w": Workload(
+        name="cfg1w", L=1000.0, N=512, precision="fp32", pair_mode="s_mu",
+        p1_edges=logbins(0.5, 10.0, 20), p2_edges=linbins(0.0, 1.0, 10),
+        out_mode="gsw", o1_edges=gsw_params(GSW_DP10), o2_edges=None,
+        qeff_mode="const", xi_w_const=GSW_DP10["xi_dw"],
+        catalog_kw=dict(_CFG1_CAT), seed=1001,
+        description="production catalogue, L=1000, 512^3, 20 log s x 10 |mu| fields, the paper's "
+                    "weighting function for d_p,max = 10 (one weighted bin, Q_eff with its xi(d_w))"),
     "cfg4tiny": Workload(
         name="cfg4tiny", L=125.0, N=64, precision="fp32", pair_mode="s_mu",
         p1_edges=logbins(0.5, 10.0, 20), p2_edges=np.array([0.0, 1.0]),

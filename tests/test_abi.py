@@ -43,12 +43,14 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, s), s
 
 
-@pytest.mark.parametrize("name", ["cfg0", "cfg1", "cfg2", "cfg3", "cfg4", "cfg4tiny"])
+@pytest.mark.parametrize("name", ["cfg0", "cfg1", "cfg2", "cfg3", "cfg4", "cfg4tiny", "cfg1w"])
 def test_out_counts_and_volumes_match_oracle(name):
     wl = CONFIGS[name]
     plan = Plan.from_workload(wl)
     table = OB.lattice_table(wl.out_mode, wl.o1_edges, wl.o2_edges, wl.L, wl.N)
     assert np.array_equal(plan.out_counts(), table[2])
+    norms = OB.lattice_weights(wl.out_mode, wl.o1_edges, wl.o2_edges, wl.L, wl.N, table)[1]
+    assert np.allclose(plan.out_norms(), norms, rtol=1e-12, atol=0)
     dmax = wl.pair_dmax if wl.pair_mode == "rp_pi" else None
     vol = OF.field_volumes(wl.pair_mode, wl.p1_edges, wl.p2_edges, dmax)
     assert np.allclose(plan.field_volumes(), vol, rtol=1e-12, atol=0)
@@ -63,6 +65,16 @@ def test_out_counts_other_modes(mode):
     o2 = None if mode == "shell" else (linbins(0.0, 1.0, 5) if mode == "r_mu" else linbins(0.0, 30.0, 4))
     plan = Plan(L, N, linbins(0.5, 10, 3), [0.0, 1.0], o1, o2, out_mode=mode)
     assert np.array_equal(plan.out_counts(), OB.lattice_table(mode, o1, o2, L, N)[2])
+
+
+def test_weighted_bin_parameters_are_validated():
+    base = dict(L=200.0, N=64, p1_edges=linbins(0.5, 8, 3), p2_edges=[0.0, 1.0], out_mode="gsw")
+    Plan(o1_edges=[15.0, 10.0, 0.8, 5.0, 60.0], **base)
+    for par in ([0.0, 10.0, 0.8, 5.0, 60.0], [15.0, 10.0, -0.8, 5.0, 60.0],
+                [15.0, 10.0, 0.8, 70.0, 60.0], [15.0, 10.0, 0.8, 5.0, 150.0],
+                [15.0, 10.0, np.nan, 5.0, 60.0]):
+        with pytest.raises(PgxError):
+            Plan(o1_edges=par, **base)
 
 
 def bad(**kw):

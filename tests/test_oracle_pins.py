@@ -413,3 +413,91 @@ def test_cic_weights_by_hand():
     assert nz.keys() == exp.keys()
     for k, v in exp.items():
         assert nz[k] == v
+
+
+# ---------------------------------------------------------------- PW: the paper's weighting function
+from synth.configs import GSW_DP10, GSW_DP30, gsw_params  # noqa: E402
+
+
+def test_pw_lattice_support_closed_form():
+    """The weighted bin holds exactly the lattice vectors with r_perp >= r_cut
+    and |r| <= r_max: for each (i', j') with i'^2 + j'^2 >= t_cut there are
+    2 floor(sqrt(t_max - i'^2 - j'^2)) + 1 values of k' (t = (r / Delta)^2)."""
+    L, N = 200.0, 64
+    par = np.array([15.0, 10.0, 0.8, 5.0, 60.0])
+    delta = L / N
+    tc, tm = (par[3] / delta) ** 2, (par[4] / delta) ** 2
+    w = int(np.floor(par[4] / delta))
+    exp = 0
+    for i in range(-w, w + 1):
+        for j in range(-w, w + 1):
+            xy = i * i + j * j
+            if xy >= tc and xy <= tm:
+                exp += 2 * math.isqrt(int(math.floor(tm - xy))) + 1
+    table = B.lattice_table("gsw", par, None, L, N)
+    assert table[2].tolist() == [exp]
+    assert np.array_equal(table[2], B.bin_counts_bruteforce("gsw", par, None, L, N))
+
+
+@pytest.mark.parametrize("row", [GSW_DP10, GSW_DP30])
+def test_pw_small_jump_at_the_cavity(row):
+    """The paper picks the parameters so that W's jump at r_cut is small
+    (Section "weighting", figure of the weighting functions): on the r_perp
+    axis W(r_cut) is under 1e-2 of W's maximum, for both rows of its table.
+    A sigmoid of the wrong sign or centre fails this."""
+    L, N = 1000.0, 8192  # fine lattice along the axis
+    delta = L / N
+    par = gsw_params(row)
+    i = np.arange(0, int(par[4] / delta))
+    W = B.gsw_weight(i, 0 * i, 0 * i, par, L, N)
+    icut = int(np.ceil(par[3] / delta))
+    assert W[icut] < 1e-2 * W.max()
+    # and the peak sits outside the cavity, beyond r_s
+    assert i[np.argmax(W)] * delta > par[1]
+
+
+def test_pw_depends_on_r_perp_and_r_par_only():
+    """W is a function of r_perp (x, y) and |r_par| (z): equal for (3, 4, k)
+    and (5, 0, k) and (0, -5, k), even in k, and not symmetric between the
+    transverse and the line-of-sight axes."""
+    L, N = 100.0, 64
+    par = np.array([12.0, 6.0, 0.7, 3.0, 40.0])
+    for k in (0, 2, 7):
+        a = B.gsw_weight(3, 4, k, par, L, N)
+        assert np.isclose(a, B.gsw_weight(5, 0, k, par, L, N), rtol=1e-14)
+        assert np.isclose(a, B.gsw_weight(0, -5, -k, par, L, N), rtol=1e-14)
+    assert not np.isclose(B.gsw_weight(5, 0, 0, par, L, N), B.gsw_weight(0, 0, 5, par, L, N))
+
+
+def test_pw_flat_limit_is_the_region_mean():
+    """With a very wide Gaussian and a steep sigmoid centred inside the
+    cavity, W is 1 on its support: the weighted bin is then the plain mean of
+    C over {r_perp >= r_cut, |r| <= r_max}, taken here with a boolean mask."""
+    rng = np.random.default_rng(4)
+    L, N = 100.0, 32
+    C = rng.normal(size=(N, N, N))
+    par = np.array([1e9, 1.0, 1e3, 7.0, 30.0])
+    table = B.lattice_table("gsw", par, None, L, N)
+    bw = B.lattice_weights("gsw", par, None, L, N, table)
+    got = B.bin_average(C, table, 1, bw)[0]
+    a = np.arange(N)
+    a = np.where(a < N // 2, a, a - N) * (L / N)
+    X, Y, Z = np.meshgrid(a, a, a, indexing="ij")
+    mask = (X * X + Y * Y >= 7.0 ** 2) & (X * X + Y * Y + Z * Z <= 30.0 ** 2)
+    assert np.isclose(got, C[mask].mean(), rtol=1e-12)
+
+
+def test_pw_pair_field_equal_galaxy_field_gives_b_one():
+    """P6 with the weighting function: the weighted estimator is normalised
+    so that a pair field equal to the galaxy field has b_pg = 1."""
+    rng = np.random.default_rng(2)
+    L, N = 100.0, 32
+    pos = rng.random((2000, 3)) * L
+    pos[:500] = np.mod(pos[500:1000] + rng.normal(0, 3, (500, 3)), L)
+    d = overdensity(cic_assign(pos, None, N, L), 2000.0)
+    par = np.array([12.0, 6.0, 0.7, 3.0, 40.0])
+    table = B.lattice_table("gsw", par, None, L, N)
+    bw = B.lattice_weights("gsw", par, None, L, N, table)
+    xi = B.bin_average(fft_corr(d, d), table, 1, bw)
+    fin = FZ.finalize(xi, xi[None, :], np.array([10.0]), 2000.0, L, np.array([1.0]), "const", 0.362)
+    assert np.allclose(fin["b_pg"], 1.0, rtol=1e-13)
