@@ -13,7 +13,11 @@ def __getattr__(name):
     if name in ("PairGalaxyXi", "pair_galaxy_xi", "hod_weights"):
         from . import autograd
         return getattr(autograd, name)
+    if name in ("HodFit", "fit_hod", "projected_2pcf"):
+        from . import hodfit
+        return getattr(hodfit, "fit" if name == "fit_hod" else name)
     raise AttributeError(name)
 
 
-__all__ = ["Plan", "PgxError", "load_library", "PairGalaxyXi", "pair_galaxy_xi", "hod_weights"]
+__all__ = ["Plan", "PgxError", "load_library", "PairGalaxyXi", "pair_galaxy_xi", "hod_weights",
+           "HodFit", "fit_hod", "projected_2pcf"]

@@ -1,0 +1,119 @@
+"""HOD fitting on the adjoint (gradient descent on the HOD parameters through
+the autograd wrapper), with the projected 2PCF as a second loss term, on the
+tiny HOD subset.  Targets come from the oracle at the alpha = 1.05 row of the
+paper's HOD-parameter table."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import grad as OG
+from oracle.finalize import field_volumes
+from oracle.pipeline import forward as oracle_forward
+from synth import get_config
+from synth.configs import HOD_FIDUCIAL, HOD_TARGET, linbins, logbins
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+KEYS = ("logMcut", "logM1", "sigma", "alpha")
+TH0 = np.array([HOD_FIDUCIAL[k] for k in KEYS])
+THT = np.array([HOD_TARGET[k] for k in KEYS])
+DMAX = 10.0
+RP = linbins(0.0, 8.0, 8)
+
+
+def _say(m):
+    print(m, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def dev(a, dt=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+
+
+def rp_workload(wl):
+    # one |pi| bin over the pair sphere; the output bins are not used by the loss
+    return wl.scaled(name="rp", pair_mode="rp_pi", p1_edges=RP, p2_edges=np.array([0.0, DMAX]),
+                     pair_dmax=DMAX, out_mode="shell", o1_edges=logbins(10.0, 60.0, 2))
+
+
+def oracle_wp(cat, wl_rp, w):
+    o = oracle_forward(cat, wl_rp, w=w)
+    V = field_volumes("rp_pi", RP, np.array([0.0, DMAX]), DMAX)
+    return o["xi_dp"] * V / (np.pi * (RP[1:] ** 2 - RP[:-1] ** 2))
+
+
+def setup():
+    from paper_1705_03464_amd import HodFit, Plan
+    wl = get_config("cfg4tiny")
+    wl_rp = rp_workload(wl)
+    cat = wl.catalog()
+    w_t = OG.hod_weights(cat.halo_mass, cat.kind, THT).astype(np.float32).astype(np.float64)
+    ot = oracle_forward(cat, wl, w=w_t)
+    tb = ot["b_pg"]
+    # b_pg divides by xi_gg: use the bins where it is well away from zero
+    mask = np.broadcast_to(np.abs(ot["xi_gg"])[None, :] > 0.05, tb.shape)
+    tw = oracle_wp(cat, wl_rp, w_t)
+    pb = Plan.from_workload(wl, precision="fp32")
+    pb.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
+    pw = Plan.from_workload(wl_rp, precision="fp32")
+    pw.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
+    hm = dev(cat.halo_mass)
+    kind = torch.as_tensor(cat.kind.astype(np.int64), device="cuda")
+    scale = dev(np.maximum(np.abs(tw), 1.0))
+    hf = HodFit(pb, hm, kind, dev(tb), plan_w=pw, rp_edges=RP, target_w=dev(tw), scale_w=scale,
+                mask_b=torch.as_tensor(np.ascontiguousarray(mask), device="cuda"))
+    return wl, wl_rp, cat, hf
+
+
+def test_projected_2pcf_and_its_gradient_match_the_oracle():
+    from paper_1705_03464_amd import hod_weights, pair_galaxy_xi, projected_2pcf
+    from paper_1705_03464_amd.hodfit import annulus_areas
+    wl, wl_rp, cat, hf = setup()
+    w_np = OG.hod_weights(cat.halo_mass, cat.kind, TH0).astype(np.float32).astype(np.float64)
+    theta = torch.tensor(TH0, dtype=torch.float64, device="cuda", requires_grad=True)
+    w = hod_weights(theta, hf.hm, hf.kind)
+    out = pair_galaxy_xi(hf.plan_w, w)
+    wp = projected_2pcf(out["xi_dp"], hf.vol_w, hf.area_w)
+    ref = oracle_wp(cat, wl_rp, w_np)
+    _say(f"  w_p gpu {wp.detach().cpu().numpy()} oracle {ref}")
+    assert np.allclose(wp.detach().cpu().numpy(), ref, rtol=1e-9, atol=1e-12)
+    assert np.allclose(annulus_areas(RP), np.pi * (RP[1:] ** 2 - RP[:-1] ** 2))
+    g = np.random.default_rng(4).normal(size=ref.size)
+    (wp * dev(g)).sum().backward()
+    gth = theta.grad.cpu().numpy()
+    V = field_volumes("rp_pi", RP, np.array([0.0, DMAX]), DMAX)
+    gx = g * V / (np.pi * (RP[1:] ** 2 - RP[:-1] ** 2))
+    gw_ref, _ = OG.weight_gradient(cat, wl_rp, w_np, g_xidp=gx)
+    exp = gw_ref @ OG.hod_weight_jacobian(cat.halo_mass, cat.kind, TH0)
+    _say(f"  d<g, w_p>/d theta gpu {gth} oracle {exp}")
+    assert np.allclose(gth, exp, rtol=2e-3, atol=1e-3 * np.abs(exp).max())
+
+
+def test_gradient_descent_fit_reduces_the_loss():
+    """Adam on theta from the fiducial HOD: the combined loss (b_pg on the
+    well-conditioned bins and the projected 2PCF) falls by at least 5x in 60
+    steps, and alpha (the parameter the table's perturbed row changes) moves
+    toward its target; the loss at the target parameters is far below the
+    starting one (the GPU and the oracle agree on the targets).  The other
+    parameters need not approach theirs: on 2 000 candidates the loss has
+    near-degenerate directions (sigma moves away as alpha and log Mcut move
+    in)."""
+    from paper_1705_03464_amd import fit_hod
+    wl, wl_rp, cat, hf = setup()
+    th_t = torch.tensor(THT, dtype=torch.float64, device="cuda")
+    with torch.no_grad():
+        l_t = [float(v) for v in hf.loss(th_t)]
+    theta, hist = fit_hod(hf, TH0, steps=60, lr=0.01,
+                          callback=lambda k, th, h: _say(f"  step {k}: loss {h[0]:.4e} (b {h[1]:.3e}, w {h[2]:.3e}) theta {np.round(th, 4)}") if k % 10 == 0 else None)
+    _say(f"  loss start {hist[0][0]:.4e} end {hist[-1][0]:.4e}; at target {l_t[0]:.3e}; theta {theta.cpu().numpy()} target {THT}")
+    assert hist[-1][0] <= hist[0][0] / 5.0
+    assert l_t[0] <= 1e-3 * hist[0][0]
+    assert abs(float(theta[3]) - THT[3]) < abs(TH0[3] - THT[3])

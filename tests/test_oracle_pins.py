@@ -501,3 +501,40 @@ def test_pw_pair_field_equal_galaxy_field_gives_b_one():
     xi = B.bin_average(fft_corr(d, d), table, 1, bw)
     fin = FZ.finalize(xi, xi[None, :], np.array([10.0]), 2000.0, L, np.array([1.0]), "const", 0.362)
     assert np.allclose(fin["b_pg"], 1.0, rtol=1e-13)
+
+
+# ---------------------------------------------------------------- projected 2PCF (HOD-fit loss)
+def test_projected_2pcf_thin_annulus_is_the_paper_column():
+    """The projected correlation per r_p bin is xi(d_p) V / A (V the annulus-
+    slab volume cut by the pair sphere, A the annulus area).  For a thin
+    annulus V / A is the column length 2 d_par,max = 2 sqrt(d_max^2 - d_perp^2)
+    of the paper's equation 2PCF_los_integrated_explicit."""
+    dmax = 30.0
+    for r in (1.0, 10.0, 25.0, 29.0):
+        e = np.array([r, r + 1e-4])
+        V = FZ.field_volumes("rp_pi", e, np.array([0.0, dmax]), dmax)[0]
+        A = math.pi * (e[1] ** 2 - e[0] ** 2)
+        assert np.isclose(V / A, 2.0 * math.sqrt(dmax * dmax - r * r), rtol=1e-4)
+
+
+def test_projected_2pcf_of_a_poisson_catalogue_is_zero():
+    """Uniform random galaxies: every r_p bin's projected correlation is
+    consistent with zero (within 4 Poisson standard deviations)."""
+    from oracle.pairs import pairs_for
+    from synth.catalog import Catalog
+    rng = np.random.default_rng(9)
+    L, n, dmax = 100.0, 20000, 10.0
+    pos = rng.random((n, 3)) * L
+    cat = Catalog(L, pos[:, 0].copy(), pos[:, 1].copy(), pos[:, 2].copy(), np.zeros(n), np.zeros(n, np.int8))
+    rp = linbins(0.0, 8.0, 4)
+    wl = Workload(name="t", L=L, N=64, precision="fp64", pair_mode="rp_pi", p1_edges=rp,
+                  p2_edges=np.array([0.0, dmax]), pair_dmax=dmax, out_mode="shell",
+                  o1_edges=logbins(5.0, 20.0, 2), o2_edges=None, catalog_kw={})
+    pr = pairs_for(cat, wl)
+    V = FZ.field_volumes("rp_pi", rp, np.array([0.0, dmax]), dmax)
+    xdp = FZ.xi_dp(pr["wsum"], float(n), L, V)
+    A = np.pi * (rp[1:] ** 2 - rp[:-1] ** 2)
+    wp = xdp * V / A
+    expected = n * n / 2.0 * V / L ** 3
+    sd = np.sqrt(expected) / expected * V / A
+    assert np.all(np.abs(wp) < 4.0 * sd), (wp, sd)
