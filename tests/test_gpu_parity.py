@@ -40,10 +40,14 @@ def dev(cat):
     return f(cat.x), f(cat.y), f(cat.z)
 
 
-def run(wl, cat, precision, w=None, batch=0):
+def run(wl, cat, precision, w=None, batch=0, algo=None, autotune=False):
     from paper_1705_03464_amd import Plan
     plan = Plan.from_workload(wl, precision=precision, batch=batch)
     P, counts = plan.pairs_build(*dev(cat))
+    if algo is not None:
+        plan.set_schedule(plan.schedule()["batch"], 0, 0, 0, algo)
+    if autotune:
+        _say(f"  autotuned {plan.autotune()}")
     wt = None if w is None else torch.as_tensor(np.asarray(w, np.float32), device="cuda")
     out = plan.forward(wt)
     torch.cuda.synchronize()
@@ -195,7 +199,8 @@ def test_forward_small_grids(case, precision):
         assert_fp32_parity(out, ref)
 
 
-def test_empty_field_gives_nan_rows():
+@pytest.mark.parametrize("algo", [0, 1])
+def test_empty_field_gives_nan_rows(algo):
     L = 100.0
     wl = Workload(name="t", L=L, N=64, precision="fp32", pair_mode="s_mu",
                   p1_edges=np.array([0.5, 1.0, 2.0, 9.0]), p2_edges=np.array([0.0, 1.0]),
@@ -206,12 +211,39 @@ def test_empty_field_gives_nan_rows():
     cat = Catalog(L, pos[:, 0].copy(), pos[:, 1].copy(), pos[:, 2].copy(), np.zeros(300),
                   np.zeros(300, np.int8))
     ref = oracle_forward(cat, wl)
-    _, _, counts, out = run(wl, cat, "fp32")
+    _, _, counts, out = run(wl, cat, "fp32", algo=algo)
     assert np.array_equal(counts, ref["counts"])
     for f in range(wl.n_fields):
         if counts[f] == 0:
             assert np.all(np.isnan(out["xi_pg"][f])) and np.all(np.isnan(out["b_pg"][f]))
     assert_fp32_parity(out, ref)
+
+
+@pytest.mark.parametrize("algo", [0, 1])
+def test_catalogue_without_pairs(algo):
+    """Galaxies but no close pair at all: every pair field is empty (NaN
+    rows), xi_gg still meets the oracle, and the adjoint runs (galaxy term
+    only) and meets the oracle's gradient."""
+    from oracle import grad as OG
+    L = 100.0
+    wl = Workload(name="t", L=L, N=64, precision="fp32", pair_mode="s_mu",
+                  p1_edges=np.array([0.5, 1.0, 2.0]), p2_edges=np.array([0.0, 1.0]),
+                  out_mode="shell", o1_edges=logbins(6.0, 40.0, 4), o2_edges=None, catalog_kw={})
+    g = np.arange(4) * 25.0 + 3.0
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")  # 64 galaxies 25 apart: no pair within 2
+    cat = Catalog(L, X.ravel().copy(), Y.ravel().copy(), Z.ravel().copy(), np.zeros(64),
+                  np.zeros(64, np.int8))
+    ref = oracle_forward(cat, wl)
+    plan, P, counts, out = run(wl, cat, "fp32", algo=algo)
+    assert P == 0 and not counts.any()
+    assert np.all(np.isnan(out["xi_pg"]))
+    assert xi_err_ok(out["xi_gg"], ref["xi_gg"]) <= 1.0
+    w = np.random.default_rng(1).uniform(0.5, 1.5, 64).astype(np.float32).astype(np.float64)
+    gg = np.random.default_rng(2).normal(size=wl.n_out)
+    gref, _ = OG.weight_gradient(cat, wl, w, g_xigg=gg)
+    plan.forward(torch.as_tensor(w, dtype=torch.float32, device="cuda"))
+    gw = plan.backward(g_xi_gg=torch.as_tensor(gg, device="cuda")).cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(gw - gref) <= 1e-3 * np.linalg.norm(gref)
 
 
 def test_no_galaxies_is_rejected_cleanly_or_empty():
@@ -246,14 +278,14 @@ def test_cfg2_full_size_sampled_fields():
 
 
 def test_cfg1_full_size_bench_configuration():
-    """The 512^3 production workload in the launch configuration the bench times:
-    all pair counts bit-exact, xi_gg and two sampled pair fields against the
-    FP64 oracle."""
+    """The 512^3 production workload in the launch configuration the bench times
+    (the autotuned schedule): all pair counts bit-exact, xi_gg and two sampled
+    pair fields against the FP64 oracle."""
     wl = get_config("cfg1")
     cat = wl.catalog()
     _say(f"cfg1 n_gal={cat.n}")
     pairs = pairs_for(cat, wl)
-    _, P, counts, out = run(wl, cat, "fp32")
+    _, P, counts, out = run(wl, cat, "fp32", autotune=True)
     assert P == pairs["key"].size
     assert np.array_equal(counts, pairs["counts"])
     fields = [13, 157]
