@@ -6,7 +6,9 @@
 //   U_b  = IDFT(S^_b G)  (= N^3 (S_b * g~), the bin kernel convolved with the
 //                         DC-free galaxy field),
 // with U_b(m_p) the CIC interpolation of U_b at the pair midpoint: the same
-// identity as the adjoint of CIC assignment, exact on the grid.  Bins are
+// identity as the adjoint of CIC assignment, exact on the grid.  The last
+// inverse transform (along x) and that interpolation run together in a
+// sweep along z that holds each point's four CIC lines in LDS.  Bins are
 // packed in pairs (b1, b2) as U = U_b1 + i U_b2 (both real, since S_b is real
 // and even and g is real).  The kernel columns S_b1 + i S_b2 come from the
 // adjoint's kernel generator (x and y transforms of the window) with
@@ -135,41 +137,93 @@ k_zconv(const C<T>* __restrict__ ky_in, int64_t ky_slot, int n_slots, int pwz,
   }
 }
 
-// CIC interpolation of the packed real-space grids U_q (q < n_slots, bins
-// b0 + 2q and b0 + 2q + 1) at every pair midpoint: gv[b][p] (FP32, no pair
-// weight).  One thread per pair; the lower CIC node is (x0, y0, z0) with
-// (y0, z0) from the pair's sort key, weights (1 - f, f) per axis.
-template <typename T>
-static __global__ void k_dual_gather(const int32_t* __restrict__ key, const int32_t* __restrict__ x0,
-                                     const T* __restrict__ fx, const T* __restrict__ fy,
-                                     const T* __restrict__ fz, int64_t P, int N,
-                                     const C<T>* __restrict__ U, int64_t u_slot, int n_slots,
-                                     int b0, int R, float* __restrict__ gv) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= P) return;
-  const int64_t NN = (int64_t)N * N;
-  const int64_t line = key[p] % NN;
-  const int z0 = (int)(line / N), y0 = (int)(line % N), xa = x0[p];
-  const int z1 = (z0 + 1) & (N - 1), y1 = (y0 + 1) & (N - 1), xb = (xa + 1) & (N - 1);
-  const T ax = fx[p], ay = fy[p], az = fz[p];
-  const T wz[2] = {(T)1 - az, az}, wy[2] = {(T)1 - ay, ay};
-  const int zz[2] = {z0, z1}, yy[2] = {y0, y1};
-  for (int q = 0; q < n_slots; ++q) {
-    const C<T>* u = U + q * u_slot;
-    C<T> s{0, 0};
+// Inverse x pass of the dual form fused with the CIC gather, as a sweep
+// along z.  Block = (tile of YT base lines in y, segment of z, slot).  It
+// keeps two z rows of YT + 1 lines in LDS (the lines y_base .. y_base + YT,
+// inverse transformed along x): with row z0 and row z0 + 1 resident, every
+// point whose base line is (y0, z0), y0 in the tile, finds all four lines of
+// its CIC footprint in the block, and its value is written once (no
+// atomics, deterministic).  Then row z0 + 2 replaces row z0, its global
+// loads issued before the gather so they are in flight during it.  Points
+// come from the line-major catalogue (x0, fractions; perm = field-major
+// index of gv).  Bins b1 = b0 + 2 slot, b2 = b1 + 1 (< R).
+template <typename T, typename Sh, int YT>
+static __global__ void __launch_bounds__((YT + 1) * Sh::TPL)
+k_xinv_gather_sweep(PointSet<T> ps, const int32_t* __restrict__ perm, int64_t P,
+                    const C<T>* __restrict__ U, int64_t u_slot, int zlen, int b0, int R,
+                    float* __restrict__ gv, const C<T>* __restrict__ tw_g) {
+  constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>(), NG = YT + 1;
+  constexpr int64_t NN = (int64_t)N * N;
+  __shared__ C<T> tw_s[Sh::tw_entries()];
+  __shared__ C<T> rows[2][NG][LL];
+  load_twiddles<T, Sh>(tw_s, tw_g);
+  const int g = threadIdx.x / TPL, t = threadIdx.x % TPL;
+  const int y_base = blockIdx.x * YT;
+  const int y = (y_base + g) & (N - 1);  // the line this group transforms
+  const int z_lo = blockIdx.y * zlen, z_hi = min(z_lo + zlen, N);
+  const int slot = blockIdx.z;
+  const C<T>* us = U + (int64_t)slot * u_slot;
+  const int b1 = b0 + 2 * slot, b2 = b1 + 1;
+  float* g1 = gv + (int64_t)b1 * P;
+  float* g2 = gv + (int64_t)b2 * P;
+  // row z of this group's line into registers
+  auto load_row = [&](int z, C<T>* v) {
+    const C<T>* src = us + ((int64_t)(z & (N - 1)) * N + y) * N;
 #pragma unroll
-    for (int dz = 0; dz < 2; ++dz)
+    for (int m = 0; m < E; ++m) v[m] = src[t + TPL * m];
+  };
+  // inverse transform of v in buffer `buf`, result stored there
+  auto transform_into = [&](int buf, C<T>* v) {
+    C<T>* line = rows[buf][g];
+    line_fft<Sh, 1>(v, t, line, tw_s, block_sync);
+    block_sync();  // every group has read its last-stage inputs
 #pragma unroll
-      for (int dy = 0; dy < 2; ++dy) {
-        const C<T>* row = u + ((int64_t)zz[dz] * N + yy[dy]) * N;
-        const C<T> a = row[xa], b = row[xb];
-        const T w = wz[dz] * wy[dy];
-        s.x += w * (((T)1 - ax) * a.x + ax * b.x);
-        s.y += w * (((T)1 - ax) * a.y + ax * b.y);
+    for (int m = 0; m < E; ++m) line[lpad(t + TPL * m)] = v[m];
+  };
+  C<T> v[E];
+  load_row(z_lo, v);
+  block_sync();  // twiddles
+  transform_into(0, v);
+  load_row(z_lo + 1, v);
+  block_sync();
+  transform_into(1, v);
+  block_sync();
+  for (int z0 = z_lo; z0 < z_hi; ++z0) {
+    const int cur = (z0 - z_lo) & 1;
+    const bool more = z0 + 1 < z_hi;
+    if (more) load_row(z0 + 2, v);  // in flight during the gather
+    // gather: group g < YT serves base line (y_base + g, z0)
+    const int y0 = y_base + g;
+    if (g < YT && y0 < N) {
+      const C<T>* a0 = rows[cur][g];
+      const C<T>* a1 = rows[cur][g + 1];
+      const C<T>* c0 = rows[cur ^ 1][g];
+      const C<T>* c1 = rows[cur ^ 1][g + 1];
+      const int key = z0 * N + y0;
+      const int s = ps.line_start[key], e = ps.line_start[key + 1];
+      for (int k = s + t; k < e; k += TPL) {
+        const T fx = ps.fx[k], fy = ps.fy[k], fz = ps.fz[k];
+        const int xa = ps.x0[k], xb = (xa + 1) & (N - 1);
+        const int la = lpad(xa), lb = lpad(xb);
+        const T w00 = ((T)1 - fy) * ((T)1 - fz), w10 = fy * ((T)1 - fz);
+        const T w01 = ((T)1 - fy) * fz, w11 = fy * fz;
+        const T ax = (T)1 - fx;
+        const C<T> p00a = a0[la], p00b = a0[lb], p10a = a1[la], p10b = a1[lb];
+        const C<T> p01a = c0[la], p01b = c0[lb], p11a = c1[la], p11b = c1[lb];
+        const T sx = w00 * (ax * p00a.x + fx * p00b.x) + w10 * (ax * p10a.x + fx * p10b.x) +
+                     w01 * (ax * p01a.x + fx * p01b.x) + w11 * (ax * p11a.x + fx * p11b.x);
+        const T sy = w00 * (ax * p00a.y + fx * p00b.y) + w10 * (ax * p10a.y + fx * p10b.y) +
+                     w01 * (ax * p01a.y + fx * p01b.y) + w11 * (ax * p11a.y + fx * p11b.y);
+        const int64_t p = perm[k];
+        g1[p] = (float)sx;
+        if (b2 < R) g2[p] = (float)sy;
       }
-    const int b1 = b0 + 2 * q, b2 = b1 + 1;
-    gv[(int64_t)b1 * P + p] = (float)s.x;
-    if (b2 < R) gv[(int64_t)b2 * P + p] = (float)s.y;
+    }
+    block_sync();  // row z0 is no longer read
+    if (more) {
+      transform_into(cur, v);  // row z0 + 2 takes row z0's buffer
+      block_sync();
+    }
   }
 }
 

@@ -204,6 +204,11 @@ template <typename T, int N> struct Engine : EngineBase {
   static constexpr int NT = W * TPL;
   static constexpr int WX = (256 / TPL) > 1 ? (256 / TPL) : 1;
   static constexpr int NTX = WX * TPL;
+  // dual form, fused inverse x + gather: base lines per y tile (two z rows of
+  // YTS + 1 lines fit in LDS) and z segments per launch
+  static constexpr int YTS =
+      (size_t)2 * 16 * lds_line_elems<N>() * sizeof(C<T>) <= (size_t)150 * 1024 ? 15 : 7;
+  static constexpr int kZSeg = 8;
   // dual form, z passes: tile width of the second variant (half the columns,
   // so that two blocks share a compute unit)
   static constexpr int WH = W / 2 >= 4 ? W / 2 : W;
@@ -1193,7 +1198,8 @@ template <typename T, int N> struct Engine : EngineBase {
 
   // Dual form of the pair-field part (see pgx_dual.hpp): for each batch of B
   // bin pairs, the kernel fields S_b1 + i S_b2 (x, y transforms of the
-  // window), the z pass with G, inverse y and x transforms, and the gather at
+  // window, from the store when kept), the z pass with G, the inverse y
+  // transform, and the inverse x transform swept along z with the gather at
   // every pair midpoint; then the per-field sums.
   // Kernel-field store of the dual form (all (R+1)/2 bin pairs, y
   // transformed): one allocation attempt per plan, at the first dual-form
@@ -1283,17 +1289,14 @@ template <typename T, int N> struct Engine : EngineBase {
             x, x, NC, NC, NN, NN, N, N, 0, nullptr, nullptr, 0, nullptr, twp);
         launch_check("yinv(dual)");
       });
-      prof.run("dual_xinv", s, 2.0 * nq * NC * cb, [&] {
-        for (int j = 0; j < nq; ++j)
-          k_xdense<T, Sh, WX, 1><<<(int)(NN / WX), NTX, 0, s>>>(x + (int64_t)j * NC, twp);
-        launch_check("xinv(dual)");
-      });
       if (n_pairs > 0) {
-        prof.run("dual_gather", s, (double)n_pairs * (20.0 + 8.0 * nq * (4.0 + 2.0 * cb)), [&] {
-          k_dual_gather<T><<<grid_for(n_pairs), 256, 0, s>>>(
-              p_key.as<int32_t>(), p_x0.as<int32_t>(), p_fx.as<T>(), p_fy.as<T>(), p_fz.as<T>(),
-              n_pairs, N, x, NC, nq, 2 * q0, R, gv);
-          launch_check("gather(dual)");
+        const int zlen = N / kZSeg;
+        // the y-transformed grids once, the point records, the gathered values
+        const double bytes = (double)nq * NC * cb + (double)n_pairs * (20.0 + 8.0 * nq) + (double)NN * 4.0;
+        prof.run("dual_xinv_gather", s, bytes, [&] {
+          k_xinv_gather_sweep<T, Sh, YTS><<<dim3((N + YTS - 1) / YTS, kZSeg, nq), (YTS + 1) * TPL, 0, s>>>(
+              line_set(), l_p.as<int32_t>(), n_pairs, x, NC, zlen, 2 * q0, R, gv, twp);
+          launch_check("xinv_gather(dual)");
         });
       }
     }
