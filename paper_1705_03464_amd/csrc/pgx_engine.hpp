@@ -204,10 +204,11 @@ template <typename T, int N> struct Engine : EngineBase {
   static constexpr int NT = W * TPL;
   static constexpr int WX = (256 / TPL) > 1 ? (256 / TPL) : 1;
   static constexpr int NTX = WX * TPL;
-  // dual form, fused inverse x + gather: base lines per y tile (two z rows of
-  // YTS + 1 lines fit in LDS) and z segments per launch
-  static constexpr int YTS =
-      (size_t)2 * 16 * lds_line_elems<N>() * sizeof(C<T>) <= (size_t)150 * 1024 ? 15 : 7;
+  // dual form, fused inverse x + gather: base lines per y tile and z segments
+  // per launch.  Small tiles (two z rows of 4 lines, 35 KB of LDS at 512^3)
+  // let several blocks share a compute unit; measured at 512^3: 3.6 ms per
+  // launch against 3.7 ms for 7 and 4.3 ms for 15 base lines per tile.
+  static constexpr int YTS = 3;
   static constexpr int kZSeg = 8;
   // dual form, z passes: tile width of the second variant (half the columns,
   // so that two blocks share a compute unit)
