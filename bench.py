@@ -197,8 +197,10 @@ def main(argv=None):
             wt = ones.clone().requires_grad_(True)
         out = pair_galaxy_xi(plan, wt)
         b = out["b_pg"]
-        m = torch.isfinite(b)
-        loss = ((b[m] - 1.0) ** 2).sum()
+        # sum over the finite entries, without a data-dependent shape (no
+        # host synchronisation inside the step)
+        r = torch.where(torch.isfinite(b), b - 1.0, torch.zeros_like(b))
+        loss = (r * r).sum()
         loss.backward()
         return out
 

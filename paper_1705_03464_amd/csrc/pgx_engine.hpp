@@ -228,6 +228,8 @@ template <typename T, int N> struct Engine : EngineBase {
   std::vector<int64_t> batch_task_off;  // host, n_batches + 1
   std::vector<int64_t> field_counts_h;  // host, pairs per field
   std::vector<int64_t> build_print;     // schedule and buffers of the last pair build
+  // the line flags and x-pass task lists match the current catalogue
+  bool tasks_ready = false;
 
   // kernel variants picked by the autotuner (0 = default): forward y pass,
   // inverse y pass (radix schedule), z pass (twiddle source; for the dual
@@ -553,30 +555,24 @@ template <typename T, int N> struct Engine : EngineBase {
       l_wt.get<T>(P);
       counts_to_starts(lln, P, NN, s_hist.get<int32_t>(NN + 1), l_ls.get<int32_t>(NN + 1), s);
     }
-    // non-empty lines of every field pair and the x-pass task lists
-    if constexpr (std::is_same<T, float>::value) {
-      const int64_t nfl = (int64_t)cfg.n_fp * NN;
-      // one extra zero entry so the exclusive scan over nfl + 1 entries yields the total
-      uint8_t* lf = lflag.get<uint8_t>(nfl + 1);
-      k_fill_u8(lf, nfl + 1, s);
-      if (P > 0) {
-        k_mark_lines<<<grid_for(P), 256, 0, s>>>(sk, P, N, lf);
-        launch_check("mark_lines");
-      }
-      uint8_t* pf = pflag.get<uint8_t>((int64_t)cfg.n_fp * N);
-      k_plane_flags<<<grid_for((int64_t)cfg.n_fp * N), 256, 0, s>>>(lf, N, (int64_t)cfg.n_fp * N, pf);
-      launch_check("plane_flags");
-      int32_t* pos = s_pos.get<int32_t>(nfl + 1);
-      exscan_u8_i32(lf, pos, nfl + 1, s, s_tmp);  // entry nfl is the total
-      schedule(B, s);
-    }
+    // line flags and x-pass task lists of the per-field transforms: only
+    // when that algorithm is in use (the schedule builds them on demand)
+    tasks_ready = false;
+    if constexpr (std::is_same<T, float>::value)
+      if (algo == 0) schedule(B, s);
     PGX_HIP(hipStreamSynchronize(s));
     if (n_pairs_out) *n_pairs_out = P;
-    // recorded launch sequences stay valid when the new catalogue has the
-    // same schedule (sizes, per-batch task counts, per-field counts) in the
-    // same buffers, as when the same catalogue is rebuilt
-    std::vector<int64_t> fpr = {n_gal, n_pairs, (int64_t)B};
-    fpr.insert(fpr.end(), batch_task_off.begin(), batch_task_off.end());
+    built = true;
+    refresh_print();
+  }
+
+  // Recorded launch sequences stay valid when the new catalogue has the same
+  // schedule (sizes, per-batch task counts, per-field counts) in the same
+  // buffers, as when the same catalogue is rebuilt; otherwise the generation
+  // moves on and they are recorded again.
+  void refresh_print() {
+    std::vector<int64_t> fpr = {n_gal, n_pairs, (int64_t)B, tasks_ready ? 1 : 0};
+    if (tasks_ready) fpr.insert(fpr.end(), batch_task_off.begin(), batch_task_off.end());
     fpr.insert(fpr.end(), field_counts_h.begin(), field_counts_h.end());
     for (const DBuf* d : {&g_key, &g_ls, &g_x0, &g_fx, &g_fy, &g_fz, &g_idx, &g_wt, &g_tasks, &p_key,
                           &p_ls, &p_i, &p_j, &p_x0, &p_fx, &p_fy, &p_fz, &p_wt, &lflag, &pflag, &tasks, &l_ls, &l_x0, &l_fx,
@@ -586,7 +582,25 @@ template <typename T, int N> struct Engine : EngineBase {
       build_print = fpr;
       ++gen;
     }
-    built = true;
+  }
+
+  // Non-empty lines of every field pair (a byte per grid line), non-empty
+  // planes, and the exclusive scan of the line flags, from the field-major
+  // catalogue: the input of the x-pass task lists.
+  void line_flags(hipStream_t s) {
+    const int64_t nfl = (int64_t)cfg.n_fp * NN;
+    // one extra zero entry so the exclusive scan over nfl + 1 entries yields the total
+    uint8_t* lf = lflag.get<uint8_t>(nfl + 1);
+    k_fill_u8(lf, nfl + 1, s);
+    if (n_pairs > 0) {
+      k_mark_lines<<<grid_for(n_pairs), 256, 0, s>>>(p_key.as<int32_t>(), n_pairs, N, lf);
+      launch_check("mark_lines");
+    }
+    uint8_t* pf = pflag.get<uint8_t>((int64_t)cfg.n_fp * N);
+    k_plane_flags<<<grid_for((int64_t)cfg.n_fp * N), 256, 0, s>>>(lf, N, (int64_t)cfg.n_fp * N, pf);
+    launch_check("plane_flags");
+    int32_t* pos = s_pos.get<int32_t>(nfl + 1);
+    exscan_u8_i32(lf, pos, nfl + 1, s, s_tmp);  // entry nfl is the total
   }
 
   int default_batch() const {
@@ -753,6 +767,7 @@ template <typename T, int N> struct Engine : EngineBase {
     const int nfp = cfg.n_fp;
     B = std::max(1, std::min({b, nfp, kMaxSlots}));
     n_batches = (nfp + B - 1) / B;
+    if (!tasks_ready) line_flags(s);
     const int64_t nfl = (int64_t)nfp * NN;
     const uint8_t* lf = lflag.as<uint8_t>();
     const int32_t* pos = s_pos.as<int32_t>();
@@ -766,6 +781,7 @@ template <typename T, int N> struct Engine : EngineBase {
     int32_t* tk = tasks.get<int32_t>(std::max<int64_t>(hpos[n_batches], 1));
     k_emit_tasks<<<grid_for(nfl), 256, 0, s>>>(lf, pos, nfl, N, B, tk);
     launch_check("emit_tasks");
+    tasks_ready = true;
   }
 
   // pairs in the fields of batch k (host copy taken at build time)
@@ -803,7 +819,7 @@ template <typename T, int N> struct Engine : EngineBase {
     k_fill_value<int32_t><<<std::min(grid_for(nkeys + 1), 65536), 256, 0, s>>>(hist, nkeys + 1, 0);
     launch_check("fill");
     if (n > 0) {
-      k_histogram<<<grid_for(n), 256, 0, s>>>(sorted, n, hist);
+      k_run_counts<<<grid_for(n), 256, 0, s>>>(sorted, n, hist);
       launch_check("histogram");
     }
     exscan_i32(hist, starts, nkeys + 1, s, s_tmp);
@@ -910,8 +926,13 @@ template <typename T, int N> struct Engine : EngineBase {
     C<T>* spec = nullptr;
     if constexpr (std::is_same<T, float>::value)
       spec = keep_spectra && algo == 0 ? spectra_store() : nullptr;  // the dual form has no pair-field spectra
-    if constexpr (std::is_same<T, float>::value)
+    if constexpr (std::is_same<T, float>::value) {
       if (algo == 1) ensure_dual_kernels(s);
+      if (algo == 0 && !tasks_ready) {
+        schedule(B, s);
+        refresh_print();
+      }
+    }
     // the recorded body reads the weights from the plan's copy
     GraphKey key;
     key.gen = gen;

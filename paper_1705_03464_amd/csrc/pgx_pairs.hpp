@@ -107,10 +107,21 @@ static __global__ void k_gather_pos(const int32_t* __restrict__ perm, const doub
   pz[p] = z[i];
 }
 
-static __global__ void k_histogram(const int32_t* __restrict__ key, int64_t n, int32_t* __restrict__ h) {
+// Counts of sorted keys (n < 2^31): only the ends of each run of equal keys
+// touch the histogram (the first adds -p, the last p + 1), so equal keys do
+// not contend for one address.
+static __global__ void k_run_counts(const int32_t* __restrict__ key, int64_t n, int32_t* __restrict__ h) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
-  atomicAdd(&h[key[p]], 1);
+  const int32_t k = key[p];
+  const bool first = p == 0 || key[p - 1] != k;
+  const bool last = p == n - 1 || key[p + 1] != k;
+  if (first && last)
+    atomicAdd(&h[k], 1);
+  else if (first)
+    atomicAdd(&h[k], -(int32_t)p);
+  else if (last)
+    atomicAdd(&h[k], (int32_t)(p + 1));
 }
 
 // One thread per galaxy in cell order; candidates are galaxies of the 27
