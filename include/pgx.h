@@ -215,7 +215,12 @@ pgx_status pgx_keep_spectra(pgx_plan* plan, int32_t enable);
  * with the galaxy field, interpolated at every pair midpoint; the same
  * estimator exactly, up to floating-point rounding) when its per-pair values
  * (n_pairs x n_out FP32) fit in half the free device memory, with its two z
- * passes in tiles of the default width or half of it; the dual form is a
+ * passes in tiles of the default width or half of it, or reading the bin
+ * kernels' full spectra from a per-plan store (the kernels are even in each
+ * lattice axis, so the rows ky, kz <= N/2 of every x frequency hold them:
+ * (n_out + 1) / 2 x (N/2 + 1)^2 x N complex FP32, 2.7 GB at 512^3 with 20
+ * bins, allocated when it fits with 4 GiB to spare; the z passes then skip
+ * the kernel's z transform); the dual form is a
  * candidate only when its xi agree with the per-field transforms' within
  * half of 1e-5 max(|xi|, 1e-2) on every bin (pgx_dual_check).  It keeps the fastest
  * combination for later calls.  Results differ between schedules only by
@@ -225,7 +230,8 @@ pgx_status pgx_keep_spectra(pgx_plan* plan, int32_t enable);
  * the kernel-timing counters and invalidates the launch graphs.
  *   schedule: host int32[5] out (nullable): field pairs (or bin pairs) per
  *   batch, forward y-pass variant, inverse y-pass variant, z-pass variant
- *   (0 = default; for the dual form: 1 = half-width z-pass tiles), algorithm
+ *   (0 = default; for the dual form: 1 = half-width z-pass tiles, 2 = z passes
+ *   on the stored kernel spectra), algorithm
  *   (0 = one transform per field pair, 1 = dual form).  pgx_backward runs
  *   the adjoint of the algorithm the preceding pgx_forward used.
  * Errors: ESTATE before pgx_pairs_build; ENOTSUP on FP64 plans.
@@ -246,8 +252,10 @@ pgx_status pgx_schedule(pgx_plan* plan, int32_t* schedule);
 pgx_status pgx_dual_check(pgx_plan* plan, double* disagreement);
 /* Apply a schedule (host int32[5] as above, e.g. one found by an earlier
  * pgx_autotune): batch size in [1, 32] (clamped to the number of field
- * pairs), variants and algorithm 0 or 1.  Same side effects as pgx_autotune apart from the
- * timing runs.  Errors: EINVAL for values out of range, ESTATE before
+ * pairs), variants and algorithm 0 or 1, z-pass variant 2 with algorithm 1
+ * (fills the kernel-spectrum store on the stream).  Same side effects as
+ * pgx_autotune apart from the timing runs.  Errors: EINVAL for values out of
+ * range, ENOSPACE when the kernel-spectrum store does not fit, ESTATE before
  * pgx_pairs_build, ENOTSUP on FP64 plans. */
 pgx_status pgx_set_schedule(pgx_plan* plan, void* stream, const int32_t* schedule);
 

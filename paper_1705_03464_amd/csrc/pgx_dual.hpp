@@ -621,4 +621,292 @@ k_zdual_acc(const C<T>* __restrict__ x, int64_t x_slot, int n_slots,
   }
 }
 
+// ----------------------------------------------------------------------------
+// Kernel spectra.  The bin kernels are even in each lattice axis (every bin
+// depends on i'^2 + j'^2 and k'^2 only, and the window is symmetric), so the
+// full transform of a bin-pair kernel column K^ = K^_b1 + i K^_b2 satisfies
+// K^(kx, ky, kz) = K^(kx, N - ky, kz) = K^(kx, ky, N - kz).  The store keeps
+// the rows ky, kz <= N/2 of every x frequency, per slot
+//   ks[(kz (N/2 + 1) + ky) N + kx],
+// filled once per plan from the x, y transformed window columns; the z passes
+// that read it skip the kernel's z transform.
+// ----------------------------------------------------------------------------
+
+// Row order of the z passes that read the store: the rows ky and N - ky (the
+// same kernel rows) are adjacent in the logical tile order, so they run on
+// one XCD at about the same time and the second read of a kernel row is
+// served by that XCD's L2.  XCD-contiguous ranges as in xcd_tile; the grid is
+// (N / W, N).
+__device__ __forceinline__ void xcd_mirror_tile(int& xt, int& ky) {
+  const int nb = (int)(gridDim.x * gridDim.y), bid = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+  const int lt = (bid & 7) * (nb >> 3) + (bid >> 3);
+  const int n = (int)gridDim.y, rest = lt >> 1;
+  xt = rest % (int)gridDim.x;
+  const int p = rest / (int)gridDim.x;  // pair of rows, in [0, N/2)
+  ky = (lt & 1) == 0 ? p : (p == 0 ? n / 2 : n - p);
+}
+
+// Fill the store: block (xt, ky <= N/2, slot) transforms the window column
+// along z (planes pe = (z + pwz) mod N <= 2 pwz present) and keeps kz <= N/2.
+template <typename T, typename Sh, int W>
+static __global__ void __launch_bounds__(W * Sh::TPL)
+k_kspec(const C<T>* __restrict__ ky_in, int64_t ky_slot, int pwz, C<T>* __restrict__ ks,
+        int64_t ks_slot, const C<T>* __restrict__ tw_g) {
+  constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>(), H = N / 2;
+  constexpr int64_t NN = (int64_t)N * N;
+  __shared__ C<T> tw_s[Sh::tw_entries()];
+  __shared__ C<T> lines[W][LL];
+  load_twiddles<T, Sh>(tw_s, tw_g);
+  const int ky = blockIdx.y, slot = blockIdx.z;
+  const int c = threadIdx.x % W, t = threadIdx.x / W;
+  const int x = blockIdx.x * W + c;
+  const C<T>* kin = ky_in + slot * ky_slot + (int64_t)ky * N + x;
+  C<T> k[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int pe = (t + TPL * m + pwz) & (N - 1);
+    const bool ok = pe <= 2 * pwz;
+    const C<T> b = kin[ok ? (int64_t)pe * NN : (int64_t)0];
+    k[m].x = ok ? b.x : (T)0;
+    k[m].y = ok ? b.y : (T)0;
+  }
+  block_sync();
+  line_fft<Sh, -1>(k, t, lines[c], tw_s, block_sync);
+  C<T>* o = ks + slot * ks_slot + (int64_t)ky * N + x;
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int kz = t + TPL * m;
+    if (kz <= H) o[(int64_t)kz * (H + 1) * N] = k[m];
+  }
+}
+
+// Offset (elements) of kernel row (kz, ky) at x frequency x in one slot of
+// the store.
+template <int N>
+__device__ __forceinline__ int64_t ks_index(int kz, int kyr, int x) {
+  constexpr int H = N / 2;
+  const int kzr = kz <= H ? kz : N - kz;
+  return ((int64_t)kzr * (H + 1) + kyr) * N + x;
+}
+
+// z pass of the dual form on the kernel spectra: per slot, K^ G (K^ from the
+// store), inverse z transform, stored dense.  The next slot's kernel values
+// are loaded at the top of each trip, in flight during the transform.
+template <typename T, typename Sh, int W>
+static __global__ void __launch_bounds__(W * Sh::TPL)
+k_zconv_ks(const C<T>* __restrict__ ks, int64_t ks_slot, int n_slots, const C<T>* __restrict__ fg,
+           C<T>* __restrict__ out, int64_t out_slot, const C<T>* __restrict__ tw_g) {
+  constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>(), H = N / 2;
+  constexpr int64_t NN = (int64_t)N * N;
+  constexpr bool PIPE = E <= 8;
+  __shared__ C<T> tw_s[tw_lds_entries<Sh, kZTwReg>()];
+  __shared__ C<T> lines[W][LL];
+  int xt, ky;
+  xcd_mirror_tile(xt, ky);
+  const int c = threadIdx.x % W, t = threadIdx.x / W;
+  TwAuto<Sh, T, kZTwReg> twa;
+  twa.init(tw_s, tw_g, t);
+  const int kyr = ky <= H ? ky : N - ky, x = xt * W + c;
+  const int64_t col = (int64_t)ky * N + x;
+  constexpr bool BUF = NN * N * (int64_t)sizeof(C<T>) < ((int64_t)1 << 31);
+  constexpr bool BUFK = (int64_t)(H + 1) * (H + 1) * N * (int64_t)sizeof(C<T>) < ((int64_t)1 << 31);
+  constexpr uint32_t CB = sizeof(C<T>);
+  constexpr uint32_t ZST = BUF ? (uint32_t)(TPL * NN * CB) : 0u;
+  const int64_t tile = (int64_t)ky * N + xt * W;
+  const uint32_t vo = (uint32_t)((c + (int64_t)t * NN) * CB);
+  auto load_k = [&](int slot, C<T>* k) {
+    if constexpr (BUFK) {
+      const Buf<T> bk(ks + slot * ks_slot);
+#pragma unroll
+      for (int m = 0; m < E; ++m) k[m] = bk.load((uint32_t)(ks_index<N>(t + TPL * m, kyr, x) * CB), 0u);
+    } else {
+#pragma unroll
+      for (int m = 0; m < E; ++m) k[m] = ks[slot * ks_slot + ks_index<N>(t + TPL * m, kyr, x)];
+    }
+  };
+  C<T> ka[E], kb[PIPE ? E : 1], g[E];
+  load_k(0, ka);
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    if constexpr (BUF) g[m] = Buf<T>(fg + tile).load(vo, (uint32_t)m * ZST);
+    else g[m] = fg[col + (int64_t)(t + TPL * m) * NN];
+  }
+  auto body = [&](int slot, C<T>* v) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = cmul(v[m], g[m]);
+    block_sync();
+    twa.template fft<1>(v, t, lines[c]);
+    if constexpr (BUF) {
+      const Buf<T> bo(out + slot * out_slot + tile);
+#pragma unroll
+      for (int m = 0; m < E; ++m) bo.store(v[m], vo, (uint32_t)m * ZST);
+    } else {
+      C<T>* dst = out + slot * out_slot + col;
+#pragma unroll
+      for (int m = 0; m < E; ++m) dst[(int64_t)(t + TPL * m) * NN] = v[m];
+    }
+  };
+  if constexpr (PIPE) {
+    auto trip = [&](int slot, const C<T>* cur, C<T>* nxt) {
+      if (slot + 1 < n_slots) load_k(slot + 1, nxt);
+      __builtin_amdgcn_sched_barrier(0);
+      C<T> v[E];
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = cur[m];
+      body(slot, v);
+    };
+    int slot = 0;
+    for (; slot + 1 < n_slots; slot += 2) {
+      trip(slot, ka, kb);
+      trip(slot + 1, kb, ka);
+    }
+    if (slot < n_slots) trip(slot, ka, kb);
+  } else {
+    for (int slot = 0; slot < n_slots; ++slot) {
+      if (slot > 0) load_k(slot, ka);
+      C<T> v[E];
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = ka[m];
+      body(slot, v);
+    }
+  }
+}
+
+// Scale of the galaxy kernel in terms of the stored bin-pair spectra: the
+// galaxy-side kernel of the adjoint is sum_b a_gg,b S_b, and slot q of the
+// store holds (S^_b1 + i S^_b2) s_b (s_b the FP32 bin scale), so
+// K^_g = sum_q (gc_q.x Re + gc_q.y Im) with gc_q = (a_gg,b1 / s_b1, a_gg,b2 / s_b2).
+static __global__ void k_gal_coef(const double* __restrict__ agg, int R,
+                                  const float* __restrict__ bscale, int Q,
+                                  float2* __restrict__ gc) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= Q) return;
+  const int b1 = 2 * q, b2 = b1 + 1;
+  float2 c;
+  c.x = (float)(agg[b1] / (double)bscale[b1]);
+  c.y = b2 < R ? (float)(agg[b2] / (double)bscale[b2]) : 0.0f;
+  gc[q] = c;
+}
+
+// z pass of the galaxy-side adjoint on the kernel spectra.  Per slot: forward
+// z transform of the Pi columns, acc += Pi^ conj(K^) / 2, and the galaxy
+// kernel's spectrum kg += gc.x Re K^ + gc.y Im K^ (kept in LDS: each thread
+// owns its planes' entries, so no barrier guards them).  Then
+//   A = acc + kg G   (first batch of bin pairs), A += acc + kg G (later ones),
+// which also takes the place of the separate galaxy-kernel pass.  Slot
+// pipeline: the current slot's kernel values and the next slot's Pi columns
+// are issued at the top of each trip.
+template <typename T, typename Sh, int W>
+static __global__ void __launch_bounds__(W * Sh::TPL)
+k_zdual_acc_ks(const C<T>* __restrict__ x, int64_t x_slot, int n_slots,
+               const C<T>* __restrict__ ks, int64_t ks_slot, const float2* __restrict__ gc,
+               const C<T>* __restrict__ fg, int first, C<T>* __restrict__ acc_out,
+               const C<T>* __restrict__ tw_g) {
+  constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>(), H = N / 2;
+  constexpr int64_t NN = (int64_t)N * N;
+  constexpr bool PIPE = E <= 8;
+  __shared__ C<T> tw_s[tw_lds_entries<Sh, kZTwReg>()];
+  __shared__ C<T> lines[W][LL];
+  __shared__ T kgs[W][N];
+  int xt, ky;
+  xcd_mirror_tile(xt, ky);
+  const int c = threadIdx.x % W, t = threadIdx.x / W;
+  TwAuto<Sh, T, kZTwReg> twa;
+  twa.init(tw_s, tw_g, t);
+  const int kyr = ky <= H ? ky : N - ky, xx = xt * W + c;
+  const int64_t col = (int64_t)ky * N + xx;
+  constexpr bool BUF = NN * N * (int64_t)sizeof(C<T>) < ((int64_t)1 << 31);
+  constexpr bool BUFK = (int64_t)(H + 1) * (H + 1) * N * (int64_t)sizeof(C<T>) < ((int64_t)1 << 31);
+  constexpr uint32_t CB = sizeof(C<T>);
+  constexpr uint32_t ZST = BUF ? (uint32_t)(TPL * NN * CB) : 0u;
+  const int64_t tile = (int64_t)ky * N + xt * W;
+  const uint32_t vo = (uint32_t)((c + (int64_t)t * NN) * CB);
+  auto load_pi = [&](int slot, bool take, C<T>* v) {
+    if constexpr (BUF) {
+      const Buf<T> bi(x + slot * x_slot + tile);
+      const uint32_t kill = take ? 0u : kBufOff;
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = bi.load((vo + (uint32_t)m * ZST) | kill, 0u);
+    } else {
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const C<T> b = x[slot * x_slot + col + (int64_t)(t + TPL * m) * NN];
+        v[m].x = take ? b.x : (T)0;
+        v[m].y = take ? b.y : (T)0;
+      }
+    }
+  };
+  auto load_k = [&](int slot, C<T>* k) {
+    if constexpr (BUFK) {
+      const Buf<T> bk(ks + slot * ks_slot);
+#pragma unroll
+      for (int m = 0; m < E; ++m) k[m] = bk.load((uint32_t)(ks_index<N>(t + TPL * m, kyr, xx) * CB), 0u);
+    } else {
+#pragma unroll
+      for (int m = 0; m < E; ++m) k[m] = ks[slot * ks_slot + ks_index<N>(t + TPL * m, kyr, xx)];
+    }
+  };
+  C<T> acc[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    acc[m] = C<T>{0, 0};
+    kgs[c][t + TPL * m] = (T)0;
+  }
+  auto body = [&](int slot, C<T>* v, const C<T>* k) {
+    block_sync();
+    twa.template fft<-1>(v, t, lines[c]);
+    // the kernel values are first used after the transform, so their loads
+    // are in flight during it
+    const float2 q = gc[slot];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const C<T> pk = cmulc(v[m], k[m]);
+      acc[m].x += (T)0.5 * pk.x;
+      acc[m].y += (T)0.5 * pk.y;
+      kgs[c][t + TPL * m] += (T)q.x * k[m].x + (T)q.y * k[m].y;
+    }
+  };
+  C<T> pa[E], pb[PIPE ? E : 1];
+  load_pi(0, true, pa);
+  if constexpr (PIPE) {
+    auto trip = [&](int slot, const C<T>* cur, C<T>* nxt) {
+      const bool more = slot + 1 < n_slots;
+      C<T> k[E];
+      load_k(slot, k);
+      load_pi(more ? slot + 1 : slot, more, nxt);
+      __builtin_amdgcn_sched_barrier(0);
+      C<T> v[E];
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = cur[m];
+      body(slot, v, k);
+    };
+    int slot = 0;
+    for (; slot + 1 < n_slots; slot += 2) {
+      trip(slot, pa, pb);
+      trip(slot + 1, pb, pa);
+    }
+    if (slot < n_slots) trip(slot, pa, pb);
+  } else {
+    for (int slot = 0; slot < n_slots; ++slot) {
+      if (slot > 0) load_pi(slot, true, pa);
+      C<T> k[E];
+      load_k(slot, k);
+      body(slot, pa, k);
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int64_t idx = col + (int64_t)(t + TPL * m) * NN;
+    const C<T> g = fg[idx];
+    const T kg = kgs[c][t + TPL * m];
+    C<T> r = C<T>{acc[m].x + kg * g.x, acc[m].y + kg * g.y};
+    if (!first) {
+      const C<T> o = acc_out[idx];
+      r.x += o.x;
+      r.y += o.y;
+    }
+    acc_out[idx] = r;
+  }
+}
+
 }  // namespace pgx

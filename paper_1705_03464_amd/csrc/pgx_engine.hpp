@@ -271,6 +271,11 @@ template <typename T, int N> struct Engine : EngineBase {
   // depend only on the binning; kept for the plan's lifetime when they fit
   DBuf KC;
   bool kc_tried = false, kc_valid = false;
+  // dual form, z-pass variant 2: the full kernel spectra (rows ky, kz <= N/2
+  // of every x frequency; the bin kernels are even in each axis), filled once
+  // per plan, and the galaxy kernel's coefficients on them
+  DBuf KS, gcoef;
+  bool ks_tried = false, ks_valid = false;
 
   // room for the kept spectra: already allocated, or fits in free device
   // memory with 4 GiB to spare
@@ -689,20 +694,27 @@ template <typename T, int N> struct Engine : EngineBase {
                                hipMemcpyDeviceToDevice, s));
         schedule(best[0], s);
         algo = 1;
-        for (int v = 0; v < 2; ++v) {
+        double dis[3] = {-1.0, -1.0, -1.0};
+        for (int v = 0; v < 3; ++v) {
+          // variant 2 reads the kernel-spectrum store: only when it fits
+          if (v == 2 && !ensure_kernel_spectra(s)) break;
           v_zpass = v;
           prof.reset();
           prof.on = false;
           weights(wl, s);
           forward_batched(s, nullptr, wl);
-          if (v == 0) {
+          if (v != 1) {
             double* r = dis_d.get<double>(1);
             k_xi_disagreement<<<1, 256, 0, s>>>(sref, S.as<double>(), nbd.as<double>(),
                                                 wsum_d.as<double>(), wg_d.as<double>(), F, R, 1e-5, r);
             launch_check("xi_disagreement");
-            PGX_HIP(hipMemcpyAsync(&dual_disagreement, r, sizeof(double), hipMemcpyDeviceToHost, s));
+            PGX_HIP(hipMemcpyAsync(&dis[v], r, sizeof(double), hipMemcpyDeviceToHost, s));
             PGX_HIP(hipStreamSynchronize(s));
-            if (!(dual_disagreement <= 0.5)) break;
+            if (v == 0) dual_disagreement = dis[0];
+            if (!(dis[v] <= 0.5)) {
+              if (v == 0) break;
+              continue;
+            }
           }
           prof.on = true;
           weights(wl, s);
@@ -717,6 +729,9 @@ template <typename T, int N> struct Engine : EngineBase {
             best_vz_dual = v;
           }
         }
+        // the check of the variant in use (variants 0 and 1 differ only in
+        // tile shape, not in arithmetic)
+        if (best_algo == 1 && best_vz_dual == 2) dual_disagreement = dis[2];
         algo = 0;
       }
       prof.reset();
@@ -736,7 +751,9 @@ template <typename T, int N> struct Engine : EngineBase {
   void set_schedule(const int32_t* in, hipStream_t s) override {
     PGX_REQUIRE(built, PGX_ESTATE, "pgx_pairs_build has not been called");
     PGX_REQUIRE(in[0] >= 1 && in[0] <= kMaxSlots, PGX_EINVAL, "batch size must be in [1, 32]");
-    for (int i = 1; i < 5; ++i) PGX_REQUIRE(in[i] == 0 || in[i] == 1, PGX_EINVAL, "variants are 0 or 1");
+    for (int i = 1; i < 5; ++i)
+      PGX_REQUIRE(in[i] == 0 || in[i] == 1 || (i == 3 && in[i] == 2 && in[4] == 1), PGX_EINVAL,
+                  "variants and algorithm are 0 or 1 (z-pass variant 2 with the dual form)");
     if constexpr (!std::is_same<T, float>::value) {
       throw Error(PGX_ENOTSUP, "schedules apply to the FP32 batched path");
     } else {
@@ -748,6 +765,9 @@ template <typename T, int N> struct Engine : EngineBase {
       ++gen;
       forward_done = false;
       spectra_valid = false;
+      if (v_zpass == 2)
+        PGX_REQUIRE(ensure_kernel_spectra(s), PGX_ENOSPACE,
+                    "the kernel spectra of z-pass variant 2 do not fit in free device memory");
     }
   }
 
@@ -937,7 +957,8 @@ template <typename T, int N> struct Engine : EngineBase {
     GraphKey key;
     key.gen = gen;
     key.p = spec;
-    key.flags = (w_given ? 1 : 0) | (n_gal > 0 ? 2 : 0) | (algo << 2) | (kc_valid ? 64 : 0);
+    key.flags = (w_given ? 1 : 0) | (n_gal > 0 ? 2 : 0) | (algo << 2) | (kc_valid ? 64 : 0) |
+                (ks_valid ? 128 : 0);
     graphed(gf, key, s, [&](hipStream_t st) {
       weights(wl, st);
       if constexpr (std::is_same<T, float>::value)
@@ -966,7 +987,9 @@ template <typename T, int N> struct Engine : EngineBase {
       const int64_t len[5] = {(int64_t)F * R, (int64_t)F * R, (int64_t)F * R, R, F};
       double* up = gup.get<double>(3 * (int64_t)F * R + R + F);
       const double* cp[5];
-      int flags = (spectra_valid ? 1 : 0) | (w_given ? 2 : 0) | (fwd_dual ? 256 : 0) | (kc_valid ? 512 : 0);
+      if (fwd_dual) ensure_dual_kernels(s);
+      int flags = (spectra_valid ? 1 : 0) | (w_given ? 2 : 0) | (fwd_dual ? 256 : 0) | (kc_valid ? 512 : 0) |
+                  (ks_valid ? 1024 : 0);
       double* dst = up;
       for (int i = 0; i < 5; ++i) {
         cp[i] = src[i] ? dst : nullptr;
@@ -977,7 +1000,6 @@ template <typename T, int N> struct Engine : EngineBase {
         dst += len[i];
       }
       float* gw = gw_out.get<float>(std::max<int64_t>(n_gal, 1));
-      if (fwd_dual) ensure_dual_kernels(s);
       GraphKey key;
       key.gen = gen;
       key.p = spectra_valid ? SPEC.p : nullptr;
@@ -1036,7 +1058,11 @@ template <typename T, int N> struct Engine : EngineBase {
     k_fill_value<float><<<grid_for(std::max<int64_t>(n_gal, 1)), 256, 0, s>>>(gbg, std::max<int64_t>(n_gal, 1), 0.f);
     k_fill_value<double><<<grid_for(std::max<int64_t>(n_gal, 1)), 256, 0, s>>>(gd, std::max<int64_t>(n_gal, 1), 0.0);
     launch_check("fill");
-    // galaxy kernel field -> A = K^_g G
+    // galaxy kernel field -> A = K^_g G (on the kernel-spectrum path of the
+    // dual form the z pass of the pairs computes K^_g G from the stored
+    // spectra instead)
+    const bool ksp = fwd_dual && ks_path() && n_pairs > 0;
+    if (!ksp) {
     prof.run("bwd_kgen", s, (double)kx_slot * cb, [&] {
       k_kgen_x<T, Sh, WX><<<dim3(nblkK, 1, 1), NTX, 0, s>>>(aa.agg, R, gslot_fa.as<int32_t>(),
                                                              gslot_fb.as<int32_t>(), pwx(), pwy(),
@@ -1053,8 +1079,9 @@ template <typename T, int N> struct Engine : EngineBase {
       k_zinit<T, Sh, W><<<dim3(N / W, N, 1), NT, 0, s>>>(ky, pwz(), fg, A, twp);
       launch_check("zinit");
     });
+    }
     if (fwd_dual) {
-      backward_dual_pairs(s, aa.apg, x, A, gb, twp, bm);
+      backward_dual_pairs(s, aa.apg, aa.agg, x, A, gb, twp, bm);
     } else {
       for (int k = 0; k < n_batches; ++k) {
         const int nb = std::min(B, cfg.n_fp - k * B);
@@ -1151,10 +1178,16 @@ template <typename T, int N> struct Engine : EngineBase {
   // Pair-field part of the adjoint after a dual-form forward (see
   // pgx_dual.hpp): the pair side from the values the forward gathered, the
   // galaxy side through the per-bin pair fields, accumulated into A.
-  void backward_dual_pairs(hipStream_t s, const double* apg, C<T>* x, C<T>* A, float* gb,
-                           const C<T>* twp, const BinMap& bm) {
+  void backward_dual_pairs(hipStream_t s, const double* apg, const double* agg, C<T>* x, C<T>* A,
+                           float* gb, const C<T>* twp, const BinMap& bm) {
     const int R = cfg.R, F = cfg.F, Q = (R + 1) / 2;
-    if (n_pairs == 0) return;
+    if (n_pairs == 0) return;  // A holds the galaxy term alone
+    const bool ksp = ks_path();
+    float2* gcf = ksp ? gcoef.get<float2>(Q) : nullptr;
+    if (ksp) {
+      k_gal_coef<<<(Q + 255) / 256, 256, 0, s>>>(agg, R, bscale.as<float>(), Q, gcf);
+      launch_check("gal_coef");
+    }
     const int nz = win_len(pwz());
     const int64_t ky_slot = (int64_t)nz * NN;
     C<T>* kc = kernel_store();
@@ -1171,7 +1204,7 @@ template <typename T, int N> struct Engine : EngineBase {
     const double pts = (double)n_pairs * (12.0 + 4.0 * sizeof(T)) + (double)NN * 4.0;
     for (int q0 = 0; q0 < Q; q0 += B) {
       const int nq = std::min(B, Q - q0);
-      C<T>* ky = dual_kernels(s, q0, nq, kc, twp, bm, "bwd_dual_kgen", "bwd_dual_kgen_y");
+      C<T>* ky = ksp ? nullptr : dual_kernels(s, q0, nq, kc, twp, bm, "bwd_dual_kgen", "bwd_dual_kgen_y");
       prof.run("bwd_dual_xscatter", s, (double)nq * ((double)NC * cb + pts), [&] {
         k_xscatter_dual<T, Sh, WX><<<(int)(NN / WX), NTX, 0, s>>>(line_set(), l_f.as<int32_t>(), cf, F,
                                                                  q0, nq, x, NC, twp);
@@ -1182,6 +1215,18 @@ template <typename T, int N> struct Engine : EngineBase {
             x, x, NC, NC, NN, NN, N, N, 0, nullptr, nullptr, 0, nullptr, twp);
         launch_check("ypass(dual adjoint)");
       });
+      if (ksp) {
+        // Pi columns, every stored kernel row once, G, and A written (read
+        // too after the first batch)
+        const double bytes = ((double)nq * (NC + ks_slot()) + (q0 == 0 ? 2.0 : 3.0) * NC) * cb;
+        prof.run("bwd_dual_zacc", s, bytes, [&] {
+          k_zdual_acc_ks<T, Sh, W><<<dim3(N / W, N, 1), NT, 0, s>>>(
+              x, NC, nq, KS.as<C<T>>() + q0 * ks_slot(), ks_slot(), gcf + q0, Fg.as<C<T>>(),
+              q0 == 0 ? 1 : 0, A, twp);
+          launch_check("zacc(ks)");
+        });
+        continue;
+      }
       prof.run("bwd_dual_zacc", s, (double)nq * (NC + ky_slot) * cb + 2.0 * NC * cb, [&] {
         if (v_zpass == 0)
           k_zdual_acc<T, Sh, W><<<dim3(N / W, N, 1), NT, 0, s>>>(x, NC, nq, ky, ky_slot, pwz(), A, twp);
@@ -1279,13 +1324,57 @@ template <typename T, int N> struct Engine : EngineBase {
   // uses it, so that the body's launch sequence is the same from the first call
   void ensure_dual_kernels(hipStream_t s) {
     C<T>* kc = kernel_store();
-    if (!kc || kc_valid) return;
-    const int Q = (cfg.R + 1) / 2;
-    const BinMap bm = binmap();
-    for (int q0 = 0; q0 < Q; q0 += B)
-      dual_kernels(s, q0, std::min(B, Q - q0), kc, tw.as<C<T>>(), bm, "dual_kgen", "dual_kgen_y");
-    kc_valid = true;
+    if (kc && !kc_valid) {
+      const int Q = (cfg.R + 1) / 2;
+      const BinMap bm = binmap();
+      for (int q0 = 0; q0 < Q; q0 += B)
+        dual_kernels(s, q0, std::min(B, Q - q0), kc, tw.as<C<T>>(), bm, "dual_kgen", "dual_kgen_y");
+      kc_valid = true;
+    }
+    if (v_zpass == 2) ensure_kernel_spectra(s);
   }
+
+  static constexpr int64_t ks_slot() { return (int64_t)(N / 2 + 1) * (N / 2 + 1) * N; }
+
+  // The kernel-spectrum store: allocated once when free memory holds it with
+  // 4 GiB to spare, filled once per plan (from the window columns, kept or
+  // regenerated).  Returns whether it is ready.
+  bool ensure_kernel_spectra(hipStream_t s) {
+    if (ks_valid) return true;
+    const int Q = (cfg.R + 1) / 2;
+    if (!ks_tried) {
+      ks_tried = true;
+      const size_t need = (size_t)Q * (size_t)ks_slot() * sizeof(C<T>);
+      size_t fr = 0, tot = 0;
+      PGX_HIP(hipMemGetInfo(&fr, &tot));
+      if (fr >= need + ((size_t)4 << 30)) {
+        if (hipMalloc(&KS.p, need) == hipSuccess) {
+          KS.bytes = need;
+        } else {
+          (void)hipGetLastError();
+          KS.p = nullptr;
+        }
+      }
+    }
+    if (!KS.p) return false;
+    C<T>* kc = kernel_store();
+    const BinMap bm = binmap();
+    const int64_t ky_slot = (int64_t)win_len(pwz()) * NN;
+    for (int q0 = 0; q0 < Q; q0 += B) {
+      const int nq = std::min(B, Q - q0);
+      const C<T>* ky = dual_kernels(s, q0, nq, kc, tw.as<C<T>>(), bm, "dual_kgen", "dual_kgen_y");
+      k_kspec<T, Sh, W><<<dim3(N / W, N / 2 + 1, nq), NT, 0, s>>>(ky, ky_slot, pwz(),
+                                                                  KS.as<C<T>>() + q0 * ks_slot(),
+                                                                  ks_slot(), tw.as<C<T>>());
+      launch_check("kspec");
+    }
+    if (kc) kc_valid = true;
+    ks_valid = true;
+    return true;
+  }
+
+  // the dual form's z passes read the kernel-spectrum store
+  bool ks_path() const { return algo == 1 && v_zpass == 2 && ks_valid; }
 
   void forward_dual_pairs(hipStream_t s, C<T>* x, const C<T>* fg, const C<T>* twp, const BinMap& bm,
                           double* Sd, const float* wl) {
@@ -1295,17 +1384,29 @@ template <typename T, int N> struct Engine : EngineBase {
     const double cb = (double)sizeof(C<T>);
     float* gv = GV.get<float>(std::max<int64_t>((int64_t)R * n_pairs, 1));
     C<T>* kc = kernel_store();
+    const bool ksp = ks_path();
     for (int q0 = 0; q0 < Q; q0 += B) {
       const int nq = std::min(B, Q - q0);
-      C<T>* ky = dual_kernels(s, q0, nq, kc, twp, bm, "dual_kgen", "dual_kgen_y");
-      prof.run("dual_zconv", s, (double)(nq * ky_slot + NC + nq * NC) * cb, [&] {
-        if (v_zpass == 0)
-          k_zconv<T, Sh, W><<<dim3(N / W, N, 1), NT, 0, s>>>(ky, ky_slot, nq, pwz(), fg, x, NC, twp);
-        else
-          k_zconv<T, Sh, WH><<<dim3(N / WH, N, 1), WH * TPL, 0, s>>>(ky, ky_slot, nq, pwz(), fg, x, NC,
-                                                                  twp);
-        launch_check("zconv");
-      });
+      if (ksp) {
+        // every stored kernel row once (the reads for the mirrored rows
+        // ky, N - ky and planes kz, N - kz are meant to hit the caches)
+        const double kb = (double)nq * (double)ks_slot();
+        prof.run("dual_zconv", s, (kb + (double)NC + (double)nq * NC) * cb, [&] {
+          k_zconv_ks<T, Sh, W><<<dim3(N / W, N, 1), NT, 0, s>>>(KS.as<C<T>>() + q0 * ks_slot(), ks_slot(),
+                                                                nq, fg, x, NC, twp);
+          launch_check("zconv(ks)");
+        });
+      } else {
+        C<T>* ky = dual_kernels(s, q0, nq, kc, twp, bm, "dual_kgen", "dual_kgen_y");
+        prof.run("dual_zconv", s, (double)(nq * ky_slot + NC + nq * NC) * cb, [&] {
+          if (v_zpass == 0)
+            k_zconv<T, Sh, W><<<dim3(N / W, N, 1), NT, 0, s>>>(ky, ky_slot, nq, pwz(), fg, x, NC, twp);
+          else
+            k_zconv<T, Sh, WH><<<dim3(N / WH, N, 1), WH * TPL, 0, s>>>(ky, ky_slot, nq, pwz(), fg, x,
+                                                                    NC, twp);
+          launch_check("zconv");
+        });
+      }
       prof.run("dual_yinv", s, 2.0 * nq * NC * cb, [&] {
         k_strided<T, Sh, W, 1, IN_DENSE, OUT_DENSE><<<dim3(N / W, N, nq), NT, 0, s>>>(
             x, x, NC, NC, NN, NN, N, N, 0, nullptr, nullptr, 0, nullptr, twp);

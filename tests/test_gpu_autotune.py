@@ -15,12 +15,12 @@ from synth.configs import Workload, linbins, logbins
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-from test_gpu_parity import SMALL, assert_fp32_parity, clustered_catalog  # noqa: E402
+from test_gpu_parity import ALGOS, SMALL, assert_fp32_parity, clustered_catalog  # noqa: E402
 
 # (batch, forward y variant, inverse y variant, z variant, algorithm: 1 = dual
 # form, whose z variant 1 is the half-width tile)
 SCHEDULES = [(2, 1, 1, 1, 0), (1, 1, 0, 1, 0), (3, 0, 1, 0, 0), (2, 0, 0, 0, 1), (1, 0, 0, 0, 1),
-             (5, 0, 0, 0, 1), (3, 0, 0, 1, 1)]
+             (5, 0, 0, 0, 1), (3, 0, 0, 1, 1), (2, 0, 0, 2, 1), (1, 0, 0, 2, 1), (5, 0, 0, 2, 1)]
 
 
 def _say(m):
@@ -181,7 +181,7 @@ def test_schedule_rejects_bad_values():
         plan.autotune()  # before the pair build
     plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
     for bad in [(0, 0, 0, 0, 0), (33, 0, 0, 0, 0), (2, 2, 0, 0, 0), (2, 0, -1, 0, 0),
-                (2, 0, 0, 5, 0), (2, 0, 0, 0, 2)]:
+                (2, 0, 0, 5, 0), (2, 0, 0, 0, 2), (2, 0, 0, 2, 0), (2, 0, 0, 3, 1)]:
         with pytest.raises(PgxError):
             plan.set_schedule(*bad)
 
@@ -214,19 +214,20 @@ def test_dual_form_matches_per_field_path_at_512():
     cat = wl.catalog()
     _say(f"cfg1 dual vs per-field: n_gal={cat.n}")
     outs = []
-    for algo in (0, 1):
+    for algo in (0, 1, 2):
         plan = Plan.from_workload(wl, precision="fp32")
         plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
-        plan.set_schedule(8, 0, 0, 0, algo)
+        plan.set_schedule(8, 0, 0, *ALGOS[algo])
         outs.append({k: v.cpu().numpy() for k, v in plan.forward().items()})
         plan.close()
-    for k in ("xi_gg", "xi_pg"):
-        worst = _worst(outs[1][k], outs[0][k], 2e-5)
-        _say(f"  {k}: worst |d| / (2e-5 max(|xi|,1e-2)) = {worst:.3f}")
-        assert worst <= 1.0, k
+    for a in (1, 2):
+        for k in ("xi_gg", "xi_pg"):
+            worst = _worst(outs[a][k], outs[0][k], 2e-5)
+            _say(f"  evaluation {a} {k}: worst |d| / (2e-5 max(|xi|,1e-2)) = {worst:.3f}")
+            assert worst <= 1.0, (a, k)
 
 
-@pytest.mark.parametrize("zvar", [0, 1])
+@pytest.mark.parametrize("zvar", [0, 1, 2])
 def test_dual_adjoint_matches_per_field_adjoint_at_512(zvar):
     """The adjoint of the dual form against the per-field adjoint on the full
     512^3 production workload, with random upstream gradients on xi_pg and
@@ -280,10 +281,10 @@ def test_sparse_1024_keeps_per_field_transforms():
     ref = {k: v.cpu().numpy() for k, v in p64.forward(w).items()}
     p64.close()
     grads, worst = [], {}
-    for algo in (0, 1):
+    for algo in (0, 1, 2):
         plan = Plan.from_workload(wl, precision="fp32", batch=2)
         plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
-        plan.set_schedule(2, 0, 0, 0, algo)
+        plan.set_schedule(2, 0, 0, *ALGOS[algo])
         out = {k: v.cpu().numpy() for k, v in plan.forward(w).items()}
         grads.append(plan.backward(g_xi_pg=g_xipg, g_xi_gg=g_xigg).cpu().numpy().astype(np.float64))
         for k in ("xi_gg", "xi_pg"):
@@ -298,11 +299,12 @@ def test_sparse_1024_keeps_per_field_transforms():
             assert plan.dual_check() > 0.5
         plan.close()
     assert worst[0, "xi_gg"] <= 1.0 and worst[0, "xi_pg"] <= 1.0
-    assert worst[1, "xi_gg"] <= 1.0 and worst[1, "xi_pg"] <= 5.0
-    l2 = np.linalg.norm(grads[1] - grads[0]) / np.linalg.norm(grads[0])
-    mx = np.max(np.abs(grads[1] - grads[0])) / np.max(np.abs(grads[0]))
-    _say(f"  adjoint: rel l2 {l2:.2e} rel max {mx:.2e}")
-    assert l2 <= 1e-3 and mx <= 1e-3
+    for a in (1, 2):
+        assert worst[a, "xi_gg"] <= 1.0 and worst[a, "xi_pg"] <= 5.0
+        l2 = np.linalg.norm(grads[a] - grads[0]) / np.linalg.norm(grads[0])
+        mx = np.max(np.abs(grads[a] - grads[0])) / np.max(np.abs(grads[0]))
+        _say(f"  adjoint of evaluation {a}: rel l2 {l2:.2e} rel max {mx:.2e}")
+        assert l2 <= 1e-3 and mx <= 1e-3
 
 
 def test_both_algorithms_meet_fp64_on_production_512():
@@ -316,10 +318,10 @@ def test_both_algorithms_meet_fp64_on_production_512():
     p64.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
     ref = {k: v.cpu().numpy() for k, v in p64.forward().items()}
     p64.close()
-    for algo in (0, 1):
+    for algo in (0, 1, 2):
         plan = Plan.from_workload(wl, precision="fp32")
         plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
-        plan.set_schedule(16, 0, 0, 0, algo)
+        plan.set_schedule(16, 0, 0, *ALGOS[algo])
         out = {k: v.cpu().numpy() for k, v in plan.forward().items()}
         if algo == 1:
             sched = plan.autotune()

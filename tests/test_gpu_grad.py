@@ -13,6 +13,9 @@ from synth import get_config
 from synth.catalog import Catalog
 from synth.configs import HOD_FIDUCIAL, HOD_TARGET, Workload, linbins, logbins
 
+sys.path.insert(0, __file__.rsplit("/", 1)[0])
+from test_gpu_parity import ALGOS  # noqa: E402
+
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
@@ -67,12 +70,14 @@ def mask_ill_conditioned_q(g, wl, o):
 
 def gpu_grad(wl, cat, w, g, batch=0, algo=None):
     """Forward and adjoint on the device; ``algo`` picks the forward's
-    algorithm (0 per-field transforms, 1 dual form), whose adjoint follows."""
+    evaluation (0 per-field transforms, 1 dual form, 2 dual form on the stored
+    kernel spectra), whose adjoint follows."""
     from paper_1705_03464_amd import Plan
     plan = Plan.from_workload(wl, precision="fp32", batch=batch)
     plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
     if algo is not None:
-        plan.set_schedule(plan.schedule()["batch"], 0, 0, 0, algo)
+        zp, al = ALGOS[algo]
+        plan.set_schedule(plan.schedule()["batch"], 0, 0, zp, al)
     out = plan.forward(dev(w, torch.float32))
     gw = plan.backward(g_b_pg=dev(g["g_b"]), g_q_eff=dev(g["g_q"]), g_xi_pg=dev(g["g_xipg"]),
                        g_xi_gg=dev(g["g_xigg"]), g_xi_dp=dev(g["g_xidp"]))
@@ -84,7 +89,7 @@ def tiny_weights(cat, theta=THETA0):
     return OG.hod_weights(cat.halo_mass, cat.kind, theta).astype(np.float32).astype(np.float64)
 
 
-@pytest.mark.parametrize("algo", [0, 1])
+@pytest.mark.parametrize("algo", [0, 1, 2])
 def test_weight_gradient_cfg4tiny_vs_oracle_adjoint(algo):
     wl = get_config("cfg4tiny")
     cat = wl.catalog()
@@ -100,7 +105,7 @@ def test_weight_gradient_cfg4tiny_vs_oracle_adjoint(algo):
     assert grad_close(gw, ref)
 
 
-@pytest.mark.parametrize("algo", [0, 1])
+@pytest.mark.parametrize("algo", [0, 1, 2])
 def test_weight_gradient_matches_finite_differences(algo):
     """Central differences (h = 1e-3) of J = <g, (xi_pg, xi_gg, xi_dp)>.  b_pg and
     Q_eff divide by xi_gg, which sits near zero in some bins of this small box,
@@ -122,7 +127,7 @@ def test_weight_gradient_matches_finite_differences(algo):
     assert np.all(err <= 1e-3 * np.abs(gw).max())
 
 
-@pytest.mark.parametrize("algo", [0, 1])
+@pytest.mark.parametrize("algo", [0, 1, 2])
 @pytest.mark.parametrize("mode", ["shell", "r_mu", "rp_pi"])
 def test_weight_gradient_modes_small_grid(mode, algo):
     """All pair and output binnings; the shell case has an odd number of
@@ -241,5 +246,6 @@ def test_dual_adjoint_matches_per_field_adjoint_cfg2():
     g["g_b"] = np.zeros_like(g["g_b"])
     g["g_q"] = np.zeros_like(g["g_q"])
     _say(f"cfg2 n_gal={cat.n} F={wl.n_fields} R={wl.n_out}")
-    grads = [gpu_grad(wl, cat, w, g, algo=a)[2] for a in (0, 1)]
+    grads = [gpu_grad(wl, cat, w, g, algo=a)[2] for a in (0, 1, 2)]
     assert grad_close(grads[1], grads[0])
+    assert grad_close(grads[2], grads[0])

@@ -9,6 +9,9 @@ import pytest
 
 from synth import get_config
 
+sys.path.insert(0, __file__.rsplit("/", 1)[0])
+from test_gpu_parity import ALGOS  # noqa: E402
+
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
@@ -50,11 +53,12 @@ def make(wl, cat, graphs, keep=False, algo=0):
     plan.use_graphs(graphs)
     plan.keep_spectra(keep)
     plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
-    plan.set_schedule(2, 0, 0, 0, algo)
+    zp, al = ALGOS[algo]
+    plan.set_schedule(2, 0, 0, zp, al)
     return plan
 
 
-@pytest.mark.parametrize("algo", [0, 1])
+@pytest.mark.parametrize("algo", [0, 1, 2])
 @pytest.mark.parametrize("name", ["cfg4tiny", "cfg2"])
 def test_forward_graph_replays_match_eager(name, algo):
     wl = get_config(name)
@@ -75,7 +79,7 @@ def test_forward_graph_replays_match_eager(name, algo):
     assert pe.graph_replays() == (0, 0)
 
 
-@pytest.mark.parametrize("keep,algo", [(False, 0), (True, 0), (False, 1)])
+@pytest.mark.parametrize("keep,algo", [(False, 0), (True, 0), (False, 1), (False, 2)])
 def test_adjoint_graph_replays_match_eager(keep, algo):
     wl = get_config("cfg4tiny")
     cat = wl.catalog()

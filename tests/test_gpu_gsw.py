@@ -15,7 +15,7 @@ from synth.configs import Workload, linbins, logbins
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-from test_gpu_parity import assert_fp32_parity, assert_fp64_parity, clustered_catalog, xi_err_ok  # noqa: E402
+from test_gpu_parity import ALGOS, assert_fp32_parity, assert_fp64_parity, clustered_catalog, xi_err_ok  # noqa: E402
 
 PAR = np.array([15.0, 10.0, 0.8, 5.0, 60.0])  # sigma, r_s, s_0, r_cut, r_max (L = 200, 64^3)
 
@@ -46,14 +46,14 @@ def small(precision="fp32"):
     return wl, cat, w
 
 
-@pytest.mark.parametrize("algo", [0, 1])
+@pytest.mark.parametrize("algo", [0, 1, 2])
 def test_gsw_forward_small_grid(algo):
     from paper_1705_03464_amd import Plan
     wl, cat, w = small()
     ref = oracle_forward(cat, wl, w=w)
     plan = Plan.from_workload(wl, precision="fp32", batch=2)
     P, counts = plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
-    plan.set_schedule(2, 0, 0, 0, algo)
+    plan.set_schedule(2, 0, 0, *ALGOS[algo])
     out = {k: v.cpu().numpy() for k, v in plan.forward(dev(w, torch.float32)).items()}
     _say(f"gsw 64^3 algorithm {algo}: n_gal={cat.n} pairs={P} xi_gg={ref['xi_gg'][0]:.4f}")
     assert np.array_equal(counts.cpu().numpy(), ref["counts"])
@@ -73,7 +73,7 @@ def test_gsw_forward_small_grid_fp64():
     assert_fp64_parity(out, ref)
 
 
-@pytest.mark.parametrize("algo", [0, 1])
+@pytest.mark.parametrize("algo", [0, 1, 2])
 def test_gsw_adjoint_small_grid(algo):
     from paper_1705_03464_amd import Plan
     wl, cat, w = small()
@@ -83,7 +83,7 @@ def test_gsw_adjoint_small_grid(algo):
     ref, _ = OG.weight_gradient(cat, wl, w, **g)
     plan = Plan.from_workload(wl, precision="fp32", batch=2)
     plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
-    plan.set_schedule(2, 0, 0, 0, algo)
+    plan.set_schedule(2, 0, 0, *ALGOS[algo])
     plan.forward(dev(w, torch.float32))
     gw = plan.backward(g_b_pg=dev(g["g_b"]), g_xi_pg=dev(g["g_xipg"]), g_xi_gg=dev(g["g_xigg"]),
                        g_xi_dp=dev(g["g_xidp"])).cpu().numpy().astype(np.float64)
@@ -103,10 +103,10 @@ def test_gsw_production_512_against_fp64():
     p64.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
     ref = {k: v.cpu().numpy() for k, v in p64.forward().items()}
     p64.close()
-    for algo in (0, 1):
+    for algo in (0, 1, 2):
         plan = Plan.from_workload(wl, precision="fp32")
         plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
-        plan.set_schedule(16, 0, 0, 0, algo)
+        plan.set_schedule(16, 0, 0, *ALGOS[algo])
         out = {k: v.cpu().numpy() for k, v in plan.forward().items()}
         plan.close()
         for k in ("xi_gg", "xi_pg"):

@@ -40,12 +40,18 @@ def dev(cat):
     return f(cat.x), f(cat.y), f(cat.z)
 
 
+# The three FP32 evaluations as (z-pass variant, algorithm): per-field
+# transforms, the dual form, the dual form on the stored kernel spectra.
+ALGOS = {0: (0, 0), 1: (0, 1), 2: (2, 1)}
+
+
 def run(wl, cat, precision, w=None, batch=0, algo=None, autotune=False):
     from paper_1705_03464_amd import Plan
     plan = Plan.from_workload(wl, precision=precision, batch=batch)
     P, counts = plan.pairs_build(*dev(cat))
     if algo is not None:
-        plan.set_schedule(plan.schedule()["batch"], 0, 0, 0, algo)
+        zp, al = ALGOS[algo]
+        plan.set_schedule(plan.schedule()["batch"], 0, 0, zp, al)
     if autotune:
         _say(f"  autotuned {plan.autotune()}")
     wt = None if w is None else torch.as_tensor(np.asarray(w, np.float32), device="cuda")
@@ -199,7 +205,7 @@ def test_forward_small_grids(case, precision):
         assert_fp32_parity(out, ref)
 
 
-@pytest.mark.parametrize("algo", [0, 1])
+@pytest.mark.parametrize("algo", [0, 1, 2])
 def test_empty_field_gives_nan_rows(algo):
     L = 100.0
     wl = Workload(name="t", L=L, N=64, precision="fp32", pair_mode="s_mu",
@@ -219,7 +225,7 @@ def test_empty_field_gives_nan_rows(algo):
     assert_fp32_parity(out, ref)
 
 
-@pytest.mark.parametrize("algo", [0, 1])
+@pytest.mark.parametrize("algo", [0, 1, 2])
 def test_catalogue_without_pairs(algo):
     """Galaxies but no close pair at all: every pair field is empty (NaN
     rows), xi_gg still meets the oracle, and the adjoint runs (galaxy term
