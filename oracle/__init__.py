@@ -24,5 +24,9 @@ What it computes (paper: Yuan, Eisenstein & Garrison 2017):
              2PCF_d_collapsed), b = xi_pg/xi_gg (Introduction, eq. 1),
              Q_eff (Methodology, equations Qeff and Qeff_notsq);
   grad       central finite differences and a direct-sum adjoint (no FFT)
-             for gradients w.r.t. per-galaxy weights and HOD parameters.
+             for gradients w.r.t. per-galaxy weights and HOD parameters;
+  multipoles Legendre multipoles of xi_pg in the angle between the pair
+             axis and the pair-to-galaxy direction (the other reading of the
+             pair-orientation cosine), by definition and by the addition
+             theorem of spherical harmonics.
 """
