@@ -190,6 +190,30 @@ pgx_status pgx_backward(pgx_plan* plan, void* stream, const double* g_b_pg, cons
                         float* grad_w);
 
 /*
+ * Multipoles of the pair-galaxy cross-correlation in the angle between the
+ * pair axis and the pair-to-galaxy direction: the other reading of the
+ * pair-orientation cosine, the pair axis against the direction to the
+ * galaxy instead of against the z line of sight, with the cosine
+ * mu' = d^ . r^ expanded in Legendre polynomials.  Over the lattice vectors
+ * r of output shell b:
+ *   xi_l[f][b] = (2l + 1) / (n_b Wsum_f) sum_{p in f} w_p sum_{r in b}
+ *                P_l(d^_p . r^) (CIC interpolation of delta_g at m_p + r),
+ * for l = 0, 2, .., lmax (even l: the pair axis has no sign; d = x_j - x_i,
+ * minimum image; a pair with d = 0 counts for l = 0 only).  l = 0 is xi_pg.
+ * Computed by the dual form with the addition theorem (one bin kernel per
+ * shell and harmonic Y_lm, gathered at the midpoints, per-field sums
+ * weighted by Y_lm of each pair axis), from the weights and galaxy
+ * spectrum of the last pgx_forward; eager launches.
+ *   lmax: 0, 2 or 4.
+ *   xi_l: device FP64 out [F][R][lmax/2 + 1]; NaN rows for empty fields.
+ * Device memory: n_pairs x R x (number of harmonics: 1, 6, 15) FP32 for the
+ * gathered values.  Errors: EINVAL for another lmax, an output mode other
+ * than shells, or a first shell edge of 0; ESTATE without a preceding
+ * pgx_forward; ENOTSUP on FP64 plans.
+ */
+pgx_status pgx_multipoles(pgx_plan* plan, void* stream, int32_t lmax, double* xi_l);
+
+/*
  * Spectrum keeping for the adjoint.  With enable = 1, each later pgx_forward
  * on an FP32 batched plan also writes every pair-field spectrum (one complex
  * N^3 grid per two fields: n_fields/2 rounded up, 1 GiB each at N = 512) into

@@ -67,6 +67,7 @@ _SIGS = {
     "pgx_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
     "pgx_schedule": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "pgx_dual_check": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    "pgx_multipoles": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "pgx_set_schedule": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
     "pgx_graph_replays": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "pgx_profile": (C.c_int, [C.c_void_p, C.c_int32]),
@@ -252,6 +253,17 @@ class Plan:
         _check(load_library().pgx_backward(self._h, _stream(stream), *[_ptr(g) for g in gs],
                                            _ptr(grad)))
         return grad
+
+    def multipoles(self, lmax: int = 2, stream=None):
+        """Legendre multipoles l = 0, 2, .., lmax of xi_pg in the angle between
+        the pair axis and the pair-to-galaxy direction, for the weights and
+        galaxy spectrum of the last forward (pgx_multipoles): FP64 tensor
+        [n_fields, n_out, lmax // 2 + 1]."""
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        out = torch.empty(self.n_fields, self.n_out, lmax // 2 + 1, dtype=torch.float64, device=dev)
+        _check(load_library().pgx_multipoles(self._h, _stream(stream), int(lmax), _ptr(out)))
+        return out
 
     def keep_spectra(self, enable: bool = True):
         """Keep the pair-field spectra of each forward for the adjoint (memory

@@ -146,7 +146,7 @@ static __global__ void __launch_bounds__(W * Sh::TPL)
 k_kgen_x(const double* __restrict__ coef, int R, const int32_t* __restrict__ slot_fa,
          const int32_t* __restrict__ slot_fb, int pwx, int pwy, int pwz, BinMap bm,
          C<T>* __restrict__ out, int64_t out_slot, const C<T>* __restrict__ tw_g,
-         const float* __restrict__ fscale = nullptr) {
+         const float* __restrict__ fscale = nullptr, int nh = 0) {
   constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>();
   __shared__ C<T> tw_s[Sh::tw_entries()];
   __shared__ C<T> lines[W][LL];
@@ -172,8 +172,12 @@ k_kgen_x(const double* __restrict__ coef, int R, const int32_t* __restrict__ slo
         const double sa = fscale && fa >= 0 ? (double)fscale[fa] : 1.0;
         const double sb = fscale && fb >= 0 ? (double)fscale[fb] : 1.0;
         const double wb = bin_weight(bm, px - pwx, py - pwy, pz - pwz);
-        v[m].x = fa >= 0 ? (T)(coef[(int64_t)fa * R + b] * wb / sa) : (T)0;
-        v[m].y = fb >= 0 ? (T)(coef[(int64_t)fb * R + b] * wb / sb) : (T)0;
+        // multipole kernels (nh > 0): "field" fa is a (bin, harmonic) combo
+        // c = b nh + h, and the kernel carries Y_h of the lattice direction
+        const double ya = nh > 0 && fa >= 0 ? real_ylm_dir(fa % nh, px - pwx, py - pwy, pz - pwz) : 1.0;
+        const double yb = nh > 0 && fb >= 0 ? real_ylm_dir(fb % nh, px - pwx, py - pwy, pz - pwz) : 1.0;
+        v[m].x = fa >= 0 ? (T)(coef[(int64_t)fa * R + b] * wb * ya / sa) : (T)0;
+        v[m].y = fb >= 0 ? (T)(coef[(int64_t)fb * R + b] * wb * yb / sb) : (T)0;
       }
     }
   }

@@ -909,4 +909,67 @@ k_zdual_acc_ks(const C<T>* __restrict__ x, int64_t x_slot, int n_slots,
   }
 }
 
+// ----------------------------------------------------------------------------
+// Multipoles in the angle between the pair axis and the pair-to-galaxy
+// direction, by the dual form.  With P_l(a . b) = 4 pi / (2l + 1)
+// sum_m Y_lm(a) Y_lm(b), the sum over the lattice vectors r of shell b
+//   sum_p w_p sum_r (2l + 1) P_l(d^_p . r^) g'(m_p + r)
+//     = 4 pi sum_m sum_p w_p Y_lm(d^_p) U_{b,lm}(m_p),
+//   U_{b,lm} = IDFT(S^_{b,lm} G),  S_{b,lm}(r) = [r in b] Y_lm(r^),
+// so each (bin, harmonic) combo is one more bin kernel of the dual form
+// (generated with the harmonic factor), gathered at the midpoints like the
+// bins, and the per-field sums weight each pair by Y_lm of its axis.
+// ----------------------------------------------------------------------------
+
+// yp[h P + p] = Y_h(axis of pair p) (FP32), the axis d = x_j - x_i with each
+// component folded once into [-L/2, L/2), from the kept galaxy positions.
+static __global__ void k_pair_harm(const int32_t* __restrict__ pi, const int32_t* __restrict__ pj,
+                                   const double* __restrict__ x, const double* __restrict__ y,
+                                   const double* __restrict__ z, int64_t P, double L, int nh,
+                                   float* __restrict__ yp) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const int i = pi[p], j = pj[p];
+  const double h = 0.5 * L;
+  auto fold = [&](double d) { return d >= h ? d - L : (d < -h ? d + L : d); };
+  const double dx = fold(x[j] - x[i]), dy = fold(y[j] - y[i]), dz = fold(z[j] - z[i]);
+  for (int k = 0; k < nh; ++k) yp[(int64_t)k * P + p] = (float)real_ylm_dir(k, dx, dy, dz);
+}
+
+// S[(f R + b) nl + il] = 4 pi sum_{h of degree 2 il} sum_{p in f}
+//   w_p Y_h(d^_p) gv[b nh + h][p] / s_{b nh + h}
+// (FP64 pair weights; one 256-thread block per (field, bin, degree), fixed
+// partition: deterministic).
+static __global__ void k_dual_reduce_mp(const int32_t* __restrict__ line_start, int64_t nn,
+                                        const double* __restrict__ wp, const float* __restrict__ gv,
+                                        const float* __restrict__ yp, int64_t P, int R, int nh, int nl,
+                                        const float* __restrict__ bscale, double* __restrict__ S) {
+  constexpr double PI = 3.14159265358979323846;
+  __shared__ double sh[256];
+  const int f = blockIdx.x, b = blockIdx.y / nl, il = blockIdx.y % nl;
+  const int h0 = il == 0 ? 0 : (il == 1 ? 1 : 6), h1 = il == 0 ? 1 : (il == 1 ? 6 : 15);
+  const int64_t s = line_start[(int64_t)f * nn], e = line_start[(int64_t)(f + 1) * nn];
+  double acc = 0.0;
+  for (int h = h0; h < h1; ++h) {
+    const int c = b * nh + h;
+    const float* g = gv + (int64_t)c * P;
+    const float* yh = yp + (int64_t)h * P;
+    double a = 0.0;
+    for (int64_t p = s + threadIdx.x; p < e; p += 256) a += wp[p] * (double)yh[p] * (double)g[p];
+    acc += a / (double)bscale[c];
+  }
+  const double r = block_sum256(acc, sh);
+  if (threadIdx.x == 0) S[((int64_t)f * R + b) * nl + il] = 4.0 * PI * r;
+}
+
+// xi_l[f][b][il] = S / (n_b Wsum_f W_g), the normalisation of xi_pg.
+static __global__ void k_finalize_mp(const double* __restrict__ S, const double* __restrict__ nb,
+                                     const double* __restrict__ wsum, const double* __restrict__ wg,
+                                     int F, int R, int nl, double* __restrict__ xi) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)F * R * nl) return;
+  const int f = (int)(i / ((int64_t)R * nl)), b = (int)((i / nl) % R);
+  xi[i] = S[i] / (nb[b] * wsum[f] * wg[0]);
+}
+
 }  // namespace pgx

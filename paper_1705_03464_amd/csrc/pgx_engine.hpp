@@ -181,6 +181,7 @@ struct EngineBase {
   virtual void autotune(hipStream_t s, int32_t* out) = 0;
   virtual void schedule_info(int32_t* out) const = 0;
   virtual void set_schedule(const int32_t* in, hipStream_t s) = 0;
+  virtual void multipoles(hipStream_t s, int lmax, double* xi) = 0;
   bool built = false;
   bool forward_done = false;
   // keep each pair-field spectrum from the forward for the adjoint (when the
@@ -276,6 +277,10 @@ template <typename T, int N> struct Engine : EngineBase {
   // per plan, and the galaxy kernel's coefficients on them
   DBuf KS, gcoef;
   bool ks_tried = false, ks_valid = false;
+  // multipoles of the pair axis against the pair-to-galaxy direction: the
+  // galaxy positions of the last build (for the pair axes), the pair
+  // harmonics, the gathered values of every (bin, harmonic) combo, tables
+  DBuf pos_x, pos_y, pos_z, MPY, MPG, MPS, mp_coef, mp_scale, mp_fa, mp_fb;
 
   // room for the kept spectra: already allocated, or fits in free device
   // memory with 4 GiB to spare
@@ -413,6 +418,12 @@ template <typename T, int N> struct Engine : EngineBase {
     PGX_HIP(hipStreamSynchronize(s));
     PGX_REQUIRE(!(herr & 1), PGX_EINVAL, "non-finite galaxy position");
     PGX_REQUIRE(!(herr & 2), PGX_EINVAL, "galaxy position outside [0, L)");
+    if (n > 0) {
+      // kept for the pair axes of the multipoles
+      PGX_HIP(hipMemcpyAsync(pos_x.get<double>(n), x, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      PGX_HIP(hipMemcpyAsync(pos_y.get<double>(n), y, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      PGX_HIP(hipMemcpyAsync(pos_z.get<double>(n), z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
 
     // cell list: side >= maximum pair separation
     int nc = (int)std::floor(cfg.L / (cfg.smax * (1.0 + 1e-12)));
@@ -1318,6 +1329,86 @@ template <typename T, int N> struct Engine : EngineBase {
       launch_check("kgen_y(dual)");
     });
     return ky;
+  }
+
+  // Multipoles of xi_pg in the angle between the pair axis and the
+  // pair-to-galaxy direction (even l <= lmax) over the shell bins, by the
+  // dual form: one bin kernel per (bin, harmonic) combo c = b nh + h, carrying
+  // Y_h(r^) and 1 / n_b; z transform times G, inverse y, inverse x fused with
+  // the gather at the midpoints; per-field sums weighted by Y_h of each pair
+  // axis.  Uses the weights and galaxy spectrum of the last forward.  Eager
+  // launches (not recorded).
+  void multipoles(hipStream_t s, int lmax, double* xi) override {
+    PGX_REQUIRE(lmax == 0 || lmax == 2 || lmax == 4, PGX_EINVAL, "lmax must be 0, 2 or 4");
+    PGX_REQUIRE(xi != nullptr, PGX_EINVAL, "xi_l must not be NULL");
+    if constexpr (!std::is_same<T, float>::value) {
+      throw Error(PGX_ENOTSUP, "multipoles are implemented on the FP32 batched path");
+    } else {
+      PGX_REQUIRE(cfg.out_mode == 0, PGX_EINVAL, "multipoles are taken over shell output bins");
+      PGX_REQUIRE(cfg.o1[0] > 0.0, PGX_EINVAL, "the first shell edge must be > 0 for multipoles");
+      PGX_REQUIRE(built && forward_done, PGX_ESTATE, "pgx_multipoles needs a preceding pgx_forward");
+      const int R = cfg.R, F = cfg.F, nh = harm_count(lmax), nl = lmax / 2 + 1;
+      const int RC = R * nh, QC = (RC + 1) / 2;
+      // combo tables: coefficient 1 / n_b (FP32 value) for bin b(c) = c / nh
+      std::vector<double> ci((size_t)RC * R, 0.0);
+      std::vector<float> bs((size_t)RC, 1.0f);
+      for (int c = 0; c < RC; ++c) {
+        const int b = c / nh;
+        bs[c] = (float)(cfg.nbw[b] > 0 ? 1.0 / cfg.nbw[b] : 1.0);
+        ci[(size_t)c * R + b] = (double)bs[c];
+      }
+      std::vector<int32_t> qa((size_t)QC + kMaxSlots, -1), qb((size_t)QC + kMaxSlots, -1);
+      for (int q = 0; q < QC; ++q) {
+        qa[q] = 2 * q;
+        qb[q] = 2 * q + 1 < RC ? 2 * q + 1 : -1;
+      }
+      upload(mp_coef, ci);
+      upload(mp_scale, bs);
+      upload(mp_fa, qa);
+      upload(mp_fb, qb);
+      const int64_t P = n_pairs;
+      float* yp = MPY.get<float>(std::max<int64_t>((int64_t)nh * P, 1));
+      float* gv = MPG.get<float>(std::max<int64_t>((int64_t)RC * P, 1));
+      double* Sm = MPS.get<double>((int64_t)F * R * nl);
+      if (P > 0) {
+        k_pair_harm<<<grid_for(P), 256, 0, s>>>(p_i.as<int32_t>(), p_j.as<int32_t>(), pos_x.as<double>(),
+                                                pos_y.as<double>(), pos_z.as<double>(), P, cfg.L, nh, yp);
+        launch_check("pair_harm");
+        const int ny = win_len(pwy()), nz = win_len(pwz());
+        const int nblkK = (ny * nz + WX - 1) / WX;
+        const int64_t kx_slot = (int64_t)nz * ny * N, ky_slot = (int64_t)nz * NN;
+        C<T>* kx = KX.get<C<T>>((int64_t)B * kx_slot);
+        C<T>* ky = KY.get<C<T>>((int64_t)B * ky_slot);
+        C<T>* x = X.get<C<T>>((int64_t)B * NC);
+        const C<T>* fg = Fg.as<C<T>>();
+        const C<T>* twp = tw.as<C<T>>();
+        const BinMap bm = binmap();
+        for (int q0 = 0; q0 < QC; q0 += B) {
+          const int nq = std::min(B, QC - q0);
+          k_kgen_x<T, Sh, WX><<<dim3(nblkK, 1, nq), NTX, 0, s>>>(
+              mp_coef.as<double>(), R, mp_fa.as<int32_t>() + q0, mp_fb.as<int32_t>() + q0, pwx(), pwy(),
+              pwz(), bm, kx, kx_slot, twp, nullptr, nh);
+          launch_check("kgen(multipoles)");
+          k_strided<T, Sh, W, -1, IN_WINDOW, OUT_DENSE><<<dim3(N / W, nz, nq), NT, 0, s>>>(
+              kx, ky, kx_slot, ky_slot, (int64_t)ny * N, NN, N, N, pwy(), nullptr, nullptr, 0, nullptr, twp);
+          launch_check("kgen_y(multipoles)");
+          k_zconv<T, Sh, W><<<dim3(N / W, N, 1), NT, 0, s>>>(ky, ky_slot, nq, pwz(), fg, x, NC, twp);
+          launch_check("zconv(multipoles)");
+          k_strided<T, Sh, W, 1, IN_DENSE, OUT_DENSE><<<dim3(N / W, N, nq), NT, 0, s>>>(
+              x, x, NC, NC, NN, NN, N, N, 0, nullptr, nullptr, 0, nullptr, twp);
+          launch_check("yinv(multipoles)");
+          k_xinv_gather_sweep<T, Sh, YTS><<<dim3((N + YTS - 1) / YTS, kZSeg, nq), (YTS + 1) * TPL, 0, s>>>(
+              line_set(), l_p.as<int32_t>(), P, x, NC, N / kZSeg, 2 * q0, RC, gv, twp);
+          launch_check("xinv_gather(multipoles)");
+        }
+      }
+      k_dual_reduce_mp<<<dim3(F, R * nl), 256, 0, s>>>(p_ls.as<int32_t>(), NN, p_wd.as<double>(), gv, yp, P, R,
+                                                       nh, nl, mp_scale.as<float>(), Sm);
+      launch_check("reduce(multipoles)");
+      k_finalize_mp<<<grid_for((int64_t)F * R * nl), 256, 0, s>>>(Sm, nbd.as<double>(), wsum_d.as<double>(),
+                                                                  wg_d.as<double>(), F, R, nl, xi);
+      launch_check("finalize(multipoles)");
+    }
   }
 
   // fill the kernel-field store (when there is one) before a recorded body

@@ -7,6 +7,7 @@
 #pragma once
 #include "pgx_fft.hpp"
 #include "pgx_weight.hpp"
+#include "pgx_harm.hpp"
 
 #include <type_traits>
 
