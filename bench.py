@@ -26,6 +26,8 @@ kernel per pair of output bins instead, beats that floor.  `roofline` is for
 the kernel with the largest share of the profiled pass: algorithmic bytes per
 launch / mean launch time, both measured in this run with HIP events on the
 launch stream.
+`multipoles` times pgx_multipoles (l = 0, 2 of every field in the angle
+between the pair axis and the pair-to-galaxy direction) after a forward;
 `fp64_plain` times the one-field-at-a-time FP64 GPU path's forward;
 `cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
 workload on this host.
@@ -136,6 +138,7 @@ def main(argv=None):
     ap.add_argument("--no-fp64-plain", action="store_true",
                     help="skip timing the one-field-at-a-time FP64 GPU path")
     ap.add_argument("--kernels", action="store_true", help="print the per-kernel table to stderr")
+    ap.add_argument("--no-multipoles", action="store_true", help="skip timing pgx_multipoles")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (torch) three times; used to "
                          "scale the FETCH_SIZE / WRITE_SIZE counters of a profiler run")
@@ -250,6 +253,20 @@ def main(argv=None):
         fwd_only = {"value": round(v_f, 2), "unit": "pair fields/s", "ms_per_step": round(ms_f, 3),
                     "hbm_floor_frac": round(floor_bytes_per_field(wl.N, fpb, "fwd") * v_f / (HBM_PEAK_GBS * 1e9), 4)}
         _log(f"[bench] forward only: {ms_f:.2f} ms/step")
+    multipoles = None
+    if not a.no_multipoles and wl.out_mode == "shell" and float(wl.o1_edges[0]) > 0:
+        step_fwd()  # the forward whose weights and galaxy spectrum it reads
+        plan.multipoles(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            plan.multipoles(2)
+        torch.cuda.synchronize()
+        ms_m = (time.perf_counter() - t0) * 1e3 / 3
+        multipoles = {"lmax": 2, "bin_kernels": wl.n_out * 6, "ms_per_call": round(ms_m, 2),
+                      "value": round(wl.n_fields / (ms_m * 1e-3), 2),
+                      "unit": "pair fields/s (l = 0 and 2 of every field)"}
+        _log(f"[bench] multipoles (l <= 2): {ms_m:.2f} ms/call")
     if a.kernels:
         for name, n, ms, by in prof:
             _log(f"  {name:16s} launches {n:5d}  {ms / max(n, 1):8.3f} ms/launch  "
@@ -302,6 +319,8 @@ def main(argv=None):
     }
     if fwd_only is not None:
         rec["forward_only"] = fwd_only
+    if multipoles is not None:
+        rec["multipoles"] = multipoles
     if not a.no_fp64_plain:
         _log("[bench] timing the one-field-at-a-time FP64 GPU path (forward) ...")
         p64 = Plan.from_workload(wl, precision="fp64")
