@@ -214,6 +214,22 @@ pgx_status pgx_backward(pgx_plan* plan, void* stream, const double* g_b_pg, cons
 pgx_status pgx_multipoles(pgx_plan* plan, void* stream, int32_t lmax, double* xi_l);
 
 /*
+ * Adjoint of the last pgx_multipoles call (after the last pgx_forward):
+ * gradient of a scalar loss with respect to the galaxy weights, by the same
+ * hand-written chain as pgx_backward through the harmonic bin kernels (pair
+ * side from the values that call gathered; galaxy side through the pair
+ * fields weighted by each pair axis's harmonics) and the normalisations
+ * Wsum_f, W_g.
+ *   g_xi_l: device FP64 [F][R][lmax/2 + 1] upstream gradient (entries of
+ *   empty fields and non-finite entries are ignored).
+ *   grad_w: device FP32 [n_gal] out.
+ * Eager launches.  Errors: ESTATE without a pgx_multipoles after the last
+ * pgx_forward or pgx_pairs_build; EINVAL for NULL arguments; ENOTSUP on
+ * FP64 plans.
+ */
+pgx_status pgx_multipoles_backward(pgx_plan* plan, void* stream, const double* g_xi_l, float* grad_w);
+
+/*
  * Spectrum keeping for the adjoint.  With enable = 1, each later pgx_forward
  * on an FP32 batched plan also writes every pair-field spectrum (one complex
  * N^3 grid per two fields: n_fields/2 rounded up, 1 GiB each at N = 512) into

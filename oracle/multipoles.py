@@ -182,3 +182,32 @@ def multipoles_fft(cat, wl, pairs, dg, ells=(0, 2), Fg=None):
                 S += np.bincount(b, weights=Yr[m] * C[idx], minlength=R)
             xi[f, :, il] = 4.0 * np.pi * S / (counts * ws)
     return xi
+
+
+def multipoles_for_weights(cat, wl, w, pairs, ells=(0, 2)):
+    """xi_l for galaxy weights w (pair weights w_i w_j, galaxy overdensity
+    with weights w), reusing an existing pair catalogue's (i, j, key, mid)."""
+    from .pipeline import galaxy_side
+    w = np.asarray(w, np.float64)
+    p = dict(pairs)
+    p["w"] = w[p["i"]] * w[p["j"]]
+    gal = galaxy_side(cat, wl, w=w)
+    return multipoles_fft(cat, wl, p, gal["dg"], ells=ells, Fg=gal["Fg"])
+
+
+def fd_weight_gradient(cat, wl, w, idx, g, pairs, ells=(0, 2), h=1e-3):
+    """Central differences of J(w) = sum g xi_l(w) (non-finite entries of
+    xi_l or g count as 0) at the weight coordinates idx."""
+    w = np.asarray(w, np.float64)
+    g = np.where(np.isfinite(g), g, 0.0)
+
+    def J(wv):
+        xi = multipoles_for_weights(cat, wl, wv, pairs, ells)
+        return float(np.sum(np.where(np.isfinite(xi), xi, 0.0) * g))
+
+    out = np.zeros(len(idx))
+    for k, i in enumerate(idx):
+        wp = w.copy(); wp[i] += h
+        wm = w.copy(); wm[i] -= h
+        out[k] = (J(wp) - J(wm)) / (2 * h)
+    return out

@@ -10,7 +10,7 @@ from ._lib import Plan, PgxError, load_library
 
 def __getattr__(name):
     # torch-dependent helpers are imported on first use
-    if name in ("PairGalaxyXi", "pair_galaxy_xi", "hod_weights"):
+    if name in ("PairGalaxyXi", "pair_galaxy_xi", "hod_weights", "MultipoleXi", "pair_galaxy_multipoles"):
         from . import autograd
         return getattr(autograd, name)
     if name in ("HodFit", "fit_hod", "projected_2pcf"):
@@ -20,4 +20,4 @@ def __getattr__(name):
 
 
 __all__ = ["Plan", "PgxError", "load_library", "PairGalaxyXi", "pair_galaxy_xi", "hod_weights",
-           "HodFit", "fit_hod", "projected_2pcf"]
+           "MultipoleXi", "pair_galaxy_multipoles", "HodFit", "fit_hod", "projected_2pcf"]

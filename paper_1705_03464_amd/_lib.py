@@ -68,6 +68,7 @@ _SIGS = {
     "pgx_schedule": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "pgx_dual_check": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "pgx_multipoles": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "pgx_multipoles_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pgx_set_schedule": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
     "pgx_graph_replays": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "pgx_profile": (C.c_int, [C.c_void_p, C.c_int32]),
@@ -264,6 +265,15 @@ class Plan:
         out = torch.empty(self.n_fields, self.n_out, lmax // 2 + 1, dtype=torch.float64, device=dev)
         _check(load_library().pgx_multipoles(self._h, _stream(stream), int(lmax), _ptr(out)))
         return out
+
+    def multipoles_backward(self, g_xi_l, stream=None):
+        """dL/dw for the last multipoles call given dL/dxi_l (pgx_multipoles_backward)."""
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        g = g_xi_l.to(device=dev, dtype=torch.float64).contiguous()
+        grad = torch.empty(self.n_gal, dtype=torch.float32, device=dev)
+        _check(load_library().pgx_multipoles_backward(self._h, _stream(stream), _ptr(g), _ptr(grad)))
+        return grad
 
     def keep_spectra(self, enable: bool = True):
         """Keep the pair-field spectra of each forward for the adjoint (memory

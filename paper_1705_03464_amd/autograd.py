@@ -44,6 +44,34 @@ def pair_galaxy_xi(plan: Plan, w: torch.Tensor):
     return dict(xi_gg=xi_gg, xi_pg=xi_pg, xi_dp=xi_dp, b_pg=b_pg, q_eff=q_eff)
 
 
+class MultipoleXi(torch.autograd.Function):
+    """xi_l [F][R][lmax/2 + 1] = f(w): the multipoles of xi_pg in the angle
+    between the pair axis and the pair-to-galaxy direction, differentiable in
+    the galaxy weights (forward, then pgx_multipoles; the backward is
+    pgx_multipoles_backward)."""
+
+    @staticmethod
+    def forward(ctx, w: torch.Tensor, plan: Plan, lmax: int):
+        plan.keep_spectra(False)
+        plan.forward(w.detach().contiguous())
+        out = plan.multipoles(lmax)
+        ctx.plan = plan
+        ctx.count = plan.forward_count
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        plan = ctx.plan
+        if plan.forward_count != ctx.count:
+            raise RuntimeError("the plan ran another forward before this backward")
+        return plan.multipoles_backward(g), None, None
+
+
+def pair_galaxy_multipoles(plan: Plan, w: torch.Tensor, lmax: int = 2) -> torch.Tensor:
+    """Differentiable multipoles xi_l, l = 0, 2, .., lmax."""
+    return MultipoleXi.apply(w, plan, lmax)
+
+
 def hod_weights(theta: torch.Tensor, halo_mass: torch.Tensor, kind: torch.Tensor,
                 n_candidates: int = 49, per_candidate: bool = True) -> torch.Tensor:
     """Occupation weights of central (kind 1) and satellite (kind 2) candidates.

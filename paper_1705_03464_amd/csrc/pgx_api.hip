@@ -256,6 +256,11 @@ pgx_status pgx_multipoles(pgx_plan* plan, void* stream, int32_t lmax, double* xi
   return guarded([&] { plan->engine().multipoles((hipStream_t)stream, lmax, xi_l); });
 }
 
+pgx_status pgx_multipoles_backward(pgx_plan* plan, void* stream, const double* g_xi_l, float* grad_w) {
+  if (!plan) return fail(PGX_EINVAL, "plan is NULL");
+  return guarded([&] { plan->engine().multipoles_backward((hipStream_t)stream, g_xi_l, grad_w); });
+}
+
 pgx_status pgx_keep_spectra(pgx_plan* plan, int32_t enable) {
   if (!plan) return fail(PGX_EINVAL, "plan is NULL");
   return guarded([&] { plan->keep_spectra = enable != 0; });

@@ -32,6 +32,7 @@
 
 #include <climits>
 
+#include "pgx_adjoint.hpp"
 #include "pgx_kernels.hpp"
 
 namespace pgx {
@@ -402,12 +403,16 @@ struct WaveRuns {
 // every thread (most lines have at most TPL points) stays in registers
 // across the slots, with its coefficients for the next slot loaded one slot
 // ahead; further points of crowded lines are read again per slot.  Every one
-// of the N*N lines is written (zero lines transform to zero).
-template <typename T, typename Sh, int W>
+// of the N*N lines is written (zero lines transform to zero).  With HARM
+// (the multipoles' adjoint) the slots hold (bin, harmonic) combos c = b nh + h
+// and each pair's coefficient is also multiplied by its harmonic
+// yl[h P + p] (line-major pair index p).
+template <typename T, typename Sh, int W, bool HARM = false>
 static __global__ void __launch_bounds__(W * Sh::TPL)
 k_xscatter_dual(PointSet<T> ps, const int32_t* __restrict__ lfield, const float2* __restrict__ coef,
                 int F, int q0, int nq, C<T>* __restrict__ out, int64_t out_slot,
-                const C<T>* __restrict__ tw_g) {
+                const C<T>* __restrict__ tw_g, const float* __restrict__ yl = nullptr, int nh = 1,
+                int64_t P = 0) {
   constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>();
   __shared__ C<T> tw_s[Sh::tw_entries()];
   __shared__ C<T> lines[W][LL];
@@ -420,12 +425,22 @@ k_xscatter_dual(PointSet<T> ps, const int32_t* __restrict__ lfield, const float2
   lr.init(ps, y, z, N);
   const bool has0 = t < lr.n;
   T wa0 = (T)0, wb0 = (T)0;
-  int xa0 = 0, f0 = 0;
+  int xa0 = 0, f0 = 0, p0 = 0;
   if (has0) {
     const int q = lr.range(t), p = lr.point(t, q);
     cic_on_line(ps, p, q, wa0, wb0, xa0);
     f0 = lfield[p];
+    p0 = p;
   }
+  // the pair's harmonic factors of the slot's two combos (multipoles)
+  auto harm = [&](float2 c, int p, int slot) {
+    if constexpr (HARM) {
+      const int c1 = 2 * (q0 + slot);
+      c.x *= yl[(int64_t)(c1 % nh) * P + p];
+      c.y *= yl[(int64_t)((c1 + 1) % nh) * P + p];
+    }
+    return c;
+  };
   const int xb0 = (xa0 + 1) & (N - 1);
   // one line per wavefront: contributions of points on the same x node are
   // summed across the wavefront first (the points of a base line run in x
@@ -435,7 +450,7 @@ k_xscatter_dual(PointSet<T> ps, const int32_t* __restrict__ lfield, const float2
   if constexpr (RUNS) r0.init(has0 ? lr.range(t) * N + xa0 : 4 * N + t);
   float2 cn = has0 ? coef[(int64_t)q0 * F + f0] : float2{0.f, 0.f};
   for (int slot = 0; slot < nq; ++slot) {
-    const float2 c0 = cn;
+    const float2 c0 = has0 ? harm(cn, p0, slot) : cn;
     if (has0 && slot + 1 < nq) cn = coef[(int64_t)(q0 + slot + 1) * F + f0];
     if (slot > 0) block_sync();  // the previous slot's transform has left the LDS line
 #pragma unroll
@@ -462,7 +477,7 @@ k_xscatter_dual(PointSet<T> ps, const int32_t* __restrict__ lfield, const float2
           q = lr.range(i);
           const int p = lr.point(i, q);
           cic_on_line(ps, p, q, wa, wb, xa);
-          c = cq[lfield[p]];
+          c = harm(cq[lfield[p]], p, slot);
         }
         WaveRuns r;
         r.init(act ? q * N + xa : 4 * N + t);
@@ -488,7 +503,7 @@ k_xscatter_dual(PointSet<T> ps, const int32_t* __restrict__ lfield, const float2
         T wa, wb;
         int xa;
         cic_on_line(ps, p, q, wa, wb, xa);
-        const float2 c = cq[lfield[p]];
+        const float2 c = harm(cq[lfield[p]], p, slot);
         const int xb = (xa + 1) & (N - 1);
         atomicAdd(&line[lpad(xa)].x, wa * (T)c.x);
         atomicAdd(&line[lpad(xa)].y, wa * (T)c.y);
@@ -970,6 +985,96 @@ static __global__ void k_finalize_mp(const double* __restrict__ S, const double*
   if (i >= (int64_t)F * R * nl) return;
   const int f = (int)(i / ((int64_t)R * nl)), b = (int)((i / nl) % R);
   xi[i] = S[i] / (nb[b] * wsum[f] * wg[0]);
+}
+
+// ----------------------------------------------------------------------------
+// Adjoint of the multipoles.  With a_{f,b,l} = dL/dS_l(f, b) and the
+// combo coefficients A_{f,c} = 4 pi a_{f,b(c),l(c)} / s_c:
+//   pair side    dL/dw_p = sum_c A_{f(p),c} Y_h(c)(d^_p) gv[c][p],
+//   galaxy side  Pi_c = sum_p A_{f(p),c} Y_h(c)(d^_p) w_p CIC(m_p), through
+//                the harmonic bin kernels exactly as the dual form's adjoint.
+// ----------------------------------------------------------------------------
+
+// degree index (0, 1, 2 for l = 0, 2, 4) of harmonic h
+__device__ __forceinline__ int harm_degree_index(int h) { return h == 0 ? 0 : (h < 6 ? 1 : 2); }
+
+// dL/dS_l(f, b) = g / (n_b Wsum_f W_g) and the explicit normalisation terms
+// dL/dWsum_f = -sum g xi / Wsum_f, dL/dW_g = -sum g xi / W_g (one block of
+// 256 threads; terms that are not finite, and empty fields, carry none).
+static __global__ void k_finalize_adjoint_mp(const double* __restrict__ S, const double* __restrict__ g,
+                                             const double* __restrict__ nb,
+                                             const double* __restrict__ wsum,
+                                             const double* __restrict__ wg, int F, int R, int nl,
+                                             double* __restrict__ a, double* __restrict__ gws,
+                                             double* __restrict__ gwg) {
+  __shared__ double sh[256];
+  const double w = wg[0];
+  double wacc = 0.0;
+  for (int f = threadIdx.x; f < F; f += 256) {
+    const double ws = wsum[f];
+    const bool ok = ws > 0.0;
+    double gs = 0.0;
+    for (int o = 0; o < R * nl; ++o) {
+      const int64_t i = (int64_t)f * R * nl + o;
+      const int b = o / nl;
+      if (ok) {
+        const double gi = fin0(g[i]);
+        const double xi = S[i] / (nb[b] * ws * w);
+        gs += -fin0(gi * xi / ws);
+        wacc += -fin0(gi * xi / w);
+        a[i] = gi / (nb[b] * ws * w);
+      } else {
+        a[i] = 0.0;
+      }
+    }
+    gws[f] = ok ? gs : 0.0;
+  }
+  const double tot = block_sum256(wacc, sh);
+  if (threadIdx.x == 0) gwg[0] = tot;
+}
+
+// coef[q F + f] = (A_{f,2q}, A_{f,2q+1}) (zero past the last combo)
+static __global__ void k_mp_coef(const double* __restrict__ a, int F, int R, int nh, int nl,
+                                 const float* __restrict__ bscale, int QC, float2* __restrict__ coef) {
+  constexpr double PI = 3.14159265358979323846;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)QC * F) return;
+  const int q = (int)(i / F), f = (int)(i - (int64_t)q * F);
+  const int RC = R * nh;
+  auto one = [&](int c) -> float {
+    if (c >= RC) return 0.0f;
+    const int b = c / nh, il = harm_degree_index(c % nh);
+    return (float)(4.0 * PI * a[((int64_t)f * R + b) * nl + il] / (double)bscale[c]);
+  };
+  coef[i] = float2{one(2 * q), one(2 * q + 1)};
+}
+
+// pair side: acc[p] = sum_c A_{f(p),c} Y_h(c)(d^_p) gv[c][p], FP64 sum
+static __global__ void k_mp_pair_grad(const int32_t* __restrict__ key, int64_t P, int64_t nn,
+                                      const double* __restrict__ a, int R, int nh, int nl,
+                                      const float* __restrict__ gv, const float* __restrict__ yp,
+                                      const float* __restrict__ bscale, float* __restrict__ acc) {
+  constexpr double PI = 3.14159265358979323846;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const double* af = a + (int64_t)(key[p] / nn) * R * nl;
+  double s = 0.0;
+  for (int b = 0; b < R; ++b)
+    for (int h = 0; h < nh; ++h) {
+      const int c = b * nh + h;
+      s += af[b * nl + harm_degree_index(h)] * (double)yp[(int64_t)h * P + p] *
+           (double)gv[(int64_t)c * P + p] / (double)bscale[c];
+    }
+  acc[p] = (float)(4.0 * PI * s);
+}
+
+// line-major copy of the pair harmonics: yl[h P + k] = yp[h P + lp[k]]
+static __global__ void k_harm_line_major(const int32_t* __restrict__ lp, const float* __restrict__ yp,
+                                         int64_t P, int nh, float* __restrict__ yl) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= P) return;
+  const int64_t p = lp[k];
+  for (int h = 0; h < nh; ++h) yl[(int64_t)h * P + k] = yp[(int64_t)h * P + p];
 }
 
 }  // namespace pgx

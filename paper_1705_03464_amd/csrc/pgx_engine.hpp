@@ -182,6 +182,7 @@ struct EngineBase {
   virtual void schedule_info(int32_t* out) const = 0;
   virtual void set_schedule(const int32_t* in, hipStream_t s) = 0;
   virtual void multipoles(hipStream_t s, int lmax, double* xi) = 0;
+  virtual void multipoles_backward(hipStream_t s, const double* g, float* grad_w) = 0;
   bool built = false;
   bool forward_done = false;
   // keep each pair-field spectrum from the forward for the adjoint (when the
@@ -280,7 +281,8 @@ template <typename T, int N> struct Engine : EngineBase {
   // multipoles of the pair axis against the pair-to-galaxy direction: the
   // galaxy positions of the last build (for the pair axes), the pair
   // harmonics, the gathered values of every (bin, harmonic) combo, tables
-  DBuf pos_x, pos_y, pos_z, MPY, MPG, MPS, mp_coef, mp_scale, mp_fa, mp_fb;
+  DBuf pos_x, pos_y, pos_z, MPY, MPG, MPS, mp_coef, mp_scale, mp_fa, mp_fb, MPA, MPL, mp_cf;
+  int mp_lmax = -1;  // lmax of the last multipoles call (-1: none since the last forward)
 
   // room for the kept spectra: already allocated, or fits in free device
   // memory with 4 GiB to spare
@@ -404,6 +406,7 @@ template <typename T, int N> struct Engine : EngineBase {
     PGX_REQUIRE(n == 0 || (x && y && z), PGX_EINVAL, "positions must not be NULL");
     built = false;
     forward_done = false;
+    mp_lmax = -1;
     n_gal = n;
     const int F = cfg.F;
     // validate
@@ -950,6 +953,7 @@ template <typename T, int N> struct Engine : EngineBase {
     S.get<double>((int64_t)cfg.F * cfg.R);
     Sgg.get<double>(cfg.R);
     forward_done = false;
+    mp_lmax = -1;
     spectra_valid = false;
     w_given = w != nullptr;
     float* wl = w_given && n_gal > 0 ? w_last.get<float>(n_gal) : nullptr;
@@ -1155,6 +1159,16 @@ template <typename T, int N> struct Engine : EngineBase {
         }
       }
     }
+    galaxy_adjoint_tail(s, A, gb, gbg, gd, aa.gws, aa.gwg, grad_w, twp);
+  }
+
+  // Galaxy side and weight chain of the adjoint, after A holds the spectral
+  // accumulation: dL/drho_g = 2 Re IDFT(A) with A(0) removed, gathered at the
+  // galaxies; then the per-galaxy gradient from the pair terms (gb, pair
+  // weights w_i w_j, dL/dWsum_f) and the galaxy terms (dL/dW_g).
+  void galaxy_adjoint_tail(hipStream_t s, C<T>* A, const float* gb, float* gbg, double* gd,
+                           const double* gws_d, const double* gwg_d, float* grad_w, const C<T>* twp) {
+    const double cb = (double)sizeof(C<T>);
     // galaxy side: dL/drho_g = 2 Re IDFT(A) with A(0) removed
     k_zero_dc<T><<<1, 64, 0, s>>>(A);
     prof.run("bwd_gal_zinv", s, 2.0 * NC * cb, [&] {
@@ -1176,11 +1190,11 @@ template <typename T, int N> struct Engine : EngineBase {
     const float* wl = w_given ? w_last.as<float>() : nullptr;
     if (n_pairs > 0) {
       k_pair_grad<<<grid_for(n_pairs), 256, 0, s>>>(p_key.as<int32_t>(), p_i.as<int32_t>(),
-                                                    p_j.as<int32_t>(), gb, n_pairs, NN, aa.gws, wl, gd);
+                                                    p_j.as<int32_t>(), gb, n_pairs, NN, gws_d, wl, gd);
       launch_check("pair_grad");
     }
     if (n_gal > 0) {
-      k_gal_grad<<<grid_for(n_gal), 256, 0, s>>>(g_idx.as<int32_t>(), gbg, n_gal, aa.gwg, gd);
+      k_gal_grad<<<grid_for(n_gal), 256, 0, s>>>(g_idx.as<int32_t>(), gbg, n_gal, gwg_d, gd);
       k_grad_out<<<grid_for(n_gal), 256, 0, s>>>(gd, n_gal, grad_w);
       launch_check("grad_out");
     }
@@ -1408,6 +1422,83 @@ template <typename T, int N> struct Engine : EngineBase {
       k_finalize_mp<<<grid_for((int64_t)F * R * nl), 256, 0, s>>>(Sm, nbd.as<double>(), wsum_d.as<double>(),
                                                                   wg_d.as<double>(), F, R, nl, xi);
       launch_check("finalize(multipoles)");
+      mp_lmax = lmax;
+    }
+  }
+
+  // Adjoint of the last multipoles call: dL/dw for upstream gradients g of
+  // xi_l [F][R][lmax/2 + 1].  Pair side from the gathered values of that
+  // call; galaxy side through the harmonic bin kernels (Pi scatter with each
+  // pair's harmonic, y pass, z pass accumulating into A), then the galaxy
+  // side and weight chain of the main adjoint.  Eager launches.
+  void multipoles_backward(hipStream_t s, const double* g, float* grad_w) override {
+    if constexpr (!std::is_same<T, float>::value) {
+      throw Error(PGX_ENOTSUP, "multipoles are implemented on the FP32 batched path");
+    } else {
+      PGX_REQUIRE(built && forward_done && mp_lmax >= 0, PGX_ESTATE,
+                  "pgx_multipoles_backward needs a preceding pgx_multipoles after the last pgx_forward");
+      PGX_REQUIRE(g != nullptr, PGX_EINVAL, "g_xi_l must not be NULL");
+      PGX_REQUIRE(grad_w != nullptr || n_gal == 0, PGX_EINVAL, "grad_w must not be NULL");
+      const int lmax = mp_lmax, R = cfg.R, F = cfg.F, nh = harm_count(lmax), nl = lmax / 2 + 1;
+      const int RC = R * nh, QC = (RC + 1) / 2;
+      const int64_t P = n_pairs;
+      const double cb = (double)sizeof(C<T>);
+      (void)cb;
+      const C<T>* twp = tw.as<C<T>>();
+      C<T>* A = Aacc.get<C<T>>(NC);
+      C<T>* x = X.get<C<T>>((int64_t)B * NC);
+      float* gb = gbuf.get<float>(std::max<int64_t>(P, 1));
+      float* gbg = gbuf_g.get<float>(std::max<int64_t>(n_gal, 1));
+      double* gd = grad_d.get<double>(std::max<int64_t>(n_gal, 1));
+      double* a = MPA.get<double>((int64_t)F * R * nl);
+      double* gws_d = gws.get<double>(F);
+      double* gwg_d = gwg.get<double>(1);
+      k_finalize_adjoint_mp<<<1, 256, 0, s>>>(MPS.as<double>(), g, nbd.as<double>(), wsum_d.as<double>(),
+                                               wg_d.as<double>(), F, R, nl, a, gws_d, gwg_d);
+      launch_check("finalize_adjoint(multipoles)");
+      k_fill_value<float><<<grid_for(std::max<int64_t>(P, 1)), 256, 0, s>>>(gb, std::max<int64_t>(P, 1), 0.f);
+      k_fill_value<float><<<grid_for(std::max<int64_t>(n_gal, 1)), 256, 0, s>>>(gbg, std::max<int64_t>(n_gal, 1), 0.f);
+      k_fill_value<double><<<grid_for(std::max<int64_t>(n_gal, 1)), 256, 0, s>>>(gd, std::max<int64_t>(n_gal, 1), 0.0);
+      // A = 0 (the multipoles have no galaxy auto-correlation term)
+      k_fill_value<T><<<std::min(grid_for(2 * NC), 65536), 256, 0, s>>>(reinterpret_cast<T*>(A), 2 * NC, (T)0);
+      launch_check("fill");
+      if (P > 0) {
+        k_mp_pair_grad<<<grid_for(P), 256, 0, s>>>(p_key.as<int32_t>(), P, NN, a, R, nh, nl, MPG.as<float>(),
+                                                   MPY.as<float>(), mp_scale.as<float>(), gb);
+        launch_check("pair_grad(multipoles)");
+        float2* cf = mp_cf.get<float2>((int64_t)QC * F);
+        k_mp_coef<<<grid_for((int64_t)QC * F), 256, 0, s>>>(a, F, R, nh, nl, mp_scale.as<float>(), QC, cf);
+        launch_check("coef(multipoles)");
+        float* yl = MPL.get<float>((int64_t)nh * P);
+        k_harm_line_major<<<grid_for(P), 256, 0, s>>>(l_p.as<int32_t>(), MPY.as<float>(), P, nh, yl);
+        launch_check("harm_line_major");
+        gather(l_p.as<int32_t>(), p_wt.as<T>(), l_wt.as<T>(), P, s);
+        const int ny = win_len(pwy()), nz = win_len(pwz());
+        const int nblkK = (ny * nz + WX - 1) / WX;
+        const int64_t kx_slot = (int64_t)nz * ny * N, ky_slot = (int64_t)nz * NN;
+        C<T>* kx = KX.get<C<T>>((int64_t)B * kx_slot);
+        C<T>* ky = KY.get<C<T>>((int64_t)B * ky_slot);
+        const BinMap bm = binmap();
+        for (int q0 = 0; q0 < QC; q0 += B) {
+          const int nq = std::min(B, QC - q0);
+          k_kgen_x<T, Sh, WX><<<dim3(nblkK, 1, nq), NTX, 0, s>>>(
+              mp_coef.as<double>(), R, mp_fa.as<int32_t>() + q0, mp_fb.as<int32_t>() + q0, pwx(), pwy(),
+              pwz(), bm, kx, kx_slot, twp, nullptr, nh);
+          launch_check("kgen(multipoles adjoint)");
+          k_strided<T, Sh, W, -1, IN_WINDOW, OUT_DENSE><<<dim3(N / W, nz, nq), NT, 0, s>>>(
+              kx, ky, kx_slot, ky_slot, (int64_t)ny * N, NN, N, N, pwy(), nullptr, nullptr, 0, nullptr, twp);
+          launch_check("kgen_y(multipoles adjoint)");
+          k_xscatter_dual<T, Sh, WX, true><<<(int)(NN / WX), NTX, 0, s>>>(
+              line_set(), l_f.as<int32_t>(), cf, F, q0, nq, x, NC, twp, yl, nh, P);
+          launch_check("xscatter(multipoles adjoint)");
+          k_strided<T, Sh, W, -1, IN_DENSE, OUT_DENSE><<<dim3(N / W, N, nq), NT, 0, s>>>(
+              x, x, NC, NC, NN, NN, N, N, 0, nullptr, nullptr, 0, nullptr, twp);
+          launch_check("ypass(multipoles adjoint)");
+          k_zdual_acc<T, Sh, W><<<dim3(N / W, N, 1), NT, 0, s>>>(x, NC, nq, ky, ky_slot, pwz(), A, twp);
+          launch_check("zacc(multipoles adjoint)");
+        }
+      }
+      galaxy_adjoint_tail(s, A, gb, gbg, gd, gws_d, gwg_d, grad_w, twp);
     }
   }
 

@@ -141,3 +141,64 @@ def test_multipoles_production_512():
          f"|xi_2| max {np.nanmax(np.abs(m[..., 1])):.3f}")
     assert worst0 <= 1.0
     assert np.all(np.isfinite(m[np.isfinite(out["xi_pg"])]))
+
+
+def small_fd(seed=33):
+    L = 120.0
+    wl = Workload(name="mpfd", L=L, N=64, precision="fp32", pair_mode="s_mu",
+                  p1_edges=logbins(0.5, 9.0, 2), p2_edges=linbins(0.0, 1.0, 2), out_mode="shell",
+                  o1_edges=logbins(6.0, 40.0, 4), o2_edges=None, catalog_kw={})
+    cat = clustered_catalog(L, 150, 1500, seed=seed, sat=6, spread=2.0)
+    w = np.random.default_rng(seed).uniform(0.5, 1.5, cat.n).astype(np.float32).astype(np.float64)
+    return wl, cat, w
+
+
+@pytest.mark.parametrize("lmax", [2, 4])
+def test_multipole_gradient_matches_oracle_finite_differences(lmax):
+    """dL/dw of L = sum g xi_l through pgx_multipoles_backward against central
+    differences of the oracle's multipoles (the 1e-3 gradient bar, relative
+    to the largest gradient entry)."""
+    from paper_1705_03464_amd import Plan
+    wl, cat, w = small_fd()
+    ells = OM.EVEN_L[: lmax // 2 + 1]
+    ref = oracle_forward(cat, wl, w=w)
+    plan = Plan.from_workload(wl, precision="fp32", batch=4)
+    plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
+    plan.forward(dev(w, torch.float32))
+    xi = plan.multipoles(lmax).cpu().numpy()
+    g = np.random.default_rng(lmax).normal(size=xi.shape)
+    g[~np.isfinite(xi)] = 0.0
+    gw = plan.multipoles_backward(dev(g)).cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(7)
+    idx = np.concatenate([np.argsort(-np.abs(gw))[:6], rng.choice(cat.n, 6, replace=False)])
+    fd = OM.fd_weight_gradient(cat, wl, w, idx, g, ref["pairs"], ells=ells, h=1e-3)
+    err = np.abs(gw[idx] - fd)
+    _say(f"multipole adjoint lmax {lmax}: pairs={ref['pairs']['key'].size} fd max abs err {err.max():.3e} "
+         f"scale {np.abs(gw).max():.3e}")
+    assert np.all(err <= 1e-3 * np.abs(gw).max())
+
+
+def test_multipole_autograd_and_state():
+    from paper_1705_03464_amd import PgxError, Plan, pair_galaxy_multipoles
+    wl, cat, w = small_fd(seed=34)
+    plan = Plan.from_workload(wl, precision="fp32", batch=4)
+    plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
+    plan.forward(dev(w, torch.float32))
+    with pytest.raises(PgxError) as e:
+        plan.multipoles_backward(torch.zeros(wl.n_fields, wl.n_out, 2, dtype=torch.float64, device="cuda"))
+    assert e.value.code == 5  # no multipoles after the forward
+    wt = dev(w, torch.float32).requires_grad_(True)
+    xi = pair_galaxy_multipoles(plan, wt, 2)
+    G = dev(np.random.default_rng(2).normal(size=tuple(xi.shape)))
+    loss = (torch.where(torch.isfinite(xi), xi, torch.zeros_like(xi)) * G).sum()
+    loss.backward()
+    plan.forward(dev(w, torch.float32))
+    xi2 = plan.multipoles(2)
+    Gm = torch.where(torch.isfinite(xi2), G, torch.zeros_like(G))
+    direct = plan.multipoles_backward(Gm).cpu().numpy().astype(np.float64)
+    got = wt.grad.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(got - direct)) <= 1e-5 * np.max(np.abs(direct))
+    plan.forward(dev(w, torch.float32))
+    with pytest.raises(PgxError) as e:
+        plan.multipoles_backward(Gm)  # a new forward invalidates the multipoles
+    assert e.value.code == 5

@@ -107,3 +107,18 @@ def test_quarter_turn_invariance():
         out.append(OM.multipoles_fft(c, wl, ref["pairs"], gal["dg"], ells=OM.EVEN_L, Fg=gal["Fg"]))
     assert np.array_equal(np.isnan(out[0]), np.isnan(out[1]))
     assert np.nanmax(np.abs(out[0] - out[1])) <= 1e-11 * np.nanmax(np.abs(out[0]))
+
+
+def test_finite_differences_of_a_linear_functional_are_exact_in_g():
+    """The oracle's finite-difference gradient of J = sum g xi_l is linear in
+    g: doubling g doubles it, and g = 0 gives 0 (a check of the helper the
+    GPU adjoint test uses)."""
+    cat, wl = small()
+    ref = forward(cat, wl)
+    w = np.random.default_rng(3).uniform(0.5, 1.5, cat.n)
+    g = np.random.default_rng(4).normal(size=(wl.n_fields, wl.n_out, 2))
+    idx = [0, 5, 40]
+    a = OM.fd_weight_gradient(cat, wl, w, idx, g, ref["pairs"])
+    b = OM.fd_weight_gradient(cat, wl, w, idx, 2 * g, ref["pairs"])
+    assert np.allclose(b, 2 * a, rtol=1e-9, atol=1e-12)
+    assert np.all(OM.fd_weight_gradient(cat, wl, w, idx, 0 * g, ref["pairs"]) == 0)
