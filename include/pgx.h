@@ -57,6 +57,7 @@ typedef enum { PGX_PAIR_S_MU = 0, PGX_PAIR_RP_PI = 1 } pgx_pair_mode;
 typedef enum { PGX_OUT_SHELL = 0, PGX_OUT_R_MU = 1, PGX_OUT_RP_PI = 2, PGX_OUT_GSW = 3 } pgx_out_mode;
 typedef enum { PGX_FP64_PLAIN = 0, PGX_FP32_BATCHED = 1 } pgx_precision;
 typedef enum { PGX_QEFF_NOTSQ = 0, PGX_QEFF_SQUEEZED = 1, PGX_QEFF_CONST_XIW = 2 } pgx_qeff_mode;
+typedef enum { PGX_ASSIGN_CIC = 0, PGX_ASSIGN_TSC = 1 } pgx_assignment;
 
 /*
  * Plan parameters.  Edge arrays are HOST arrays of n+1 strictly ascending
@@ -88,6 +89,15 @@ typedef enum { PGX_QEFF_NOTSQ = 0, PGX_QEFF_SQUEEZED = 1, PGX_QEFF_CONST_XIW = 2
  *             SQUEEZED (equation Qeff), CONST_XIW (Qeff_notsq with xi(d_w) =
  *             xi_w_const, the paper's weighting-function table value).
  *   batch: field pairs per batch on the batched path (0 = automatic).
+ *   assignment: mass assignment of galaxies and pair midpoints to the grid.
+ *             CIC (default; every path), or TSC, the paper's triangular-
+ *             shaped cloud (Implementation section, "Mass assignment
+ *             function": the point spreads over its nearest node and both
+ *             neighbours on each axis with weights 3/4 - d^2 and
+ *             (1/2 -+ d)^2 / 2, d the offset from that node in cells; ties
+ *             at d = 1/2 go to the lower node), on the FP64_PLAIN path only
+ *             (ENOTSUP with FP32_BATCHED, whose fused kernels hold the CIC
+ *             footprint of four lines and two nodes per line).
  */
 typedef struct {
   double L;
@@ -109,6 +119,7 @@ typedef struct {
   int32_t batch;
   /* out_mode GSW only */
   double w_sigma, w_rs, w_s0, w_rcut, w_rmax;
+  int32_t assignment;
 } pgx_params;
 
 /* Create a plan.  Validates the parameters (PGX_EINVAL / PGX_ENOTSUP) and

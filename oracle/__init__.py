@@ -13,7 +13,7 @@ What it computes (paper: Yuan, Eisenstein & Garrison 2017):
              catalogue"; Methodology, the pair overdensity equation
              delta_pi_x places a pair at its midpoint);
   cic        cloud-in-cell densities on a periodic N^3 grid (the paper uses
-             TSC; mass-assignment section);
+             TSC; mass-assignment section), and TSC as a scheme;
   corr       C(r) = N_c^-1 sum_x delta_p(x) delta_g(x+r), by FFT and by a
              direct grid sum (Methodology, equation bpg_initial: the
              W-weighted average of Re(conj(dg) dp), which by Parseval is the

@@ -10,7 +10,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import bins as _bins
-from .cic import cic_assign, overdensity
+from .cic import assign, overdensity
 from .corr import irfftn, rfftn
 from .finalize import field_volumes, finalize
 from .pairs import pairs_for
@@ -25,7 +25,7 @@ def galaxy_side(cat, wl, w=None):
     N, L = wl.N, wl.L
     w = weights_or_ones(cat) if w is None else np.asarray(w, np.float64)
     wg = float(np.sum(w))
-    rho_g = cic_assign(cat.positions(), w, N, L)
+    rho_g = assign(cat.positions(), w, N, L, getattr(wl, "assignment", "cic"))
     dg = overdensity(rho_g, wg)
     Fg = rfftn(dg)
     table = _bins.lattice_table(wl.out_mode, wl.o1_edges, wl.o2_edges, L, N)
@@ -43,7 +43,7 @@ def pair_field_xi(pairs, f, gal, wl):
     ws = float(np.sum(pairs["w"][sel]))
     if ws == 0.0:
         return np.full(gal["R"], np.nan)
-    rho_f = cic_assign(pairs["mid"][sel], pairs["w"][sel], N, L)
+    rho_f = assign(pairs["mid"][sel], pairs["w"][sel], N, L, getattr(wl, "assignment", "cic"))
     df = overdensity(rho_f, ws)
     C = irfftn(np.conj(rfftn(df)) * gal["Fg"], df.shape) / df.size
     return _bins.bin_average(C, gal["table"], gal["R"], gal["bw"])

@@ -23,6 +23,7 @@ PAIR_MODES = {"s_mu": 0, "rp_pi": 1}
 OUT_MODES = {"shell": 0, "r_mu": 1, "rp_pi": 2, "gsw": 3}
 PRECISIONS = {"fp64": 0, "fp32": 1}
 QEFF_MODES = {"notsq": 0, "squeezed": 1, "const": 2}
+ASSIGNMENTS = {"cic": 0, "tsc": 1}
 
 
 class PgxError(RuntimeError):
@@ -42,6 +43,7 @@ class _Params(C.Structure):
         ("qeff_mode", C.c_int32), ("xi_w_const", C.c_double), ("batch", C.c_int32),
         ("w_sigma", C.c_double), ("w_rs", C.c_double), ("w_s0", C.c_double),
         ("w_rcut", C.c_double), ("w_rmax", C.c_double),
+        ("assignment", C.c_int32),
     ]
 
 
@@ -133,7 +135,7 @@ class Plan:
                  o1_edges: Sequence[float], o2_edges: Optional[Sequence[float]] = None, *,
                  precision: str = "fp32", pair_mode: str = "s_mu", out_mode: str = "shell",
                  pair_dmax: float = 0.0, qeff_mode: str = "notsq", xi_w_const: float = 0.0,
-                 batch: int = 0):
+                 batch: int = 0, assignment: str = "cic"):
         lib = load_library()
         gsw = out_mode == "gsw"
         wpar = [float(v) for v in o1_edges] if gsw else [0.0] * 5
@@ -146,7 +148,8 @@ class Plan:
         prm = _Params(float(L), int(N), PRECISIONS[precision], PAIR_MODES[pair_mode],
                       e1.size - 1, dp(e1), e2.size - 1, dp(e2), float(pair_dmax),
                       OUT_MODES[out_mode], e3.size - 1, dp(e3), e4.size - 1, dp(e4),
-                      QEFF_MODES[qeff_mode], float(xi_w_const), int(batch), *wpar)
+                      QEFF_MODES[qeff_mode], float(xi_w_const), int(batch), *wpar,
+                      ASSIGNMENTS[assignment])
         h = C.c_void_p()
         _check(lib.pgx_plan_create(C.byref(prm), C.byref(h)))
         self._h = h
@@ -163,7 +166,8 @@ class Plan:
         return cls(wl.L, wl.N, wl.p1_edges, wl.p2_edges, wl.o1_edges, wl.o2_edges,
                    precision=precision or wl.precision, pair_mode=wl.pair_mode,
                    out_mode=wl.out_mode, pair_dmax=wl.pair_dmax, qeff_mode=wl.qeff_mode,
-                   xi_w_const=wl.xi_w_const, batch=batch)
+                   xi_w_const=wl.xi_w_const, batch=batch,
+                   assignment=getattr(wl, "assignment", "cic"))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -74,12 +74,17 @@ void build_cfg(const pgx_params* p, pgx::PlanCfg& c) {
               "unknown out_mode");
   PGX_REQUIRE(p->qeff_mode >= PGX_QEFF_NOTSQ && p->qeff_mode <= PGX_QEFF_CONST_XIW, PGX_EINVAL,
               "unknown qeff_mode");
+  PGX_REQUIRE(p->assignment == PGX_ASSIGN_CIC || p->assignment == PGX_ASSIGN_TSC, PGX_EINVAL,
+              "unknown assignment");
+  PGX_REQUIRE(p->assignment == PGX_ASSIGN_CIC || p->precision == PGX_FP64_PLAIN, PGX_ENOTSUP,
+              "TSC assignment is implemented on the FP64 plain path");
   c.L = p->L;
   c.N = N;
   c.precision = p->precision;
   c.pair_mode = p->pair_mode;
   c.out_mode = p->out_mode;
   c.qeff_mode = p->qeff_mode;
+  c.assignment = p->assignment;
   c.xi_w_const = p->xi_w_const;
   c.batch = p->batch;
   c.pair_dmax = p->pair_dmax;

@@ -14,6 +14,7 @@ namespace pgx {
 struct PlanCfg {
   double L = 0, pair_dmax = 0, xi_w_const = 0, smax = 0;
   int N = 0, precision = 1, pair_mode = 0, out_mode = 0, qeff_mode = 0, batch = 0;
+  int assignment = 0;  // 0 CIC, 1 TSC (plain FP64 path)
   std::vector<double> p1, p2, o1, o2;
   int F = 0, R = 0, n_fp = 0;
   int pw[3] = {0, 0, 0};
@@ -1728,7 +1729,10 @@ template <typename T, int N> struct Engine : EngineBase {
                      int64_t k1, C<T>* grid, hipStream_t s) {
     k_fill_zero<T><<<4096, 256, 0, s>>>(grid, NC);
     launch_check("fill_zero");
-    k_scatter_atomic<T><<<2048, 256, 0, s>>>(ls, k0, k1, key, ps, N, grid);
+    if (cfg.assignment == 1)
+      k_scatter_atomic_tsc<T><<<2048, 256, 0, s>>>(ls, k0, k1, key, ps, N, grid);
+    else
+      k_scatter_atomic<T><<<2048, 256, 0, s>>>(ls, k0, k1, key, ps, N, grid);
     launch_check("scatter_atomic");
   }
 

@@ -253,6 +253,46 @@ static __global__ void k_scatter_atomic(const int32_t* __restrict__ line_start, 
   }
 }
 
+// TSC variant: the point spreads over its nearest node c and both neighbours
+// on each axis, weights 3/4 - d^2 (c) and (1/2 -+ d)^2 / 2 (c - 1, c + 1),
+// d = u - c in [-1/2, 1/2].  From the CIC corner x0 and fraction f of the
+// point set: c = x0, d = f when f <= 1/2, else c = x0 + 1, d = f - 1 (a
+// point at exactly one half takes the lower node; both give the same
+// weights).
+template <typename T>
+__device__ __forceinline__ void tsc_axis(int x0, T f, int& lo, T* w) {
+  const bool up = f > (T)0.5;
+  const T d = up ? f - (T)1 : f;
+  lo = x0 + (up ? 1 : 0) - 1;
+  w[0] = (T)0.5 * ((T)0.5 - d) * ((T)0.5 - d);
+  w[1] = (T)0.75 - d * d;
+  w[2] = (T)0.5 * ((T)0.5 + d) * ((T)0.5 + d);
+}
+
+template <typename T>
+static __global__ void k_scatter_atomic_tsc(const int32_t* __restrict__ line_start, int64_t k0, int64_t k1,
+                                            const int32_t* __restrict__ key, PointSet<T> ps, int N,
+                                            C<T>* __restrict__ grid) {
+  const int64_t s = line_start[k0], e = line_start[k1];
+  const int64_t NN = (int64_t)N * N;
+  for (int64_t p = s + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < e;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t l = (int64_t)key[p] % NN;
+    int lx, ly, lz;
+    T wx[3], wy[3], wz[3];
+    tsc_axis<T>(ps.x0[p], ps.fx[p], lx, wx);
+    tsc_axis<T>((int)(l % N), ps.fy[p], ly, wy);
+    tsc_axis<T>((int)(l / N), ps.fz[p], lz, wz);
+    const T w = ps.wt[p];
+    for (int c = 0; c < 27; ++c) {
+      const int ox = c % 3, oy = (c / 3) % 3, oz = c / 9;
+      const int64_t idx = ((int64_t)((lz + oz) & (N - 1)) * N + ((ly + oy) & (N - 1))) * N +
+                          ((lx + ox) & (N - 1));
+      atomicAdd(&grid[idx].x, w * wx[ox] * wy[oy] * wz[oz]);
+    }
+  }
+}
+
 // a[i] *= conj(b[i]); with SELF, a[i] = |a[i]|^2 after zeroing a[0] (the k = 0 mode)
 template <typename T, bool SELF>
 static __global__ void k_mul_conj(C<T>* __restrict__ a, const C<T>* __restrict__ b, int64_t n) {

@@ -77,6 +77,15 @@ def test_weighted_bin_parameters_are_validated():
             Plan(o1_edges=par, **base)
 
 
+def test_tsc_assignment_only_on_the_plain_path():
+    base = dict(L=100.0, N=64, p1_edges=linbins(0.5, 10, 3), p2_edges=[0.0, 1.0],
+                o1_edges=logbins(10, 40, 5), assignment="tsc")
+    Plan(precision="fp64", **base).close()
+    with pytest.raises(PgxError) as e:
+        Plan(precision="fp32", **base)
+    assert e.value.code == 4
+
+
 def bad(**kw):
     base = dict(L=100.0, N=64, p1_edges=linbins(0.5, 10, 3), p2_edges=[0.0, 1.0],
                 o1_edges=logbins(10, 40, 5))
