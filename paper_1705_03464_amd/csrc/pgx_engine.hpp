@@ -250,7 +250,10 @@ template <typename T, int N> struct Engine : EngineBase {
       fidx, neg1;
   // catalogue
   DBuf g_key, g_ls, g_x0, g_fx, g_fy, g_fz, g_idx, g_wt, g_tasks;
-  DBuf p_key, p_ls, p_i, p_j, p_x0, p_fx, p_fy, p_fz, p_wt;
+  // field-major pair catalogue; p_fs holds the field boundaries (F + 1), p_ls
+  // the (field, line) starts that only the per-field transforms read (built
+  // with their task lists)
+  DBuf p_key, p_ls, p_fs, p_i, p_j, p_x0, p_fx, p_fy, p_fz, p_wt;
   DBuf p_wd, wg_part;  // FP64 pair weights of the current forward; partial weight sums
   // line-major copy of the pair catalogue (all fields together): line starts,
   // CIC corner and fractions, field, field-major index, weight (adjoint of the
@@ -512,11 +515,12 @@ template <typename T, int N> struct Engine : EngineBase {
     gather(pp, ufy, p_fy.get<T>(P), P, s);
     gather(pp, ufz, p_fz.get<T>(P), P, s);
     p_wt.get<T>(P);
-    int32_t* pls = p_ls.get<int32_t>(nkeys + 1);
-    counts_to_starts(sk, P, nkeys, s_hist.get<int32_t>(nkeys + 1), pls, s);
+    int32_t* pfs = p_fs.get<int32_t>(F + 1);
+    k_field_starts<<<grid_for(F + 1), 256, 0, s>>>(sk, P, NN, F, pfs);
+    launch_check("field_starts");
     {
       int64_t* cdev = s_cnt.get<int64_t>(std::max<int64_t>(n + 1, F));
-      k_field_counts<<<grid_for(F), 256, 0, s>>>(pls, NN, F, cdev);
+      k_field_counts<<<grid_for(F), 256, 0, s>>>(pfs, 1, F, cdev);
       launch_check("field_counts");
       field_counts_h.assign(F, 0);
       PGX_HIP(hipMemcpyAsync(field_counts_h.data(), cdev, F * sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -595,7 +599,7 @@ template <typename T, int N> struct Engine : EngineBase {
     if (tasks_ready) fpr.insert(fpr.end(), batch_task_off.begin(), batch_task_off.end());
     fpr.insert(fpr.end(), field_counts_h.begin(), field_counts_h.end());
     for (const DBuf* d : {&g_key, &g_ls, &g_x0, &g_fx, &g_fy, &g_fz, &g_idx, &g_wt, &g_tasks, &p_key,
-                          &p_ls, &p_i, &p_j, &p_x0, &p_fx, &p_fy, &p_fz, &p_wt, &lflag, &pflag, &tasks, &l_ls, &l_x0, &l_fx,
+                          &p_ls, &p_fs, &p_i, &p_j, &p_x0, &p_fx, &p_fy, &p_fz, &p_wt, &lflag, &pflag, &tasks, &l_ls, &l_x0, &l_fx,
                           &l_fy, &l_fz, &l_f, &l_p, &l_wt})
       fpr.push_back((int64_t)(intptr_t)d->p);
     if (fpr != build_print) {
@@ -608,6 +612,10 @@ template <typename T, int N> struct Engine : EngineBase {
   // planes, and the exclusive scan of the line flags, from the field-major
   // catalogue: the input of the x-pass task lists.
   void line_flags(hipStream_t s) {
+    // (field, line) starts of the field-major catalogue
+    const int64_t nkeys = (int64_t)cfg.F * NN;
+    counts_to_starts(p_key.as<int32_t>(), n_pairs, nkeys, s_hist.get<int32_t>(nkeys + 1),
+                     p_ls.get<int32_t>(nkeys + 1), s);
     const int64_t nfl = (int64_t)cfg.n_fp * NN;
     // one extra zero entry so the exclusive scan over nfl + 1 entries yields the total
     uint8_t* lf = lflag.get<uint8_t>(nfl + 1);
@@ -887,7 +895,7 @@ template <typename T, int N> struct Engine : EngineBase {
       k_pair_wprod<<<grid_for(n_pairs), 256, 0, s>>>(p_i.as<int32_t>(), p_j.as<int32_t>(), w, n_pairs, wp);
       launch_check("pair_wprod");
     }
-    k_field_wsum<<<F, 256, 0, s>>>(p_ls.as<int32_t>(), NN, wp, wsum_d.get<double>(F));
+    k_field_wsum<<<F, 256, 0, s>>>(p_fs.as<int32_t>(), 1, wp, wsum_d.get<double>(F));
     launch_check("field_wsum");
     k_field_scale<<<grid_for(F), 256, 0, s>>>(wsum_d.as<double>(), F, FSC.get<float>(std::max(F, 1)));
     launch_check("field_scale");
@@ -1417,7 +1425,7 @@ template <typename T, int N> struct Engine : EngineBase {
           launch_check("xinv_gather(multipoles)");
         }
       }
-      k_dual_reduce_mp<<<dim3(F, R * nl), 256, 0, s>>>(p_ls.as<int32_t>(), NN, p_wd.as<double>(), gv, yp, P, R,
+      k_dual_reduce_mp<<<dim3(F, R * nl), 256, 0, s>>>(p_fs.as<int32_t>(), 1, p_wd.as<double>(), gv, yp, P, R,
                                                        nh, nl, mp_scale.as<float>(), Sm);
       launch_check("reduce(multipoles)");
       k_finalize_mp<<<grid_for((int64_t)F * R * nl), 256, 0, s>>>(Sm, nbd.as<double>(), wsum_d.as<double>(),
@@ -1606,7 +1614,7 @@ template <typename T, int N> struct Engine : EngineBase {
         });
       }
     }
-    k_dual_reduce<<<dim3(F, R), 256, 0, s>>>(p_ls.as<int32_t>(), NN, p_wd.as<double>(), gv, n_pairs,
+    k_dual_reduce<<<dim3(F, R), 256, 0, s>>>(p_fs.as<int32_t>(), 1, p_wd.as<double>(), gv, n_pairs,
                                              R, bscale.as<float>(), Sd);
     launch_check("reduce(dual)");
     if (kc) kc_valid = true;
@@ -1779,8 +1787,7 @@ template <typename T, int N> struct Engine : EngineBase {
     fft3(h, 1, s);
     bins_plain(h, gslot_fa.as<int32_t>(), Sgg.as<double>(), s);
     for (int f = 0; f < cfg.F; ++f) {
-      scatter_plain(pair_set(), p_key.as<int32_t>(), p_ls.as<int32_t>(), (int64_t)f * NN,
-                    (int64_t)(f + 1) * NN, h, s);
+      scatter_plain(pair_set(), p_key.as<int32_t>(), p_fs.as<int32_t>(), f, f + 1, h, s);
       fft3(h, -1, s);
       k_mul_conj<T, false><<<4096, 256, 0, s>>>(h, g, NC);
       launch_check("product");

@@ -17,6 +17,24 @@ static __global__ void k_fill_value(V* __restrict__ p, int64_t n, V v) {
     p[i] = v;
 }
 
+// fs[f] = first index of the sorted keys with key >= f nn, for f in [0, F]
+// (binary search; the field boundaries of a field-major catalogue)
+static __global__ void k_field_starts(const int32_t* __restrict__ key, int64_t n, int64_t nn, int F,
+                                      int32_t* __restrict__ fs) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f > F) return;
+  const int64_t t = (int64_t)f * nn;
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)key[mid] < t)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  fs[f] = (int32_t)lo;
+}
+
 static __global__ void k_field_counts(const int32_t* __restrict__ line_start, int64_t nn, int F,
                                int64_t* __restrict__ counts) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
