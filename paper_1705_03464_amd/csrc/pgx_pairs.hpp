@@ -150,8 +150,9 @@ static __global__ void k_pairs(PairCfg c, const double* __restrict__ px, const d
     const int nz = (cz + o % 3 - 1 + nc) % nc;
     const int nb = (nx * nc + ny) * nc + nz;
     const int s = cell_start[nb], e = cell_start[nb + 1];
-    for (int q = s; q < e; ++q) {
-      if (q <= p) continue;
+    // each pair once, by its lower cell-order index: start past p (a cell
+    // wholly before p's position is skipped at once)
+    for (int q = s > (int)p ? s : (int)p + 1; q < e; ++q) {
       const int ib = perm[q];
       const double bx = px[q], by = py[q], bz = pz[q];
       // i < j by catalogue index, d = x_j - x_i
