@@ -705,21 +705,25 @@ __device__ __forceinline__ int64_t ks_index(int kz, int kyr, int x) {
 }
 
 // z pass of the dual form on the kernel spectra: per slot, K^ G (K^ from the
-// store), inverse z transform, stored dense.  The next slot's kernel values
-// are loaded at the top of each trip, in flight during the transform.
+// store), inverse z transform, stored dense.  Shapes of at most 8 elements
+// per thread are held to 64 VGPRs (stage twiddles from the LDS table, no
+// prefetch of the next slot), so two 16-wave blocks share a compute unit and
+// one block's memory stream overlaps the other's transforms: 4.35 ms per
+// launch at 512^3 against 4.85 ms with one block per unit and the next
+// slot's kernel values prefetched in registers.
 template <typename T, typename Sh, int W>
-static __global__ void __launch_bounds__(W * Sh::TPL)
+static __global__ void __launch_bounds__(W * Sh::TPL, Sh::E <= 8 ? 8 : 1)
 k_zconv_ks(const C<T>* __restrict__ ks, int64_t ks_slot, int n_slots, const C<T>* __restrict__ fg,
            C<T>* __restrict__ out, int64_t out_slot, const C<T>* __restrict__ tw_g) {
   constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>(), H = N / 2;
   constexpr int64_t NN = (int64_t)N * N;
-  constexpr bool PIPE = E <= 8;
-  __shared__ C<T> tw_s[tw_lds_entries<Sh, kZTwReg>()];
+  constexpr bool PIPE = false;
+  __shared__ C<T> tw_s[tw_lds_entries<Sh, false>()];
   __shared__ C<T> lines[W][LL];
   int xt, ky;
   xcd_mirror_tile(xt, ky);
   const int c = threadIdx.x % W, t = threadIdx.x / W;
-  TwAuto<Sh, T, kZTwReg> twa;
+  TwAuto<Sh, T, false> twa;
   twa.init(tw_s, tw_g, t);
   const int kyr = ky <= H ? ky : N - ky, x = xt * W + c;
   const int64_t col = (int64_t)ky * N + x;
