@@ -202,3 +202,33 @@ def test_multipole_autograd_and_state():
     with pytest.raises(PgxError) as e:
         plan.multipoles_backward(Gm)  # a new forward invalidates the multipoles
     assert e.value.code == 5
+
+
+def test_multipoles_empty_fields_and_their_adjoint_128():
+    """A sparse catalogue on a 128^3 grid: pair fields without pairs give NaN
+    rows (as xi_pg does), the others meet the oracle, and the adjoint
+    ignores whatever upstream gradient sits on the NaN rows."""
+    from paper_1705_03464_amd import Plan
+    L = 200.0
+    wl = Workload(name="mpe", L=L, N=128, precision="fp32", pair_mode="s_mu",
+                  p1_edges=np.array([0.1, 0.3, 3.0, 9.0]), p2_edges=linbins(0.0, 1.0, 2), out_mode="shell",
+                  o1_edges=logbins(6.0, 40.0, 4), o2_edges=None, catalog_kw={})
+    cat = clustered_catalog(L, 60, 3000, seed=44, sat=4, spread=2.5)
+    w = np.random.default_rng(44).uniform(0.5, 1.5, cat.n).astype(np.float32).astype(np.float64)
+    exp, ref = oracle_multipoles(wl, cat, w, (0, 2))
+    plan = Plan.from_workload(wl, precision="fp32", batch=4)
+    P, counts = plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
+    plan.forward(dev(w, torch.float32))
+    got = plan.multipoles(2).cpu().numpy()
+    counts = counts.cpu().numpy()
+    _say(f"multipoles 128^3 sparse: pairs={P} per field {counts.tolist()}")
+    assert np.any(counts == 0) and np.any(counts > 0)
+    assert np.all(np.isnan(got[counts == 0]))
+    for il in range(2):
+        assert xi_err_ok(got[..., il], exp[..., il]) <= 1.0, il
+    g = np.random.default_rng(5).normal(size=got.shape)
+    g0 = np.where(np.isfinite(got), g, 0.0)
+    a = plan.multipoles_backward(dev(g)).cpu().numpy()
+    b = plan.multipoles_backward(dev(g0)).cpu().numpy()
+    assert np.all(np.isfinite(a))
+    assert np.max(np.abs(a - b)) <= 1e-6 * max(np.max(np.abs(b)), 1e-30)
