@@ -708,16 +708,15 @@ __device__ __forceinline__ int64_t ks_index(int kz, int kyr, int x) {
 // store), inverse z transform, stored dense.  Shapes of at most 8 elements
 // per thread are held to 64 VGPRs (stage twiddles from the LDS table, no
 // prefetch of the next slot), so two 16-wave blocks share a compute unit and
-// one block's memory stream overlaps the other's transforms: 4.35 ms per
-// launch at 512^3 against 4.85 ms with one block per unit and the next
-// slot's kernel values prefetched in registers.
+// one block's memory stream overlaps the other's transforms; at 512^3 that
+// beats one block per unit with the next slot's kernel values prefetched in
+// registers by about 14 %.
 template <typename T, typename Sh, int W>
 static __global__ void __launch_bounds__(W * Sh::TPL, Sh::E <= 8 ? 8 : 1)
 k_zconv_ks(const C<T>* __restrict__ ks, int64_t ks_slot, int n_slots, const C<T>* __restrict__ fg,
            C<T>* __restrict__ out, int64_t out_slot, const C<T>* __restrict__ tw_g) {
   constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>(), H = N / 2;
   constexpr int64_t NN = (int64_t)N * N;
-  constexpr bool PIPE = false;
   __shared__ C<T> tw_s[tw_lds_entries<Sh, false>()];
   __shared__ C<T> lines[W][LL];
   int xt, ky;
@@ -743,8 +742,7 @@ k_zconv_ks(const C<T>* __restrict__ ks, int64_t ks_slot, int n_slots, const C<T>
       for (int m = 0; m < E; ++m) k[m] = ks[slot * ks_slot + ks_index<N>(t + TPL * m, kyr, x)];
     }
   };
-  C<T> ka[E], kb[PIPE ? E : 1], g[E];
-  load_k(0, ka);
+  C<T> g[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     if constexpr (BUF) g[m] = Buf<T>(fg + tile).load(vo, (uint32_t)m * ZST);
@@ -765,29 +763,10 @@ k_zconv_ks(const C<T>* __restrict__ ks, int64_t ks_slot, int n_slots, const C<T>
       for (int m = 0; m < E; ++m) dst[(int64_t)(t + TPL * m) * NN] = v[m];
     }
   };
-  if constexpr (PIPE) {
-    auto trip = [&](int slot, const C<T>* cur, C<T>* nxt) {
-      if (slot + 1 < n_slots) load_k(slot + 1, nxt);
-      __builtin_amdgcn_sched_barrier(0);
-      C<T> v[E];
-#pragma unroll
-      for (int m = 0; m < E; ++m) v[m] = cur[m];
-      body(slot, v);
-    };
-    int slot = 0;
-    for (; slot + 1 < n_slots; slot += 2) {
-      trip(slot, ka, kb);
-      trip(slot + 1, kb, ka);
-    }
-    if (slot < n_slots) trip(slot, ka, kb);
-  } else {
-    for (int slot = 0; slot < n_slots; ++slot) {
-      if (slot > 0) load_k(slot, ka);
-      C<T> v[E];
-#pragma unroll
-      for (int m = 0; m < E; ++m) v[m] = ka[m];
-      body(slot, v);
-    }
+  for (int slot = 0; slot < n_slots; ++slot) {
+    C<T> v[E];
+    load_k(slot, v);
+    body(slot, v);
   }
 }
 
