@@ -229,21 +229,23 @@ k_xinv_gather_sweep(PointSet<T> ps, const int32_t* __restrict__ perm, int64_t P,
 }
 
 // S[f][b] = sum over the pairs of field f of (w_i w_j) gv[b][p] (FP64 pair
-// weights from k_pair_wprod; one 256-thread block per (field, bin), fixed
-// partition: deterministic).
+// weights from k_pair_wprod), divided by the bin's kernel scale (the FP32
+// value the kernel generator applied).  Block (f, b, k) of a grid (F, R, K)
+// writes the partial sum of chunk k of the field's range to
+// part[(f R + b) K + k]; k_sum_chunks adds them in order (deterministic).
 static __global__ void k_dual_reduce(const int32_t* __restrict__ line_start, int64_t nn,
                                      const double* __restrict__ wp, const float* __restrict__ gv,
                                      int64_t P, int R, const float* __restrict__ bscale,
-                                     double* __restrict__ S) {
+                                     double* __restrict__ part) {
   __shared__ double sh[256];
-  const int f = blockIdx.x, b = blockIdx.y;
-  const int64_t s = line_start[(int64_t)f * nn], e = line_start[(int64_t)(f + 1) * nn];
+  const int f = blockIdx.x, b = blockIdx.y, k = blockIdx.z, K = gridDim.z;
+  int64_t cs, ce;
+  chunk_of(line_start[(int64_t)f * nn], line_start[(int64_t)(f + 1) * nn], k, K, cs, ce);
   const float* g = gv + (int64_t)b * P;
   double acc = 0.0;
-  for (int64_t p = s + threadIdx.x; p < e; p += 256) acc += wp[p] * (double)g[p];
+  for (int64_t p = cs + threadIdx.x; p < ce; p += 256) acc += wp[p] * (double)g[p];
   const double r = block_sum256(acc, sh);
-  // undo the bin's kernel scale (the FP32 value the kernel generator applied)
-  if (threadIdx.x == 0) S[(int64_t)f * R + b] = r / (double)bscale[b];
+  if (threadIdx.x == 0) part[((int64_t)f * R + b) * K + k] = r / (double)bscale[b];
 }
 
 // ----------------------------------------------------------------------------
@@ -936,17 +938,19 @@ static __global__ void k_pair_harm(const int32_t* __restrict__ pi, const int32_t
 
 // S[(f R + b) nl + il] = 4 pi sum_{h of degree 2 il} sum_{p in f}
 //   w_p Y_h(d^_p) gv[b nh + h][p] / s_{b nh + h}
-// (FP64 pair weights; one 256-thread block per (field, bin, degree), fixed
-// partition: deterministic).
+// (FP64 pair weights).  Block (f, b nl + il, k) of a grid (F, R nl, K) writes
+// the partial sum of chunk k of the field's range to part[i K + k], i the
+// output index; k_sum_chunks adds them in order (deterministic).
 static __global__ void k_dual_reduce_mp(const int32_t* __restrict__ line_start, int64_t nn,
                                         const double* __restrict__ wp, const float* __restrict__ gv,
                                         const float* __restrict__ yp, int64_t P, int R, int nh, int nl,
-                                        const float* __restrict__ bscale, double* __restrict__ S) {
+                                        const float* __restrict__ bscale, double* __restrict__ part) {
   constexpr double PI = 3.14159265358979323846;
   __shared__ double sh[256];
-  const int f = blockIdx.x, b = blockIdx.y / nl, il = blockIdx.y % nl;
+  const int f = blockIdx.x, b = blockIdx.y / nl, il = blockIdx.y % nl, k = blockIdx.z, K = gridDim.z;
   const int h0 = il == 0 ? 0 : (il == 1 ? 1 : 6), h1 = il == 0 ? 1 : (il == 1 ? 6 : 15);
-  const int64_t s = line_start[(int64_t)f * nn], e = line_start[(int64_t)(f + 1) * nn];
+  int64_t s, e;
+  chunk_of(line_start[(int64_t)f * nn], line_start[(int64_t)(f + 1) * nn], k, K, s, e);
   double acc = 0.0;
   for (int h = h0; h < h1; ++h) {
     const int c = b * nh + h;
@@ -957,7 +961,7 @@ static __global__ void k_dual_reduce_mp(const int32_t* __restrict__ line_start, 
     acc += a / (double)bscale[c];
   }
   const double r = block_sum256(acc, sh);
-  if (threadIdx.x == 0) S[((int64_t)f * R + b) * nl + il] = 4.0 * PI * r;
+  if (threadIdx.x == 0) part[(((int64_t)f * R + b) * nl + il) * K + k] = 4.0 * PI * r;
 }
 
 // xi_l[f][b][il] = S / (n_b Wsum_f W_g), the normalisation of xi_pg.

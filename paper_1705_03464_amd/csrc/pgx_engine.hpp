@@ -255,6 +255,7 @@ template <typename T, int N> struct Engine : EngineBase {
   // with their task lists)
   DBuf p_key, p_ls, p_fs, p_i, p_j, p_x0, p_fx, p_fy, p_fz, p_wt;
   DBuf p_wd, wg_part;  // FP64 pair weights of the current forward; partial weight sums
+  DBuf ws_part, red_part, mp_part;  // partial sums of the chunked segmented reductions
   // line-major copy of the pair catalogue (all fields together): line starts,
   // CIC corner and fractions, field, field-major index, weight (adjoint of the
   // dual form)
@@ -474,8 +475,7 @@ template <typename T, int N> struct Engine : EngineBase {
     int64_t P = 0;
     if (n > 0) {
       k_pairs<false, T><<<grid_for(n), 256, 0, s>>>(pc, px, py, pz, perm, cks, cstart, n, cnt,
-                                                    nullptr, nullptr, nullptr, nullptr, nullptr,
-                                                    nullptr, nullptr);
+                                                    nullptr, nullptr, nullptr);
       launch_check("pair_count");
       exscan_i64(cnt, off, n, s, s_tmp);
       int64_t last[2] = {0, 0};
@@ -489,13 +489,9 @@ template <typename T, int N> struct Engine : EngineBase {
     int32_t* uk = s_k0.get<int32_t>(P);
     int32_t* ui = s_i.get<int32_t>(P);
     int32_t* uj = s_j.get<int32_t>(P);
-    int32_t* ux0 = s_x0.get<int32_t>(P);
-    T* ufx = s_fx.get<T>(P);
-    T* ufy = s_fy.get<T>(P);
-    T* ufz = s_fz.get<T>(P);
     if (P > 0) {
       k_pairs<true, T><<<grid_for(n), 256, 0, s>>>(pc, px, py, pz, perm, cks, cstart, n, off, uk,
-                                                   ui, uj, ux0, ufx, ufy, ufz);
+                                                   ui, uj);
       launch_check("pair_emit");
     }
     // bucket by (field, line)
@@ -510,10 +506,15 @@ template <typename T, int N> struct Engine : EngineBase {
     sort_pairs_i32(uk, sk, iota, pp, P, bits_for(nkeys), s, s_tmp);
     gather(pp, ui, p_i.get<int32_t>(P), P, s);
     gather(pp, uj, p_j.get<int32_t>(P), P, s);
-    gather(pp, ux0, p_x0.get<int32_t>(P), P, s);
-    gather(pp, ufx, p_fx.get<T>(P), P, s);
-    gather(pp, ufy, p_fy.get<T>(P), P, s);
-    gather(pp, ufz, p_fz.get<T>(P), P, s);
+    int32_t* px0 = p_x0.get<int32_t>(P);
+    T* pfx = p_fx.get<T>(P);
+    T* pfy = p_fy.get<T>(P);
+    T* pfz = p_fz.get<T>(P);
+    if (P > 0) {
+      k_pair_cic<T><<<grid_for(P), 256, 0, s>>>(pc, x, y, z, p_i.as<int32_t>(), p_j.as<int32_t>(), P, px0,
+                                                pfx, pfy, pfz);
+      launch_check("pair_cic");
+    }
     p_wt.get<T>(P);
     int32_t* pfs = p_fs.get<int32_t>(F + 1);
     k_field_starts<<<grid_for(F + 1), 256, 0, s>>>(sk, P, NN, F, pfs);
@@ -895,8 +896,13 @@ template <typename T, int N> struct Engine : EngineBase {
       k_pair_wprod<<<grid_for(n_pairs), 256, 0, s>>>(p_i.as<int32_t>(), p_j.as<int32_t>(), w, n_pairs, wp);
       launch_check("pair_wprod");
     }
-    k_field_wsum<<<F, 256, 0, s>>>(p_fs.as<int32_t>(), 1, wp, wsum_d.get<double>(F));
-    launch_check("field_wsum");
+    {
+      const int K = reduce_chunks(F);
+      double* part = ws_part.get<double>((int64_t)F * K);
+      k_field_wsum<<<dim3(F, K), 256, 0, s>>>(p_fs.as<int32_t>(), 1, wp, part);
+      k_sum_chunks<<<grid_for(F), 256, 0, s>>>(part, F, K, wsum_d.get<double>(F));
+      launch_check("field_wsum");
+    }
     k_field_scale<<<grid_for(F), 256, 0, s>>>(wsum_d.as<double>(), F, FSC.get<float>(std::max(F, 1)));
     launch_check("field_scale");
     double* wpart = wg_part.get<double>(kWtBlocks);
@@ -1425,9 +1431,14 @@ template <typename T, int N> struct Engine : EngineBase {
           launch_check("xinv_gather(multipoles)");
         }
       }
-      k_dual_reduce_mp<<<dim3(F, R * nl), 256, 0, s>>>(p_fs.as<int32_t>(), 1, p_wd.as<double>(), gv, yp, P, R,
-                                                       nh, nl, mp_scale.as<float>(), Sm);
-      launch_check("reduce(multipoles)");
+      {
+        const int K = reduce_chunks((int64_t)F * R * nl);
+        double* part = mp_part.get<double>((int64_t)F * R * nl * K);
+        k_dual_reduce_mp<<<dim3(F, R * nl, K), 256, 0, s>>>(p_fs.as<int32_t>(), 1, p_wd.as<double>(), gv, yp,
+                                                            P, R, nh, nl, mp_scale.as<float>(), part);
+        k_sum_chunks<<<grid_for((int64_t)F * R * nl), 256, 0, s>>>(part, (int64_t)F * R * nl, K, Sm);
+        launch_check("reduce(multipoles)");
+      }
       k_finalize_mp<<<grid_for((int64_t)F * R * nl), 256, 0, s>>>(Sm, nbd.as<double>(), wsum_d.as<double>(),
                                                                   wg_d.as<double>(), F, R, nl, xi);
       launch_check("finalize(multipoles)");
@@ -1614,8 +1625,11 @@ template <typename T, int N> struct Engine : EngineBase {
         });
       }
     }
-    k_dual_reduce<<<dim3(F, R), 256, 0, s>>>(p_fs.as<int32_t>(), 1, p_wd.as<double>(), gv, n_pairs,
-                                             R, bscale.as<float>(), Sd);
+    const int K = reduce_chunks((int64_t)F * R);
+    double* part = red_part.get<double>((int64_t)F * R * K);
+    k_dual_reduce<<<dim3(F, R, K), 256, 0, s>>>(p_fs.as<int32_t>(), 1, p_wd.as<double>(), gv, n_pairs,
+                                                R, bscale.as<float>(), part);
+    k_sum_chunks<<<grid_for((int64_t)F * R), 256, 0, s>>>(part, (int64_t)F * R, K, Sd);
     launch_check("reduce(dual)");
     if (kc) kc_valid = true;
   }

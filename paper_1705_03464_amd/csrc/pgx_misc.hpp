@@ -92,18 +92,43 @@ __device__ __forceinline__ double block_sum256(double v, double* sh) {
   return r;
 }
 
-// Sum of products w_i w_j in FP64 (k_pair_wprod) over each field's contiguous
-// range of the sorted pair list: one block (256 threads) per field, fixed
-// partition.
+// Segmented sums over the fields' contiguous ranges of the sorted pair list
+// are split into K equal chunks per segment (K fixed by the plan's sizes, so
+// the partition, hence the rounding, does not depend on the data): block
+// (segment, chunk k) sums chunk k, and k_sum_chunks adds the K partial sums
+// of each segment in order.  Enough blocks for the whole GPU even when a few
+// fields hold hundreds of millions of pairs.
+__host__ __device__ inline int reduce_chunks(int64_t segments) {
+  const int64_t k = (4096 + segments - 1) / (segments > 0 ? segments : 1);
+  return (int)(k < 1 ? 1 : (k > 256 ? 256 : k));
+}
+// bounds [cs, ce) of chunk k of K of the range [s, e)
+__device__ __forceinline__ void chunk_of(int64_t s, int64_t e, int k, int K, int64_t& cs, int64_t& ce) {
+  cs = s + (e - s) * k / K;
+  ce = s + (e - s) * (k + 1) / K;
+}
+// out[i] = sum_{k < K} part[i K + k], in order
+static __global__ void k_sum_chunks(const double* __restrict__ part, int64_t n, int K,
+                                    double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double a = 0.0;
+  for (int k = 0; k < K; ++k) a += part[i * K + k];
+  out[i] = a;
+}
+
+// Partial sums of the products w_i w_j in FP64 (k_pair_wprod) over each
+// field's range: block (f, k) of a grid (F, K).
 static __global__ void k_field_wsum(const int32_t* __restrict__ line_start, int64_t nn,
-                                    const double* __restrict__ wp, double* __restrict__ wsum) {
+                                    const double* __restrict__ wp, double* __restrict__ part) {
   __shared__ double sh[256];
-  const int f = blockIdx.x;
-  const int64_t s = line_start[(int64_t)f * nn], e = line_start[(int64_t)(f + 1) * nn];
+  const int f = blockIdx.x, k = blockIdx.y, K = gridDim.y;
+  int64_t cs, ce;
+  chunk_of(line_start[(int64_t)f * nn], line_start[(int64_t)(f + 1) * nn], k, K, cs, ce);
   double acc = 0.0;
-  for (int64_t p = s + threadIdx.x; p < e; p += 256) acc += wp[p];
+  for (int64_t p = cs + threadIdx.x; p < ce; p += 256) acc += wp[p];
   const double r = block_sum256(acc, sh);
-  if (threadIdx.x == 0) wsum[f] = r;
+  if (threadIdx.x == 0) part[(int64_t)f * K + k] = r;
 }
 
 // Largest disagreement between two sets of bin sums of the same estimator,

@@ -126,14 +126,16 @@ static __global__ void k_run_counts(const int32_t* __restrict__ key, int64_t n, 
 
 // One thread per galaxy in cell order; candidates are galaxies of the 27
 // neighbour cells with a larger cell-order index.  COUNT: cnt[p] = number of
-// kept pairs.  EMIT: pairs written at off[p] + local index.
+// kept pairs.  EMIT: pairs written at off[p] + local index: the sort key
+// (field, base line of the midpoint) and the catalogue indices i < j only;
+// the midpoint's CIC corner and fractions are recomputed after the sort by
+// k_pair_cic, with coalesced stores.
 template <bool EMIT, typename T>
 static __global__ void k_pairs(PairCfg c, const double* __restrict__ px, const double* __restrict__ py,
                         const double* __restrict__ pz, const int32_t* __restrict__ perm,
                         const int32_t* __restrict__ cell_of, const int32_t* __restrict__ cell_start,
                         int64_t n, int64_t* __restrict__ cnt_off, int32_t* __restrict__ skey,
-                        int32_t* __restrict__ oi, int32_t* __restrict__ oj, int32_t* __restrict__ ox0,
-                        T* __restrict__ ofx, T* __restrict__ ofy, T* __restrict__ ofz) {
+                        int32_t* __restrict__ oi, int32_t* __restrict__ oj) {
 #pragma clang fp contract(off)
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
@@ -168,23 +170,51 @@ static __global__ void k_pairs(PairCfg c, const double* __restrict__ px, const d
         mx = mx >= c.L ? mx - c.L : (mx < 0.0 ? mx + c.L : mx);
         my = my >= c.L ? my - c.L : (my < 0.0 ? my + c.L : my);
         mz = mz >= c.L ? mz - c.L : (mz < 0.0 ? mz + c.L : mz);
-        int x0, y0, z0;
-        double fx, fy, fz;
-        cic_of(mx, c.gscale, c.N, x0, fx);
+        int y0, z0;
+        double fy, fz;
+        (void)mx;
         cic_of(my, c.gscale, c.N, y0, fy);
         cic_of(mz, c.gscale, c.N, z0, fz);
         skey[w] = (int32_t)((int64_t)key * NN + (int64_t)z0 * c.N + y0);
         oi[w] = fwd ? ia : ib;
         oj[w] = fwd ? ib : ia;
-        ox0[w] = x0;
-        ofx[w] = (T)fx;
-        ofy[w] = (T)fy;
-        ofz[w] = (T)fz;
       }
       ++w;
     }
   }
   if constexpr (!EMIT) cnt_off[p] = w;
+}
+
+// CIC corner and fractions of each pair's midpoint, in sorted order, from the
+// catalogue positions of its members (i < j): the same FP64 operations as the
+// pair search (d = x_j - x_i folded once into [-L/2, L/2), m = x_i + d / 2
+// wrapped into [0, L)), so the result matches the key the search gave.
+template <typename T>
+static __global__ void k_pair_cic(PairCfg c, const double* __restrict__ x, const double* __restrict__ y,
+                                  const double* __restrict__ z, const int32_t* __restrict__ pi,
+                                  const int32_t* __restrict__ pj, int64_t P, int32_t* __restrict__ ox0,
+                                  T* __restrict__ ofx, T* __restrict__ ofy, T* __restrict__ ofz) {
+#pragma clang fp contract(off)
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const int i = pi[p], j = pj[p];
+  const double xi = x[i], yi = y[i], zi = z[i];
+  const double dx = fold(x[j] - xi, c.L, c.halfL);
+  const double dy = fold(y[j] - yi, c.L, c.halfL);
+  const double dz = fold(z[j] - zi, c.L, c.halfL);
+  double mx = xi + 0.5 * dx, my = yi + 0.5 * dy, mz = zi + 0.5 * dz;
+  mx = mx >= c.L ? mx - c.L : (mx < 0.0 ? mx + c.L : mx);
+  my = my >= c.L ? my - c.L : (my < 0.0 ? my + c.L : my);
+  mz = mz >= c.L ? mz - c.L : (mz < 0.0 ? mz + c.L : mz);
+  int x0, y0, z0;
+  double fx, fy, fz;
+  cic_of(mx, c.gscale, c.N, x0, fx);
+  cic_of(my, c.gscale, c.N, y0, fy);
+  cic_of(mz, c.gscale, c.N, z0, fz);
+  ox0[p] = x0;
+  ofx[p] = (T)fx;
+  ofy[p] = (T)fy;
+  ofz[p] = (T)fz;
 }
 
 // galaxy CIC points: key = z0*N + y0
