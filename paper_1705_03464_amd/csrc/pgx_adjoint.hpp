@@ -487,81 +487,6 @@ k_xgather(const int32_t* __restrict__ tasks, int n_tasks, PointSet<T> ps,
 }
 
 // grad[i] += w_j (acc[p] + gws[f]), grad[j] += w_i (...) for every pair
-// Segmented inclusive sums over one wavefront (64 lanes) of runs of equal
-// keys in adjacent lanes, for any key order (equal keys that are not adjacent
-// stay separate runs).  Lane L starts a run when its key differs from lane
-// L - 1's.  A Hillis-Steele scan with run-start flags: row shifts of 1, 2, 4
-// and 8 lanes within rows of 16 (DPP), then the carries from lanes 15, 31 and
-// 47 across rows; each step adds the shifted partial sum only while no run
-// start lies in between, so a lane ends with the sum of its run up to
-// itself, and the last lane of each run (`tail`) holds the whole run.  The
-// steps taken depend on the keys only and are computed once; all 64 lanes
-// must take part.
-struct SegRuns {
-  uint32_t m;
-  bool tail;
-  __device__ __forceinline__ void init(int key) {
-    const int lane = (int)(threadIdx.x & 63u), lr = lane & 15, row = lane >> 4;
-    const int prev = __builtin_amdgcn_ds_bpermute(((lane + 63) & 63) << 2, key);
-    const int next = __builtin_amdgcn_ds_bpermute(((lane + 1) & 63) << 2, key);
-    int h = (lane == 0 || prev != key) ? 1 : 0;  // a run starts at or after the span's start
-    tail = lane == 63 || next != key;
-    m = 0u;
-    const int hs1 = __builtin_amdgcn_update_dpp(1, h, 0x111, 0xF, 0xF, false);
-    if (lr >= 1 && !h) { m |= 1u; h |= hs1; }
-    const int hs2 = __builtin_amdgcn_update_dpp(1, h, 0x112, 0xF, 0xF, false);
-    if (lr >= 2 && !h) { m |= 2u; h |= hs2; }
-    const int hs4 = __builtin_amdgcn_update_dpp(1, h, 0x114, 0xF, 0xF, false);
-    if (lr >= 4 && !h) { m |= 4u; h |= hs4; }
-    const int hs8 = __builtin_amdgcn_update_dpp(1, h, 0x118, 0xF, 0xF, false);
-    if (lr >= 8 && !h) { m |= 8u; h |= hs8; }
-    const int c15 = __builtin_amdgcn_readlane(h, 15);
-    if (row == 1 && !h) { m |= 16u; h |= c15; }
-    const int c31 = __builtin_amdgcn_readlane(h, 31);
-    if (row == 2 && !h) { m |= 32u; h |= c31; }
-    const int c47 = __builtin_amdgcn_readlane(h, 47);
-    if (row == 3 && !h) { m |= 64u; h |= c47; }
-  }
-  __device__ __forceinline__ static double shr(double v, int ctrl_sel) {
-    const int2 b = __builtin_bit_cast(int2, v);
-    int lo, hi;
-    switch (ctrl_sel) {
-      case 1: lo = __builtin_amdgcn_update_dpp(0, b.x, 0x111, 0xF, 0xF, false);
-              hi = __builtin_amdgcn_update_dpp(0, b.y, 0x111, 0xF, 0xF, false); break;
-      case 2: lo = __builtin_amdgcn_update_dpp(0, b.x, 0x112, 0xF, 0xF, false);
-              hi = __builtin_amdgcn_update_dpp(0, b.y, 0x112, 0xF, 0xF, false); break;
-      case 4: lo = __builtin_amdgcn_update_dpp(0, b.x, 0x114, 0xF, 0xF, false);
-              hi = __builtin_amdgcn_update_dpp(0, b.y, 0x114, 0xF, 0xF, false); break;
-      default: lo = __builtin_amdgcn_update_dpp(0, b.x, 0x118, 0xF, 0xF, false);
-               hi = __builtin_amdgcn_update_dpp(0, b.y, 0x118, 0xF, 0xF, false); break;
-    }
-    return __builtin_bit_cast(double, make_int2(lo, hi));
-  }
-  __device__ __forceinline__ static double lane_value(double v, int l) {
-    const int2 b = __builtin_bit_cast(int2, v);
-    return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_readlane(b.x, l),
-                                                __builtin_amdgcn_readlane(b.y, l)));
-  }
-  __device__ __forceinline__ double add(double v) const {
-    double s;
-    s = shr(v, 1);
-    v += (m & 1u) ? s : 0.0;
-    s = shr(v, 2);
-    v += (m & 2u) ? s : 0.0;
-    s = shr(v, 4);
-    v += (m & 4u) ? s : 0.0;
-    s = shr(v, 8);
-    v += (m & 8u) ? s : 0.0;
-    s = lane_value(v, 15);
-    v += (m & 16u) ? s : 0.0;
-    s = lane_value(v, 31);
-    v += (m & 32u) ? s : 0.0;
-    s = lane_value(v, 47);
-    v += (m & 64u) ? s : 0.0;
-    return v;
-  }
-};
-
 // Pair terms of the weight gradient: grad[i] += w_j g_p, grad[j] += w_i g_p
 // with g_p = acc[p] + dL/dWsum_f.  Within a (field, line) the pairs keep the
 // order of the pair search, which emits each galaxy's pairs together, so

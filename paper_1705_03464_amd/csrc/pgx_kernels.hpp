@@ -8,6 +8,7 @@
 #include "pgx_fft.hpp"
 #include "pgx_weight.hpp"
 #include "pgx_harm.hpp"
+#include "pgx_wave.hpp"
 
 #include <type_traits>
 
@@ -123,7 +124,11 @@ template <typename Sh, bool PREFER_REG> constexpr int tw_lds_entries() {
 // (A) x pass with the CIC scatter fused in.  One task per non-empty line of a
 // field pair.  The line is built in LDS from the points of the four base lines
 // whose CIC footprint reaches it (LDS atomics), transformed along x and
-// written once.  task word = slot * N*N + line (line = z*N + y).
+// written once.  task word = slot * N*N + line (line = z*N + y).  When a line
+// is one or more whole wavefronts, each wavefront first sums the
+// contributions of adjacent points on the same x node (clustered catalogues
+// put many points on one node, and same-address LDS atomics serialise), and
+// only the last point of each run adds to the line.
 // ----------------------------------------------------------------------------
 template <typename T, typename Sh, int W>
 static __global__ void __launch_bounds__(W * Sh::TPL)
@@ -133,6 +138,7 @@ k_xscatter(const int32_t* __restrict__ tasks, int n_tasks, PointSet<T> ps,
            const float* __restrict__ fscale = nullptr) {
   constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>();
   constexpr int64_t NN = (int64_t)N * N;
+  constexpr bool kRuns = TPL % 64 == 0;
   __shared__ C<T> tw_s[Sh::tw_entries()];
   __shared__ C<T> lines[W][LL];
   load_twiddles<T, Sh>(tw_s, tw_g);
@@ -165,16 +171,35 @@ k_xscatter(const int32_t* __restrict__ tasks, int n_tasks, PointSet<T> ps,
         const int by = (q & 1) ? ym : y, bz = (q & 2) ? zm : z;
         const int64_t key = fbase + (int64_t)bz * N + by;
         const int s = ps.line_start[key], e = ps.line_start[key + 1];
-        for (int p = s + t; p < e; p += TPL) {
-          const T fy = ps.fy[p], fz = ps.fz[p], fx = ps.fx[p];
-          const T wy = (q & 1) ? fy : (T)1 - fy;
-          const T wz = (q & 2) ? fz : (T)1 - fz;
-          const T w = ps.wt[p] * sc * wy * wz;
-          const int x0 = ps.x0[p];
-          T* a0 = part == 0 ? &line[lpad(x0)].x : &line[lpad(x0)].y;
-          T* a1 = part == 0 ? &line[lpad((x0 + 1) & (N - 1))].x : &line[lpad((x0 + 1) & (N - 1))].y;
-          atomicAdd(a0, w * ((T)1 - fx));
-          atomicAdd(a1, w * fx);
+        // every lane of a wavefront takes the same trips (one line per wavefront)
+        for (int b0 = s; b0 < e; b0 += TPL) {
+          const int p = b0 + t;
+          const bool ok = p < e;
+          T lo = (T)0, hi = (T)0;
+          int x0 = -1 - (int)(threadIdx.x & 63u);  // idle lanes: keys no node has
+          if (ok) {
+            const T fy = ps.fy[p], fz = ps.fz[p], fx = ps.fx[p];
+            const T wy = (q & 1) ? fy : (T)1 - fy;
+            const T wz = (q & 2) ? fz : (T)1 - fz;
+            const T w = ps.wt[p] * sc * wy * wz;
+            x0 = ps.x0[p];
+            lo = w * ((T)1 - fx);
+            hi = w * fx;
+          }
+          bool issue = ok;
+          if constexpr (kRuns) {
+            SegRuns r;
+            r.init(x0);
+            lo = r.add(lo);
+            hi = r.add(hi);
+            issue = ok && r.tail;
+          }
+          if (issue) {
+            T* a0 = part == 0 ? &line[lpad(x0)].x : &line[lpad(x0)].y;
+            T* a1 = part == 0 ? &line[lpad((x0 + 1) & (N - 1))].x : &line[lpad((x0 + 1) & (N - 1))].y;
+            atomicAdd(a0, lo);
+            atomicAdd(a1, hi);
+          }
         }
       }
     }
