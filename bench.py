@@ -144,7 +144,7 @@ def main(argv=None):
                          "scale the FETCH_SIZE / WRITE_SIZE counters of a profiler run")
     a = ap.parse_args(argv)
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {a.gpus}); this build has no multi-GPU path",
+        print(f"bench.py runs on one GPU only (asked for {a.gpus}); the library has no multi-GPU path",
               file=sys.stderr)
         return 2
 
