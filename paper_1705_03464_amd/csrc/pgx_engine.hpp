@@ -233,6 +233,8 @@ template <typename T, int N> struct Engine : EngineBase {
   std::vector<int64_t> build_print;     // schedule and buffers of the last pair build
   // the line flags and x-pass task lists match the current catalogue
   bool tasks_ready = false;
+  // the dual form's line-major copy of the pairs matches the current catalogue
+  bool lm_ready = false;
 
   // kernel variants picked by the autotuner (0 = default): forward y pass,
   // inverse y pass (radix schedule), z pass (twiddle source; for the dual
@@ -552,14 +554,55 @@ template <typename T, int N> struct Engine : EngineBase {
     g_wt.get<T>(n);
     counts_to_starts(gks, n, NN, s_hist.get<int32_t>(NN + 1), g_ls.get<int32_t>(NN + 1), s);
 
-    // line-major copy of the pairs (stable sort of the field-major order by
-    // base line, then x node)
+    // line-major copy of the pairs (the dual form's): only when that
+    // algorithm is in use (its entry points build it on demand)
+    lm_ready = false;
+    if constexpr (std::is_same<T, float>::value)
+      if (algo == 1) line_major(s);
+    // line flags and x-pass task lists of the per-field transforms: only
+    // when that algorithm is in use (the schedule builds them on demand)
+    tasks_ready = false;
+    if constexpr (std::is_same<T, float>::value)
+      if (algo == 0) schedule(B, s);
+    PGX_HIP(hipStreamSynchronize(s));
+    if (n_pairs_out) *n_pairs_out = P;
+    built = true;
+    refresh_print();
+  }
+
+  // Recorded launch sequences stay valid when the new catalogue has the same
+  // schedule (sizes, per-batch task counts, per-field counts) in the same
+  // buffers, as when the same catalogue is rebuilt; otherwise the generation
+  // moves on and they are recorded again.
+  void refresh_print() {
+    std::vector<int64_t> fpr = {n_gal, n_pairs, (int64_t)B, tasks_ready ? 1 : 0, lm_ready ? 1 : 0};
+    if (tasks_ready) fpr.insert(fpr.end(), batch_task_off.begin(), batch_task_off.end());
+    fpr.insert(fpr.end(), field_counts_h.begin(), field_counts_h.end());
+    for (const DBuf* d : {&g_key, &g_ls, &g_x0, &g_fx, &g_fy, &g_fz, &g_idx, &g_wt, &g_tasks, &p_key,
+                          &p_ls, &p_fs, &p_i, &p_j, &p_x0, &p_fx, &p_fy, &p_fz, &p_wt, &lflag, &pflag, &tasks, &l_ls, &l_x0, &l_fx,
+                          &l_fy, &l_fz, &l_f, &l_p, &l_wt})
+      fpr.push_back((int64_t)(intptr_t)d->p);
+    if (fpr != build_print) {
+      build_print = fpr;
+      ++gen;
+    }
+  }
+
+  // Line-major copy of the pairs for the dual form: a stable sort of the
+  // field-major order by (base line, x node), the CIC data and field of each
+  // pair in that order, and the line starts.
+  void line_major(hipStream_t s) {
     if constexpr (std::is_same<T, float>::value) {
+      const int64_t P = n_pairs;
+      int32_t* iota = s_v0.get<int32_t>(P);
       int32_t* lk = s_k0.get<int32_t>(P);
       int32_t* lks = s_i.get<int32_t>(P);
       int32_t* lln = s_j.get<int32_t>(P);
       int32_t* lp = l_p.get<int32_t>(P);
+      const int32_t* sk = p_key.as<int32_t>();
       if (P > 0) {
+        k_iota<<<grid_for(P), 256, 0, s>>>(iota, P);
+        launch_check("iota");
         k_line_x_key<<<grid_for(P), 256, 0, s>>>(sk, p_x0.as<int32_t>(), P, NN, N, lk);
         launch_check("line_x_key");
       }
@@ -580,32 +623,15 @@ template <typename T, int N> struct Engine : EngineBase {
       l_wt.get<T>(P);
       counts_to_starts(lln, P, NN, s_hist.get<int32_t>(NN + 1), l_ls.get<int32_t>(NN + 1), s);
     }
-    // line flags and x-pass task lists of the per-field transforms: only
-    // when that algorithm is in use (the schedule builds them on demand)
-    tasks_ready = false;
-    if constexpr (std::is_same<T, float>::value)
-      if (algo == 0) schedule(B, s);
-    PGX_HIP(hipStreamSynchronize(s));
-    if (n_pairs_out) *n_pairs_out = P;
-    built = true;
-    refresh_print();
+    lm_ready = true;
   }
 
-  // Recorded launch sequences stay valid when the new catalogue has the same
-  // schedule (sizes, per-batch task counts, per-field counts) in the same
-  // buffers, as when the same catalogue is rebuilt; otherwise the generation
-  // moves on and they are recorded again.
-  void refresh_print() {
-    std::vector<int64_t> fpr = {n_gal, n_pairs, (int64_t)B, tasks_ready ? 1 : 0};
-    if (tasks_ready) fpr.insert(fpr.end(), batch_task_off.begin(), batch_task_off.end());
-    fpr.insert(fpr.end(), field_counts_h.begin(), field_counts_h.end());
-    for (const DBuf* d : {&g_key, &g_ls, &g_x0, &g_fx, &g_fy, &g_fz, &g_idx, &g_wt, &g_tasks, &p_key,
-                          &p_ls, &p_fs, &p_i, &p_j, &p_x0, &p_fx, &p_fy, &p_fz, &p_wt, &lflag, &pflag, &tasks, &l_ls, &l_x0, &l_fx,
-                          &l_fy, &l_fz, &l_f, &l_p, &l_wt})
-      fpr.push_back((int64_t)(intptr_t)d->p);
-    if (fpr != build_print) {
-      build_print = fpr;
-      ++gen;
+  // Builds the line-major copy if the current catalogue has none yet (before
+  // anything that records launches).
+  void ensure_line_major(hipStream_t s) {
+    if (!lm_ready) {
+      line_major(s);
+      refresh_print();
     }
   }
 
@@ -717,6 +743,7 @@ template <typename T, int N> struct Engine : EngineBase {
         PGX_HIP(hipMemcpyAsync(sref, S.as<double>(), (size_t)F * R * sizeof(double),
                                hipMemcpyDeviceToDevice, s));
         schedule(best[0], s);
+        ensure_line_major(s);
         algo = 1;
         double dis[3] = {-1.0, -1.0, -1.0};
         for (int v = 0; v < 3; ++v) {
@@ -977,7 +1004,10 @@ template <typename T, int N> struct Engine : EngineBase {
     if constexpr (std::is_same<T, float>::value)
       spec = keep_spectra && algo == 0 ? spectra_store() : nullptr;  // the dual form has no pair-field spectra
     if constexpr (std::is_same<T, float>::value) {
-      if (algo == 1) ensure_dual_kernels(s);
+      if (algo == 1) {
+        ensure_line_major(s);
+        ensure_dual_kernels(s);
+      }
       if (algo == 0 && !tasks_ready) {
         schedule(B, s);
         refresh_print();
@@ -1376,6 +1406,7 @@ template <typename T, int N> struct Engine : EngineBase {
       PGX_REQUIRE(cfg.out_mode == 0, PGX_EINVAL, "multipoles are taken over shell output bins");
       PGX_REQUIRE(cfg.o1[0] > 0.0, PGX_EINVAL, "the first shell edge must be > 0 for multipoles");
       PGX_REQUIRE(built && forward_done, PGX_ESTATE, "pgx_multipoles needs a preceding pgx_forward");
+      ensure_line_major(s);
       const int R = cfg.R, F = cfg.F, nh = harm_count(lmax), nl = lmax / 2 + 1;
       const int RC = R * nh, QC = (RC + 1) / 2;
       // combo tables: coefficient 1 / n_b (FP32 value) for bin b(c) = c / nh
@@ -1457,6 +1488,7 @@ template <typename T, int N> struct Engine : EngineBase {
     } else {
       PGX_REQUIRE(built && forward_done && mp_lmax >= 0, PGX_ESTATE,
                   "pgx_multipoles_backward needs a preceding pgx_multipoles after the last pgx_forward");
+      ensure_line_major(s);
       PGX_REQUIRE(g != nullptr, PGX_EINVAL, "g_xi_l must not be NULL");
       PGX_REQUIRE(grad_w != nullptr || n_gal == 0, PGX_EINVAL, "grad_w must not be NULL");
       const int lmax = mp_lmax, R = cfg.R, F = cfg.F, nh = harm_count(lmax), nl = lmax / 2 + 1;
