@@ -146,6 +146,21 @@ static __global__ void k_pairs(PairCfg c, const double* __restrict__ px, const d
   const int ia = perm[p];
   int64_t w = EMIT ? cnt_off[p] : 0;
   const int64_t NN = (int64_t)c.N * c.N;
+  // emitted pairs wait in registers until they fill an aligned group of
+  // four output slots, which is then written as one 16-byte store per array
+  // (a thread's pairs occupy its own contiguous output range); kb[k] holds
+  // the pair of slot w - 4 + k, the last nbuf of them not yet written
+  int32_t kb[4] = {0, 0, 0, 0}, ib[4] = {0, 0, 0, 0}, jb[4] = {0, 0, 0, 0};
+  int nbuf = 0;
+  auto flush = [&]() {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (k >= 4 - nbuf) {
+        skey[w - 4 + k] = kb[k];
+        oi[w - 4 + k] = ib[k];
+        oj[w - 4 + k] = jb[k];
+      }
+  };
   for (int o = 0; o < 27; ++o) {
     const int nx = (cx + o / 9 - 1 + nc) % nc;
     const int ny = (cy + (o / 3) % 3 - 1 + nc) % nc;
@@ -155,10 +170,10 @@ static __global__ void k_pairs(PairCfg c, const double* __restrict__ px, const d
     // each pair once, by its lower cell-order index: start past p (a cell
     // wholly before p's position is skipped at once)
     for (int q = s > (int)p ? s : (int)p + 1; q < e; ++q) {
-      const int ib = perm[q];
+      const int ib_ = perm[q];
       const double bx = px[q], by = py[q], bz = pz[q];
       // i < j by catalogue index, d = x_j - x_i
-      const bool fwd = ia < ib;
+      const bool fwd = ia < ib_;
       const double xi = fwd ? ax : bx, yi = fwd ? ay : by, zi = fwd ? az : bz;
       const double dx = fold((fwd ? bx : ax) - xi, c.L, c.halfL);
       const double dy = fold((fwd ? by : ay) - yi, c.L, c.halfL);
@@ -175,14 +190,39 @@ static __global__ void k_pairs(PairCfg c, const double* __restrict__ px, const d
         (void)mx;
         cic_of(my, c.gscale, c.N, y0, fy);
         cic_of(mz, c.gscale, c.N, z0, fz);
-        skey[w] = (int32_t)((int64_t)key * NN + (int64_t)z0 * c.N + y0);
-        oi[w] = fwd ? ia : ib;
-        oj[w] = fwd ? ib : ia;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          kb[k] = kb[k + 1];
+          ib[k] = ib[k + 1];
+          jb[k] = jb[k + 1];
+        }
+        kb[3] = (int32_t)((int64_t)key * NN + (int64_t)z0 * c.N + y0);
+        ib[3] = fwd ? ia : ib_;
+        jb[3] = fwd ? ib_ : ia;
+        nbuf = nbuf < 4 ? nbuf + 1 : 4;
       }
       ++w;
+      if constexpr (EMIT) {
+        if ((w & 3) == 0) {
+          if (nbuf == 4) {
+            *reinterpret_cast<int4*>(skey + w - 4) = make_int4(kb[0], kb[1], kb[2], kb[3]);
+            *reinterpret_cast<int4*>(oi + w - 4) = make_int4(ib[0], ib[1], ib[2], ib[3]);
+            *reinterpret_cast<int4*>(oj + w - 4) = make_int4(jb[0], jb[1], jb[2], jb[3]);
+          } else {
+            flush();
+          }
+          nbuf = 0;
+        }
+      }
     }
   }
-  if constexpr (!EMIT) cnt_off[p] = w;
+  if constexpr (EMIT) {
+    // the last, unaligned group: slots w - nbuf .. w - 1 hold kb[4 - nbuf .. 3]
+    // (kb[k] is slot w - 4 + k whatever w mod 4 is)
+    flush();
+  } else {
+    cnt_off[p] = w;
+  }
 }
 
 // CIC corner and fractions of each pair's midpoint, in sorted order, from the
