@@ -170,6 +170,83 @@ def test_p2_shell_counts_closed_form():
     assert np.array_equal(table[2], exp)
 
 
+# P2 for the two-dimensional output bins: closed-form lattice counts, written
+# without the oracle's classifier.  The grid spacing is 1 (L = N) and every
+# edge is chosen so that lattice vectors lie exactly on it, so a flipped
+# comparison (>= against >, < against <=) on either axis changes a count.
+def _r2(n):
+    """Number of integer (a, b) with a^2 + b^2 = n (sum-of-two-squares count)."""
+    if n < 0:
+        return 0
+    c = 0
+    for a in range(-math.isqrt(n), math.isqrt(n) + 1):
+        b2 = n - a * a
+        b = math.isqrt(b2)
+        if b * b == b2:
+            c += 1 if b == 0 else 2
+    return c
+
+
+def test_p2_rp_pi_counts_closed_form_on_edges():
+    """(r_p, |pi|) bins: the count of bin (b, k) is the number of (i', j') in
+    the annulus e_b <= r_p < e_{b+1} (a sum of r2(n) over n in [e_b^2,
+    e_{b+1}^2)) times the number of k' in the slab p_k <= |k'| < p_{k+1}
+    (2 (p_{k+1} - p_k) integers, one fewer when p_k = 0).  Integer edges put
+    vectors such as (3, 4, k') and (0, 5, k') exactly on r_p = 5 and k' = +-2
+    exactly on |pi| = 2."""
+    L = N = 64
+    rp = np.array([0.0, 3.0, 5.0, 8.0, 13.0])
+    pi = np.array([0.0, 2.0, 4.0, 7.0])
+    got = B.lattice_table("rp_pi", rp, pi, float(L), N)[2]
+    ann = [sum(_r2(n) for n in range(int(rp[b]) ** 2, int(rp[b + 1]) ** 2)) for b in range(rp.size - 1)]
+    slab = [2 * int(pi[k + 1] - pi[k]) - (1 if pi[k] == 0 else 0) for k in range(pi.size - 1)]
+    exp = np.array([a * s for a in ann for s in slab], np.int64)
+    assert np.array_equal(got, exp), (got, exp)
+    # the edges are hit: vectors with r_p exactly 5 and 8, |k'| exactly 2, 4, 7
+    assert _r2(25) > 0 and _r2(64) > 0 and _r2(169) > 0
+
+
+def test_p2_r_mu_counts_closed_form_on_edges():
+    """(r, |mu|) bins: every lattice vector with i'^2 + j'^2 + k'^2 = m and
+    k'^2 = K has the same bin, and there are r2(m - K) (times 2 for the sign
+    of k' when K > 0) of them.  The shell is decided on m against the
+    integer squares of the r edges; |mu| on K >= mu_e^2 m, the squares taken
+    in FP64 as the bins are defined (ties go to the upper bin, mu = 1 to the
+    last).  Here the r edges are integers and the |mu| edges 1/3, 0.6 and
+    6/7 are ones whose FP64 squares make K = mu_e^2 m exact for vectors such
+    as (2, 2, 1), (0, 4, 3) and (2, 3, 6); those ties are checked to be
+    exact in rational arithmetic too, so this count does not rest on the
+    rounding of the products."""
+    from fractions import Fraction
+    L = N = 64
+    r = np.array([2.0, 3.0, 5.0, 7.0, 9.0, 10.0, 14.0])
+    mu = np.array([0.0, 1.0 / 3.0, 0.6, 6.0 / 7.0, 1.0])
+    got = B.lattice_table("r_mu", r, mu, float(L), N)[2]
+    n2 = mu.size - 1
+    exp = np.zeros((r.size - 1) * n2, np.int64)
+    ties = 0
+    W = int(r[-1])
+    for m in range(W * W + 1):
+        sb = [b for b in range(r.size - 1) if int(r[b]) ** 2 <= m < int(r[b + 1]) ** 2]
+        if not sb:
+            continue
+        for k in range(0, math.isqrt(m) + 1):
+            K = k * k
+            n = _r2(m - K) * (2 if k > 0 else 1)
+            if n == 0:
+                continue
+            # largest e with K >= mu_e^2 m (FP64 squares); the top edge is closed
+            e = max(i for i in range(n2 + 1) if K >= (mu[i] * mu[i]) * m)
+            for i in range(n2 + 1):
+                tie = K == (mu[i] * mu[i]) * m
+                ties += int(tie and 0 < i < n2)
+                exact = Fraction(K) >= Fraction(float(mu[i])) ** 2 * m
+                assert exact == (K >= (mu[i] * mu[i]) * m), (m, K, i)
+            exp[sb[0] * n2 + min(e, n2 - 1)] += n
+    assert ties >= 3
+    assert np.array_equal(got, exp), (got, exp)
+
+
 # ---------------------------------------------------------------- P3 node-placed special case
 def test_p3_node_placed_equals_integer_histogram():
     rng = np.random.default_rng(11)
