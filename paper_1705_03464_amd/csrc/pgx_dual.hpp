@@ -971,7 +971,7 @@ static __global__ void k_finalize_mp(const double* __restrict__ S, const double*
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)F * R * nl) return;
   const int f = (int)(i / ((int64_t)R * nl)), b = (int)((i / nl) % R);
-  xi[i] = S[i] / (nb[b] * wsum[f] * wg[0]);
+  xi[i] = wsum[f] > 0.0 ? S[i] / (nb[b] * wsum[f] * wg[0]) : __builtin_nan("");
 }
 
 // ----------------------------------------------------------------------------

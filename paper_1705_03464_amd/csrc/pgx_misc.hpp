@@ -255,7 +255,9 @@ static __global__ void k_finalize(FinalizeArgs a) {
   if (i >= a.F * a.R) return;
   const int f = i / a.R, b = i % a.R;
   const double xgg = a.Sgg[b] / (a.nb[b] * wg * wg);
-  const double xpg = a.S[i] / (a.nb[b] * a.wsum[f] * wg);
+  // an empty field (no pairs, or zero pair weight) has no correlation: NaN,
+  // also where its grid partner's rounding left a nonzero sum
+  const double xpg = a.wsum[f] > 0.0 ? a.S[i] / (a.nb[b] * a.wsum[f] * wg) : __builtin_nan("");
   const double x = 2.0 * a.wsum[f] * a.L * a.L * a.L / (wg * wg * a.vol[f]) - 1.0;
   const double bb = xpg / xgg;
   const double xw = a.qmode == 2 ? a.xi_w_const : xgg;

@@ -66,6 +66,7 @@ def xi_err_ok(got, exp, rel=1e-5, floor=1e-2):
     got = np.asarray(got); exp = np.asarray(exp)
     fin = np.isfinite(exp)
     assert np.array_equal(fin, np.isfinite(got)), "NaN pattern differs"
+    assert np.array_equal(np.isnan(exp), np.isnan(got)), "empty fields must give NaN"
     d = np.abs(got[fin] - exp[fin])
     bound = rel * np.maximum(np.abs(exp[fin]), floor)
     worst = float(np.max(d / bound)) if d.size else 0.0
