@@ -24,12 +24,15 @@
  *     FP64; the top |mu| edge is closed.  Field index f = b1 * n_p2 + b2,
  *     output bin index b = o1 * n_o2 + o2 (n_o2 = 1 for shells).
  *   - Arrays marked "device" are HIP device memory owned by the caller; the
- *     library never frees them.  The plan owns its own device work memory
- *     (grown on demand, released by pgx_plan_destroy).
+ *     library never frees them.  Work memory: by default the plan allocates
+ *     its own (grown on demand, released by pgx_plan_destroy); with a
+ *     workspace attached (pgx_set_workspace) every device buffer of the plan
+ *     is placed in that caller-owned region instead and the plan calls
+ *     neither hipMalloc nor hipFree.
  *   - `stream` is a hipStream_t (NULL = the null stream).  Calls enqueue work
  *     on it; calls that return host values synchronise it (stated below).
  *   - Every call returns a pgx_status; no exception or abort crosses the ABI.
- *     On a non-OK status pgx_last_error() describes the failure (per thread).
+ *     On a non-OK status pgx_last_error(plan) describes the failure.
  *   - A plan is not thread-safe: use one plan per host thread and stream.
  */
 #ifndef PGX_H
@@ -152,16 +155,25 @@ pgx_status pgx_field_volumes(const pgx_plan* plan, double* vol);
 
 /*
  * Pair catalogue (steps: validate, cell list, close-pair search with integer
- * keys, bucketing by field and grid line) and the galaxy point set.
+ * keys, bucketing by field and grid line) and the galaxy point set.  Every
+ * unordered pair closer than the largest pair separation is kept (a close
+ * triplet gives three pairs) and sits at its midpoint (Implementation
+ * section, pair catalogue; Methodology, equation delta_pi_x).
  *   x, y, z: device FP64 [n_gal] positions in [0, L).
+ *   w:       device FP32 [n_gal] galaxy weights (>= 0, finite) or NULL (unit
+ *            weights); read only for validation and wsum.
  *   n_pairs: HOST out, total number of pairs (this call synchronises stream).
  *   counts:  device int64 [F] out (nullable), pairs per field.
- * Positions are not referenced after the call returns.  Errors: EINVAL for
- * non-finite or out-of-box positions, n_gal < 0 or >= 2^31; ENOTSUP when the
- * pair count reaches 2^31.
+ *   wsum:    device FP64 [F] out (nullable), sum of pair weights w_i w_j per
+ *            field (the weighted pair count of xi(d_p), 2PCF section).
+ * Inputs are not referenced after the call returns.  Errors: EINVAL for
+ * non-finite or out-of-box positions, invalid weights, n_gal < 0 or >= 2^31;
+ * ENOTSUP when the pair count reaches 2^31; ENOSPACE when the workspace (if
+ * attached) is too small.
  */
 pgx_status pgx_pairs_build(pgx_plan* plan, const double* x, const double* y, const double* z,
-                           int64_t n_gal, void* stream, int64_t* n_pairs, int64_t* counts);
+                           const float* w, int64_t n_gal, void* stream, int64_t* n_pairs,
+                           int64_t* counts, double* wsum);
 
 /* Copy the bucketed pair list to device arrays [n_pairs]: field index, and the
  * catalogue indices i < j.  Order: by field, then by grid line of the
@@ -342,8 +354,37 @@ pgx_status pgx_profile(pgx_plan* plan, int32_t enable);
 pgx_status pgx_profile_read(pgx_plan* plan, int32_t k, const char** name, int64_t* launches,
                             double* ms, double* bytes);
 
-/* Message for the last non-OK status returned on this thread. */
-const char* pgx_last_error(void);
+/* Message for the last non-OK status returned by a call on `plan`; with
+ * plan = NULL, the last one on this thread (e.g. of pgx_plan_create).  The
+ * string is owned by the plan (or the thread) and valid until its next
+ * failing call. */
+const char* pgx_last_error(const pgx_plan* plan);
+
+/*
+ * Caller-owned workspace.
+ * pgx_workspace_bytes: an upper bound of the device memory the plan's buffers
+ * reach for a catalogue of n_gal galaxies and n_pairs pairs (n_pairs from a
+ * pgx_pairs_build or an estimate): the pair build, pgx_forward, pgx_backward
+ * and pgx_autotune with their batch slots (up to twice the default batch),
+ * the galaxy spectrum, the dual form's gathered values and kernel stores,
+ * and the kept spectra when pgx_keep_spectra is on; 10 % and 64 MiB are
+ * added for small tables and first-fit fragmentation.  pgx_multipoles needs
+ * n_pairs x (h + n_out h) x 4 bytes more (h harmonics: 1, 6, 15 for lmax 0,
+ * 2, 4).  No device work.
+ * pgx_set_workspace: from now on every device buffer of the plan is carved
+ * from [ws, ws + bytes) (first fit, 256-byte aligned), a region of device
+ * memory the caller allocated on the plan's device and keeps alive until the
+ * plan is destroyed or another workspace is set; the plan then calls neither
+ * hipMalloc nor hipFree.  Optional stores (kernel stores of the dual form,
+ * kept spectra) are made only when they fit in the free part of it.  Setting
+ * (or clearing, ws = NULL) a workspace discards the plan's device state: the
+ * next call must be pgx_pairs_build.  A call that needs more than the free
+ * part returns ENOSPACE.  Errors: EINVAL when ws is not 256-byte aligned.
+ * pgx_workspace_used: bytes of the workspace in use now and at most so far.
+ */
+pgx_status pgx_workspace_bytes(const pgx_plan* plan, int64_t n_gal, int64_t n_pairs, size_t* bytes);
+pgx_status pgx_set_workspace(pgx_plan* plan, void* ws, size_t bytes);
+pgx_status pgx_workspace_used(const pgx_plan* plan, size_t* in_use, size_t* peak);
 
 #ifdef __cplusplus
 }

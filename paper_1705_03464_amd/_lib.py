@@ -57,8 +57,9 @@ _SIGS = {
     "pgx_out_counts": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     "pgx_out_norms": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "pgx_field_volumes": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
-    "pgx_pairs_build": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
-                                  C.c_void_p, C.POINTER(C.c_int64), C.c_void_p]),
+    "pgx_pairs_build": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_int64, C.c_void_p, C.POINTER(C.c_int64), C.c_void_p,
+                                  C.c_void_p]),
     "pgx_pairs_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pgx_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -77,7 +78,10 @@ _SIGS = {
     "pgx_profile_read": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_char_p),
                                    C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                    C.POINTER(C.c_double)]),
-    "pgx_last_error": (C.c_char_p, []),
+    "pgx_last_error": (C.c_char_p, [C.c_void_p]),
+    "pgx_workspace_bytes": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
+    "pgx_set_workspace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "pgx_workspace_used": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
 }
 
 
@@ -99,9 +103,11 @@ def load_library(path: Optional[str] = None):
     return lib
 
 
-def _check(code: int):
+def _check(code: int, plan=None):
+    """Raise PgxError for a non-OK status, with the plan's (or, without a
+    plan, the thread's) last error message."""
     if code != 0:
-        msg = load_library().pgx_last_error()
+        msg = load_library().pgx_last_error(plan)
         raise PgxError(code, msg.decode() if msg else "")
 
 
@@ -183,34 +189,74 @@ class Plan:
     # host-side queries
     def out_counts(self) -> np.ndarray:
         a = np.zeros(self.n_out, np.int64)
-        _check(load_library().pgx_out_counts(self._h, a.ctypes.data_as(C.POINTER(C.c_int64))))
+        _check(load_library().pgx_out_counts(self._h, a.ctypes.data_as(C.POINTER(C.c_int64))), self._h)
         return a
 
     def out_norms(self) -> np.ndarray:
         """Denominator of xi per output bin: n_b, or sum of W for "gsw"."""
         a = np.zeros(self.n_out, np.float64)
-        _check(load_library().pgx_out_norms(self._h, a.ctypes.data_as(C.POINTER(C.c_double))))
+        _check(load_library().pgx_out_norms(self._h, a.ctypes.data_as(C.POINTER(C.c_double))), self._h)
         return a
 
     def field_volumes(self) -> np.ndarray:
         a = np.zeros(self.n_fields, np.float64)
-        _check(load_library().pgx_field_volumes(self._h, a.ctypes.data_as(C.POINTER(C.c_double))))
+        _check(load_library().pgx_field_volumes(self._h, a.ctypes.data_as(C.POINTER(C.c_double))), self._h)
         return a
 
     # device calls
-    def pairs_build(self, x, y, z, stream=None):
+    def pairs_build(self, x, y, z, stream=None, w=None, with_wsum: bool = False):
+        """Pair catalogue of the galaxies at (x, y, z) (float64 device
+        tensors); returns (n_pairs, counts[F]), and the per-field pair-weight
+        sums for the weights w (float32, None = unit) when with_wsum."""
         import torch
         n = int(x.shape[0])
         for t in (x, y, z):
             if t.dtype != torch.float64 or t.shape[0] != n:
                 raise ValueError("positions must be float64 tensors of equal length")
+        if w is not None and (w.dtype != torch.float32 or w.shape[0] != n):
+            raise ValueError("weights must be a float32 tensor of length n_gal")
         counts = torch.zeros(self.n_fields, dtype=torch.int64, device=x.device)
+        wsum = torch.empty(self.n_fields, dtype=torch.float64, device=x.device) if with_wsum else None
         np_ = C.c_int64()
-        _check(load_library().pgx_pairs_build(self._h, _ptr(x), _ptr(y), _ptr(z), n, _stream(stream),
-                                              C.byref(np_), _ptr(counts)))
+        _check(load_library().pgx_pairs_build(self._h, _ptr(x), _ptr(y), _ptr(z), _ptr(w), n,
+                                              _stream(stream), C.byref(np_), _ptr(counts),
+                                              _ptr(wsum)), self._h)
         self.n_gal = n
         self.n_pairs = np_.value
+        if with_wsum:
+            return np_.value, counts, wsum
         return np_.value, counts
+
+    # caller-owned workspace (device memory allocated with torch)
+    def workspace_bytes(self, n_gal: int, n_pairs: int) -> int:
+        """Upper bound of the plan's device memory for such a catalogue
+        (pgx_workspace_bytes)."""
+        b = C.c_size_t()
+        _check(load_library().pgx_workspace_bytes(self._h, int(n_gal), int(n_pairs), C.byref(b)),
+               self._h)
+        return b.value
+
+    def set_workspace(self, nbytes: Optional[int], device=None):
+        """Place every device buffer of the plan in a torch-allocated region
+        of `nbytes` bytes (None: back to the plan's own allocations).  This
+        discards the plan's device state; call pairs_build next."""
+        import torch
+        lib = load_library()
+        if nbytes is None:
+            _check(lib.pgx_set_workspace(self._h, None, 0), self._h)
+            self._ws = None
+            return None
+        dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        ws = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
+        _check(lib.pgx_set_workspace(self._h, ws.data_ptr(), ws.numel()), self._h)
+        self._ws = ws  # kept alive as long as the plan uses it
+        return ws
+
+    def workspace_used(self) -> tuple:
+        """(bytes in use, peak bytes) of the attached workspace."""
+        a, b = C.c_size_t(), C.c_size_t()
+        _check(load_library().pgx_workspace_used(self._h, C.byref(a), C.byref(b)), self._h)
+        return a.value, b.value
 
     def pairs_export(self, stream=None):
         import torch
@@ -218,10 +264,10 @@ class Plan:
         f = torch.empty(self.n_pairs, dtype=torch.int32, device=dev)
         i = torch.empty_like(f)
         j = torch.empty_like(f)
-        _check(load_library().pgx_pairs_export(self._h, _ptr(f), _ptr(i), _ptr(j), _stream(stream)))
+        _check(load_library().pgx_pairs_export(self._h, _ptr(f), _ptr(i), _ptr(j), _stream(stream)), self._h)
         return f, i, j
 
-    def forward(self, w=None, stream=None) -> dict:
+    def _outputs(self, w):
         import torch
         dev = torch.device("cuda", torch.cuda.current_device())
         if w is not None:
@@ -229,12 +275,15 @@ class Plan:
                 raise ValueError("weights must be a float32 tensor of length n_gal")
         F, R = self.n_fields, self.n_out
         kw = dict(dtype=torch.float64, device=dev)
-        out = dict(wsum=torch.empty(F, **kw), xi_gg=torch.empty(R, **kw),
-                   xi_pg=torch.empty(F, R, **kw), xi_dp=torch.empty(F, **kw),
-                   b_pg=torch.empty(F, R, **kw), q_eff=torch.empty(F, R, **kw))
+        return dict(wsum=torch.empty(F, **kw), xi_gg=torch.empty(R, **kw),
+                    xi_pg=torch.empty(F, R, **kw), xi_dp=torch.empty(F, **kw),
+                    b_pg=torch.empty(F, R, **kw), q_eff=torch.empty(F, R, **kw))
+
+    def forward(self, w=None, stream=None) -> dict:
+        out = self._outputs(w)
         _check(load_library().pgx_forward(self._h, _ptr(w), _stream(stream), _ptr(out["wsum"]),
                                           _ptr(out["xi_gg"]), _ptr(out["xi_pg"]), _ptr(out["xi_dp"]),
-                                          _ptr(out["b_pg"]), _ptr(out["q_eff"])))
+                                          _ptr(out["b_pg"]), _ptr(out["q_eff"])), self._h)
         self.forward_count = getattr(self, "forward_count", 0) + 1
         return out
 
@@ -256,7 +305,7 @@ class Plan:
               prep(g_xi_gg, (R,)), prep(g_xi_dp, (F,))]
         grad = torch.empty(self.n_gal, dtype=torch.float32, device=dev)
         _check(load_library().pgx_backward(self._h, _stream(stream), *[_ptr(g) for g in gs],
-                                           _ptr(grad)))
+                                           _ptr(grad)), self._h)
         return grad
 
     def multipoles(self, lmax: int = 2, stream=None):
@@ -267,7 +316,7 @@ class Plan:
         import torch
         dev = torch.device("cuda", torch.cuda.current_device())
         out = torch.empty(self.n_fields, self.n_out, lmax // 2 + 1, dtype=torch.float64, device=dev)
-        _check(load_library().pgx_multipoles(self._h, _stream(stream), int(lmax), _ptr(out)))
+        _check(load_library().pgx_multipoles(self._h, _stream(stream), int(lmax), _ptr(out)), self._h)
         return out
 
     def multipoles_backward(self, g_xi_l, stream=None):
@@ -276,25 +325,25 @@ class Plan:
         dev = torch.device("cuda", torch.cuda.current_device())
         g = g_xi_l.to(device=dev, dtype=torch.float64).contiguous()
         grad = torch.empty(self.n_gal, dtype=torch.float32, device=dev)
-        _check(load_library().pgx_multipoles_backward(self._h, _stream(stream), _ptr(g), _ptr(grad)))
+        _check(load_library().pgx_multipoles_backward(self._h, _stream(stream), _ptr(g), _ptr(grad)), self._h)
         return grad
 
     def keep_spectra(self, enable: bool = True):
         """Keep the pair-field spectra of each forward for the adjoint (memory
         permitting); see pgx_keep_spectra."""
-        _check(load_library().pgx_keep_spectra(self._h, 1 if enable else 0))
+        _check(load_library().pgx_keep_spectra(self._h, 1 if enable else 0), self._h)
 
     def autotune(self, stream=None) -> dict:
         """Time candidate batch sizes and kernel variants on the current pair
         catalogue and keep the fastest; returns the schedule (pgx_autotune)."""
         out = (C.c_int32 * 5)()
-        _check(load_library().pgx_autotune(self._h, _stream(stream), out))
+        _check(load_library().pgx_autotune(self._h, _stream(stream), out), self._h)
         return self._sched(out)
 
     def schedule(self) -> dict:
         """The batch size and kernel variants in use."""
         out = (C.c_int32 * 5)()
-        _check(load_library().pgx_schedule(self._h, out))
+        _check(load_library().pgx_schedule(self._h, out), self._h)
         return self._sched(out)
 
     def dual_check(self) -> float:
@@ -302,14 +351,14 @@ class Plan:
         the last autotune, in units of 1e-5 max(|xi|, 1e-2); -1 if not
         measured (pgx_dual_check)."""
         d = C.c_double()
-        _check(load_library().pgx_dual_check(self._h, C.byref(d)))
+        _check(load_library().pgx_dual_check(self._h, C.byref(d)), self._h)
         return d.value
 
     def set_schedule(self, batch: int, ypass_variant: int = 0, yinv_variant: int = 0,
                      zpass_variant: int = 0, algorithm: int = 0, stream=None):
         """Apply a schedule (pgx_set_schedule); algorithm 1 = dual form."""
         arr = (C.c_int32 * 5)(batch, ypass_variant, yinv_variant, zpass_variant, algorithm)
-        _check(load_library().pgx_set_schedule(self._h, _stream(stream), arr))
+        _check(load_library().pgx_set_schedule(self._h, _stream(stream), arr), self._h)
 
     @staticmethod
     def _sched(out) -> dict:
@@ -319,17 +368,17 @@ class Plan:
     def use_graphs(self, enable: bool = True):
         """Record the forward / adjoint launch sequences into HIP graphs and
         replay them (default on); see pgx_use_graphs."""
-        _check(load_library().pgx_use_graphs(self._h, 1 if enable else 0))
+        _check(load_library().pgx_use_graphs(self._h, 1 if enable else 0), self._h)
 
     def graph_replays(self) -> tuple:
         """(forward, backward) graph replay counts."""
         f, b = C.c_int64(0), C.c_int64(0)
-        _check(load_library().pgx_graph_replays(self._h, C.byref(f), C.byref(b)))
+        _check(load_library().pgx_graph_replays(self._h, C.byref(f), C.byref(b)), self._h)
         return f.value, b.value
 
     def profile(self, enable: bool = True):
         """Start (clearing counters) or stop per-kernel event timing."""
-        _check(load_library().pgx_profile(self._h, 1 if enable else 0))
+        _check(load_library().pgx_profile(self._h, 1 if enable else 0), self._h)
 
     def profile_read(self) -> list:
         """[(name, launches, ms, algorithmic bytes)] for every timed kernel kind."""
@@ -341,7 +390,7 @@ class Plan:
             code = lib.pgx_profile_read(self._h, k, C.byref(nm), C.byref(n), C.byref(ms), C.byref(by))
             if code == 1:
                 break
-            _check(code)
+            _check(code, self._h)
             res.append((nm.value.decode(), n.value, ms.value, by.value))
             k += 1
         return res

@@ -1,19 +1,29 @@
 // C-ABI of the pair-galaxy correlation library: plan creation and validation,
 // output-bin tables, pair-bin volumes, and dispatch to the engines.
+#include <atomic>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <utility>
 
 #include "pgx_engine.hpp"
 
 namespace pgx {
 EngineBase* make_engine_f32(const PlanCfg& c);
 EngineBase* make_engine_f64(const PlanCfg& c);
+size_t memory_bound_f32(const PlanCfg& c, int64_t n, int64_t P, bool spectra);
+size_t memory_bound_f64(const PlanCfg& c, int64_t n, int64_t P, bool spectra);
 }  // namespace pgx
 
 struct pgx_plan {
   pgx::PlanCfg cfg;
   bool keep_spectra = false;
   bool use_graphs = true;
+  // caller-owned workspace (null base: the plan allocates its own memory);
+  // declared before the engine, whose buffers it may hold, so that it
+  // outlives them
+  pgx::Heap ws;
+  mutable std::string last_error;  // message of the last failed call on this plan
   std::unique_ptr<pgx::EngineBase> eng;  // created on first device use
   pgx::EngineBase& engine() {
     if (!eng) {
@@ -30,24 +40,39 @@ namespace {
 
 thread_local std::string g_last_error;
 
-pgx_status fail(pgx_status code, const std::string& msg) {
+pgx_status fail(const pgx_plan* plan, pgx_status code, const std::string& msg) {
   g_last_error = msg;
+  if (plan) plan->last_error = msg;
   return code;
 }
+pgx_status fail(pgx_status code, const std::string& msg) { return fail(nullptr, code, msg); }
 
-template <typename F> pgx_status guarded(F&& f) {
+// The plan's workspace is the current Heap for the duration of a call.
+struct HeapScope {
+  pgx::Heap* prev;
+  explicit HeapScope(const pgx_plan* plan) : prev(pgx::t_heap) {
+    pgx::t_heap = (plan && plan->ws.base) ? const_cast<pgx::Heap*>(&plan->ws) : nullptr;
+  }
+  ~HeapScope() { pgx::t_heap = prev; }
+};
+
+template <typename F> pgx_status guarded(const pgx_plan* plan, F&& f) {
   try {
+    HeapScope hs(plan);
     f();
     return PGX_OK;
   } catch (const pgx::Error& e) {
-    return fail(e.code, e.what());
+    return fail(plan, e.code, e.what());
   } catch (const std::bad_alloc&) {
-    return fail(PGX_ENOSPACE, "host allocation failed");
+    return fail(plan, PGX_ENOSPACE, "host allocation failed");
   } catch (const std::exception& e) {
-    return fail(PGX_EHIP, e.what());
+    return fail(plan, PGX_EHIP, e.what());
   } catch (...) {
-    return fail(PGX_EHIP, "unknown error");
+    return fail(plan, PGX_EHIP, "unknown error");
   }
+}
+template <typename F> pgx_status guarded(F&& f) {
+  return guarded(static_cast<const pgx_plan*>(nullptr), std::forward<F>(f));
 }
 
 std::vector<double> edges(const double* p, int n, const char* name) {
@@ -222,22 +247,23 @@ pgx_status pgx_field_volumes(const pgx_plan* plan, double* vol) {
 }
 
 pgx_status pgx_pairs_build(pgx_plan* plan, const double* x, const double* y, const double* z,
-                           int64_t n_gal, void* stream, int64_t* n_pairs, int64_t* counts) {
+                           const float* w, int64_t n_gal, void* stream, int64_t* n_pairs,
+                           int64_t* counts, double* wsum) {
   if (!plan) return fail(PGX_EINVAL, "plan is NULL");
-  return guarded([&] {
-    plan->engine().pairs_build(x, y, z, n_gal, (hipStream_t)stream, n_pairs, counts);
+  return guarded(plan, [&] {
+    plan->engine().pairs_build(x, y, z, w, n_gal, (hipStream_t)stream, n_pairs, counts, wsum);
   });
 }
 
 pgx_status pgx_pairs_export(pgx_plan* plan, int32_t* field, int32_t* i, int32_t* j, void* stream) {
   if (!plan) return fail(PGX_EINVAL, "plan is NULL");
-  return guarded([&] { plan->engine().pairs_export(field, i, j, (hipStream_t)stream); });
+  return guarded(plan, [&] { plan->engine().pairs_export(field, i, j, (hipStream_t)stream); });
 }
 
 pgx_status pgx_forward(pgx_plan* plan, const float* w, void* stream, double* wsum, double* xi_gg,
                        double* xi_pg, double* xi_dp, double* b_pg, double* q_eff) {
   if (!plan) return fail(PGX_EINVAL, "plan is NULL");
-  return guarded([&] {
+  return guarded(plan, [&] {
     auto& e = plan->engine();
     e.keep_spectra = plan->keep_spectra;
     e.use_graphs = plan->use_graphs;
@@ -249,7 +275,7 @@ pgx_status pgx_backward(pgx_plan* plan, void* stream, const double* g_b_pg, cons
                         const double* g_xi_pg, const double* g_xi_gg, const double* g_xi_dp,
                         float* grad_w) {
   if (!plan) return fail(PGX_EINVAL, "plan is NULL");
-  return guarded([&] {
+  return guarded(plan, [&] {
     auto& e = plan->engine();
     e.use_graphs = plan->use_graphs;
     e.backward((hipStream_t)stream, g_b_pg, g_q_eff, g_xi_pg, g_xi_gg, g_xi_dp, grad_w);
@@ -258,50 +284,50 @@ pgx_status pgx_backward(pgx_plan* plan, void* stream, const double* g_b_pg, cons
 
 pgx_status pgx_multipoles(pgx_plan* plan, void* stream, int32_t lmax, double* xi_l) {
   if (!plan) return fail(PGX_EINVAL, "plan is NULL");
-  return guarded([&] { plan->engine().multipoles((hipStream_t)stream, lmax, xi_l); });
+  return guarded(plan, [&] { plan->engine().multipoles((hipStream_t)stream, lmax, xi_l); });
 }
 
 pgx_status pgx_multipoles_backward(pgx_plan* plan, void* stream, const double* g_xi_l, float* grad_w) {
   if (!plan) return fail(PGX_EINVAL, "plan is NULL");
-  return guarded([&] { plan->engine().multipoles_backward((hipStream_t)stream, g_xi_l, grad_w); });
+  return guarded(plan, [&] { plan->engine().multipoles_backward((hipStream_t)stream, g_xi_l, grad_w); });
 }
 
 pgx_status pgx_keep_spectra(pgx_plan* plan, int32_t enable) {
   if (!plan) return fail(PGX_EINVAL, "plan is NULL");
-  return guarded([&] { plan->keep_spectra = enable != 0; });
+  return guarded(plan, [&] { plan->keep_spectra = enable != 0; });
 }
 
 pgx_status pgx_autotune(pgx_plan* plan, void* stream, int32_t* schedule) {
   if (!plan) return fail(PGX_EINVAL, "plan is NULL");
-  return guarded([&] { plan->engine().autotune((hipStream_t)stream, schedule); });
+  return guarded(plan, [&] { plan->engine().autotune((hipStream_t)stream, schedule); });
 }
 
 pgx_status pgx_schedule(pgx_plan* plan, int32_t* schedule) {
   if (!plan) return fail(PGX_EINVAL, "plan is NULL");
   if (!schedule) return fail(PGX_EINVAL, "schedule is NULL");
-  return guarded([&] { plan->engine().schedule_info(schedule); });
+  return guarded(plan, [&] { plan->engine().schedule_info(schedule); });
 }
 
 pgx_status pgx_dual_check(pgx_plan* plan, double* disagreement) {
   if (!plan) return fail(PGX_EINVAL, "plan is NULL");
   if (!disagreement) return fail(PGX_EINVAL, "disagreement is NULL");
-  return guarded([&] { *disagreement = plan->eng ? plan->eng->dual_disagreement : -1.0; });
+  return guarded(plan, [&] { *disagreement = plan->eng ? plan->eng->dual_disagreement : -1.0; });
 }
 
 pgx_status pgx_set_schedule(pgx_plan* plan, void* stream, const int32_t* schedule) {
   if (!plan) return fail(PGX_EINVAL, "plan is NULL");
   if (!schedule) return fail(PGX_EINVAL, "schedule is NULL");
-  return guarded([&] { plan->engine().set_schedule(schedule, (hipStream_t)stream); });
+  return guarded(plan, [&] { plan->engine().set_schedule(schedule, (hipStream_t)stream); });
 }
 
 pgx_status pgx_use_graphs(pgx_plan* plan, int32_t enable) {
   if (!plan) return fail(PGX_EINVAL, "plan is NULL");
-  return guarded([&] { plan->use_graphs = enable != 0; });
+  return guarded(plan, [&] { plan->use_graphs = enable != 0; });
 }
 
 pgx_status pgx_graph_replays(pgx_plan* plan, int64_t* forward, int64_t* backward) {
   if (!plan) return fail(PGX_EINVAL, "plan is NULL");
-  return guarded([&] {
+  return guarded(plan, [&] {
     const int64_t f = plan->eng ? plan->eng->gf.replays : 0;
     const int64_t b = plan->eng ? plan->eng->gb.replays : 0;
     if (forward) *forward = f;
@@ -311,7 +337,7 @@ pgx_status pgx_graph_replays(pgx_plan* plan, int64_t* forward, int64_t* backward
 
 pgx_status pgx_profile(pgx_plan* plan, int32_t enable) {
   if (!plan) return fail(PGX_EINVAL, "plan is NULL");
-  return guarded([&] {
+  return guarded(plan, [&] {
     auto& pr = plan->engine().prof;
     pr.reset();
     pr.on = enable != 0;
@@ -321,7 +347,7 @@ pgx_status pgx_profile(pgx_plan* plan, int32_t enable) {
 pgx_status pgx_profile_read(pgx_plan* plan, int32_t k, const char** name, int64_t* launches,
                             double* ms, double* bytes) {
   if (!plan) return fail(PGX_EINVAL, "plan is NULL");
-  return guarded([&] {
+  return guarded(plan, [&] {
     auto& pr = plan->engine().prof;
     pr.collect();
     PGX_REQUIRE(k >= 0 && k < (int32_t)pr.cats.size(), PGX_EINVAL, "no such profile entry");
@@ -333,6 +359,40 @@ pgx_status pgx_profile_read(pgx_plan* plan, int32_t k, const char** name, int64_
   });
 }
 
-const char* pgx_last_error(void) { return g_last_error.c_str(); }
+const char* pgx_last_error(const pgx_plan* plan) {
+  return plan ? plan->last_error.c_str() : g_last_error.c_str();
+}
+
+pgx_status pgx_workspace_bytes(const pgx_plan* plan, int64_t n_gal, int64_t n_pairs, size_t* bytes) {
+  if (!plan || !bytes) return fail(plan, PGX_EINVAL, "NULL argument");
+  if (n_gal < 0 || n_pairs < 0) return fail(plan, PGX_EINVAL, "negative size");
+  return guarded(plan, [&] {
+    *bytes = plan->cfg.precision == PGX_FP32_BATCHED
+                 ? pgx::memory_bound_f32(plan->cfg, n_gal, n_pairs, plan->keep_spectra)
+                 : pgx::memory_bound_f64(plan->cfg, n_gal, n_pairs, false);
+  });
+}
+
+pgx_status pgx_set_workspace(pgx_plan* plan, void* ws, size_t bytes) {
+  if (!plan) return fail(PGX_EINVAL, "plan is NULL");
+  if (ws && (reinterpret_cast<uintptr_t>(ws) & (pgx::Heap::kAlign - 1)) != 0)
+    return fail(plan, PGX_EINVAL, "workspace must be 256-byte aligned");
+  if (ws && bytes < pgx::Heap::kAlign) return fail(plan, PGX_EINVAL, "workspace too small");
+  return guarded(plan, [&] {
+    if (plan->eng) PGX_HIP(hipDeviceSynchronize());
+    {
+      HeapScope hs(plan);  // the old buffers go back where they came from
+      plan->eng.reset();
+    }
+    plan->ws.reset(ws, ws ? bytes : 0);
+  });
+}
+
+pgx_status pgx_workspace_used(const pgx_plan* plan, size_t* in_use, size_t* peak) {
+  if (!plan) return fail(PGX_EINVAL, "plan is NULL");
+  if (in_use) *in_use = plan->ws.in_use;
+  if (peak) *peak = plan->ws.peak;
+  return PGX_OK;
+}
 
 }  // extern "C"

@@ -12,4 +12,14 @@ EngineBase* make_engine_f64(const PlanCfg& c) {
     default: return nullptr;
   }
 }
+size_t memory_bound_f64(const PlanCfg& c, int64_t n, int64_t P, bool spectra) {
+  switch (c.N) {
+    case 64: return Engine<double, 64>::memory_bound(c, n, P, spectra);
+    case 128: return Engine<double, 128>::memory_bound(c, n, P, spectra);
+    case 256: return Engine<double, 256>::memory_bound(c, n, P, spectra);
+    case 512: return Engine<double, 512>::memory_bound(c, n, P, spectra);
+    case 1024: return Engine<double, 1024>::memory_bound(c, n, P, spectra);
+    default: return 0;
+  }
+}
 }  // namespace pgx

@@ -172,8 +172,9 @@ struct EngineBase {
     ++g.replays;
   }
 
-  virtual void pairs_build(const double* x, const double* y, const double* z, int64_t n,
-                           hipStream_t s, int64_t* n_pairs, int64_t* counts) = 0;
+  virtual void pairs_build(const double* x, const double* y, const double* z, const float* w,
+                           int64_t n, hipStream_t s, int64_t* n_pairs, int64_t* counts,
+                           double* wsum) = 0;
   virtual void pairs_export(int32_t* f, int32_t* i, int32_t* j, hipStream_t s) = 0;
   virtual void forward(const float* w, hipStream_t s, double* wsum, double* xi_gg, double* xi_pg,
                        double* xi_dp, double* b_pg, double* q_eff) = 0;
@@ -184,6 +185,8 @@ struct EngineBase {
   virtual void set_schedule(const int32_t* in, hipStream_t s) = 0;
   virtual void multipoles(hipStream_t s, int lmax, double* xi) = 0;
   virtual void multipoles_backward(hipStream_t s, const double* g, float* grad_w) = 0;
+  virtual int64_t gal_count() const = 0;
+  virtual int64_t pair_count() const = 0;
   bool built = false;
   bool forward_done = false;
   // keep each pair-field spectrum from the forward for the adjoint (when the
@@ -228,6 +231,8 @@ template <typename T, int N> struct Engine : EngineBase {
   int B = 1;          // field pairs per batch
   int n_batches = 0;
   int64_t n_gal = 0, n_pairs = 0;
+  int64_t gal_count() const override { return n_gal; }
+  int64_t pair_count() const override { return n_pairs; }
   std::vector<int64_t> batch_task_off;  // host, n_batches + 1
   std::vector<int64_t> field_counts_h;  // host, pairs per field
   std::vector<int64_t> build_print;     // schedule and buffers of the last pair build
@@ -296,19 +301,58 @@ template <typename T, int N> struct Engine : EngineBase {
   C<T>* spectra_store() {
     const size_t need = (size_t)cfg.n_fp * (size_t)NC * sizeof(C<T>);
     if (need == 0) return nullptr;
-    if (SPEC.bytes < need) {
-      size_t fr = 0, tot = 0;
-      PGX_HIP(hipMemGetInfo(&fr, &tot));
-      if (fr + SPEC.bytes < need + ((size_t)4 << 30)) return nullptr;
-      SPEC.release();
-      if (hipMalloc(&SPEC.p, need) != hipSuccess) {
-        (void)hipGetLastError();
-        SPEC.p = nullptr;
-        return nullptr;
-      }
-      SPEC.bytes = need;
-    }
+    if (!SPEC.try_ensure(need)) return nullptr;
     return SPEC.as<C<T>>();
+  }
+
+  // Upper bound of the device memory the plan's buffers reach for a catalogue
+  // of n galaxies and P pairs, summed over everything the pair build, the
+  // forward, the adjoint and the autotuner hold at once: point and pair
+  // records with their build scratch, per-(field, line) tables, batch slots
+  // of up to twice the default batch, the galaxy spectrum and accumulator,
+  // the dual form's gathered values and kernel stores, the kept spectra when
+  // asked for; plus 10 % and 64 MiB for tables and first-fit fragmentation.
+  // The multipoles' harmonic buffers are not included.
+  static size_t memory_bound(const PlanCfg& c, int64_t n, int64_t P, bool spectra) {
+    const double cb = (double)sizeof(C<T>), tb = (double)sizeof(T);
+    const double F = c.F, R = c.R, Q = (c.R + 1) / 2, nfp = c.n_fp;
+    const double nz = win_len(c.pw[2]), ny = win_len(c.pw[1]), nx = win_len(c.pw[0]);
+    const double nd = (double)std::max<int64_t>(n, 1), pd = (double)std::max<int64_t>(P, 1);
+    int nc = (int)std::floor(c.L / (c.smax * (1.0 + 1e-12)));
+    const double ncell = std::max(27.0, (double)nc * nc * nc);
+    double b = 0.0;
+    // galaxies: positions kept for the multipoles, cell-list scratch, point
+    // records, weights and gradients
+    b += nd * (24.0 + 24.0 + 16.0 + 16.0 + 12.0 + 4.0 * tb + 4.0 + 3.0 * tb + 4.0 + 4.0 + 8.0 + 4.0);
+    // pairs: build scratch (six int32 arrays over max(n, P)), radix-sort
+    // temporaries, field-major records, FP64 weights, line-major copy, gradient
+    b += std::max(nd, pd) * 24.0 + (std::max(nd, pd) * 8.0 + (32 << 20));
+    b += pd * (16.0 + 4.0 * tb + 8.0 + 12.0 + 4.0 * tb + 4.0);
+    // per-(field, line) starts, counting table, line flags, task positions
+    const double fl = F * NN + 1.0, pl = nfp * NN + 1.0;
+    b += fl * 4.0 + (std::max({ncell, fl, (double)NN}) + 1.0) * 8.0 + pl * (1.0 + 4.0 + 4.0) + nfp * N +
+         2.0 * (NN + 1.0) * 4.0;
+    const double tiny = 16.0 * F * R * 8.0 + 4.0 * (F + R) * 8.0 + ((size_t)8 << 20);
+    if (c.precision == PGX_FP64_PLAIN) {
+      const double nblk = std::ceil(nx * ny * nz / 256.0);
+      b += 2.0 * NC * cb + nblk * 2.0 * R * 8.0 + tiny;
+    } else {
+      const int b0 = std::max(1, std::min({c.batch > 0 ? c.batch : (N >= 512 ? 8 : (N >= 256 ? 16 : 32)),
+                                           c.n_fp, kMaxSlots}));
+      const double Bm = std::min<double>(kMaxSlots, 2.0 * b0);
+      const double nblkE = std::ceil(ny * nz / (double)WX);
+      // batch slots: transformed fields, pruned inverse z and y outputs, the
+      // adjoint's kernel fields
+      b += Bm * (NC + nz * NN + nz * ny * N + nz * ny * N + nz * NN) * cb;
+      b += Bm * nblkE * 2.0 * R * 8.0;
+      // galaxy spectrum, adjoint accumulator; dual form: gathered values,
+      // kernel-field and kernel-spectrum stores
+      b += 2.0 * NC * cb + R * pd * 4.0;
+      b += Q * nz * NN * cb + Q * (N / 2 + 1.0) * (N / 2 + 1.0) * N * cb;
+      if (spectra) b += nfp * NC * cb;
+      b += 3.0 * F * R * reduce_chunks((int64_t)F * R) * 8.0 + tiny;
+    }
+    return (size_t)(1.1 * b) + ((size_t)64 << 20);
   }
 
   explicit Engine(const PlanCfg& c) : cfg(c) {
@@ -407,8 +451,8 @@ template <typename T, int N> struct Engine : EngineBase {
   // ------------------------------------------------------------------------
   // pair catalogue
   // ------------------------------------------------------------------------
-  void pairs_build(const double* x, const double* y, const double* z, int64_t n, hipStream_t s,
-                   int64_t* n_pairs_out, int64_t* counts) override {
+  void pairs_build(const double* x, const double* y, const double* z, const float* w, int64_t n,
+                   hipStream_t s, int64_t* n_pairs_out, int64_t* counts, double* wsum) override {
     PGX_REQUIRE(n >= 0 && n < INT32_MAX, PGX_EINVAL, "n_gal must be in [0, 2^31)");
     PGX_REQUIRE(n == 0 || (x && y && z), PGX_EINVAL, "positions must not be NULL");
     built = false;
@@ -420,7 +464,7 @@ template <typename T, int N> struct Engine : EngineBase {
     int* err = s_err.get<int>(1);
     k_fill_i32(err, 1, s);
     if (n > 0) {
-      k_validate<<<grid_for(n), 256, 0, s>>>(x, y, z, nullptr, n, cfg.L, err);
+      k_validate<<<grid_for(n), 256, 0, s>>>(x, y, z, w, n, cfg.L, err);
       launch_check("validate");
     }
     int herr = 0;
@@ -428,6 +472,7 @@ template <typename T, int N> struct Engine : EngineBase {
     PGX_HIP(hipStreamSynchronize(s));
     PGX_REQUIRE(!(herr & 1), PGX_EINVAL, "non-finite galaxy position");
     PGX_REQUIRE(!(herr & 2), PGX_EINVAL, "galaxy position outside [0, L)");
+    PGX_REQUIRE(!(herr & 4), PGX_EINVAL, "weights must be finite and >= 0");
     if (n > 0) {
       // kept for the pair axes of the multipoles
       PGX_HIP(hipMemcpyAsync(pos_x.get<double>(n), x, n * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -564,6 +609,20 @@ template <typename T, int N> struct Engine : EngineBase {
     tasks_ready = false;
     if constexpr (std::is_same<T, float>::value)
       if (algo == 0) schedule(B, s);
+    if (wsum) {
+      // weighted pair sum of every field, the numerator of xi(d_p) (the same
+      // kernels and order as the forward's)
+      double* wp = p_wd.get<double>(std::max<int64_t>(P, 1));
+      if (P > 0) {
+        k_pair_wprod<<<grid_for(P), 256, 0, s>>>(p_i.as<int32_t>(), p_j.as<int32_t>(), w, P, wp);
+        launch_check("pair_wprod");
+      }
+      const int K = reduce_chunks(F);
+      double* part = ws_part.get<double>((int64_t)F * K);
+      k_field_wsum<<<dim3(F, K), 256, 0, s>>>(p_fs.as<int32_t>(), 1, wp, part);
+      k_sum_chunks<<<grid_for(F), 256, 0, s>>>(part, F, K, wsum);
+      launch_check("field_wsum");
+    }
     PGX_HIP(hipStreamSynchronize(s));
     if (n_pairs_out) *n_pairs_out = P;
     built = true;
@@ -681,9 +740,8 @@ template <typename T, int N> struct Engine : EngineBase {
       const int64_t slot_bytes =
           (NC + (int64_t)win_len(pwz()) * NN + (int64_t)win_len(pwz()) * win_len(pwy()) * N) *
           (int64_t)sizeof(C<T>);
-      size_t fr = 0, tot = 0;
-      PGX_HIP(hipMemGetInfo(&fr, &tot));
-      const double room = (double)fr + (double)(X.bytes + P1.bytes + P2.bytes) - (double)((size_t)4 << 30);
+      const double room = (double)free_device_bytes() + (double)(X.bytes + P1.bytes + P2.bytes) -
+                          (double)spare_device_bytes();
       std::vector<int> cands;
       for (int b : {b0 / 2, b0, 2 * b0}) {
         const int bb = std::max(1, std::min({b, nfp, kMaxSlots}));
@@ -1328,9 +1386,11 @@ template <typename T, int N> struct Engine : EngineBase {
   // whether the dual form fits: its per-pair, per-bin gathered values must
   // fit in half the free device memory
   bool dual_fits() const {
-    size_t fr = 0, tot = 0;
-    if (hipMemGetInfo(&fr, &tot) != hipSuccess) return false;
-    return (double)cfg.R * (double)std::max<int64_t>(n_pairs, 1) * 4.0 + (double)GV.bytes < 0.5 * (double)fr;
+    const double fr = (double)free_device_bytes();
+    const double need = (double)cfg.R * (double)std::max<int64_t>(n_pairs, 1) * 4.0;
+    // from the HIP allocator: at most half the free memory; in a workspace:
+    // whatever is free
+    return need < (t_heap ? fr + (double)GV.bytes : 0.5 * (fr + (double)GV.bytes));
   }
 
   // Dual form of the pair-field part (see pgx_dual.hpp): for each batch of B
@@ -1348,16 +1408,7 @@ template <typename T, int N> struct Engine : EngineBase {
       kc_tried = true;
       const int Q = (cfg.R + 1) / 2;
       const size_t need = (size_t)Q * (size_t)win_len(pwz()) * (size_t)NN * sizeof(C<T>);
-      size_t fr = 0, tot = 0;
-      PGX_HIP(hipMemGetInfo(&fr, &tot));
-      if (fr >= need + ((size_t)4 << 30)) {
-        if (hipMalloc(&KC.p, need) == hipSuccess) {
-          KC.bytes = need;
-        } else {
-          (void)hipGetLastError();
-          KC.p = nullptr;
-        }
-      }
+      (void)KC.try_ensure(need);
     }
     return KC.as<C<T>>();
   }
@@ -1579,16 +1630,7 @@ template <typename T, int N> struct Engine : EngineBase {
     if (!ks_tried) {
       ks_tried = true;
       const size_t need = (size_t)Q * (size_t)ks_slot() * sizeof(C<T>);
-      size_t fr = 0, tot = 0;
-      PGX_HIP(hipMemGetInfo(&fr, &tot));
-      if (fr >= need + ((size_t)4 << 30)) {
-        if (hipMalloc(&KS.p, need) == hipSuccess) {
-          KS.bytes = need;
-        } else {
-          (void)hipGetLastError();
-          KS.p = nullptr;
-        }
-      }
+      (void)KS.try_ensure(need);
     }
     if (!KS.p) return false;
     C<T>* kc = kernel_store();

@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <iterator>
+#include <map>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -39,31 +41,191 @@ inline void launch_check(const char* what) {
   if (e != hipSuccess) throw Error(PGX_EHIP, std::string("launch ") + what + ": " + hipGetErrorString(e));
 }
 
-// Owned device allocation that only grows.
+// ----------------------------------------------------------------------------
+// Device memory placement.  A plan's buffers are hipMalloc allocations it owns,
+// unless a Heap is current on the calling thread: then they are carved from
+// the Heap's region of device memory (a workspace the caller owns, or the
+// library's fixed scratch array), first fit, 256-byte aligned, and the plan
+// calls neither hipMalloc nor hipFree.
+// ----------------------------------------------------------------------------
+struct Heap {
+  static constexpr size_t kAlign = 256;
+  char* base = nullptr;
+  size_t size = 0;
+  std::map<size_t, size_t> free_;  // offset -> length of each free run (coalesced)
+  size_t in_use = 0, peak = 0;
+  void reset(void* b, size_t n) {
+    base = static_cast<char*>(b);
+    size = n & ~(kAlign - 1);
+    free_.clear();
+    if (size) free_[0] = size;
+    in_use = peak = 0;
+  }
+  static size_t round(size_t n) { return (n + kAlign - 1) & ~(kAlign - 1); }
+  size_t largest_free() const {
+    size_t m = 0;
+    for (const auto& f : free_) m = std::max(m, f.second);
+    return m;
+  }
+  void* try_alloc(size_t n) {
+    n = round(n == 0 ? 1 : n);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < n) continue;
+      const size_t off = it->first, len = it->second;
+      free_.erase(it);
+      if (len > n) free_[off + n] = len - n;
+      in_use += n;
+      peak = std::max(peak, in_use);
+      return base + off;
+    }
+    return nullptr;
+  }
+  void* alloc(size_t n, const char* what) {
+    void* q = try_alloc(n);
+    if (!q)
+      throw Error(PGX_ENOSPACE, std::string(what) + ": " + std::to_string(round(n)) +
+                                    " bytes do not fit (largest free run " +
+                                    std::to_string(largest_free()) + " of " + std::to_string(size) + ")");
+    return q;
+  }
+  void release(void* q, size_t n) {
+    if (!q) return;
+    n = round(n == 0 ? 1 : n);
+    size_t off = (size_t)(static_cast<char*>(q) - base);
+    in_use -= n;
+    auto nx = free_.lower_bound(off);
+    if (nx != free_.end() && off + n == nx->first) {  // merge with the run after
+      n += nx->second;
+      nx = free_.erase(nx);
+    }
+    if (nx != free_.begin()) {  // merge with the run before
+      auto pv = std::prev(nx);
+      if (pv->first + pv->second == off) {
+        pv->second += n;
+        return;
+      }
+    }
+    free_[off] = n;
+  }
+};
+
+// A fixed-scratch session: every buffer a call touches is carved afresh from
+// the session's Heap (whatever the buffer held before is set aside, not
+// freed) and put back as it was when the session ends, so that the call
+// allocates nothing and leaves the plan's own buffers unchanged.
+struct DBuf;
+struct Session {
+  Heap heap;
+  uint64_t id = 0;
+  struct Saved {
+    DBuf* d;
+    void* p;
+    size_t bytes;
+    Heap* owner;
+  };
+  std::vector<Saved> saved;
+  inline void restore();
+};
+
+inline thread_local Heap* t_heap = nullptr;        // workspace of the plan being called
+inline thread_local Session* t_session = nullptr;  // fixed-scratch session of the call
+
+// Free device memory available to the plan's buffers: the largest free run of
+// the current Heap, or the device's free memory.
+inline size_t free_device_bytes() {
+  if (t_session) return t_session->heap.largest_free();
+  if (t_heap) return t_heap->largest_free();
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return fr;
+}
+// Memory left to other users of the device when an optional store is
+// allocated: 4 GiB from the HIP allocator, none inside a caller's workspace.
+inline size_t spare_device_bytes() { return (t_heap || t_session) ? 0 : ((size_t)4 << 30); }
+
+// Device allocation that only grows (see Heap for where it lives).
 struct DBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  Heap* owner = nullptr;  // the Heap the memory came from; null: hipMalloc
+  uint64_t session = 0;   // id of the fixed-scratch session that carved it
   DBuf() = default;
   DBuf(const DBuf&) = delete;
   DBuf& operator=(const DBuf&) = delete;
   ~DBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (owner) owner->release(p, bytes);
+      else (void)hipFree(p);
+    }
     p = nullptr;
     bytes = 0;
+    owner = nullptr;
+    session = 0;
   }
   void* ensure(size_t n) {
     if (n == 0) n = 1;
+    if (t_session) {
+      if (session == t_session->id && n <= bytes) return p;
+      if (session != t_session->id) {
+        t_session->saved.push_back(Session::Saved{this, p, bytes, owner});
+      } else {
+        t_session->heap.release(p, bytes);
+      }
+      p = t_session->heap.alloc(n, "fixed scratch");
+      bytes = n;
+      owner = &t_session->heap;
+      session = t_session->id;
+      return p;
+    }
     if (n > bytes) {
       release();
-      PGX_HIP(hipMalloc(&p, n));
+      if (t_heap) {
+        p = t_heap->alloc(n, "workspace");
+        owner = t_heap;
+      } else {
+        PGX_HIP(hipMalloc(&p, n));
+      }
       bytes = n;
     }
     return p;
   }
+  // Optional store: allocate n bytes only when they fit with the spare
+  // memory left over (spare_device_bytes); false, with nothing allocated,
+  // otherwise.
+  bool try_ensure(size_t n) {
+    if (n <= bytes && p) return true;
+    if (t_session) return false;
+    if (free_device_bytes() + bytes < n + spare_device_bytes()) return false;
+    release();
+    if (t_heap) {
+      p = t_heap->try_alloc(n);
+      if (!p) return false;
+      owner = t_heap;
+    } else if (hipMalloc(&p, n) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      return false;
+    }
+    bytes = n;
+    return true;
+  }
   template <typename V> V* as() const { return static_cast<V*>(p); }
   template <typename V> V* get(size_t count) { return static_cast<V*>(ensure(count * sizeof(V))); }
 };
+
+inline void Session::restore() {
+  for (auto it = saved.rbegin(); it != saved.rend(); ++it) {
+    it->d->p = it->p;
+    it->d->bytes = it->bytes;
+    it->d->owner = it->owner;
+    it->d->session = 0;
+  }
+  saved.clear();
+}
 
 inline int grid_for(int64_t n, int threads = 256) {
   int64_t g = (n + threads - 1) / threads;

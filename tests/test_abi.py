@@ -113,3 +113,37 @@ def test_valid_plans_touch_no_device():
     for wl in CONFIGS.values():
         p = Plan.from_workload(wl)
         p.close()
+
+
+def test_workspace_bound_needs_no_device():
+    """pgx_workspace_bytes is host arithmetic: it grows with the catalogue,
+    covers at least the batch slots and galaxy spectrum of the FP32 path and
+    the two grids of the FP64 path, and rejects negative sizes (the message
+    is kept on the plan)."""
+    wl = CONFIGS["cfg1"]
+    p32 = Plan.from_workload(wl)
+    a = p32.workspace_bytes(10 ** 6, 3 * 10 ** 6)
+    b = p32.workspace_bytes(2 * 10 ** 6, 3 * 10 ** 8)
+    assert b > a > (8 + 2) * 512 ** 3 * 8
+    p32.keep_spectra(True)
+    assert p32.workspace_bytes(10 ** 6, 3 * 10 ** 6) > a + 100 * 512 ** 3 * 8
+    p64 = Plan.from_workload(wl, precision="fp64")
+    assert p64.workspace_bytes(10 ** 6, 3 * 10 ** 6) > 2 * 512 ** 3 * 16
+    with pytest.raises(PgxError) as e:
+        p32.workspace_bytes(-1, 0)
+    assert e.value.code == 1
+    assert "negative" in load_library().pgx_last_error(p32._h).decode()
+    p32.close(); p64.close()
+
+
+def test_workspace_argument_errors_need_no_device():
+    import ctypes as C
+    lib = load_library()
+    p32 = Plan.from_workload(CONFIGS["cfg4tiny"])
+    # a workspace must be 256-byte aligned
+    assert lib.pgx_set_workspace(p32._h, C.c_void_p(0x1001), 1 << 20) == 1
+    assert "aligned" in lib.pgx_last_error(p32._h).decode()
+    # per-plan messages: a failure on one plan leaves another plan's message alone
+    p2 = Plan.from_workload(CONFIGS["cfg4tiny"])
+    assert lib.pgx_last_error(p2._h).decode() == ""
+    p32.close(); p2.close()
