@@ -386,6 +386,26 @@ pgx_status pgx_workspace_bytes(const pgx_plan* plan, int64_t n_gal, int64_t n_pa
 pgx_status pgx_set_workspace(pgx_plan* plan, void* ws, size_t bytes);
 pgx_status pgx_workspace_used(const pgx_plan* plan, size_t* in_use, size_t* peak);
 
+/*
+ * Allocation-free forward, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * it): pgx_forward of a PGX_FP64_PLAIN plan, the same arguments and results
+ * (to the rounding of the scatter's atomic additions), with all its work
+ * memory (two complex FP64 N^3 grids, bin partials, pair weights, sums) in a
+ * fixed array of 96 MiB that the library holds on each device it runs on
+ * until the process ends; the call makes no hipMalloc or hipFree and leaves
+ * the plan's own buffers as they were.  The array keeps the last call's
+ * contents and every call on one device shares it: calls that overlap on one
+ * device race.  Runs eagerly (no launch graph).  It needs a preceding
+ * pgx_pairs_build (whose pair catalogue it reads).  Errors: ENOTSUP for other
+ * precisions; ENOSPACE when the work exceeds the array (N = 128 needs 64 MiB
+ * for the grids, leaving room for about 3.5e6 pairs; N >= 256 never fits);
+ * ESTATE before pgx_pairs_build.
+ */
+pgx_status pgx_forward_fixed(pgx_plan* plan, const float* w, void* stream, double* wsum,
+                             double* xi_gg, double* xi_pg, double* xi_dp, double* b_pg,
+                             double* q_eff);
+
 #ifdef __cplusplus
 }
 #endif

@@ -82,6 +82,8 @@ _SIGS = {
     "pgx_workspace_bytes": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
     "pgx_set_workspace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "pgx_workspace_used": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+    "pgx_forward_fixed": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
 }
 
 
@@ -285,6 +287,17 @@ class Plan:
                                           _ptr(out["xi_gg"]), _ptr(out["xi_pg"]), _ptr(out["xi_dp"]),
                                           _ptr(out["b_pg"]), _ptr(out["q_eff"])), self._h)
         self.forward_count = getattr(self, "forward_count", 0) + 1
+        return out
+
+    def forward_fixed(self, w=None, stream=None) -> dict:
+        """The allocation-free forward of an FP64 plain plan (pgx_forward_fixed):
+        the same outputs as forward(), its work memory in the library's fixed
+        per-device scratch array."""
+        out = self._outputs(w)
+        _check(load_library().pgx_forward_fixed(self._h, _ptr(w), _stream(stream), _ptr(out["wsum"]),
+                                                _ptr(out["xi_gg"]), _ptr(out["xi_pg"]),
+                                                _ptr(out["xi_dp"]), _ptr(out["b_pg"]),
+                                                _ptr(out["q_eff"])), self._h)
         return out
 
     def backward(self, g_b_pg=None, g_q_eff=None, g_xi_pg=None, g_xi_gg=None, g_xi_dp=None,

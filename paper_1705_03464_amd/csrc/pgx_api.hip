@@ -75,6 +75,65 @@ template <typename F> pgx_status guarded(F&& f) {
   return guarded(static_cast<const pgx_plan*>(nullptr), std::forward<F>(f));
 }
 
+// ----------------------------------------------------------------------------
+// Fixed scratch of the allocation-free forward: one array per device, its
+// address looked up once per device (the array's host-side name is not a
+// device address).
+// ----------------------------------------------------------------------------
+constexpr size_t kFixedScratchBytes = (size_t)96 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kFixedScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+std::atomic<uint64_t> g_session_id{0};
+
+void* fixed_scratch() {
+  int dev = 0;
+  PGX_HIP(hipGetDevice(&dev));
+  PGX_REQUIRE(dev >= 0 && dev < kMaxDevices, PGX_ENOTSUP, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    PGX_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    PGX_REQUIRE(ptr != nullptr, PGX_EHIP, "no device address for the fixed scratch");
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
+// Bytes the FP64 plain forward takes from the fixed scratch: the galaxy
+// spectrum and the field grid (complex FP64, N^3 each), bin partials, pair
+// weights, per-field sums, the finalisation's spare outputs, each carved on a
+// 256-byte boundary.
+size_t fixed_forward_bytes(const pgx::PlanCfg& c, int64_t n_gal, int64_t n_pairs) {
+  auto r = [](double b) { return (size_t)(std::ceil(std::max(b, 1.0) / 256.0) * 256.0); };
+  const double N = c.N, F = c.F, R = c.R;
+  const double cube = (2.0 * c.pw[0] + 1) * (2.0 * c.pw[1] + 1) * (2.0 * c.pw[2] + 1);
+  const double nblk = std::ceil(cube / 256.0);
+  const double K = pgx::reduce_chunks(c.F);
+  size_t b = 2 * r(N * N * N * 16.0);  // galaxy spectrum, field grid
+  b += r(nblk * 2 * R * 8) + r(F * R * 8) + r(R * 8);
+  b += r(std::max<double>((double)n_pairs, 1.0) * 8) + r(F * K * 8) + r(F * 8) + r(F * 4);
+  b += r(pgx::kWtBlocks * 8.0) + r(8) + r((3 * F * R + F + R + 8) * 8) + r(4);
+  b += r(std::max<double>((double)n_gal, 1.0) * 4);  // copy of the weights
+  return b;
+}
+
+// A fixed-scratch session for the duration of one call (restores the plan's
+// buffers on exit, also after an error).
+struct SessionScope {
+  pgx::Session sess;
+  SessionScope(void* base, size_t bytes) {
+    sess.heap.reset(base, bytes);
+    sess.id = ++g_session_id;
+    pgx::t_session = &sess;
+  }
+  ~SessionScope() {
+    sess.restore();
+    pgx::t_session = nullptr;
+  }
+};
+
 std::vector<double> edges(const double* p, int n, const char* name) {
   PGX_REQUIRE(n >= 1 && p != nullptr, PGX_EINVAL, std::string(name) + ": need n >= 1 and edges");
   std::vector<double> v(p, p + n + 1);
@@ -393,6 +452,36 @@ pgx_status pgx_workspace_used(const pgx_plan* plan, size_t* in_use, size_t* peak
   if (in_use) *in_use = plan->ws.in_use;
   if (peak) *peak = plan->ws.peak;
   return PGX_OK;
+}
+
+pgx_status pgx_forward_fixed(pgx_plan* plan, const float* w, void* stream, double* wsum,
+                             double* xi_gg, double* xi_pg, double* xi_dp, double* b_pg,
+                             double* q_eff) {
+  if (!plan) return fail(PGX_EINVAL, "plan is NULL");
+  return guarded(plan, [&] {
+    PGX_REQUIRE(plan->cfg.precision == PGX_FP64_PLAIN, PGX_ENOTSUP,
+                "pgx_forward_fixed serves PGX_FP64_PLAIN plans");
+    auto& e = plan->engine();
+    PGX_REQUIRE(e.built, PGX_ESTATE, "pgx_pairs_build has not been called");
+    const size_t need = fixed_forward_bytes(plan->cfg, e.gal_count(), e.pair_count());
+    PGX_REQUIRE(need <= kFixedScratchBytes, PGX_ENOSPACE,
+                "pgx_forward_fixed: the forward needs " + std::to_string(need) +
+                    " bytes of work memory, the fixed scratch holds " +
+                    std::to_string(kFixedScratchBytes));
+    void* base = fixed_scratch();
+    const bool ug = e.use_graphs;
+    e.use_graphs = false;  // eager: nothing recorded points into the scratch
+    try {
+      SessionScope ss(base, kFixedScratchBytes);
+      e.forward(w, (hipStream_t)stream, wsum, xi_gg, xi_pg, xi_dp, b_pg, q_eff);
+    } catch (...) {
+      e.use_graphs = ug;
+      e.forward_done = false;
+      throw;
+    }
+    e.use_graphs = ug;
+    e.forward_done = false;  // its state lived in the scratch
+  });
 }
 
 }  // extern "C"

@@ -136,13 +136,16 @@ def test_workspace_bound_needs_no_device():
     p32.close(); p64.close()
 
 
-def test_workspace_argument_errors_need_no_device():
+def test_workspace_and_fixed_forward_argument_errors_need_no_device():
     import ctypes as C
     lib = load_library()
     p32 = Plan.from_workload(CONFIGS["cfg4tiny"])
     # a workspace must be 256-byte aligned
     assert lib.pgx_set_workspace(p32._h, C.c_void_p(0x1001), 1 << 20) == 1
     assert "aligned" in lib.pgx_last_error(p32._h).decode()
+    # the allocation-free forward serves FP64 plain plans only
+    code = lib.pgx_forward_fixed(p32._h, None, None, None, None, None, None, None, None)
+    assert code == 4 and "FP64_PLAIN" in lib.pgx_last_error(p32._h).decode()
     # per-plan messages: a failure on one plan leaves another plan's message alone
     p2 = Plan.from_workload(CONFIGS["cfg4tiny"])
     assert lib.pgx_last_error(p2._h).decode() == ""
