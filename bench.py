@@ -19,13 +19,14 @@ Prints ONE JSON line.  `value` = pair fields per second over the timed steps
 (forward + adjoint by default; `forward_only` gives the forward rate).
 `step_hbm_frac` = algorithmic bytes of every instrumented pass kernel of a
 step (the schedule in use: per-field transforms or the dual form) / step
-time / 8 TB/s.  `hbm_floor_frac` = the least bytes per field of the
-per-field pass structure (one transform chain per field pair, pruned and
-fused) x fields/s / 8 TB/s: above 1 when the dual form, which transforms one
-kernel per pair of output bins instead, beats that floor.  `roofline` is for
-the kernel with the largest share of the profiled pass: algorithmic bytes per
-launch / mean launch time, both measured in this run with HIP events on the
-launch stream.
+time / 8 TB/s.  `roofline` is for the kernel with the largest share of the
+profiled pass: algorithmic bytes per launch / mean launch time, both
+measured in this run with HIP events on the launch stream.
+Every device buffer of the plan lives in a workspace allocated with torch
+(pgx_workspace_bytes, pgx_set_workspace), sized from a first pair build.
+`hod` repeats the forward + adjoint measurement on the HOD workload (512^3,
+2e6 weighted candidates, 20 x 20 bins, the loss carried on to the HOD
+parameters), with fewer steps and no CPU baseline.
 `multipoles` times pgx_multipoles (l = 0, 2 of every field in the angle
 between the pair axis and the pair-to-galaxy direction) after a forward;
 `fp64_plain` times the one-field-at-a-time FP64 GPU path's forward;
@@ -86,19 +87,6 @@ def cpu_baseline(wl, cat, n_fields_sample=2):
     }
 
 
-def sources_digest():
-    """SHA-256 over the kernel sources (file names and contents)."""
-    import glob
-    import hashlib
-    h = hashlib.sha256()
-    d = os.path.join(ROOT, "paper_1705_03464_amd", "csrc")
-    for p in sorted(glob.glob(os.path.join(d, "*.hpp")) + glob.glob(os.path.join(d, "*.hip"))):
-        h.update(os.path.basename(p).encode())
-        with open(p, "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()
-
-
 def measured_traffic(kernel, batch):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE, WRITE_SIZE scaled by a plain copy), or None when the
@@ -109,19 +97,10 @@ def measured_traffic(kernel, batch):
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("sources_sha256") != sources_digest() or d.get("batch") != batch:
+    from paper_1705_03464_amd import build_digest
+    if d.get("sources_sha256") != build_digest() or d.get("batch") != batch:
         return None
     return d.get("bytes_per_launch", {}).get(kernel)
-
-
-def floor_bytes_per_field(N, fields_per_batch, mode):
-    """Required HBM bytes per pair field of the pruned, fused pass structure:
-    one sweep S = half spectrum (complex64, N^2 (N/2+1) entries); forward
-    4.37 S + S/B, forward + adjoint 10.8 S + 4 S/B (B fields per batch)."""
-    S = N * N * (N // 2 + 1) * 8.0
-    if mode == "fwd":
-        return (4.37 + 1.0 / fields_per_batch) * S
-    return (10.8 + 4.0 / fields_per_batch) * S
 
 
 def main(argv=None):
@@ -139,6 +118,9 @@ def main(argv=None):
                     help="skip timing the one-field-at-a-time FP64 GPU path")
     ap.add_argument("--kernels", action="store_true", help="print the per-kernel table to stderr")
     ap.add_argument("--no-multipoles", action="store_true", help="skip timing pgx_multipoles")
+    ap.add_argument("--no-hod", action="store_true", help="skip the HOD workload's record")
+    ap.add_argument("--no-workspace", action="store_true",
+                    help="let the plan allocate its own device memory")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (torch) three times; used to "
                          "scale the FETCH_SIZE / WRITE_SIZE counters of a profiler run")
@@ -165,19 +147,65 @@ def main(argv=None):
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         return 1
+    from paper_1705_03464_amd import build_digest
+    from paper_1705_03464_amd.build import sources_digest
+    digest = build_digest()
     wl = get_config(a.config)
+    res = measure(wl, a, a.steps, a.warmup, with_extras=True)
+    rec = {
+        "metric": "pair-field xi_pg cross-correlations/s at 512^3 (fwd, fwd+bwd), % HBM peak",
+        "value": res["value"],
+        "unit": "pair fields/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": res["config"],
+        "step_hbm_frac": res["step_hbm_frac"],
+        "step_gb": res["step_gb"],
+        "ms_per_step_eager_profiled": res["ms_per_step_eager_profiled"],
+        "roofline": res["roofline"],
+        "library": {"sources_sha256": digest, "matches_tree": digest == sources_digest()},
+    }
+    for k in ("forward_only", "multipoles", "fp64_plain", "workspace"):
+        if res.get(k) is not None:
+            rec[k] = res[k]
+    if not a.no_hod and a.config != "cfg4" and a.mode == "fwdbwd":
+        # the HOD workload: forward + adjoint on to the HOD parameters
+        hs = max(2, min(a.steps, 5))
+        h = measure(get_config("cfg4"), a, hs, 1, with_extras=False)
+        rec["hod"] = {k: h[k] for k in ("value", "unit", "ms_per_step", "step_hbm_frac", "step_gb",
+                                         "ms_per_step_eager_profiled", "roofline", "config",
+                                         "forward_only", "workspace") if h.get(k) is not None}
+        rec["hod"]["steps"] = hs
+    if not a.no_cpu_baseline:
+        _log("[bench] timing the CPU oracle on a bounded sample ...")
+        rec["cpu_baseline"] = cpu_baseline(wl, wl.catalog())
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+def measure(wl, a, steps, warmup, with_extras):
+    """Forward + adjoint (or forward) steps of one workload: autotuned
+    schedule, timed graph replays, an eager profiled pass with HIP events per
+    kernel, the forward-only rate; with_extras adds the multipoles and the
+    FP64 plain path's forward."""
+    import numpy as np
+    import torch
+    from paper_1705_03464_amd import Plan, hod_weights, pair_galaxy_xi
     cat = wl.catalog()
     _log(f"[bench] {wl.name}: n_gal={cat.n} N={wl.N} fields={wl.n_fields} bins={wl.n_out}")
     dev = torch.device("cuda", 0)
     x = torch.as_tensor(cat.x, dtype=torch.float64, device=dev)
     y = torch.as_tensor(cat.y, dtype=torch.float64, device=dev)
     z = torch.as_tensor(cat.z, dtype=torch.float64, device=dev)
-    w = None
-    if cat.w is not None:
-        w = torch.as_tensor(cat.w, dtype=torch.float32, device=dev)
     plan = Plan.from_workload(wl, precision="fp32", batch=a.batch)
     plan.use_graphs(not a.no_graphs)
-    from paper_1705_03464_amd import hod_weights, pair_galaxy_xi
     hod = wl.weighted
     if hod:
         from synth.configs import HOD_FIDUCIAL
@@ -186,19 +214,22 @@ def main(argv=None):
         kind = torch.as_tensor(cat.kind.astype(np.int64), device=dev)
     ones = torch.ones(cat.n, dtype=torch.float32, device=dev)
 
+    def weights(grad):
+        if hod:
+            theta = torch.tensor(th0, dtype=torch.float64, device=dev, requires_grad=grad)
+            return hod_weights(theta, hm, kind)
+        return ones.clone().requires_grad_(grad)
+
+    w_step = weights(False).detach()
+
     def step_fwd():
         plan.keep_spectra(False)  # no adjoint follows
         plan.pairs_build(x, y, z)
-        return plan.forward(w)
+        return plan.forward(w_step)
 
     def step_fwdbwd():
         plan.pairs_build(x, y, z)
-        if hod:
-            theta = torch.tensor(th0, dtype=torch.float64, device=dev, requires_grad=True)
-            wt = hod_weights(theta, hm, kind)
-        else:
-            wt = ones.clone().requires_grad_(True)
-        out = pair_galaxy_xi(plan, wt)
+        out = pair_galaxy_xi(plan, weights(True))
         b = out["b_pg"]
         # sum over the finite entries, without a data-dependent shape (no
         # host synchronisation inside the step)
@@ -207,12 +238,12 @@ def main(argv=None):
         loss.backward()
         return out
 
-    def timed(fn, steps, profile=False):
+    def timed(fn, n, profile=False):
         if profile:
             plan.profile(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for i in range(steps):
+        for _ in range(n):
             out = fn()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -220,41 +251,52 @@ def main(argv=None):
         if profile:
             prof = plan.profile_read()
             plan.profile(False)
-        return out, (t1 - t0) * 1e3 / steps, prof
+        return out, (t1 - t0) * 1e3 / n, prof
 
+    # every device buffer of the plan in a torch-allocated workspace, sized
+    # for this catalogue from a first pair build
+    workspace = None
+    if not a.no_workspace:
+        P0, _ = plan.pairs_build(x, y, z)
+        plan.keep_spectra(a.mode == "fwdbwd")
+        nb = plan.workspace_bytes(cat.n, P0)
+        plan.set_workspace(nb)
+        workspace = {"bytes": nb}
     schedule = plan.schedule() if a.no_autotune else None
     if not a.no_autotune:
         plan.pairs_build(x, y, z)
+        # the autotuner checks the dual form on the weights of the last forward:
+        # run one with the step's weights first
+        plan.keep_spectra(a.mode == "fwdbwd")
+        plan.forward(w_step)
         t0 = time.perf_counter()
         schedule = plan.autotune()
         _log(f"[bench] autotune {time.perf_counter() - t0:.1f} s: {schedule}")
     step = step_fwdbwd if a.mode == "fwdbwd" else step_fwd
-    for i in range(a.warmup):
+    for i in range(warmup):
         step()
         torch.cuda.synchronize()
-        _log(f"[bench] warmup {i + 1}/{a.warmup} done")
+        _log(f"[bench] warmup {i + 1}/{warmup} done")
     # timed region: the production configuration (launch graphs replayed)
-    out, ms_step, _ = timed(step, a.steps)
+    out, ms_step, _ = timed(step, steps)
     replays = plan.graph_replays()
-    _log(f"[bench] timed {a.steps} steps ({a.mode}): {ms_step:.2f} ms/step, n_pairs={plan.n_pairs}, "
+    _log(f"[bench] timed {steps} steps ({a.mode}): {ms_step:.2f} ms/step, n_pairs={plan.n_pairs}, "
          f"graph replays (fwd, bwd) so far {replays}")
     value = wl.n_fields / (ms_step * 1e-3)
     # the same steps again, eagerly, with HIP events around every pass kernel
-    _, ms_prof, prof = timed(step, a.steps, profile=True)
-    _log(f"[bench] profiled (eager) {a.steps} steps: {ms_prof:.2f} ms/step")
-    fpb = 2 * plan.schedule()["batch"]
+    _, ms_prof, prof = timed(step, steps, profile=True)
+    _log(f"[bench] profiled (eager) {steps} steps: {ms_prof:.2f} ms/step")
     fwd_only = None
     if a.mode == "fwdbwd":
         step_fwd()
         step_fwd()
         torch.cuda.synchronize()
-        _, ms_f, _ = timed(step_fwd, max(2, a.steps))
+        _, ms_f, _ = timed(step_fwd, max(2, steps))
         v_f = wl.n_fields / (ms_f * 1e-3)
-        fwd_only = {"value": round(v_f, 2), "unit": "pair fields/s", "ms_per_step": round(ms_f, 3),
-                    "hbm_floor_frac": round(floor_bytes_per_field(wl.N, fpb, "fwd") * v_f / (HBM_PEAK_GBS * 1e9), 4)}
+        fwd_only = {"value": round(v_f, 2), "unit": "pair fields/s", "ms_per_step": round(ms_f, 3)}
         _log(f"[bench] forward only: {ms_f:.2f} ms/step")
     multipoles = None
-    if not a.no_multipoles and wl.out_mode == "shell" and float(wl.o1_edges[0]) > 0:
+    if with_extras and not a.no_multipoles and wl.out_mode == "shell" and float(wl.o1_edges[0]) > 0:
         step_fwd()  # the forward whose weights and galaxy spectrum it reads
         plan.multipoles(2)
         torch.cuda.synchronize()
@@ -271,8 +313,8 @@ def main(argv=None):
         for name, n, ms, by in prof:
             _log(f"  {name:16s} launches {n:5d}  {ms / max(n, 1):8.3f} ms/launch  "
                  f"{by / max(n, 1) / 1e9:8.3f} GB/launch  {by / (ms * 1e-3) / 1e9 if ms > 0 else 0:8.1f} GB/s"
-                 f"  share {ms / (ms_prof * a.steps):.3f}")
-    step_bytes = sum(p[3] for p in prof) / a.steps
+                 f"  share {ms / (ms_prof * steps):.3f}")
+    step_bytes = sum(p[3] for p in prof) / steps
     step_hbm_frac = step_bytes / (ms_prof * 1e-3) / (HBM_PEAK_GBS * 1e9)
     dom = max(prof, key=lambda p: p[2])
     name, n, ms, by = dom
@@ -282,23 +324,13 @@ def main(argv=None):
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": name,
         "bytes_per_launch": by / n, "ms_per_launch": ms / n,
-        "kernel_share_of_step": round(ms / (ms_prof * a.steps), 3),
+        "kernel_share_of_step": round(ms / (ms_prof * steps), 3),
     }
+    if workspace is not None:
+        workspace["peak"] = plan.workspace_used()[1]
     finite = np.isfinite(out["xi_pg"].detach().cpu().numpy())
-    mode_key = "fwd" if a.mode == "fwd" else "fwdbwd"
-    rec = {
-        "metric": "pair-field xi_pg cross-correlations/s at 512^3 (fwd, fwd+bwd), % HBM peak",
-        "value": round(value, 2),
-        "unit": "pair fields/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": round(ms_step, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
+    res = {
+        "value": round(value, 2), "unit": "pair fields/s", "ms_per_step": round(ms_step, 3),
         "config": {
             "workload": wl.description,
             "name": wl.name, "N": wl.N, "L": wl.L, "n_gal": cat.n, "n_pairs": plan.n_pairs,
@@ -312,36 +344,32 @@ def main(argv=None):
         },
         "step_hbm_frac": round(step_hbm_frac, 4),
         "step_gb": round(step_bytes / 1e9, 2),
-        "hbm_floor_frac": round(floor_bytes_per_field(wl.N, fpb, mode_key) * value / (HBM_PEAK_GBS * 1e9), 4),
-        "hbm_floor_basis": "per-field transforms",
         "ms_per_step_eager_profiled": round(ms_prof, 3),
         "roofline": roofline,
+        "forward_only": fwd_only,
+        "multipoles": multipoles,
+        "workspace": workspace,
     }
-    if fwd_only is not None:
-        rec["forward_only"] = fwd_only
-    if multipoles is not None:
-        rec["multipoles"] = multipoles
-    if not a.no_fp64_plain:
+    plan.close()
+    if with_extras and not a.no_fp64_plain:
         _log("[bench] timing the one-field-at-a-time FP64 GPU path (forward) ...")
         p64 = Plan.from_workload(wl, precision="fp64")
         p64.pairs_build(x, y, z)
-        p64.forward(w)
+        p64.forward(w_step)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        p64.forward(w)
+        p64.forward(w_step)
         torch.cuda.synchronize()
         ms64 = (time.perf_counter() - t0) * 1e3
         p64.close()
         ms_fwd = fwd_only["ms_per_step"] if fwd_only else ms_step
-        rec["fp64_plain"] = {"ms_per_forward": round(ms64, 1),
+        res["fp64_plain"] = {"ms_per_forward": round(ms64, 1),
                              "value": round(wl.n_fields / (ms64 * 1e-3), 2), "unit": "pair fields/s",
                              "speedup_fp32_batched_fwd": round(ms64 / ms_fwd, 2)}
         _log(f"[bench] FP64 plain forward: {ms64:.1f} ms")
-    if not a.no_cpu_baseline:
-        _log("[bench] timing the CPU oracle on a bounded sample ...")
-        rec["cpu_baseline"] = cpu_baseline(wl, cat)
-    print(json.dumps(rec), flush=True)
-    return 0
+    del x, y, z
+    torch.cuda.empty_cache()
+    return res
 
 
 if __name__ == "__main__":

@@ -213,6 +213,26 @@ pgx_status pgx_backward(pgx_plan* plan, void* stream, const double* g_b_pg, cons
                         float* grad_w);
 
 /*
+ * Projected two-point correlation of the pairs (2PCF section, equation
+ * 2PCF_los_integrated_explicit): for a plan with pair_mode RP_PI, the
+ * line-of-sight integral of the pair correlation xi(d_p) inside the pair
+ * sphere, averaged over each r_p annulus,
+ *   w_p[a] = sum_b xi_dp[a n_p2 + b] V[a n_p2 + b] / (pi (rp_{a+1}^2 - rp_a^2)),
+ * V the exact annulus-slab volumes of pgx_field_volumes (pieces of zero volume
+ * contribute nothing).  With one |pi| bin covering the sphere and a thin
+ * annulus this is the paper's 2 d_par,max (xi - like) column with the
+ * annulus volume taken exactly (its printed Delta V_perp misses a factor
+ * d_perp).
+ *   xi_dp: device FP64 [F] (as pgx_forward returns it); w_p: device FP64
+ *   [n_p1] out.
+ * pgx_projected_backward: the adjoint, g_xi_dp[f] = g_w_p[a(f)] V_f / A_a
+ * (device FP64 [n_p1] in, [F] out).  Errors: EINVAL for other pair modes or
+ * NULL arrays.
+ */
+pgx_status pgx_projected(pgx_plan* plan, void* stream, const double* xi_dp, double* w_p);
+pgx_status pgx_projected_backward(pgx_plan* plan, void* stream, const double* g_w_p, double* g_xi_dp);
+
+/*
  * Multipoles of the pair-galaxy cross-correlation in the angle between the
  * pair axis and the pair-to-galaxy direction: the other reading of the
  * pair-orientation cosine, the pair axis against the direction to the
@@ -353,6 +373,11 @@ pgx_status pgx_graph_replays(pgx_plan* plan, int64_t* forward, int64_t* backward
 pgx_status pgx_profile(pgx_plan* plan, int32_t enable);
 pgx_status pgx_profile_read(pgx_plan* plan, int32_t k, const char** name, int64_t* launches,
                             double* ms, double* bytes);
+
+/* SHA-256 (hex) of the sources this library was built from (kernel and host
+ * headers, HIP translation units and this header), for tying a measurement to
+ * the code that produced it. */
+const char* pgx_build_digest(void);
 
 /* Message for the last non-OK status returned by a call on `plan`; with
  * plan = NULL, the last one on this thread (e.g. of pgx_plan_create).  The

@@ -13,6 +13,10 @@
       Q = ((1 + xi_dp) b - 2) / (2 xi_dp)
   b_pg from Q (forward relations, equations bpg_squeezed and
       bpg_notsq_dw) are provided for the round-trip checks.
+Projected 2PCF (2PCF section, equation 2PCF_los_integrated_explicit): the
+  line-of-sight integral of xi(d_p) inside the pair sphere per r_p annulus,
+      w_p[a] = sum_b xi_dp[a, b] V[a, b] / (pi (rp_{a+1}^2 - rp_a^2)),
+  pieces of zero volume (wholly outside the sphere) contributing nothing.
 xi_w is the paper's xi(d_w) (equation xi_dw).  For a thin-shell bin W the
 ratio int W xi^2 / int W xi tends to xi at the shell radius, so the default
 reading takes xi_w = xi_gg[b]; a constant xi_w can be given instead.
@@ -74,6 +78,17 @@ def field_volumes(mode, p1_edges, p2_edges, dmax=None):
 
 def xi_dp(wsum, wg, L, volumes):
     return 2.0 * np.asarray(wsum) * L ** 3 / (wg * wg * np.asarray(volumes)) - 1.0
+
+
+def projected_2pcf(xdp, volumes, rp_edges, n_p2):
+    """w_p per r_p annulus from xi(d_p) of (r_p, |pi|) pair bins (field index
+    a * n_p2 + b)."""
+    e = np.asarray(rp_edges, np.float64)
+    n1 = e.size - 1
+    x = np.asarray(xdp, np.float64).reshape(n1, n_p2)
+    v = np.asarray(volumes, np.float64).reshape(n1, n_p2)
+    col = np.where(v > 0.0, np.nan_to_num(x) * v, 0.0).sum(axis=1)
+    return col / (math.pi * (e[1:] ** 2 - e[:-1] ** 2))
 
 
 def q_eff(b, xdp, xi_w, mode="notsq"):

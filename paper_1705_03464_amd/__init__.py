@@ -5,7 +5,7 @@ The computation lives in the HIP library ``libpgx.so`` behind the C-ABI of
 package does not load the library; the first call that needs it does, and
 raises if it is missing.
 """
-from ._lib import Plan, PgxError, load_library
+from ._lib import Plan, PgxError, build_digest, load_library
 
 
 def __getattr__(name):
@@ -19,5 +19,5 @@ def __getattr__(name):
     raise AttributeError(name)
 
 
-__all__ = ["Plan", "PgxError", "load_library", "PairGalaxyXi", "pair_galaxy_xi", "hod_weights",
+__all__ = ["Plan", "PgxError", "build_digest", "load_library", "PairGalaxyXi", "pair_galaxy_xi", "hod_weights",
            "MultipoleXi", "pair_galaxy_multipoles", "HodFit", "fit_hod", "projected_2pcf"]

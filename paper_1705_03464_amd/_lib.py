@@ -70,6 +70,8 @@ _SIGS = {
     "pgx_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
     "pgx_schedule": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "pgx_dual_check": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    "pgx_projected": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pgx_projected_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pgx_multipoles": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "pgx_multipoles_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pgx_set_schedule": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
@@ -79,6 +81,7 @@ _SIGS = {
                                    C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                    C.POINTER(C.c_double)]),
     "pgx_last_error": (C.c_char_p, [C.c_void_p]),
+    "pgx_build_digest": (C.c_char_p, []),
     "pgx_workspace_bytes": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
     "pgx_set_workspace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "pgx_workspace_used": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
@@ -103,6 +106,11 @@ def load_library(path: Optional[str] = None):
         fn.argtypes = args
     _lib = lib
     return lib
+
+
+def build_digest() -> str:
+    """SHA-256 of the sources the loaded library was built from."""
+    return load_library().pgx_build_digest().decode()
 
 
 def _check(code: int, plan=None):
@@ -181,6 +189,7 @@ class Plan:
         if getattr(self, "_h", None) is not None and self._h.value:
             load_library().pgx_plan_destroy(self._h)
             self._h = None
+        self._ws = None  # the workspace outlives the plan that uses it
 
     def __del__(self):
         try:
@@ -320,6 +329,24 @@ class Plan:
         _check(load_library().pgx_backward(self._h, _stream(stream), *[_ptr(g) for g in gs],
                                            _ptr(grad)), self._h)
         return grad
+
+    def projected(self, xi_dp, stream=None):
+        """Projected 2PCF w_p [n_p1] of an (r_p, |pi|) plan from xi(d_p) [F]
+        (pgx_projected)."""
+        import torch
+        x = xi_dp.to(dtype=torch.float64).contiguous()
+        out = torch.empty(len(self._keep[0]) - 1, dtype=torch.float64, device=x.device)
+        _check(load_library().pgx_projected(self._h, _stream(stream), _ptr(x), _ptr(out)), self._h)
+        return out
+
+    def projected_backward(self, g_w_p, stream=None):
+        """dL/dxi(d_p) [F] from dL/dw_p [n_p1] (pgx_projected_backward)."""
+        import torch
+        g = g_w_p.to(dtype=torch.float64).contiguous()
+        out = torch.empty(self.n_fields, dtype=torch.float64, device=g.device)
+        _check(load_library().pgx_projected_backward(self._h, _stream(stream), _ptr(g), _ptr(out)),
+               self._h)
+        return out
 
     def multipoles(self, lmax: int = 2, stream=None):
         """Legendre multipoles l = 0, 2, .., lmax of xi_pg in the angle between

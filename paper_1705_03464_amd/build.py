@@ -6,6 +6,8 @@ Usage: python -m paper_1705_03464_amd.build [--jobs N]
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import os
 import shutil
 import subprocess
@@ -29,9 +31,24 @@ FLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
+def sources_digest() -> str:
+    """SHA-256 over the library's sources (kernel and host headers, HIP
+    translation units, the C header): file names and contents."""
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(CSRC, "*.hpp")) + glob.glob(os.path.join(CSRC, "*.hip")))
+    files.append(os.path.join(os.path.dirname(HERE), "include", "pgx.h"))
+    for p in files:
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _compile(src: str, digest: str) -> str:
     obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    # the C-ABI unit carries the digest of the sources it was built from
+    extra = [f'-DPGX_SOURCE_SHA256="{digest}"'] if src == "pgx_api.hip" else []
+    cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr[-6000:]}")
@@ -40,8 +57,9 @@ def _compile(src: str) -> str:
 
 def build(jobs: int = 4, verbose: bool = False) -> str:
     os.makedirs(OBJ, exist_ok=True)
+    digest = sources_digest()
     with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(lambda src: _compile(src, digest), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -341,6 +341,16 @@ pgx_status pgx_backward(pgx_plan* plan, void* stream, const double* g_b_pg, cons
   });
 }
 
+pgx_status pgx_projected(pgx_plan* plan, void* stream, const double* xi_dp, double* w_p) {
+  if (!plan) return fail(PGX_EINVAL, "plan is NULL");
+  return guarded(plan, [&] { plan->engine().projected((hipStream_t)stream, xi_dp, w_p, false); });
+}
+
+pgx_status pgx_projected_backward(pgx_plan* plan, void* stream, const double* g_w_p, double* g_xi_dp) {
+  if (!plan) return fail(PGX_EINVAL, "plan is NULL");
+  return guarded(plan, [&] { plan->engine().projected((hipStream_t)stream, g_w_p, g_xi_dp, true); });
+}
+
 pgx_status pgx_multipoles(pgx_plan* plan, void* stream, int32_t lmax, double* xi_l) {
   if (!plan) return fail(PGX_EINVAL, "plan is NULL");
   return guarded(plan, [&] { plan->engine().multipoles((hipStream_t)stream, lmax, xi_l); });
@@ -417,6 +427,11 @@ pgx_status pgx_profile_read(pgx_plan* plan, int32_t k, const char** name, int64_
     if (bytes) *bytes = c.bytes;
   });
 }
+
+#ifndef PGX_SOURCE_SHA256
+#define PGX_SOURCE_SHA256 "unknown"
+#endif
+const char* pgx_build_digest(void) { return PGX_SOURCE_SHA256; }
 
 const char* pgx_last_error(const pgx_plan* plan) {
   return plan ? plan->last_error.c_str() : g_last_error.c_str();

@@ -185,6 +185,7 @@ struct EngineBase {
   virtual void set_schedule(const int32_t* in, hipStream_t s) = 0;
   virtual void multipoles(hipStream_t s, int lmax, double* xi) = 0;
   virtual void multipoles_backward(hipStream_t s, const double* g, float* grad_w) = 0;
+  virtual void projected(hipStream_t s, const double* xi_dp, double* wp, bool adjoint) = 0;
   virtual int64_t gal_count() const = 0;
   virtual int64_t pair_count() const = 0;
   bool built = false;
@@ -1034,6 +1035,21 @@ template <typename T, int N> struct Engine : EngineBase {
     k_finalize<<<grid_for((int64_t)F * R + F + R), 256, 0, s>>>(a);
     launch_check("finalize");
     if (wsum) PGX_HIP(hipMemcpyAsync(wsum, wsum_d.p, F * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+
+  // projected 2PCF of (r_p, |pi|) pair bins from xi(d_p) (adjoint: the
+  // gradient with respect to xi(d_p) from the one with respect to w_p)
+  void projected(hipStream_t s, const double* in, double* out, bool adjoint) override {
+    PGX_REQUIRE(cfg.pair_mode == PGX_PAIR_RP_PI, PGX_EINVAL,
+                "the projected 2PCF needs pair bins in (r_p, |pi|)");
+    PGX_REQUIRE(in != nullptr && out != nullptr, PGX_EINVAL, "NULL argument");
+    const int n1 = (int)cfg.p1.size() - 1, n2 = (int)cfg.p2.size() - 1;
+    if (adjoint)
+      k_projected_adjoint<<<grid_for(n1 * n2), 256, 0, s>>>(in, vold.as<double>(), t1.as<double>(),
+                                                             n1, n2, out);
+    else
+      k_projected<<<grid_for(n1), 256, 0, s>>>(in, vold.as<double>(), t1.as<double>(), n1, n2, out);
+    launch_check("projected");
   }
 
   void forward(const float* w, hipStream_t s, double* wsum, double* xi_gg, double* xi_pg,

@@ -267,6 +267,39 @@ static __global__ void k_finalize(FinalizeArgs a) {
 }
 
 // ----------------------------------------------------------------------------
+// Projected 2PCF (2PCF section, equation 2PCF_los_integrated_explicit): for
+// pairs binned by (r_p, |pi|), the line-of-sight integral of the pair
+// correlation over the pair sphere, averaged over each r_p annulus:
+//   w_p[a] = sum_b xi(d_p)[a, b] V[a, b] / A_a,   A_a = pi (rp_{a+1}^2 - rp_a^2),
+// with V the exact annulus-slab volume cut by the sphere (pieces of zero
+// volume, whose xi(d_p) is 0/0, contribute nothing).  rp2 holds the squared
+// r_p edges.  Its adjoint: g_xi(d_p)[a, b] = g_w[a] V[a, b] / A_a.
+// ----------------------------------------------------------------------------
+static __global__ void k_projected(const double* __restrict__ xi_dp, const double* __restrict__ vol,
+                                   const double* __restrict__ rp2, int n1, int n2,
+                                   double* __restrict__ wp) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n1) return;
+  const double area = 3.14159265358979323846 * (rp2[a + 1] - rp2[a]);
+  double acc = 0.0;
+  for (int b = 0; b < n2; ++b) {
+    const double v = vol[a * n2 + b];
+    if (v > 0.0) acc += xi_dp[a * n2 + b] * v;
+  }
+  wp[a] = acc / area;
+}
+static __global__ void k_projected_adjoint(const double* __restrict__ g_wp, const double* __restrict__ vol,
+                                           const double* __restrict__ rp2, int n1, int n2,
+                                           double* __restrict__ g_xidp) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= n1 * n2) return;
+  const int a = f / n2;
+  const double area = 3.14159265358979323846 * (rp2[a + 1] - rp2[a]);
+  const double v = vol[f];
+  g_xidp[f] = v > 0.0 ? g_wp[a] * v / area : 0.0;
+}
+
+// ----------------------------------------------------------------------------
 // plain path
 // ----------------------------------------------------------------------------
 template <typename T>

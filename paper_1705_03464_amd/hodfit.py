@@ -13,14 +13,14 @@ Loss terms:
     correlation averaged over the annulus of area A_f is
         w_f = xi(d_p)_f V_f / A_f,
     the paper's 2 d_par,max (2 sigma_p / (n_g N_g dV_perp) - 1) with the
-    thin-annulus volume replaced by the exact one.  Its term is
+    thin-annulus volume replaced by the exact one; the library computes it
+    (pgx_projected) and its adjoint.  Its term is
     sum_f ((w_f - target_f) / scale_f)^2.
 Both plans hold the same candidate catalogue; the weights come from
 ``hod_weights`` and the gradients flow through ``pair_galaxy_xi``.
 """
 from __future__ import annotations
 
-import math
 from typing import Optional
 
 import numpy as np
@@ -30,14 +30,21 @@ from ._lib import Plan
 from .autograd import hod_weights, pair_galaxy_xi
 
 
-def annulus_areas(rp_edges) -> np.ndarray:
-    e = np.asarray(rp_edges, np.float64)
-    return math.pi * (e[1:] ** 2 - e[:-1] ** 2)
+class _Projected(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, xi_dp: torch.Tensor, plan: Plan):
+        ctx.plan = plan
+        return plan.projected(xi_dp.detach())
+
+    @staticmethod
+    def backward(ctx, g):
+        return ctx.plan.projected_backward(g.contiguous()), None
 
 
-def projected_2pcf(xi_dp: torch.Tensor, volumes: torch.Tensor, areas: torch.Tensor) -> torch.Tensor:
-    """w_f = xi(d_p)_f V_f / A_f (differentiable in xi_dp)."""
-    return xi_dp * volumes / areas
+def projected_2pcf(plan: Plan, xi_dp: torch.Tensor) -> torch.Tensor:
+    """w_p per r_p annulus of an (r_p, |pi|) plan, computed by the library
+    (pgx_projected), differentiable in xi_dp."""
+    return _Projected.apply(xi_dp, plan)
 
 
 class HodFit:
@@ -47,12 +54,12 @@ class HodFit:
     b_pg [F, R] (NaN entries ignored); mask_b (optional, bool [F, R]): the
     entries the loss uses, e.g. those whose xi_gg is well away from zero (b_pg
     divides by it).  plan_w (optional): plan with pair mode
-    (r_p, |pi|), one |pi| bin, on the same candidates; rp_edges its r_p edges;
+    (r_p, |pi|), one |pi| bin, on the same candidates;
     target_w [F_w] and scale_w [F_w] (1 if None); lam weighs that term.
     """
 
     def __init__(self, plan_b: Plan, halo_mass: torch.Tensor, kind: torch.Tensor,
-                 target_b: torch.Tensor, plan_w: Optional[Plan] = None, rp_edges=None,
+                 target_b: torch.Tensor, plan_w: Optional[Plan] = None,
                  target_w: Optional[torch.Tensor] = None, scale_w: Optional[torch.Tensor] = None,
                  lam: float = 1.0, n_candidates: int = 49,
                  mask_b: Optional[torch.Tensor] = None):
@@ -65,9 +72,6 @@ class HodFit:
         self.lam = float(lam)
         self.n_candidates = n_candidates
         if plan_w is not None:
-            dev = target_b.device
-            self.vol_w = torch.as_tensor(plan_w.field_volumes(), dtype=torch.float64, device=dev)
-            self.area_w = torch.as_tensor(annulus_areas(rp_edges), dtype=torch.float64, device=dev)
             self.target_w = target_w
             self.scale_w = torch.ones_like(target_w) if scale_w is None else scale_w
 
@@ -84,7 +88,7 @@ class HodFit:
         lw = torch.zeros((), dtype=torch.float64, device=lb.device)
         if self.plan_w is not None:
             ow = pair_galaxy_xi(self.plan_w, w)
-            wp = projected_2pcf(ow["xi_dp"], self.vol_w, self.area_w)
+            wp = projected_2pcf(self.plan_w, ow["xi_dp"])
             r = (wp - self.target_w) / self.scale_w
             mw = torch.isfinite(r)
             lw = (r[mw] ** 2).sum()

@@ -9,6 +9,7 @@ import pytest
 
 from oracle import grad as OG
 from oracle.finalize import field_volumes
+from oracle.finalize import projected_2pcf as oracle_projected
 from oracle.pipeline import forward as oracle_forward
 from synth import get_config
 from synth.configs import HOD_FIDUCIAL, HOD_TARGET, linbins, logbins
@@ -46,8 +47,7 @@ def rp_workload(wl):
 
 def oracle_wp(cat, wl_rp, w):
     o = oracle_forward(cat, wl_rp, w=w)
-    V = field_volumes("rp_pi", RP, np.array([0.0, DMAX]), DMAX)
-    return o["xi_dp"] * V / (np.pi * (RP[1:] ** 2 - RP[:-1] ** 2))
+    return oracle_projected(o["xi_dp"], o["volumes"], RP, 1)
 
 
 def setup():
@@ -68,24 +68,22 @@ def setup():
     hm = dev(cat.halo_mass)
     kind = torch.as_tensor(cat.kind.astype(np.int64), device="cuda")
     scale = dev(np.maximum(np.abs(tw), 1.0))
-    hf = HodFit(pb, hm, kind, dev(tb), plan_w=pw, rp_edges=RP, target_w=dev(tw), scale_w=scale,
+    hf = HodFit(pb, hm, kind, dev(tb), plan_w=pw, target_w=dev(tw), scale_w=scale,
                 mask_b=torch.as_tensor(np.ascontiguousarray(mask), device="cuda"))
     return wl, wl_rp, cat, hf
 
 
 def test_projected_2pcf_and_its_gradient_match_the_oracle():
     from paper_1705_03464_amd import hod_weights, pair_galaxy_xi, projected_2pcf
-    from paper_1705_03464_amd.hodfit import annulus_areas
     wl, wl_rp, cat, hf = setup()
     w_np = OG.hod_weights(cat.halo_mass, cat.kind, TH0).astype(np.float32).astype(np.float64)
     theta = torch.tensor(TH0, dtype=torch.float64, device="cuda", requires_grad=True)
     w = hod_weights(theta, hf.hm, hf.kind)
     out = pair_galaxy_xi(hf.plan_w, w)
-    wp = projected_2pcf(out["xi_dp"], hf.vol_w, hf.area_w)
+    wp = projected_2pcf(hf.plan_w, out["xi_dp"])
     ref = oracle_wp(cat, wl_rp, w_np)
     _say(f"  w_p gpu {wp.detach().cpu().numpy()} oracle {ref}")
     assert np.allclose(wp.detach().cpu().numpy(), ref, rtol=1e-9, atol=1e-12)
-    assert np.allclose(annulus_areas(RP), np.pi * (RP[1:] ** 2 - RP[:-1] ** 2))
     g = np.random.default_rng(4).normal(size=ref.size)
     (wp * dev(g)).sum().backward()
     gth = theta.grad.cpu().numpy()

@@ -592,6 +592,27 @@ def test_projected_2pcf_thin_annulus_is_the_paper_column():
         V = FZ.field_volumes("rp_pi", e, np.array([0.0, dmax]), dmax)[0]
         A = math.pi * (e[1] ** 2 - e[0] ** 2)
         assert np.isclose(V / A, 2.0 * math.sqrt(dmax * dmax - r * r), rtol=1e-4)
+        # xi(d_p) = 1 in the annulus: w_p is the column length itself
+        assert np.isclose(FZ.projected_2pcf([1.0], [V], e, 1)[0], V / A, rtol=1e-14)
+
+
+def test_projected_2pcf_over_several_pi_bins_is_that_of_the_merged_bin():
+    """Splitting the |pi| range into slabs does not change w_p: sum_b xi_b V_b
+    = (2 sum_b Wsum_b L^3 / W_g^2) - sum_b V_b, the merged bin's xi V; slabs
+    wholly outside the sphere (zero volume, xi = 0/0) add nothing."""
+    dmax, L, wg = 20.0, 500.0, 1.0e4
+    rp = np.array([0.0, 5.0, 12.0, 19.0])
+    pi_split = np.array([0.0, 4.0, 11.0, 19.5, 25.0])
+    Vs = FZ.field_volumes("rp_pi", rp, pi_split, dmax)
+    Vm = FZ.field_volumes("rp_pi", rp, np.array([0.0, 25.0]), dmax)
+    rng = np.random.default_rng(3)
+    ws = rng.uniform(10.0, 100.0, Vs.size) * (Vs > 0)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        xs = FZ.xi_dp(ws, wg, L, Vs)
+    xm = FZ.xi_dp(ws.reshape(3, 4).sum(axis=1), wg, L, Vm)
+    assert np.any(Vs == 0.0) and np.any(np.isnan(xs))
+    assert np.allclose(FZ.projected_2pcf(xs, Vs, rp, 4), FZ.projected_2pcf(xm, Vm, rp, 1),
+                       rtol=1e-12)
 
 
 def test_projected_2pcf_of_a_poisson_catalogue_is_zero():
@@ -611,7 +632,7 @@ def test_projected_2pcf_of_a_poisson_catalogue_is_zero():
     V = FZ.field_volumes("rp_pi", rp, np.array([0.0, dmax]), dmax)
     xdp = FZ.xi_dp(pr["wsum"], float(n), L, V)
     A = np.pi * (rp[1:] ** 2 - rp[:-1] ** 2)
-    wp = xdp * V / A
+    wp = FZ.projected_2pcf(xdp, V, rp, 1)
     expected = n * n / 2.0 * V / L ** 3
     sd = np.sqrt(expected) / expected * V / A
     assert np.all(np.abs(wp) < 4.0 * sd), (wp, sd)
