@@ -85,6 +85,17 @@ def assert_fp32_parity(out, ref, rel=1e-5):
     m = (np.abs(ref["xi_pg"]) > 1e-2) & (np.abs(ref["xi_gg"])[None, :] > 1e-2)
     if m.any():
         assert np.allclose(out["b_pg"][m], ref["b_pg"][m], rtol=3e-5)
+    # Q_eff (equation Qeff_notsq) there too, where its denominators are not
+    # small: the bound propagates b's 3e-5 through each term's magnitude
+    x = np.broadcast_to(ref["xi_dp"][:, None], ref["b_pg"].shape)
+    xw = np.broadcast_to(ref["xi_gg"][None, :], ref["b_pg"].shape)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        den = 2.0 * x + 1.5 * xw
+        mq = m & np.isfinite(x) & (np.abs(x) > 1e-2) & (np.abs(den) > 1e-2)
+        scale = (np.abs((1.0 + x) * ref["b_pg"]) + 2.0 + np.abs(xw / (2.0 * x))) / np.abs(den)
+    if mq.any():
+        dq = np.abs(out["q_eff"][mq] - ref["q_eff"][mq])
+        assert np.all(dq <= 3e-5 * scale[mq] + 1e-12), float(np.max(dq / (3e-5 * scale[mq])))
 
 
 def assert_fp64_parity(out, ref):
@@ -276,19 +287,17 @@ def test_cfg2_full_size_sampled_fields():
     _, P, counts, out = run(wl, cat, "fp32")
     assert P == pairs["key"].size
     assert np.array_equal(counts, pairs["counts"])
-    sub = dict(ref)
-    sub["xi_pg"] = ref["xi_pg"][fields]
-    o = dict(out)
-    o["xi_pg"] = out["xi_pg"][fields]
-    o["b_pg"] = out["b_pg"][fields]
-    sub["b_pg"] = ref["b_pg"][fields]
+    sub = dict(ref); o = dict(out)
+    for k in ("xi_pg", "b_pg", "q_eff", "xi_dp", "wsum"):
+        sub[k] = ref[k][fields]; o[k] = out[k][fields]
     assert_fp32_parity(o, sub)
 
 
 def test_cfg1_full_size_bench_configuration():
     """The 512^3 production workload in the launch configuration the bench times
-    (the autotuned schedule): all pair counts bit-exact, xi_gg and two sampled
-    pair fields against the FP64 oracle."""
+    (the autotuned schedule): all pair counts bit-exact, xi_gg and the 10 most
+    and 10 least populated pair fields (xi_pg, b_pg, Q_eff) against the FP64
+    oracle."""
     wl = get_config("cfg1")
     cat = wl.catalog()
     _say(f"cfg1 n_gal={cat.n}")
@@ -296,10 +305,12 @@ def test_cfg1_full_size_bench_configuration():
     _, P, counts, out = run(wl, cat, "fp32", autotune=True)
     assert P == pairs["key"].size
     assert np.array_equal(counts, pairs["counts"])
-    fields = [13, 157]
+    # the 10 most and the 10 least populated non-empty fields
+    order = [int(f) for f in np.argsort(pairs["counts"], kind="stable") if pairs["counts"][f] > 0]
+    fields = sorted(set(order[:10] + order[-10:]))
     ref = oracle_forward(cat, wl, pairs=pairs, fields=fields)
     sub = dict(ref); o = dict(out)
-    for k in ("xi_pg", "b_pg"):
+    for k in ("xi_pg", "b_pg", "q_eff", "xi_dp", "wsum"):
         sub[k] = ref[k][fields]; o[k] = out[k][fields]
     assert_fp32_parity(o, sub)
 
@@ -332,7 +343,7 @@ def test_512_crowded_nodes(algo):
     assert P == pairs["key"].size
     assert np.array_equal(counts, pairs["counts"])
     sub = dict(ref); o = dict(out)
-    for k in ("xi_pg", "b_pg"):
+    for k in ("xi_pg", "b_pg", "q_eff", "xi_dp", "wsum"):
         sub[k] = ref[k][fields]; o[k] = out[k][fields]
     assert_fp32_parity(o, sub)
 
@@ -350,7 +361,7 @@ def test_forward_1024_redshift_space_sampled():
     _, P, counts, out = run(wl, cat, "fp32")
     assert np.array_equal(counts, pairs["counts"])
     sub = dict(ref); o = dict(out)
-    for k in ("xi_pg", "b_pg"):
+    for k in ("xi_pg", "b_pg", "q_eff", "xi_dp", "wsum"):
         sub[k] = ref[k][fields]; o[k] = out[k][fields]
     assert_fp32_parity(o, sub)
 
