@@ -1,54 +1,94 @@
-"""How far a single-precision transform chain can get on the most clustered
-workload (CPU, no device).
+"""Where the single-precision error of the transform chain comes from, on the
+most clustered workload (CPU, no device).
 
-The FP32 path runs the forward transforms, the cross-power product and the
-inverse transform in single precision.  On the tiny HOD subset (40 halos of
-49 candidates, 64^3) xi_pg reaches ~4.5, and the rounding of FP32 transforms
-then shows on every bin at about one FP32 unit of that largest value.  This
-test evaluates the same estimator with scipy's single-precision FFT in place
-of the oracle's double-precision one, to show that the 1e-5 relative bar is
-out of reach for any FP32 chain on this catalogue while 2^-23 max|xi_pg| is
-the right order for the bound the device test states.
+The tiny HOD subset (40 halos of 50 candidates, 64^3, no field galaxies)
+reaches xi_pg ~ 4.4 while most bins hold |xi| ~ 1e-3 - 1e-2, so the bar
+1e-5 max(|xi|, 1e-2) asks for an absolute error of 1e-7, about 0.2 of one
+FP32 unit of the largest value.  A model of the device's transform schedule
+(tests/fp32_model.py: the same radix-8 stages, rotations, stage twiddles,
+LDS exchanges and FP32 storage between passes) shows:
+  * in FP32 arithmetic it misses that bar by a factor of 1.5 - 3 on this
+    catalogue, as the device kernels do (by up to 2.6);
+  * with FP64 arithmetic in every pass but the grids still stored in FP32
+    between passes, the rounding of the stored values alone takes 0.3 - 0.9
+    of the bar: no single-precision storage of the spectra holds it with a
+    margin here, whatever the arithmetic;
+  * with the grids stored in FP64 (the plain FP64 path) the error is far
+    below it.
+On the production workloads (512^3, 9e5 - 2e6 galaxies) the FP32 kernels
+stay within 0.03 of the bar (tests/test_gpu_autotune.py).
 """
+import os
+import sys
+
 import numpy as np
-import scipy.fft as sfft
+import pytest
 
-from oracle import bins as B
-from oracle.cic import cic_assign
-from oracle.pipeline import forward
-from synth import get_config
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+
+from fp32_model import Precision, line_transform, per_field_chain  # noqa: E402
+from oracle import bins as B  # noqa: E402
+from oracle.cic import cic_assign  # noqa: E402
+from oracle.pipeline import forward  # noqa: E402
+from synth import get_config  # noqa: E402
+
+F32, F64 = Precision("f32", "f32", "f32"), Precision("f64", "f64", "f64")
 
 
-def test_single_precision_chain_floor_on_tiny_hod_subset():
+@pytest.mark.parametrize("N", [64, 512])
+def test_model_is_a_dft(N):
+    """In FP64 the model's line transform is the DFT (forward and inverse, to
+    rounding); in FP32 its error is that of an FP32 FFT (~1e-7)."""
+    rng = np.random.default_rng(N)
+    a = rng.standard_normal((3, N)) + 1j * rng.standard_normal((3, N))
+    for DIR, ref in ((-1, np.fft.fft(a, axis=-1)), (+1, np.fft.ifft(a, axis=-1) * N)):
+        r, i = line_transform(a.real, a.imag, DIR, F64)
+        assert np.abs(r + 1j * i - ref).max() <= 1e-14 * np.abs(ref).max()
+        r, i = line_transform(a.real, a.imag, DIR, F32)
+        e = np.abs(r + 1j * i - ref).max() / np.abs(ref).max()
+        assert 1e-8 < e < 5e-7
+
+
+def _tiny_case(weights):
     wl = get_config("cfg4tiny")
     cat = wl.catalog()
-    ref = forward(cat, wl)
+    w = None
+    if weights == "random":
+        w = np.random.default_rng(5).uniform(0.5, 1.5, cat.n).astype(np.float32).astype(np.float64)
+    ref = forward(cat, wl, w=w)
     N, L = wl.N, wl.L
     table = B.lattice_table(wl.out_mode, wl.o1_edges, wl.o2_edges, L, N)
     R = B.n_out(wl.out_mode, wl.o1_edges, wl.o2_edges)
     pairs = ref["pairs"]
-    rho_g = cic_assign(cat.positions(), np.ones(cat.n), N, L) / ref["wg"]
-    G = sfft.rfftn(rho_g.astype(np.float32))
-    G[0, 0, 0] = 0
-    xi_ref = ref["xi_pg"]
-    peak = float(np.max(np.abs(xi_ref[np.isfinite(xi_ref)])))
-    worst_rel, worst_abs = 0.0, 0.0
+    rho_g = cic_assign(cat.positions(), np.ones(cat.n) if w is None else w, N, L) / ref["wg"]
+    rho = []
     for f in range(wl.n_fields):
-        if not np.all(np.isfinite(xi_ref[f])):
-            continue
         sel = pairs["key"] == f
-        rho_f = cic_assign(pairs["mid"][sel], pairs["w"][sel], N, L) / pairs["wsum"][f]
-        A = sfft.rfftn(rho_f.astype(np.float32))
-        A[0, 0, 0] = 0
-        assert A.dtype == np.complex64 and G.dtype == np.complex64
-        C = sfft.irfftn(np.conj(A) * G, s=rho_f.shape).astype(np.float64) * rho_f.size
-        xi = B.bin_average(C, table, R)
-        d = np.abs(xi - xi_ref[f])
-        worst_rel = max(worst_rel, float(np.max(d / (1e-5 * np.maximum(np.abs(xi_ref[f]), 1e-2)))))
-        worst_abs = max(worst_abs, float(np.max(d)))
-    # the 1e-5 bar is missed several times over by a plain FP32 chain ...
-    print(f"FP32 chain: worst ratio to the 1e-5 bar {worst_rel:.2f}, max abs {worst_abs:.2e}, "
-          f"2^-23 max|xi| {2.0 ** -23 * peak:.2e}")
-    assert worst_rel > 2.0, worst_rel
-    # ... and the miss is of the order of one FP32 unit of the largest |xi|
-    assert 0.5 * 2.0 ** -23 * peak < worst_abs < 16 * 2.0 ** -23 * peak, (worst_abs, peak)
+        ws = pairs["wsum"][f]
+        rho.append(cic_assign(pairs["mid"][sel], pairs["w"][sel], N, L) / ws if ws > 0
+                   else np.zeros((N, N, N)))
+    return ref, table, R, rho_g, rho
+
+
+def _worst(C, ref, table, R):
+    worst = 0.0
+    for f, c in enumerate(C):
+        e = ref["xi_pg"][f]
+        if not np.all(np.isfinite(e)):
+            continue
+        d = np.abs(B.bin_average(c, table, R) - e)
+        worst = max(worst, float(np.max(d / (1e-5 * np.maximum(np.abs(e), 1e-2)))))
+    return worst
+
+
+@pytest.mark.parametrize("weights", ["unit", "random"])
+def test_single_precision_storage_sets_the_floor(weights):
+    ref, table, R, rho_g, rho = _tiny_case(weights)
+    cur = _worst(per_field_chain(rho_g, rho, F32, F32, F32, F32), ref, table, R)
+    arith64 = _worst(per_field_chain(rho_g, rho, F64, F64, F64, F64), ref, table, R)
+    store64 = _worst(per_field_chain(rho_g, rho, F64, F64, F64, F64, store=np.float64), ref, table, R)
+    print(f"{weights}: FP32 arithmetic {cur:.2f}, FP64 arithmetic with FP32 storage {arith64:.2f}, "
+          f"FP64 storage {store64:.4f} of the 1e-5 bar")
+    assert cur > 1.3
+    assert 0.25 < arith64 < 1.0
+    assert store64 < 1e-3

@@ -112,19 +112,34 @@ def test_autotuned_schedule_meets_oracle(case):
         assert_fp32_parity(out, ref)
 
 
+def _floor_check(out, ref, label):
+    """The FP32 bound on catalogues where single-precision storage cannot hold
+    the 1e-5 bar: 1e-5 relative, or 2^-23 max|xi_pg| absolute where that is
+    larger (one FP32 unit of the largest value).  The strict ratio is printed."""
+    fin = np.isfinite(ref["xi_pg"])
+    floor_abs = 2.0 ** -23 * float(np.max(np.abs(ref["xi_pg"][fin])))
+    for k in ("xi_gg", "xi_pg"):
+        strict = _worst(out[k], ref[k], 1e-5)
+        e = ref[k][np.isfinite(ref[k])]
+        g = out[k][np.isfinite(ref[k])]
+        floor = float(np.max(np.abs(g - e) / np.maximum(1e-5 * np.abs(e), floor_abs)))
+        _say(f"  {label} {k}: 1e-5 max(|xi|,1e-2) ratio {strict:.2f}; "
+             f"max(1e-5 |xi|, {floor_abs:.2e}) ratio {floor:.2f}")
+        assert floor <= 1.0, k
+
+
 @pytest.mark.parametrize("algo", [0, 1])
 @pytest.mark.parametrize("weights", ["unit", "random"])
 def test_fp32_floor_on_tiny_hod_subset(algo, weights):
     """The tiny HOD subset (2 000 candidates in 40 halos of a 125 Mpc/h box,
     64^3, no field galaxies) is the most clustered workload: xi_pg reaches
-    ~4.5, and single-precision transforms leave an error of about one FP32
-    unit of that largest value on every bin of every row (the galaxy
-    transform and the inverse transform contribute most).  This is a property
-    of FP32 transforms of this catalogue, not of these kernels: the same
-    chain evaluated with a reference single-precision FFT on the CPU misses
-    the 1e-5 relative bar by 4.7x, these kernels by at most 2.6x.  The bound
-    checked here is 1e-5 relative, or 2^-23 max|xi_pg| absolute where that is
-    larger, for both the per-field transforms and the dual form."""
+    ~4.4 while most bins hold |xi| ~ 1e-3 - 1e-2.  A model of these kernels'
+    transform schedule (tests/test_fp32_floor.py) shows that single-precision
+    storage of the grids between passes alone takes 0.4 - 0.9 of the 1e-5 bar
+    there even with exact arithmetic, and that FP32 arithmetic misses it by
+    1.5 - 3x, as these kernels do; the FP64 plain path meets it (test below).
+    The bound checked here is 1e-5 relative, or one FP32 unit of the largest
+    |xi_pg| absolute where that is larger, for both algorithms."""
     from paper_1705_03464_amd import Plan
     wl = get_config("cfg4tiny")
     cat = wl.catalog()
@@ -137,16 +152,61 @@ def test_fp32_floor_on_tiny_hod_subset(algo, weights):
     plan.set_schedule(10, 0, 0, 0, algo)
     out = {k: v.cpu().numpy() for k, v in
            plan.forward(None if w is None else dev(w, torch.float32)).items()}
-    fin = np.isfinite(ref["xi_pg"])
-    floor_abs = 2.0 ** -23 * float(np.max(np.abs(ref["xi_pg"][fin])))
+    _floor_check(out, ref, f"{weights} algo {algo}")
+
+
+@pytest.mark.parametrize("weights", ["unit", "random"])
+def test_fp64_plain_meets_the_bar_on_tiny_hod_subset(weights):
+    """Where FP32 storage cannot hold the 1e-5 bar, the FP64 plain path
+    (FP64 grids and transforms, one field at a time) meets the oracle at
+    1e-9 on every bin."""
+    from paper_1705_03464_amd import Plan
+    wl = get_config("cfg4tiny")
+    cat = wl.catalog()
+    w = None
+    if weights == "random":
+        w = np.random.default_rng(5).uniform(0.5, 1.5, cat.n).astype(np.float32).astype(np.float64)
+    ref = oracle_forward(cat, wl, w=w)
+    plan = Plan.from_workload(wl, precision="fp64")
+    plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
+    out = {k: v.cpu().numpy() for k, v in
+           plan.forward(None if w is None else dev(w, torch.float32)).items()}
     for k in ("xi_gg", "xi_pg"):
-        strict = _worst(out[k], ref[k], 1e-5)
-        e = ref[k][np.isfinite(ref[k])]
-        g = out[k][np.isfinite(ref[k])]
-        floor = float(np.max(np.abs(g - e) / np.maximum(1e-5 * np.abs(e), floor_abs)))
-        _say(f"  {weights} algo {algo} {k}: 1e-5 max(|xi|,1e-2) ratio {strict:.2f}; "
-             f"max(1e-5 |xi|, {floor_abs:.2e}) ratio {floor:.2f}")
-        assert floor <= 1.0, k
+        worst = _worst(out[k], ref[k], 1e-9)
+        _say(f"  FP64 plain {weights} {k}: worst / (1e-9 max(|xi|,1e-2)) {worst:.3f}")
+        assert worst <= 1.0
+
+
+@pytest.mark.parametrize("algo", [0, 1, 2])
+def test_512_spiky_halos(algo):
+    """A harsher crowding probe at 512^3 in a 250 Mpc/h box: 200 halos of 30
+    satellites each within about 0.3 Mpc/h of the centre (up to ~260 pair
+    midpoints per node), no field galaxies, so that every |xi| at r >= 10 is
+    below 0.1 and the 1e-5 bar is 1e-7 absolute in most bins.  All three
+    evaluations are held to the bound of the tiny HOD subset (one FP32 unit
+    of the largest |xi_pg|), the FP64 plain path to the strict bar at 1e-9."""
+    from paper_1705_03464_amd import Plan
+    L = 250.0
+    wl = Workload(name="spiky", L=L, N=512, precision="fp32", pair_mode="s_mu",
+                  p1_edges=logbins(0.5, 10.0, 4), p2_edges=linbins(0.0, 1.0, 1), out_mode="shell",
+                  o1_edges=logbins(10.0, 80.0, 12), o2_edges=None, catalog_kw={})
+    cat = clustered_catalog(L, 200, 0, seed=75, sat=30, spread=0.3)
+    ref = oracle_forward(cat, wl)
+    plan = Plan.from_workload(wl, precision="fp32")
+    P, counts = plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
+    assert np.array_equal(counts.cpu().numpy(), ref["counts"])
+    plan.set_schedule(2, 0, 0, *ALGOS[algo])
+    out = {k: v.cpu().numpy() for k, v in plan.forward().items()}
+    _say(f"spiky halos 512^3, {P} pairs, algorithm {ALGOS[algo]}")
+    _floor_check(out, ref, f"algo {algo}")
+    if algo == 0:
+        p64 = Plan.from_workload(wl, precision="fp64")
+        p64.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
+        o64 = {k: v.cpu().numpy() for k, v in p64.forward().items()}
+        for k in ("xi_gg", "xi_pg"):
+            worst = _worst(o64[k], ref[k], 1e-9)
+            _say(f"  FP64 plain {k}: worst / (1e-9 max(|xi|,1e-2)) {worst:.3f}")
+            assert worst <= 1.0
 
 
 def test_autotuned_schedule_matches_default_cfg2():
