@@ -452,6 +452,12 @@ template <typename T, int N> struct Engine : EngineBase {
   // ------------------------------------------------------------------------
   // pair catalogue
   // ------------------------------------------------------------------------
+  // blocks of the pair search (one wavefront per galaxy, grid-stride)
+  static int pair_blocks(int64_t n) {
+    const int64_t b = (n + kPairWaves - 1) / kPairWaves;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(b, 1 << 16));
+  }
+
   void pairs_build(const double* x, const double* y, const double* z, const float* w, int64_t n,
                    hipStream_t s, int64_t* n_pairs_out, int64_t* counts, double* wsum) override {
     PGX_REQUIRE(n >= 0 && n < INT32_MAX, PGX_EINVAL, "n_gal must be in [0, 2^31)");
@@ -515,6 +521,8 @@ template <typename T, int N> struct Engine : EngineBase {
     pc.mode = cfg.pair_mode;
     pc.n1 = (int)cfg.p1.size() - 1;
     pc.n2 = (int)cfg.p2.size() - 1;
+    pc.step1 = 0;  // smallest power of two with 2 step1 >= n1 (the steps cover n1 - 1)
+    while (2 * pc.step1 < pc.n1) pc.step1 = pc.step1 ? 2 * pc.step1 : 1;
     pc.t1 = t1.as<double>();
     pc.t2 = t2.as<double>();
     pc.dmax2 = cfg.pair_dmax * cfg.pair_dmax;
@@ -522,8 +530,8 @@ template <typename T, int N> struct Engine : EngineBase {
     int64_t* off = s_off.get<int64_t>(n + 1);
     int64_t P = 0;
     if (n > 0) {
-      k_pairs<false, T><<<grid_for(n), 256, 0, s>>>(pc, px, py, pz, perm, cks, cstart, n, cnt,
-                                                    nullptr, nullptr, nullptr);
+      k_pairs<false, T><<<pair_blocks(n), 64 * kPairWaves, 0, s>>>(pc, px, py, pz, perm, cks, cstart,
+                                                                  n, cnt, nullptr, nullptr, nullptr);
       launch_check("pair_count");
       exscan_i64(cnt, off, n, s, s_tmp);
       int64_t last[2] = {0, 0};
@@ -538,8 +546,8 @@ template <typename T, int N> struct Engine : EngineBase {
     int32_t* ui = s_i.get<int32_t>(P);
     int32_t* uj = s_j.get<int32_t>(P);
     if (P > 0) {
-      k_pairs<true, T><<<grid_for(n), 256, 0, s>>>(pc, px, py, pz, perm, cks, cstart, n, off, uk,
-                                                   ui, uj);
+      k_pairs<true, T><<<pair_blocks(n), 64 * kPairWaves, 0, s>>>(pc, px, py, pz, perm, cks, cstart,
+                                                                 n, off, uk, ui, uj);
       launch_check("pair_emit");
     }
     // bucket by (field, line)

@@ -23,6 +23,7 @@ struct PairCfg {
   double L, halfL, gscale;  // gscale = N / L
   double side;              // cell side (>= maximum pair separation)
   int nc, N, mode, n1, n2;
+  int step1;                // largest power of two below n1 (binary search over t1)
   const double* t1;         // squared first-axis edges (n1 + 1)
   const double* t2;         // squared second-axis edges (mu^2 or pi^2) (n2 + 1)
   double dmax2;
@@ -42,8 +43,10 @@ __device__ __forceinline__ int pair_key(const PairCfg& c, double dx, double dy, 
   if (c.mode == 0) {
     if (s2 < c.t1[0] || s2 >= c.t1[c.n1]) return -1;
     if (zz < c.t2[0] * s2 || zz > c.t2[c.n2] * s2) return -1;
+    // the number of inner edges with s2 >= t1[e] (t1 ascending): binary search
     int b = 0;
-    for (int e = 1; e < c.n1; ++e) b += (s2 >= c.t1[e]) ? 1 : 0;
+    for (int step = c.step1; step > 0; step >>= 1)
+      if (b + step < c.n1 && s2 >= c.t1[b + step]) b += step;
     int k = 0;
     for (int e = 1; e < c.n2; ++e) k += (zz >= c.t2[e] * s2) ? 1 : 0;
     return b * c.n2 + k;
@@ -124,104 +127,105 @@ static __global__ void k_run_counts(const int32_t* __restrict__ key, int64_t n, 
     atomicAdd(&h[k], (int32_t)(p + 1));
 }
 
-// One thread per galaxy in cell order; candidates are galaxies of the 27
-// neighbour cells with a larger cell-order index.  COUNT: cnt[p] = number of
-// kept pairs.  EMIT: pairs written at off[p] + local index: the sort key
-// (field, base line of the midpoint) and the catalogue indices i < j only;
-// the midpoint's CIC corner and fractions are recomputed after the sort by
-// k_pair_cic, with coalesced stores.
+// One wavefront per galaxy p (in cell order); its candidates are the galaxies
+// of the 27 neighbour cells with a larger cell-order index, taken as one
+// list: neighbour cells in order o = 0..26, each cell's candidates in cell
+// order.  The lanes test 64 consecutive candidates of that list at a time;
+// each kept pair gets its place from a ballot of the lanes (the kept lanes
+// below it), so a galaxy's pairs are written contiguously and in list order
+// (coalesced stores, and the same order as a serial loop over the list).
+// COUNT: cnt[p] = number of kept pairs.  EMIT: pairs written at off[p] + rank:
+// the sort key (field, base line of the midpoint) and the catalogue indices
+// i < j only; the midpoint's CIC corner and fractions are recomputed after
+// the sort by k_pair_cic, with coalesced stores.
+constexpr int kPairWaves = 4;  // wavefronts per block
 template <bool EMIT, typename T>
-static __global__ void k_pairs(PairCfg c, const double* __restrict__ px, const double* __restrict__ py,
-                        const double* __restrict__ pz, const int32_t* __restrict__ perm,
-                        const int32_t* __restrict__ cell_of, const int32_t* __restrict__ cell_start,
-                        int64_t n, int64_t* __restrict__ cnt_off, int32_t* __restrict__ skey,
-                        int32_t* __restrict__ oi, int32_t* __restrict__ oj) {
+static __global__ void __launch_bounds__(64 * kPairWaves)
+k_pairs(PairCfg c, const double* __restrict__ px, const double* __restrict__ py,
+        const double* __restrict__ pz, const int32_t* __restrict__ perm,
+        const int32_t* __restrict__ cell_of, const int32_t* __restrict__ cell_start, int64_t n,
+        int64_t* __restrict__ cnt_off, int32_t* __restrict__ skey, int32_t* __restrict__ oi,
+        int32_t* __restrict__ oj) {
 #pragma clang fp contract(off)
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  const int cell = cell_of[p];
-  const int nc = c.nc;
-  const int cx = cell / (nc * nc), cy = (cell / nc) % nc, cz = cell % nc;
-  const double ax = px[p], ay = py[p], az = pz[p];
-  const int ia = perm[p];
-  int64_t w = EMIT ? cnt_off[p] : 0;
+  const int lane = (int)(threadIdx.x & 63);
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const int64_t NN = (int64_t)c.N * c.N;
-  // emitted pairs wait in registers until they fill an aligned group of
-  // four output slots, which is then written as one 16-byte store per array
-  // (a thread's pairs occupy its own contiguous output range); kb[k] holds
-  // the pair of slot w - 4 + k, the last nbuf of them not yet written
-  int32_t kb[4] = {0, 0, 0, 0}, ib[4] = {0, 0, 0, 0}, jb[4] = {0, 0, 0, 0};
-  int nbuf = 0;
-  auto flush = [&]() {
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (k >= 4 - nbuf) {
-        skey[w - 4 + k] = kb[k];
-        oi[w - 4 + k] = ib[k];
-        oj[w - 4 + k] = jb[k];
-      }
-  };
-  for (int o = 0; o < 27; ++o) {
-    const int nx = (cx + o / 9 - 1 + nc) % nc;
-    const int ny = (cy + (o / 3) % 3 - 1 + nc) % nc;
-    const int nz = (cz + o % 3 - 1 + nc) % nc;
-    const int nb = (nx * nc + ny) * nc + nz;
-    const int s = cell_start[nb], e = cell_start[nb + 1];
-    // each pair once, by its lower cell-order index: start past p (a cell
-    // wholly before p's position is skipped at once)
-    for (int q = s > (int)p ? s : (int)p + 1; q < e; ++q) {
-      const int ib_ = perm[q];
-      const double bx = px[q], by = py[q], bz = pz[q];
-      // i < j by catalogue index, d = x_j - x_i
-      const bool fwd = ia < ib_;
-      const double xi = fwd ? ax : bx, yi = fwd ? ay : by, zi = fwd ? az : bz;
-      const double dx = fold((fwd ? bx : ax) - xi, c.L, c.halfL);
-      const double dy = fold((fwd ? by : ay) - yi, c.L, c.halfL);
-      const double dz = fold((fwd ? bz : az) - zi, c.L, c.halfL);
-      const int key = pair_key(c, dx, dy, dz);
-      if (key < 0) continue;
-      if constexpr (EMIT) {
-        double mx = xi + 0.5 * dx, my = yi + 0.5 * dy, mz = zi + 0.5 * dz;
-        mx = mx >= c.L ? mx - c.L : (mx < 0.0 ? mx + c.L : mx);
-        my = my >= c.L ? my - c.L : (my < 0.0 ? my + c.L : my);
-        mz = mz >= c.L ? mz - c.L : (mz < 0.0 ? mz + c.L : mz);
-        int y0, z0;
-        double fy, fz;
-        (void)mx;
-        cic_of(my, c.gscale, c.N, y0, fy);
-        cic_of(mz, c.gscale, c.N, z0, fz);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          kb[k] = kb[k + 1];
-          ib[k] = ib[k + 1];
-          jb[k] = jb[k + 1];
-        }
-        kb[3] = (int32_t)((int64_t)key * NN + (int64_t)z0 * c.N + y0);
-        ib[3] = fwd ? ia : ib_;
-        jb[3] = fwd ? ib_ : ia;
-        nbuf = nbuf < 4 ? nbuf + 1 : 4;
-      }
-      ++w;
-      if constexpr (EMIT) {
-        if ((w & 3) == 0) {
-          if (nbuf == 4) {
-            *reinterpret_cast<int4*>(skey + w - 4) = make_int4(kb[0], kb[1], kb[2], kb[3]);
-            *reinterpret_cast<int4*>(oi + w - 4) = make_int4(ib[0], ib[1], ib[2], ib[3]);
-            *reinterpret_cast<int4*>(oj + w - 4) = make_int4(jb[0], jb[1], jb[2], jb[3]);
-          } else {
-            flush();
-          }
-          nbuf = 0;
-        }
-      }
+  const int nc = c.nc;
+  for (int64_t p = (int64_t)blockIdx.x * kPairWaves + (threadIdx.x >> 6); p < n;
+       p += (int64_t)gridDim.x * kPairWaves) {
+    const int cell = cell_of[p];
+    const int cx = cell / (nc * nc), cy = (cell / nc) % nc, cz = cell % nc;
+    // lane o < 27: candidates of neighbour cell o start at qs and number cn
+    // (each pair once, by its lower cell-order index: past p)
+    int qs = 0, cn = 0;
+    if (lane < 27) {
+      const int nx = (cx + lane / 9 - 1 + nc) % nc;
+      const int ny = (cy + (lane / 3) % 3 - 1 + nc) % nc;
+      const int nz = (cz + lane % 3 - 1 + nc) % nc;
+      const int nb = (nx * nc + ny) * nc + nz;
+      const int s = cell_start[nb], e = cell_start[nb + 1];
+      qs = s > (int)p ? s : (int)p + 1;
+      cn = e > qs ? e - qs : 0;
     }
-  }
-  if constexpr (EMIT) {
-    // the last, unaligned group: slots w - nbuf .. w - 1 hold kb[4 - nbuf .. 3]
-    // (kb[k] is slot w - 4 + k whatever w mod 4 is)
-    flush();
-  } else {
-    cnt_off[p] = w;
+    // exclusive prefix of the counts over the 27 cells
+    int inc = cn;
+#pragma unroll
+    for (int d = 1; d < 32; d <<= 1) {
+      const int u = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += u;
+    }
+    const int pre = inc - cn;
+    const int total = __shfl(inc, 26, 64);
+    const double ax = px[p], ay = py[p], az = pz[p];
+    const int ia = perm[p];
+    int64_t w = EMIT ? cnt_off[p] : 0;
+    for (int base = 0; base < total; base += 64) {
+      const int idx = base + lane;
+      // the neighbour cell of list entry idx: the last o with pre[o] <= idx
+      // (pre is non-decreasing in o: binary search over lanes 0..26)
+      int o = 0;
+#pragma unroll
+      for (int step = 16; step > 0; step >>= 1) {
+        const int k = o + step;
+        const int pk = __shfl(pre, k < 27 ? k : 26, 64);
+        o = (k < 27 && pk <= idx) ? k : o;
+      }
+      const int q = __shfl(qs, o, 64) + (idx - __shfl(pre, o, 64));
+      int key = -1;
+      int32_t okey = 0, oa = 0, ob = 0;
+      if (idx < total) {
+        const int ib_ = perm[q];
+        const double bx = px[q], by = py[q], bz = pz[q];
+        // i < j by catalogue index, d = x_j - x_i
+        const bool fwd = ia < ib_;
+        const double xi = fwd ? ax : bx, yi = fwd ? ay : by, zi = fwd ? az : bz;
+        const double dx = fold((fwd ? bx : ax) - xi, c.L, c.halfL);
+        const double dy = fold((fwd ? by : ay) - yi, c.L, c.halfL);
+        const double dz = fold((fwd ? bz : az) - zi, c.L, c.halfL);
+        key = pair_key(c, dx, dy, dz);
+        if (EMIT && key >= 0) {
+          double my = yi + 0.5 * dy, mz = zi + 0.5 * dz;
+          my = my >= c.L ? my - c.L : (my < 0.0 ? my + c.L : my);
+          mz = mz >= c.L ? mz - c.L : (mz < 0.0 ? mz + c.L : mz);
+          int y0, z0;
+          double fy, fz;
+          cic_of(my, c.gscale, c.N, y0, fy);
+          cic_of(mz, c.gscale, c.N, z0, fz);
+          okey = (int32_t)((int64_t)key * NN + (int64_t)z0 * c.N + y0);
+          oa = fwd ? ia : ib_;
+          ob = fwd ? ib_ : ia;
+        }
+      }
+      const uint64_t kept = __ballot(key >= 0);
+      if (EMIT && key >= 0) {
+        const int64_t at = w + __popcll(kept & below);
+        skey[at] = okey;
+        oi[at] = oa;
+        oj[at] = ob;
+      }
+      w += __popcll(kept);
+    }
+    if (!EMIT && lane == 0) cnt_off[p] = w;
   }
 }
 

@@ -10,9 +10,11 @@ force (no device).
 * The sorted-key variant used by the dual form's scatter (a step is taken
   when the shifted lane's key equals the lane's own, which is exact for
   sorted keys).
-* The pair emission's register buffer: pairs wait until they fill an aligned
-  group of four output slots; every slot of the thread's range must be
-  written exactly once, with its own pair.
+* The pair search's lane mapping: a wavefront takes one galaxy's candidates
+  from 27 neighbour cells as one list (an exclusive prefix of the cell counts
+  over lanes 0..26, a search of that prefix per lane), tests 64 entries at a
+  time and places each kept pair by a ballot rank; the result must be the
+  pairs of a serial loop over the cells, in the same order.
 """
 import numpy as np
 
@@ -106,30 +108,42 @@ def test_sorted_key_run_sums():
         assert np.array_equal(tail, etail)
 
 
-def test_emission_register_buffer_writes_each_slot_once():
-    rng = np.random.default_rng(2)
-    for trial in range(5000):
-        w0 = int(rng.integers(0, 50))
-        vals = rng.integers(0, 1 << 30, int(rng.integers(0, 30)))
-        writes = []
-        kb, nbuf, w = [0, 0, 0, 0], 0, w0
+def _wave_pairs(qs, cn, keep):
+    """Lane-level model: returns the kept (q) in output order."""
+    lane = np.arange(64)
+    cn64 = np.zeros(64, np.int64); cn64[:27] = cn
+    qs64 = np.zeros(64, np.int64); qs64[:27] = qs
+    inc = cn64.copy()
+    d = 1
+    while d < 32:  # Hillis-Steele inclusive scan, shifts up to 16
+        up = np.concatenate([np.zeros(d, np.int64), inc[:-d]])
+        inc = np.where(lane >= d, inc + up, inc)
+        d <<= 1
+    pre = inc - cn64
+    total = int(inc[26])
+    out = []
+    for base in range(0, total, 64):
+        idx = base + lane
+        o = np.zeros(64, np.int64)
+        for k in range(1, 27):
+            o = np.where(pre[k] <= idx, k, o)
+        q = qs64[o] + (idx - pre[o])
+        ok = (idx < total) & np.array([keep(int(v)) for v in q]) & (idx < total)
+        ballot = np.flatnonzero(ok)
+        for r, ln in enumerate(ballot):  # rank = kept lanes below
+            assert r == int(np.sum(ok[:ln]))
+            out.append(int(q[ln]))
+    return out
 
-        def flush():
-            for k in range(4):
-                if k >= 4 - nbuf:
-                    writes.append((w - 4 + k, kb[k]))
 
-        for val in vals:
-            kb = kb[1:] + [int(val)]
-            nbuf = min(nbuf + 1, 4)
-            w += 1
-            if w % 4 == 0:
-                if nbuf == 4:
-                    assert (w - 4) % 4 == 0  # an aligned 16-byte group
-                    writes.extend((w - 4 + k, kb[k]) for k in range(4))
-                else:
-                    flush()
-                nbuf = 0
-        flush()
-        assert sorted(p for p, _ in writes) == list(range(w0, w0 + vals.size))
-        assert all(val == vals[p - w0] for p, val in writes)
+def test_pair_search_lane_mapping_keeps_the_serial_order():
+    rng = np.random.default_rng(3)
+    for trial in range(400):
+        # 27 neighbour cells: empty, sparse or crowded, possibly cut by the
+        # galaxy's own position
+        cn = rng.choice([0, 0, 1, 2, 5, 40, 130], 27)
+        qs = np.cumsum(np.concatenate([[int(rng.integers(0, 5))], cn[:-1] + rng.integers(0, 4, 26)]))
+        keep_set = set(int(v) for v in rng.integers(0, int(qs[-1] + cn[-1] + 1), 200))
+        keep = lambda v: (v % 3 != 0) or v in keep_set
+        serial = [int(q) for o in range(27) for q in range(qs[o], qs[o] + cn[o]) if keep(int(q))]
+        assert _wave_pairs(qs, cn, keep) == serial
