@@ -2,7 +2,7 @@
 
 The paper assigns galaxies and pairs to a 512^3 grid with a triangular-shaped
 cloud (Implementation section, "Mass assignment function"); this project uses
-CIC on its batched path, and offers TSC as a scheme on the plain FP64 path.
+CIC by default and offers TSC as a scheme.
 Node (a, b, c) sits at position (a, b, c) * L/N.  CIC: a point at
 u = x*(N/L) (FP64) with i0 = floor(u), f = u - i0 gives weight (1 - f) to
 node i0 and f to node i0 + 1 along each axis, indices taken mod N.  TSC: see
@@ -96,10 +96,34 @@ def tsc_assign(pos: np.ndarray, weights, N: int, L: float) -> np.ndarray:
     return rho
 
 
+def tsc_gather(field: np.ndarray, pos: np.ndarray, N: int, L: float) -> np.ndarray:
+    """Adjoint of tsc_assign with unit weights: the TSC interpolation
+    sum_nodes W(node - u) field[node] at every point."""
+    pos = np.asarray(pos, np.float64).reshape(-1, 3)
+    u = pos * (N / L)
+    lo, ws = zip(*(tsc_weights_1d(u[:, k]) for k in range(3)))
+    out = np.zeros(pos.shape[0])
+    for ox in range(3):
+        for oy in range(3):
+            for oz in range(3):
+                out += (field[(lo[0] + ox) % N, (lo[1] + oy) % N, (lo[2] + oz) % N]
+                        * ws[0][:, ox] * ws[1][:, oy] * ws[2][:, oz])
+    return out
+
+
 def assign(pos, weights, N, L, scheme="cic"):
     """Mass assignment by scheme "cic" or "tsc"."""
     if scheme == "cic":
         return cic_assign(pos, weights, N, L)
     if scheme == "tsc":
         return tsc_assign(pos, weights, N, L)
+    raise ValueError(scheme)
+
+
+def gather(field, pos, N, L, scheme="cic"):
+    """Interpolation at the points, the adjoint of `assign` by scheme."""
+    if scheme == "cic":
+        return cic_gather(field, pos, N, L)
+    if scheme == "tsc":
+        return tsc_gather(field, pos, N, L)
     raise ValueError(scheme)

@@ -26,7 +26,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import bins as _bins
-from .cic import cic_assign, cic_gather
+from .cic import assign, gather
 from .corr import irfftn, rfftn
 from .finalize import field_volumes, xi_dp as _xi_dp
 from .pipeline import forward
@@ -199,7 +199,8 @@ def weight_gradient(cat, wl, w, g_b=None, g_q=None, g_xipg=None, g_xigg=None, g_
     conv = _conv_sum if method == "fft" else _conv_sum_direct
     pos = cat.positions()
     wg = out["wg"]
-    rho_g = cic_assign(pos, w, N, L)
+    scheme = getattr(wl, "assignment", "cic")
+    rho_g = assign(pos, w, N, L, scheme)
     dg = rho_g * (Nc / wg) - 1.0
     E = np.zeros((N, N, N))
     kg = _kappa_grid(ggg, table, N, R, bw)
@@ -212,20 +213,20 @@ def weight_gradient(cat, wl, w, g_b=None, g_q=None, g_xipg=None, g_xigg=None, g_
             continue
         mid = pairs["mid"][sel]
         pw = pairs["w"][sel]
-        rho_f = cic_assign(mid, pw, N, L)
+        rho_f = assign(mid, pw, N, L, scheme)
         df = rho_f * (Nc / ws) - 1.0
         kf = _kappa_grid(gpg[f], table, N, R, bw)
         D = corr(kf, dg)
         E += conv(kf, df)
         drho_f = D * (Nc / ws)
         gws_f = gws[f] - (Nc / ws ** 2) * float(np.sum(D * rho_f))
-        gather = cic_gather(drho_f, mid, N, L) + gws_f
+        gath = gather(drho_f, mid, N, L, scheme) + gws_f
         ii = pairs["i"][sel]; jj = pairs["j"][sel]
-        np.add.at(grad, ii, w[jj] * gather)
-        np.add.at(grad, jj, w[ii] * gather)
+        np.add.at(grad, ii, w[jj] * gath)
+        np.add.at(grad, jj, w[ii] * gath)
     drho_g = E * (Nc / wg)
     gwg_tot = gwg - (Nc / wg ** 2) * float(np.sum(E * rho_g))
-    grad += cic_gather(drho_g, pos, N, L) + gwg_tot
+    grad += gather(drho_g, pos, N, L, scheme) + gwg_tot
     return grad, out
 
 

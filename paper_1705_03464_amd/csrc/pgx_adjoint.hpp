@@ -423,7 +423,7 @@ k_zinit(const C<T>* __restrict__ ky_in, int pwz, const C<T>* __restrict__ fg,
 // line adds its share to acc[p] (real part for field a, imaginary for b):
 //   acc[p] += scale * wy * wz * ((1 - fx) line[x0] + fx line[x0 + 1]).
 // ----------------------------------------------------------------------------
-template <typename T, typename Sh, int W>
+template <typename T, typename Sh, int W, bool TSC = false>
 static __global__ void __launch_bounds__(W * Sh::TPL)
 k_xgather(const int32_t* __restrict__ tasks, int n_tasks, PointSet<T> ps,
           const int32_t* __restrict__ slot_fa, const int32_t* __restrict__ slot_fb,
@@ -467,19 +467,40 @@ k_xgather(const int32_t* __restrict__ tasks, int n_tasks, PointSet<T> ps,
       // a field whose kernel coefficients were divided by fscale[f] gives
       // values scaled by 1 / fscale[f]: undo it here
       const T sc = scale * (fscale ? (T)fscale[f] : (T)1);
+      // the base lines whose points read this line (as in the scatter)
+      constexpr int NB = TSC ? 16 : 4;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int by = (q & 1) ? ym : y, bz = (q & 2) ? zm : z;
+      for (int q = 0; q < NB; ++q) {
+        int by, bz;
+        if constexpr (TSC) {
+          by = (y + (q & 3) - 2) & (N - 1);
+          bz = (z + (q >> 2) - 2) & (N - 1);
+        } else {
+          by = (q & 1) ? ym : y;
+          bz = (q & 2) ? zm : z;
+        }
         const int64_t key = fbase + (int64_t)bz * N + by;
         const int s = ps.line_start[key], e = ps.line_start[key + 1];
         for (int p = s + t; p < e; p += TPL) {
           const T fy = ps.fy[p], fz = ps.fz[p], fx = ps.fx[p];
-          const T wy = (q & 1) ? fy : (T)1 - fy;
-          const T wz = (q & 2) ? fz : (T)1 - fz;
           const int x0 = ps.x0[p];
-          const C<T> a0 = line[lpad(x0)], a1 = line[lpad((x0 + 1) & (N - 1))];
-          const T v0 = part == 0 ? a0.x : a0.y, v1 = part == 0 ? a1.x : a1.y;
-          atomicAdd(&acc[p], (float)(sc * wy * wz * (((T)1 - fx) * v0 + fx * v1)));
+          auto val = [&](int xx) {
+            const C<T> a = line[lpad(xx & (N - 1))];
+            return part == 0 ? a.x : a.y;
+          };
+          if constexpr (TSC) {
+            const T wyz = tsc_line_weight<T>(by, fy, y, N) * tsc_line_weight<T>(bz, fz, z, N);
+            if (wyz == (T)0) continue;
+            T wx[3];
+            int lx;
+            tsc_axis<T>(x0, fx, lx, wx);
+            const T g = wx[0] * val(lx) + wx[1] * val(lx + 1) + wx[2] * val(lx + 2);
+            atomicAdd(&acc[p], (float)(sc * wyz * g));
+          } else {
+            const T wy = (q & 1) ? fy : (T)1 - fy;
+            const T wz = (q & 2) ? fz : (T)1 - fz;
+            atomicAdd(&acc[p], (float)(sc * wy * wz * (((T)1 - fx) * val(x0) + fx * val(x0 + 1))));
+          }
         }
       }
     }

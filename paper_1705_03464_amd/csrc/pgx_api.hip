@@ -160,8 +160,6 @@ void build_cfg(const pgx_params* p, pgx::PlanCfg& c) {
               "unknown qeff_mode");
   PGX_REQUIRE(p->assignment == PGX_ASSIGN_CIC || p->assignment == PGX_ASSIGN_TSC, PGX_EINVAL,
               "unknown assignment");
-  PGX_REQUIRE(p->assignment == PGX_ASSIGN_CIC || p->precision == PGX_FP64_PLAIN, PGX_ENOTSUP,
-              "TSC assignment is implemented on the FP64 plain path");
   c.L = p->L;
   c.N = N;
   c.precision = p->precision;

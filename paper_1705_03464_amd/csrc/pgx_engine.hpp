@@ -14,7 +14,7 @@ namespace pgx {
 struct PlanCfg {
   double L = 0, pair_dmax = 0, xi_w_const = 0, smax = 0;
   int N = 0, precision = 1, pair_mode = 0, out_mode = 0, qeff_mode = 0, batch = 0;
-  int assignment = 0;  // 0 CIC, 1 TSC (plain FP64 path)
+  int assignment = 0;  // 0 CIC, 1 TSC
   std::vector<double> p1, p2, o1, o2;
   int F = 0, R = 0, n_fp = 0;
   int pw[3] = {0, 0, 0};
@@ -716,7 +716,7 @@ template <typename T, int N> struct Engine : EngineBase {
     uint8_t* lf = lflag.get<uint8_t>(nfl + 1);
     k_fill_u8(lf, nfl + 1, s);
     if (n_pairs > 0) {
-      k_mark_lines<<<grid_for(n_pairs), 256, 0, s>>>(p_key.as<int32_t>(), n_pairs, N, lf);
+      k_mark_lines<<<grid_for(n_pairs), 256, 0, s>>>(p_key.as<int32_t>(), n_pairs, N, cfg.assignment, lf);
       launch_check("mark_lines");
     }
     uint8_t* pf = pflag.get<uint8_t>((int64_t)cfg.n_fp * N);
@@ -804,7 +804,9 @@ template <typename T, int N> struct Engine : EngineBase {
       int best_algo = 0, best_vz_dual = 0;
       dual_disagreement = -1.0;
       algo = 0;
-      if (dual_fits()) {
+      // the dual form's gather and scatter hold the CIC footprint: with TSC
+      // the per-field transforms serve
+      if (cfg.assignment == 0 && dual_fits()) {
         const int F = cfg.F, R = cfg.R;
         double* sref = S_ref.get<double>((int64_t)F * R);
         PGX_HIP(hipMemcpyAsync(sref, S.as<double>(), (size_t)F * R * sizeof(double),
@@ -875,6 +877,8 @@ template <typename T, int N> struct Engine : EngineBase {
     if constexpr (!std::is_same<T, float>::value) {
       throw Error(PGX_ENOTSUP, "schedules apply to the FP32 batched path");
     } else {
+      PGX_REQUIRE(in[4] == 0 || cfg.assignment == 0, PGX_ENOTSUP,
+                  "the dual form holds the CIC footprint: TSC plans use the per-field transforms");
       schedule(in[0], s);
       v_ypass = in[1];
       v_yinv = in[2];
@@ -1003,6 +1007,24 @@ template <typename T, int N> struct Engine : EngineBase {
     k_weight_partial<<<kWtBlocks, 256, 0, s>>>(w, n_gal, wpart);
     k_weight_total<<<1, 256, 0, s>>>(wpart, wg_d.get<double>(1));
     launch_check("weight_total");
+  }
+
+  // x-pass scatter and its adjoint gather with the plan's mass assignment
+  // (CIC, or TSC on the same point records)
+  void xscatter(int grid, const int32_t* tk, int nt, const PointSet<T>& ps, const int32_t* fa,
+                const int32_t* fb, C<T>* out, const C<T>* twp, const float* fsc, hipStream_t s) {
+    if (cfg.assignment == 1)
+      k_xscatter<T, Sh, WX, true><<<grid, NTX, 0, s>>>(tk, nt, ps, fa, fb, out, twp, fsc);
+    else
+      k_xscatter<T, Sh, WX><<<grid, NTX, 0, s>>>(tk, nt, ps, fa, fb, out, twp, fsc);
+  }
+  void xgather(int grid, const int32_t* tk, int nt, const PointSet<T>& ps, const int32_t* fa,
+               const int32_t* fb, const C<T>* in, T scale, float* acc, const C<T>* twp,
+               const float* fsc, hipStream_t s) {
+    if (cfg.assignment == 1)
+      k_xgather<T, Sh, WX, true><<<grid, NTX, 0, s>>>(tk, nt, ps, fa, fb, in, scale, acc, twp, fsc);
+    else
+      k_xgather<T, Sh, WX><<<grid, NTX, 0, s>>>(tk, nt, ps, fa, fb, in, scale, acc, twp, fsc);
   }
 
   PointSet<T> gal_set() const {
@@ -1255,8 +1277,8 @@ template <typename T, int N> struct Engine : EngineBase {
         } else {
           if (nt > 0) {
             prof.run("bwd_xscatter", s, pts + (double)nt * N * cb, [&] {
-              k_xscatter<T, Sh, WX><<<(int)((nt + WX - 1) / WX), NTX, 0, s>>>(
-                  tasks.as<int32_t>() + t0, (int)nt, pair_set(), fa, fb, x, twp, FSC.as<float>());
+              xscatter((int)((nt + WX - 1) / WX), tasks.as<int32_t>() + t0, (int)nt, pair_set(), fa, fb,
+                       x, twp, FSC.as<float>(), s);
               launch_check("xscatter(bwd)");
             });
           }
@@ -1278,9 +1300,8 @@ template <typename T, int N> struct Engine : EngineBase {
         });
         if (nt > 0) {
           prof.run("bwd_xgather", s, pts + (double)nt * N * cb, [&] {
-            k_xgather<T, Sh, WX><<<(int)((nt + WX - 1) / WX), NTX, 0, s>>>(
-                tasks.as<int32_t>() + t0, (int)nt, pair_set(), fa, fb, x, (T)1, gb, twp,
-                FSC.as<float>());
+            xgather((int)((nt + WX - 1) / WX), tasks.as<int32_t>() + t0, (int)nt, pair_set(), fa, fb, x,
+                    (T)1, gb, twp, FSC.as<float>(), s);
             launch_check("xgather");
           });
         }
@@ -1309,9 +1330,8 @@ template <typename T, int N> struct Engine : EngineBase {
       launch_check("gal_yinv");
     });
     prof.run("bwd_gal_xgather", s, (double)NC * cb + (double)n_gal * (4 + 4 * sizeof(T)), [&] {
-      k_xgather<T, Sh, WX><<<(int)(NN / WX), NTX, 0, s>>>(g_tasks.as<int32_t>(), (int)NN, gal_set(),
-                                                           gslot_fa.as<int32_t>(),
-                                                           gslot_fb.as<int32_t>(), A, (T)2, gbg, twp);
+      xgather((int)(NN / WX), g_tasks.as<int32_t>(), (int)NN, gal_set(), gslot_fa.as<int32_t>(),
+              gslot_fb.as<int32_t>(), A, (T)2, gbg, twp, nullptr, s);
       launch_check("gal_xgather");
     });
     const float* wl = w_given ? w_last.as<float>() : nullptr;
@@ -1474,6 +1494,7 @@ template <typename T, int N> struct Engine : EngineBase {
   // launches (not recorded).
   void multipoles(hipStream_t s, int lmax, double* xi) override {
     PGX_REQUIRE(lmax == 0 || lmax == 2 || lmax == 4, PGX_EINVAL, "lmax must be 0, 2 or 4");
+    PGX_REQUIRE(cfg.assignment == 0, PGX_ENOTSUP, "the multipoles use the CIC footprint");
     PGX_REQUIRE(xi != nullptr, PGX_EINVAL, "xi_l must not be NULL");
     if constexpr (!std::is_same<T, float>::value) {
       throw Error(PGX_ENOTSUP, "multipoles are implemented on the FP32 batched path");
@@ -1752,9 +1773,8 @@ template <typename T, int N> struct Engine : EngineBase {
     // ---- galaxy field: spectrum (DC removed) and auto-correlation
     const double cb = (double)sizeof(C<T>);
     prof.run("gal_xscatter", s, (double)n_gal * (4 + 4 * sizeof(T)) + (double)NC * cb, [&] {
-      k_xscatter<T, Sh, WX><<<(int)(NN / WX), NTX, 0, s>>>(g_tasks.as<int32_t>(), (int)NN, gal_set(),
-                                                         gslot_fa.as<int32_t>(),
-                                                         gslot_fb.as<int32_t>(), x, twp);
+      xscatter((int)(NN / WX), g_tasks.as<int32_t>(), (int)NN, gal_set(), gslot_fa.as<int32_t>(),
+               gslot_fb.as<int32_t>(), x, twp, nullptr, s);
       launch_check("xscatter(gal)");
     });
     prof.run("gal_ypass", s, 2.0 * NC * cb, [&] {
@@ -1795,8 +1815,8 @@ template <typename T, int N> struct Engine : EngineBase {
       const double pts = (double)batch_points(k) * (4 + 4 * sizeof(T));
       if (nt > 0) {
         prof.run("xscatter", s, pts + (double)nt * N * cb, [&] {
-          k_xscatter<T, Sh, WX><<<(int)((nt + WX - 1) / WX), NTX, 0, s>>>(
-              tasks.as<int32_t>() + t0, (int)nt, pair_set(), fa, fb, x, twp, FSC.as<float>());
+          xscatter((int)((nt + WX - 1) / WX), tasks.as<int32_t>() + t0, (int)nt, pair_set(), fa, fb, x,
+                   twp, FSC.as<float>(), s);
           launch_check("xscatter");
         });
       }

@@ -120,6 +120,35 @@ template <typename Sh, bool PREFER_REG> constexpr int tw_lds_entries() {
   return (PREFER_REG && Sh::E <= 8) ? 1 : Sh::tw_entries();
 }
 
+// TSC mass assignment (Implementation section, "Mass assignment function"):
+// the point spreads over its nearest node c and both neighbours
+// on each axis, weights 3/4 - d^2 (c) and (1/2 -+ d)^2 / 2 (c - 1, c + 1),
+// d = u - c in [-1/2, 1/2].  From the CIC corner x0 and fraction f of the
+// point set: c = x0, d = f when f <= 1/2, else c = x0 + 1, d = f - 1 (a
+// point at exactly one half takes the lower node; both give the same
+// weights).
+template <typename T>
+__device__ __forceinline__ void tsc_axis(int x0, T f, int& lo, T* w) {
+  const bool up = f > (T)0.5;
+  const T d = up ? f - (T)1 : f;
+  lo = x0 + (up ? 1 : 0) - 1;
+  w[0] = (T)0.5 * ((T)0.5 - d) * ((T)0.5 - d);
+  w[1] = (T)0.75 - d * d;
+  w[2] = (T)0.5 * ((T)0.5 + d) * ((T)0.5 + d);
+}
+
+// TSC weight along one axis of the point with CIC corner a0 and fraction f
+// for grid index a (0 where a is not one of the three nodes of the point).
+template <typename T>
+__device__ __forceinline__ T tsc_line_weight(int a0, T f, int a, int N) {
+  const bool up = f > (T)0.5;
+  const T d = up ? f - (T)1 : f;
+  const int j = ((a - a0 - (up ? 1 : 0) + N + 1) & (N - 1)) - 1;  // node - nearest node
+  return j == 0 ? (T)0.75 - d * d
+       : j == -1 ? (T)0.5 * ((T)0.5 - d) * ((T)0.5 - d)
+       : j == 1 ? (T)0.5 * ((T)0.5 + d) * ((T)0.5 + d) : (T)0;
+}
+
 // ----------------------------------------------------------------------------
 // (A) x pass with the CIC scatter fused in.  One task per non-empty line of a
 // field pair.  The line is built in LDS from the points of the four base lines
@@ -130,7 +159,7 @@ template <typename Sh, bool PREFER_REG> constexpr int tw_lds_entries() {
 // put many points on one node, and same-address LDS atomics serialise), and
 // only the last point of each run adds to the line.
 // ----------------------------------------------------------------------------
-template <typename T, typename Sh, int W>
+template <typename T, typename Sh, int W, bool TSC = false>
 static __global__ void __launch_bounds__(W * Sh::TPL)
 k_xscatter(const int32_t* __restrict__ tasks, int n_tasks, PointSet<T> ps,
            const int32_t* __restrict__ slot_fa, const int32_t* __restrict__ slot_fb,
@@ -166,39 +195,73 @@ k_xscatter(const int32_t* __restrict__ tasks, int n_tasks, PointSet<T> ps,
       if (f < 0) continue;
       const int64_t fbase = (int64_t)f * NN;
       const T sc = fscale ? (T)fscale[f] : (T)1;
+      // base lines (CIC corner rows) whose points reach this line: (y, z) and
+      // their lower neighbours for CIC; y - 2 .. y + 1 by z - 2 .. z + 1 for
+      // TSC, whose footprint of three rows starts one row below or at the
+      // corner row
+      constexpr int NB = TSC ? 16 : 4;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int by = (q & 1) ? ym : y, bz = (q & 2) ? zm : z;
+      for (int q = 0; q < NB; ++q) {
+        int by, bz;
+        if constexpr (TSC) {
+          by = (y + (q & 3) - 2) & (N - 1);
+          bz = (z + (q >> 2) - 2) & (N - 1);
+        } else {
+          by = (q & 1) ? ym : y;
+          bz = (q & 2) ? zm : z;
+        }
         const int64_t key = fbase + (int64_t)bz * N + by;
         const int s = ps.line_start[key], e = ps.line_start[key + 1];
         // every lane of a wavefront takes the same trips (one line per wavefront)
         for (int b0 = s; b0 < e; b0 += TPL) {
           const int p = b0 + t;
           const bool ok = p < e;
-          T lo = (T)0, hi = (T)0;
+          T lo = (T)0, mid = (T)0, hi = (T)0;
           int x0 = -1 - (int)(threadIdx.x & 63u);  // idle lanes: keys no node has
           if (ok) {
             const T fy = ps.fy[p], fz = ps.fz[p], fx = ps.fx[p];
-            const T wy = (q & 1) ? fy : (T)1 - fy;
-            const T wz = (q & 2) ? fz : (T)1 - fz;
-            const T w = ps.wt[p] * sc * wy * wz;
             x0 = ps.x0[p];
-            lo = w * ((T)1 - fx);
-            hi = w * fx;
+            if constexpr (TSC) {
+              const T w = ps.wt[p] * sc * tsc_line_weight<T>(by, fy, y, N) *
+                          tsc_line_weight<T>(bz, fz, z, N);
+              // nodes c - 1, c, c + 1 of the nearest node c; the run key is c
+              T wx[3];
+              int lx;
+              tsc_axis<T>(x0, fx, lx, wx);
+              x0 = (lx + 1) & (N - 1);
+              lo = w * wx[0];
+              mid = w * wx[1];
+              hi = w * wx[2];
+            } else {
+              const T wy = (q & 1) ? fy : (T)1 - fy;
+              const T wz = (q & 2) ? fz : (T)1 - fz;
+              const T w = ps.wt[p] * sc * wy * wz;
+              lo = w * ((T)1 - fx);
+              hi = w * fx;
+            }
           }
           bool issue = ok;
           if constexpr (kRuns) {
             SegRuns r;
             r.init(x0);
             lo = r.add(lo);
+            if constexpr (TSC) mid = r.add(mid);
             hi = r.add(hi);
             issue = ok && r.tail;
           }
           if (issue) {
-            T* a0 = part == 0 ? &line[lpad(x0)].x : &line[lpad(x0)].y;
-            T* a1 = part == 0 ? &line[lpad((x0 + 1) & (N - 1))].x : &line[lpad((x0 + 1) & (N - 1))].y;
-            atomicAdd(a0, lo);
-            atomicAdd(a1, hi);
+            auto at = [&](int xx) -> T* {
+              C<T>* c = &line[lpad(xx & (N - 1))];
+              return part == 0 ? &c->x : &c->y;
+            };
+            if constexpr (TSC) {
+              atomicAdd(at(x0 - 1), lo);
+              atomicAdd(at(x0), mid);
+              atomicAdd(at(x0 + 1), hi);
+            } else {
+              atomicAdd(at(x0), lo);
+              atomicAdd(at(x0 + 1), hi);
+            }
           }
         }
       }

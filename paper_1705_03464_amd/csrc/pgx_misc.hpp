@@ -331,22 +331,8 @@ static __global__ void k_scatter_atomic(const int32_t* __restrict__ line_start, 
   }
 }
 
-// TSC variant: the point spreads over its nearest node c and both neighbours
-// on each axis, weights 3/4 - d^2 (c) and (1/2 -+ d)^2 / 2 (c - 1, c + 1),
-// d = u - c in [-1/2, 1/2].  From the CIC corner x0 and fraction f of the
-// point set: c = x0, d = f when f <= 1/2, else c = x0 + 1, d = f - 1 (a
-// point at exactly one half takes the lower node; both give the same
-// weights).
-template <typename T>
-__device__ __forceinline__ void tsc_axis(int x0, T f, int& lo, T* w) {
-  const bool up = f > (T)0.5;
-  const T d = up ? f - (T)1 : f;
-  lo = x0 + (up ? 1 : 0) - 1;
-  w[0] = (T)0.5 * ((T)0.5 - d) * ((T)0.5 - d);
-  w[1] = (T)0.75 - d * d;
-  w[2] = (T)0.5 * ((T)0.5 + d) * ((T)0.5 + d);
-}
-
+// Plain path, TSC: each point adds to the 27 nodes of its TSC footprint
+// (tsc_axis on each axis) with global atomics.
 template <typename T>
 static __global__ void k_scatter_atomic_tsc(const int32_t* __restrict__ line_start, int64_t k0, int64_t k1,
                                             const int32_t* __restrict__ key, PointSet<T> ps, int N,

@@ -293,7 +293,7 @@ static __global__ void k_gather(const int32_t* __restrict__ perm, const V* __res
 
 // mark the (up to) four lines a point's CIC footprint touches, for the field
 // pair of its field (fp = field / 2)
-static __global__ void k_mark_lines(const int32_t* __restrict__ skey, int64_t n, int N,
+static __global__ void k_mark_lines(const int32_t* __restrict__ skey, int64_t n, int N, int tsc,
                              uint8_t* __restrict__ flags) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
@@ -302,10 +302,12 @@ static __global__ void k_mark_lines(const int32_t* __restrict__ skey, int64_t n,
   const int64_t f = k / NN, l = k % NN;
   const int y0 = (int)(l % N), z0 = (int)(l / N);
   uint8_t* fl = flags + (f >> 1) * NN;
-  for (int c = 0; c < 4; ++c) {
-    const int yy = (y0 + (c & 1)) & (N - 1), zz = (z0 + (c >> 1)) & (N - 1);
-    fl[(int64_t)zz * N + yy] = 1;
-  }
+  // the rows a point's footprint can reach: the corner row and the next
+  // (CIC), one below to two above (TSC, three of those four rows)
+  const int lo = tsc ? -1 : 0, hi = tsc ? 2 : 1;
+  for (int dz = lo; dz <= hi; ++dz)
+    for (int dy = lo; dy <= hi; ++dy)
+      fl[(int64_t)((z0 + dz) & (N - 1)) * N + ((y0 + dy) & (N - 1))] = 1;
 }
 
 // plane flag = any line of the plane non-empty

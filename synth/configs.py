@@ -44,7 +44,7 @@ class Workload:
     qeff_mode: str = "notsq"
     xi_w_const: float = 0.0
     weighted: bool = False
-    assignment: str = "cic"   # mass assignment: "cic" or "tsc" (TSC on the FP64 plain path)
+    assignment: str = "cic"   # mass assignment: "cic" or "tsc"
     seed: int = 1000
     description: str = ""
 

@@ -77,13 +77,20 @@ def test_weighted_bin_parameters_are_validated():
             Plan(o1_edges=par, **base)
 
 
-def test_tsc_assignment_only_on_the_plain_path():
+def test_tsc_assignment_on_both_paths():
     base = dict(L=100.0, N=64, p1_edges=linbins(0.5, 10, 3), p2_edges=[0.0, 1.0],
                 o1_edges=logbins(10, 40, 5), assignment="tsc")
     Plan(precision="fp64", **base).close()
-    with pytest.raises(PgxError) as e:
-        Plan(precision="fp32", **base)
-    assert e.value.code == 4
+    Plan(precision="fp32", **base).close()
+    # an unknown scheme is rejected by the library
+    import ctypes as C
+    from paper_1705_03464_amd._lib import _Params, _edges
+    e = _edges([0.5, 5.0]); o = _edges([10.0, 40.0])
+    dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    prm = _Params(100.0, 64, 1, 0, 1, dp(e), 1, dp(_edges([0.0, 1.0])), 0.0, 0, 1, dp(o), 1, dp(o),
+                  0, 0.0, 0, 0.0, 0.0, 0.0, 0.0, 0.0, 7)
+    h = C.c_void_p()
+    assert load_library().pgx_plan_create(C.byref(prm), C.byref(h)) == 1
 
 
 def bad(**kw):
