@@ -17,7 +17,8 @@
  *
  * Conventions
  *   - Lengths in the caller's unit (Mpc/h).  Line of sight = z axis.
- *   - Grid node (a, b, c) sits at (a, b, c) * L / N; cloud-in-cell assignment.
+ *   - Grid node (a, b, c) sits at (a, b, c) * L / N; cloud-in-cell assignment
+ *     unless the plan asks for TSC.
  *   - Pair (i, j), i < j by catalogue index, has d = x_j - x_i folded once
  *     into [-L/2, L/2); position x_i + d/2 wrapped into [0, L); weight w_i w_j.
  *   - Bins are half-open [e_k, e_{k+1}) and decided on squares against e*e in
@@ -98,9 +99,11 @@ typedef enum { PGX_ASSIGN_CIC = 0, PGX_ASSIGN_TSC = 1 } pgx_assignment;
  *             function": the point spreads over its nearest node and both
  *             neighbours on each axis with weights 3/4 - d^2 and
  *             (1/2 -+ d)^2 / 2, d the offset from that node in cells; ties
- *             at d = 1/2 go to the lower node), on the FP64_PLAIN path only
- *             (ENOTSUP with FP32_BATCHED, whose fused kernels hold the CIC
- *             footprint of four lines and two nodes per line).
+ *             at d = 1/2 go to the lower node).  On FP32_BATCHED plans TSC
+ *             runs with the per-field transforms (forward and adjoint); the
+ *             dual form and the multipoles, whose fused gather holds the CIC
+ *             footprint, refuse TSC plans (ENOTSUP), and the autotuner keeps
+ *             the per-field transforms for them.
  */
 typedef struct {
   double L;
@@ -197,7 +200,7 @@ pgx_status pgx_forward(pgx_plan* plan, const float* w, void* stream, double* wsu
  * Adjoint of pgx_forward: gradient of a scalar loss with respect to the
  * galaxy weights w of the last pgx_forward call.  Hand-written chain rule
  * through the finalisation, the bin sums, the inverse and forward transforms,
- * the cross-power product and the CIC assignment (which becomes a gather at
+ * the cross-power product and the mass assignment (which becomes a gather at
  * the pair midpoints and galaxies); the paper has no gradients, its HOD
  * derivatives are numerical (HOD dependency section).
  *   g_b_pg, g_q_eff, g_xi_pg [F][R], g_xi_gg [R], g_xi_dp [F]: device FP64
