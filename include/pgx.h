@@ -336,6 +336,22 @@ pgx_status pgx_schedule(pgx_plan* plan, int32_t* schedule);
  * so on sparse catalogues it can exceed the per-field transforms' error.
  *   disagreement: host double out.  No device work. */
 pgx_status pgx_dual_check(pgx_plan* plan, double* disagreement);
+/* The dual form's accuracy check of pgx_dual_check taken again on the
+ * weights of the last pgx_forward (unit weights if none), for callers whose
+ * weights have moved since pgx_autotune (an HOD fit): the forward runs once
+ * with the per-field transforms and once in the dual form of the schedule in
+ * use, and their xi are compared as in the autotuner.  The result becomes
+ * what pgx_dual_check reports.
+ *   fallback:     nonzero: when the disagreement exceeds 0.5, switch the plan
+ *                 to the per-field transforms (the batch size and y-pass
+ *                 variants kept, the per-field z-pass variant of the last
+ *                 pgx_autotune, 0 after pgx_set_schedule).
+ *   disagreement: host double out, in units of 1e-5 max(|xi|, 1e-2); -1 when
+ *                 the schedule in use is not the dual form (nothing runs).
+ * Synchronises the stream.  Discards the state of the last pgx_forward (a
+ * pgx_backward must follow a new pgx_forward) and invalidates the launch
+ * graphs.  Errors: ESTATE before pgx_pairs_build; ENOTSUP on FP64 plans. */
+pgx_status pgx_dual_recheck(pgx_plan* plan, void* stream, int32_t fallback, double* disagreement);
 /* Apply a schedule (host int32[5] as above, e.g. one found by an earlier
  * pgx_autotune): batch size in [1, 32] (clamped to the number of field
  * pairs), variants and algorithm 0 or 1, z-pass variant 2 with algorithm 1

@@ -75,6 +75,7 @@ _SIGS = {
     "pgx_multipoles": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "pgx_multipoles_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pgx_set_schedule": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
+    "pgx_dual_recheck": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_double)]),
     "pgx_graph_replays": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "pgx_profile": (C.c_int, [C.c_void_p, C.c_int32]),
     "pgx_profile_read": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_char_p),
@@ -392,6 +393,16 @@ class Plan:
         measured (pgx_dual_check)."""
         d = C.c_double()
         _check(load_library().pgx_dual_check(self._h, C.byref(d)), self._h)
+        return d.value
+
+    def dual_recheck(self, fallback: bool = True, stream=None) -> float:
+        """The dual form's check again on the last forward's weights; with
+        `fallback`, a disagreement above 0.5 switches the plan to the
+        per-field transforms.  -1 when the dual form is not in use
+        (pgx_dual_recheck).  A backward needs a new forward afterwards."""
+        d = C.c_double()
+        _check(load_library().pgx_dual_recheck(self._h, _stream(stream), int(bool(fallback)), C.byref(d)),
+               self._h)
         return d.value
 
     def set_schedule(self, batch: int, ypass_variant: int = 0, yinv_variant: int = 0,

@@ -381,6 +381,14 @@ pgx_status pgx_dual_check(pgx_plan* plan, double* disagreement) {
   return guarded(plan, [&] { *disagreement = plan->eng ? plan->eng->dual_disagreement : -1.0; });
 }
 
+pgx_status pgx_dual_recheck(pgx_plan* plan, void* stream, int32_t fallback, double* disagreement) {
+  if (!plan) return fail(PGX_EINVAL, "plan is NULL");
+  if (!disagreement) return fail(PGX_EINVAL, "disagreement is NULL");
+  return guarded(plan, [&] {
+    *disagreement = plan->engine().recheck_dual((hipStream_t)stream, fallback != 0);
+  });
+}
+
 pgx_status pgx_set_schedule(pgx_plan* plan, void* stream, const int32_t* schedule) {
   if (!plan) return fail(PGX_EINVAL, "plan is NULL");
   if (!schedule) return fail(PGX_EINVAL, "schedule is NULL");

@@ -183,6 +183,7 @@ struct EngineBase {
   virtual void autotune(hipStream_t s, int32_t* out) = 0;
   virtual void schedule_info(int32_t* out) const = 0;
   virtual void set_schedule(const int32_t* in, hipStream_t s) = 0;
+  virtual double recheck_dual(hipStream_t s, bool fallback) = 0;
   virtual void multipoles(hipStream_t s, int lmax, double* xi) = 0;
   virtual void multipoles_backward(hipStream_t s, const double* g, float* grad_w) = 0;
   virtual void projected(hipStream_t s, const double* xi_dp, double* wp, bool adjoint) = 0;
@@ -250,6 +251,9 @@ template <typename T, int N> struct Engine : EngineBase {
   // field pair, 1 = dual form (one transform per pair of output bins, then a
   // gather at the pair midpoints)
   int algo = 0;
+  // z-pass variant of the per-field transforms the autotuner found (the
+  // schedule a failed re-check of the dual form falls back to)
+  int pf_vz = 0;
   DBuf coef_id, bscale, bfa, bfb, GV;  // dual form: bin coefficients 1/norm_b (and their FP32 values), bin-pair slots, gathered values
   DBuf FSC;  // per-field FP32 transform scale 1 / Wsum_f
   // constant tables
@@ -860,6 +864,7 @@ template <typename T, int N> struct Engine : EngineBase {
       v_ypass = best[1];
       v_yinv = best[2];
       v_zpass = best_algo == 1 ? best_vz_dual : best[3];
+      pf_vz = best[3];
       algo = best_algo;
       ++gen;  // recorded launch sequences used the old schedule
       forward_done = false;
@@ -883,6 +888,7 @@ template <typename T, int N> struct Engine : EngineBase {
       v_ypass = in[1];
       v_yinv = in[2];
       v_zpass = in[3];
+      pf_vz = in[4] == 0 ? in[3] : 0;
       algo = in[4];
       ++gen;
       forward_done = false;
@@ -890,6 +896,55 @@ template <typename T, int N> struct Engine : EngineBase {
       if (v_zpass == 2)
         PGX_REQUIRE(ensure_kernel_spectra(s), PGX_ENOSPACE,
                     "the kernel spectra of z-pass variant 2 do not fit in free device memory");
+    }
+  }
+
+  // The dual form's accuracy check again, on the weights of the last
+  // forward (unit weights if none): the per-field transforms and the dual
+  // form in its z-pass variant run the forward body once each, and their xi
+  // are compared bin by bin as in the autotuner.  With `fallback` and a
+  // disagreement above 0.5 the plan switches to the per-field transforms
+  // (batch size and y variants kept, the per-field z variant the autotuner
+  // found).  Returns -1 when the schedule in use is not the dual form.
+  double recheck_dual(hipStream_t s, bool fallback) override {
+    PGX_REQUIRE(built, PGX_ESTATE, "pgx_pairs_build has not been called");
+    if constexpr (!std::is_same<T, float>::value) {
+      throw Error(PGX_ENOTSUP, "the dual form runs on the FP32 batched path");
+    } else {
+      if (algo != 1) return -1.0;
+      float* wl = w_given && n_gal > 0 ? w_last.as<float>() : nullptr;
+      const int F = cfg.F, R = cfg.R, vz_dual = v_zpass;
+      const bool prof_on = prof.on;
+      prof.on = false;
+      algo = 0;
+      v_zpass = pf_vz;
+      weights(wl, s);
+      forward_batched(s, nullptr, wl);
+      double* sref = S_ref.get<double>((int64_t)F * R);
+      PGX_HIP(hipMemcpyAsync(sref, S.as<double>(), (size_t)F * R * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+      algo = 1;
+      v_zpass = vz_dual;
+      ensure_line_major(s);
+      weights(wl, s);
+      forward_batched(s, nullptr, wl);
+      double* r = dis_d.get<double>(1);
+      k_xi_disagreement<<<1, 256, 0, s>>>(sref, S.as<double>(), nbd.as<double>(), wsum_d.as<double>(),
+                                          wg_d.as<double>(), F, R, 1e-5, r);
+      launch_check("xi_disagreement");
+      double dis = -1.0;
+      PGX_HIP(hipMemcpyAsync(&dis, r, sizeof(double), hipMemcpyDeviceToHost, s));
+      PGX_HIP(hipStreamSynchronize(s));
+      prof.on = prof_on;
+      dual_disagreement = dis;
+      if (fallback && !(dis <= 0.5)) {
+        algo = 0;
+        v_zpass = pf_vz;
+      }
+      ++gen;  // recorded launch sequences may hold the other schedule
+      forward_done = false;
+      spectra_valid = false;
+      return dis;
     }
   }
 

@@ -95,9 +95,15 @@ class HodFit:
         return lb + self.lam * lw, lb, lw
 
 
-def fit(hf: HodFit, theta0, steps: int = 50, lr: float = 0.01, callback=None):
+def fit(hf: HodFit, theta0, steps: int = 50, lr: float = 0.01, callback=None, recheck_every: int = 0):
     """Adam on theta (float64) for `steps` steps; returns (theta, history of
-    (total, b term, w term) per step, before each update)."""
+    (total, b term, w term) per step, before each update).
+
+    The autotuner checks the dual form's accuracy on the weights it sees; an
+    HOD fit moves them.  With `recheck_every` = k > 0, after every k-th step's
+    gradient each plan that runs the dual form takes that check again on the
+    step's weights and falls back to the per-field transforms when it fails
+    (Plan.dual_recheck)."""
     theta = torch.tensor(np.asarray(theta0, np.float64), dtype=torch.float64,
                          device=hf.target_b.device, requires_grad=True)
     opt = torch.optim.Adam([theta], lr=lr)
@@ -109,5 +115,9 @@ def fit(hf: HodFit, theta0, steps: int = 50, lr: float = 0.01, callback=None):
         hist.append((float(total), float(lb), float(lw)))
         if callback is not None:
             callback(k, theta.detach().cpu().numpy(), hist[-1])
+        if recheck_every > 0 and (k + 1) % recheck_every == 0:
+            for p in (hf.plan_b, hf.plan_w):
+                if p is not None:
+                    p.dual_recheck(fallback=True)
         opt.step()
     return theta.detach(), hist

@@ -357,6 +357,17 @@ def test_sparse_1024_keeps_per_field_transforms():
             _say(f"  autotuned {sched}, dual-form check {plan.dual_check():.3f}")
             assert sched["algorithm"] == 0
             assert plan.dual_check() > 0.5
+            assert plan.dual_recheck() == -1.0  # per-field schedule: nothing to check
+            # a schedule forced onto the dual form fails the re-check on these
+            # weights and falls back to the per-field transforms
+            plan.set_schedule(2, 0, 0, *ALGOS[2])
+            plan.forward(w)
+            d = plan.dual_recheck(fallback=True)
+            _say(f"  forced dual form: re-check {d:.3f}, schedule now {plan.schedule()}")
+            assert d > 0.5 and plan.dual_check() == d
+            assert plan.schedule()["algorithm"] == 0
+            out = {k: v.cpu().numpy() for k, v in plan.forward(w).items()}
+            assert _worst(out["xi_pg"], ref["xi_pg"], 1e-5) <= 1.0
         plan.close()
     assert worst[0, "xi_gg"] <= 1.0 and worst[0, "xi_pg"] <= 1.0
     for a in (1, 2):
@@ -387,6 +398,12 @@ def test_both_algorithms_meet_fp64_on_production_512():
             sched = plan.autotune()
             _say(f"  cfg1 autotuned {sched}, dual-form check {plan.dual_check():.3f}")
             assert 0.0 <= plan.dual_check() <= 0.5 and sched["algorithm"] == 1
+            # the check again on other weights: it holds, the dual form stays
+            wr = dev(np.random.default_rng(3).uniform(0.5, 1.5, cat.n).astype(np.float32), torch.float32)
+            plan.forward(wr)
+            d = plan.dual_recheck(fallback=True)
+            _say(f"  cfg1 re-check on random weights {d:.3f}")
+            assert 0.0 <= d <= 0.5 and plan.schedule() == sched
         plan.close()
         for k in ("xi_gg", "xi_pg"):
             worst = _worst(out[k], ref[k], 1e-5)

@@ -115,3 +115,23 @@ def test_gradient_descent_fit_reduces_the_loss():
     assert hist[-1][0] <= hist[0][0] / 5.0
     assert l_t[0] <= 1e-3 * hist[0][0]
     assert abs(float(theta[3]) - THT[3]) < abs(TH0[3] - THT[3])
+
+
+def test_fit_on_the_dual_form_rechecks_its_accuracy():
+    """A fit whose plans run the dual form takes the dual form's accuracy
+    check again on the moving weights (recheck_every): after it each plan
+    either still runs the dual form with a check within 0.5 or has fallen
+    back to the per-field transforms with a check above 0.5, and the loss
+    still falls."""
+    from paper_1705_03464_amd import fit_hod
+    wl, wl_rp, cat, hf = setup()
+    for p in (hf.plan_b, hf.plan_w):
+        p.set_schedule(4, 0, 0, 0, 1)
+        assert p.dual_check() == -1.0  # not measured yet
+    theta, hist = fit_hod(hf, TH0, steps=10, lr=0.01, recheck_every=5)
+    for name, p in (("b_pg", hf.plan_b), ("w_p", hf.plan_w)):
+        d, algo = p.dual_check(), p.schedule()["algorithm"]
+        _say(f"  {name} plan: re-check {d:.3f}, algorithm now {algo}")
+        assert d >= 0.0
+        assert (algo == 1 and d <= 0.5) or (algo == 0 and d > 0.5)
+    assert hist[-1][0] < hist[0][0]
