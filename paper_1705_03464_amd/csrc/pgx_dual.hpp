@@ -229,7 +229,7 @@ k_xinv_gather_sweep(PointSet<T> ps, const int32_t* __restrict__ perm, int64_t P,
 }
 
 // S[f][b] = sum over the pairs of field f of (w_i w_j) gv[b][p] (FP64 pair
-// weights from k_pair_wprod), divided by the bin's kernel scale (the FP32
+// weights from k_pair_wts), divided by the bin's kernel scale (the FP32
 // value the kernel generator applied).  Block (f, b, k) of a grid (F, R, K)
 // writes the partial sum of chunk k of the field's range to
 // part[(f R + b) K + k]; k_sum_chunks adds them in order (deterministic).

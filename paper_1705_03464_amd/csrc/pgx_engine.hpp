@@ -626,13 +626,10 @@ template <typename T, int N> struct Engine : EngineBase {
       // weighted pair sum of every field, the numerator of xi(d_p) (the same
       // kernels and order as the forward's)
       double* wp = p_wd.get<double>(std::max<int64_t>(P, 1));
-      if (P > 0) {
-        k_pair_wprod<<<grid_for(P), 256, 0, s>>>(p_i.as<int32_t>(), p_j.as<int32_t>(), w, P, wp);
-        launch_check("pair_wprod");
-      }
       const int K = reduce_chunks(F);
       double* part = ws_part.get<double>((int64_t)F * K);
-      k_field_wsum<<<dim3(F, K), 256, 0, s>>>(p_fs.as<int32_t>(), 1, wp, part);
+      k_pair_wts<T><<<dim3(F, K), 256, 0, s>>>(p_fs.as<int32_t>(), p_i.as<int32_t>(), p_j.as<int32_t>(), w,
+                                               nullptr, wp, part);
       k_sum_chunks<<<grid_for(F), 256, 0, s>>>(part, F, K, wsum);
       launch_check("field_wsum");
     }
@@ -1035,26 +1032,19 @@ template <typename T, int N> struct Engine : EngineBase {
   // ------------------------------------------------------------------------
   void weights(const float* w, hipStream_t s) {
     const int F = cfg.F;
-    if (n_pairs > 0) {
-      k_pair_weights<T><<<grid_for(n_pairs), 256, 0, s>>>(p_i.as<int32_t>(), p_j.as<int32_t>(), w,
-                                                          n_pairs, p_wt.as<T>());
-      launch_check("pair_weights");
-    }
     if (n_gal > 0) {
       k_gather_weights<T><<<grid_for(n_gal), 256, 0, s>>>(g_idx.as<int32_t>(), w, n_gal, g_wt.as<T>());
       launch_check("gal_weights");
     }
     double* wp = p_wd.get<double>(std::max<int64_t>(n_pairs, 1));
-    if (n_pairs > 0) {
-      k_pair_wprod<<<grid_for(n_pairs), 256, 0, s>>>(p_i.as<int32_t>(), p_j.as<int32_t>(), w, n_pairs, wp);
-      launch_check("pair_wprod");
-    }
     {
+      // pair weights (FP64, and in T for the scatters) with their per-field sums
       const int K = reduce_chunks(F);
       double* part = ws_part.get<double>((int64_t)F * K);
-      k_field_wsum<<<dim3(F, K), 256, 0, s>>>(p_fs.as<int32_t>(), 1, wp, part);
+      k_pair_wts<T><<<dim3(F, K), 256, 0, s>>>(p_fs.as<int32_t>(), p_i.as<int32_t>(), p_j.as<int32_t>(), w,
+                                               n_pairs > 0 ? p_wt.as<T>() : nullptr, wp, part);
       k_sum_chunks<<<grid_for(F), 256, 0, s>>>(part, F, K, wsum_d.get<double>(F));
-      launch_check("field_wsum");
+      launch_check("pair_weights");
     }
     k_field_scale<<<grid_for(F), 256, 0, s>>>(wsum_d.as<double>(), F, FSC.get<float>(std::max(F, 1)));
     launch_check("field_scale");

@@ -64,14 +64,6 @@ static __global__ void k_validate_w(const float* __restrict__ w, int64_t n, int*
 // ----------------------------------------------------------------------------
 // pair weight w_i * w_j (exact in FP64 for FP32 weights), rounded to T
 template <typename T>
-static __global__ void k_pair_weights(const int32_t* __restrict__ pi, const int32_t* __restrict__ pj,
-                               const float* __restrict__ w, int64_t n, T* __restrict__ wp) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  wp[p] = w ? (T)((double)w[pi[p]] * (double)w[pj[p]]) : (T)1;
-}
-
-template <typename T>
 static __global__ void k_gather_weights(const int32_t* __restrict__ idx, const float* __restrict__ w,
                                  int64_t n, T* __restrict__ out) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -117,16 +109,25 @@ static __global__ void k_sum_chunks(const double* __restrict__ part, int64_t n, 
   out[i] = a;
 }
 
-// Partial sums of the products w_i w_j in FP64 (k_pair_wprod) over each
-// field's range: block (f, k) of a grid (F, K).
-static __global__ void k_field_wsum(const int32_t* __restrict__ line_start, int64_t nn,
-                                    const double* __restrict__ wp, double* __restrict__ part) {
+// Pair weights w_i w_j (FP64 products, unit without weights; also rounded
+// to T into wt when it is given) and their partial sums over each field's
+// range: block (f, k) of a grid (F, K) takes chunk k of field f.  fs: the
+// field starts of the field-major pair catalogue.
+template <typename T>
+static __global__ void k_pair_wts(const int32_t* __restrict__ fs, const int32_t* __restrict__ pi,
+                                  const int32_t* __restrict__ pj, const float* __restrict__ w,
+                                  T* __restrict__ wt, double* __restrict__ wd, double* __restrict__ part) {
   __shared__ double sh[256];
   const int f = blockIdx.x, k = blockIdx.y, K = gridDim.y;
   int64_t cs, ce;
-  chunk_of(line_start[(int64_t)f * nn], line_start[(int64_t)(f + 1) * nn], k, K, cs, ce);
+  chunk_of(fs[f], fs[f + 1], k, K, cs, ce);
   double acc = 0.0;
-  for (int64_t p = cs + threadIdx.x; p < ce; p += 256) acc += wp[p];
+  for (int64_t p = cs + threadIdx.x; p < ce; p += 256) {
+    const double d = w ? (double)w[pi[p]] * (double)w[pj[p]] : 1.0;
+    wd[p] = d;
+    if (wt) wt[p] = (T)d;
+    acc += d;
+  }
   const double r = block_sum256(acc, sh);
   if (threadIdx.x == 0) part[(int64_t)f * K + k] = r;
 }
@@ -188,14 +189,6 @@ static __global__ void k_weight_total(const double* __restrict__ part, double* _
   const double r = block_sum256(acc, sh);
   if (threadIdx.x == 0) out[0] = r;
 }
-
-// FP64 pair weights w_i w_j (1 without weights), one per pair.
-static __global__ void k_pair_wprod(const int32_t* __restrict__ pi, const int32_t* __restrict__ pj,
-                                    const float* __restrict__ w, int64_t P, double* __restrict__ out) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < P) out[p] = w ? (double)w[pi[p]] * (double)w[pj[p]] : 1.0;
-}
-
 // ----------------------------------------------------------------------------
 // bin partial reduction: part[slot][nblk][2][R] -> S[f][R] for the two fields
 // of each slot (fixed order over blocks, deterministic)
