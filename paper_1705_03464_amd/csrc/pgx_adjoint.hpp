@@ -420,14 +420,19 @@ k_zinit(const C<T>* __restrict__ ky_in, int pwz, const C<T>* __restrict__ fg,
 // Inverse x pass fused with the CIC gather.  One task per non-empty line of a
 // field pair (same task words as the forward scatter).  The line is inverse
 // transformed, kept in LDS, and every point whose CIC footprint reaches the
-// line adds its share to acc[p] (real part for field a, imaginary for b):
-//   acc[p] += scale * wy * wz * ((1 - fx) line[x0] + fx line[x0 + 1]).
+// line takes its share (real part for field a, imaginary for b):
+//   scale * wy * wz * ((1 - fx) line[x0] + fx line[x0 + 1]).
+// With qs > 0 (CIC, every footprint line of every point among the tasks)
+// the share of the line at offset (dy, dz) in {0, 1}^2 from the point's base
+// line is stored to acc[(dy + 2 dz) qs + p]: each entry is written exactly
+// once, no atomics, and the reader sums the four in a fixed order.  With
+// qs = 0 (TSC) the shares are added to acc[p] with atomics.
 // ----------------------------------------------------------------------------
 template <typename T, typename Sh, int W, bool TSC = false>
 static __global__ void __launch_bounds__(W * Sh::TPL)
 k_xgather(const int32_t* __restrict__ tasks, int n_tasks, PointSet<T> ps,
           const int32_t* __restrict__ slot_fa, const int32_t* __restrict__ slot_fb,
-          const C<T>* __restrict__ in, T scale, float* __restrict__ acc,
+          const C<T>* __restrict__ in, T scale, float* __restrict__ acc, int64_t qs,
           const C<T>* __restrict__ tw_g, const float* __restrict__ fscale = nullptr) {
   constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>();
   constexpr int64_t NN = (int64_t)N * N;
@@ -499,7 +504,11 @@ k_xgather(const int32_t* __restrict__ tasks, int n_tasks, PointSet<T> ps,
           } else {
             const T wy = (q & 1) ? fy : (T)1 - fy;
             const T wz = (q & 2) ? fz : (T)1 - fz;
-            atomicAdd(&acc[p], (float)(sc * wy * wz * (((T)1 - fx) * val(x0) + fx * val(x0 + 1))));
+            const float g = (float)(sc * wy * wz * (((T)1 - fx) * val(x0) + fx * val(x0 + 1)));
+            if (qs > 0)
+              acc[q * qs + p] = g;
+            else
+              atomicAdd(&acc[p], g);
           }
         }
       }
@@ -507,15 +516,23 @@ k_xgather(const int32_t* __restrict__ tasks, int n_tasks, PointSet<T> ps,
   }
 }
 
-// grad[i] += w_j (acc[p] + gws[f]), grad[j] += w_i (...) for every pair
+// Sum of the nc components acc[c cs + p] (the gather's per-line shares, or
+// one value), in FP64 and in component order.
+__device__ __forceinline__ double acc_sum(const float* __restrict__ acc, int nc, int64_t cs, int64_t p) {
+  double a = (double)acc[p];
+  for (int c = 1; c < nc; ++c) a += (double)acc[c * cs + p];
+  return a;
+}
+
 // Pair terms of the weight gradient: grad[i] += w_j g_p, grad[j] += w_i g_p
-// with g_p = acc[p] + dL/dWsum_f.  Within a (field, line) the pairs keep the
-// order of the pair search, which emits each galaxy's pairs together, so
-// runs of one galaxy in adjacent lanes are summed across the wavefront
-// first and only the last lane of each run adds to the galaxy's entry.
+// with g_p = acc[p] + dL/dWsum_f (acc of nc components, stride cs).  Within a
+// (field, line) the pairs keep the order of the pair search, which emits each
+// galaxy's pairs together, so runs of one galaxy in adjacent lanes are
+// summed across the wavefront first and only the last lane of each run adds
+// to the galaxy's entry.
 static __global__ void k_pair_grad(const int32_t* __restrict__ pkey, const int32_t* __restrict__ pi,
                                    const int32_t* __restrict__ pj, const float* __restrict__ acc,
-                                   int64_t n, int64_t nn, const double* __restrict__ gws,
+                                   int nc, int64_t cs, int64_t n, int64_t nn, const double* __restrict__ gws,
                                    const float* __restrict__ w, double* __restrict__ grad) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool act = p < n;  // every lane of the wavefront takes part in the run sums
@@ -524,7 +541,7 @@ static __global__ void k_pair_grad(const int32_t* __restrict__ pkey, const int32
   double gi = 0.0, gj = 0.0;
   if (act) {
     const int f = (int)(pkey[p] / nn);
-    const double gval = (double)acc[p] + gws[f];
+    const double gval = acc_sum(acc, nc, cs, p) + gws[f];
     i = pi[p];
     j = pj[p];
     const double wi = w ? (double)w[i] : 1.0, wj = w ? (double)w[j] : 1.0;
@@ -541,13 +558,14 @@ static __global__ void k_pair_grad(const int32_t* __restrict__ pkey, const int32
   if (act && rj.tail) atomicAdd(&grad[j], sj);
 }
 
-// galaxy term: grad[idx[p]] += acc[p] + gwg (each galaxy appears once)
-static __global__ void k_gal_grad(const int32_t* __restrict__ idx, const float* __restrict__ acc,
-                                  int64_t n, const double* __restrict__ gwg,
+// galaxy term: grad[idx[p]] += acc[p] + gwg (each galaxy appears once; acc
+// of nc components, stride cs)
+static __global__ void k_gal_grad(const int32_t* __restrict__ idx, const float* __restrict__ acc, int nc,
+                                  int64_t cs, int64_t n, const double* __restrict__ gwg,
                                   double* __restrict__ grad) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
-  grad[idx[p]] += (double)acc[p] + gwg[0];
+  grad[idx[p]] += acc_sum(acc, nc, cs, p) + gwg[0];
 }
 
 static __global__ void k_grad_out(const double* __restrict__ g, int64_t n, float* __restrict__ out) {

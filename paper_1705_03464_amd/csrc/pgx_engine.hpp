@@ -266,6 +266,7 @@ template <typename T, int N> struct Engine : EngineBase {
   // the (field, line) starts that only the per-field transforms read (built
   // with their task lists)
   DBuf p_key, p_ls, p_fs, p_i, p_j, p_x0, p_fx, p_fy, p_fz, p_wt;
+  DBuf tasks_s, t_key, t_key2;  // the scatter's task order (most crowded line first) and its sort keys
   DBuf p_wd, wg_part;  // FP64 pair weights of the current forward; partial weight sums
   DBuf ws_part, red_part, mp_part;  // partial sums of the chunked segmented reductions
   // line-major copy of the pair catalogue (all fields together): line starts,
@@ -328,14 +329,15 @@ template <typename T, int N> struct Engine : EngineBase {
     double b = 0.0;
     // galaxies: positions kept for the multipoles, cell-list scratch, point
     // records, weights and gradients
-    b += nd * (24.0 + 24.0 + 16.0 + 16.0 + 12.0 + 4.0 * tb + 4.0 + 3.0 * tb + 4.0 + 4.0 + 8.0 + 4.0);
+    b += nd * (24.0 + 24.0 + 16.0 + 16.0 + 12.0 + 4.0 * tb + 4.0 + 3.0 * tb + 4.0 + 4.0 + 8.0 + 16.0);
     // pairs: build scratch (six int32 arrays over max(n, P)), radix-sort
     // temporaries, field-major records, FP64 weights, line-major copy, gradient
     b += std::max(nd, pd) * 24.0 + (std::max(nd, pd) * 8.0 + (32 << 20));
-    b += pd * (16.0 + 4.0 * tb + 8.0 + 12.0 + 4.0 * tb + 4.0);
+    b += pd * (16.0 + 4.0 * tb + 8.0 + 12.0 + 4.0 * tb + 16.0);
     // per-(field, line) starts, counting table, line flags, task positions
     const double fl = F * NN + 1.0, pl = nfp * NN + 1.0;
-    b += fl * 4.0 + (std::max({ncell, fl, (double)NN}) + 1.0) * 8.0 + pl * (1.0 + 4.0 + 4.0) + nfp * N +
+    // (and the task order's keys, sorted copies and sort temporaries)
+    b += fl * 4.0 + (std::max({ncell, fl, (double)NN}) + 1.0) * 8.0 + pl * (1.0 + 4.0 + 4.0 + 24.0) + nfp * N +
          2.0 * (NN + 1.0) * 4.0;
     const double tiny = 16.0 * F * R * 8.0 + 4.0 * (F + R) * 8.0 + ((size_t)8 << 20);
     if (c.precision == PGX_FP64_PLAIN) {
@@ -648,7 +650,7 @@ template <typename T, int N> struct Engine : EngineBase {
     if (tasks_ready) fpr.insert(fpr.end(), batch_task_off.begin(), batch_task_off.end());
     fpr.insert(fpr.end(), field_counts_h.begin(), field_counts_h.end());
     for (const DBuf* d : {&g_key, &g_ls, &g_x0, &g_fx, &g_fy, &g_fz, &g_idx, &g_wt, &g_tasks, &p_key,
-                          &p_ls, &p_fs, &p_i, &p_j, &p_x0, &p_fx, &p_fy, &p_fz, &p_wt, &lflag, &pflag, &tasks, &l_ls, &l_x0, &l_fx,
+                          &p_ls, &p_fs, &p_i, &p_j, &p_x0, &p_fx, &p_fy, &p_fz, &p_wt, &lflag, &pflag, &tasks, &tasks_s, &l_ls, &l_x0, &l_fx,
                           &l_fy, &l_fz, &l_f, &l_p, &l_wt})
       fpr.push_back((int64_t)(intptr_t)d->p);
     if (fpr != build_print) {
@@ -972,9 +974,30 @@ template <typename T, int N> struct Engine : EngineBase {
     }
     PGX_HIP(hipStreamSynchronize(s));
     batch_task_off.assign(hpos.begin(), hpos.end());
-    int32_t* tk = tasks.get<int32_t>(std::max<int64_t>(hpos[n_batches], 1));
+    const int64_t ntk = std::max<int64_t>(hpos[n_batches], 1);
+    int32_t* tk = tasks.get<int32_t>(ntk);
     k_emit_tasks<<<grid_for(nfl), 256, 0, s>>>(lf, pos, nfl, N, B, tk);
     launch_check("emit_tasks");
+    // the copy in run order: within each batch most crowded line first
+    // (stable, so equal counts keep line order), so that a clustered
+    // catalogue's few crowded lines start early instead of trailing the
+    // launch and the lines sharing a block have similar point counts.  The
+    // TSC gather keeps line order: its global atomics on the per-pair values
+    // contend less when the lines that share a point run at different times.
+    int32_t* tks = tasks_s.get<int32_t>(ntk);
+    PGX_HIP(hipMemcpyAsync(tks, tk, (size_t)ntk * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    if (hpos[n_batches] > 0) {
+      int32_t* key = t_key.get<int32_t>(ntk);
+      int32_t* key2 = t_key2.get<int32_t>(ntk);
+      k_task_cost<<<grid_for(nfl), 256, 0, s>>>(lf, pos, nfl, N, cfg.F, cfg.assignment == 1 ? 4 : 2,
+                                                p_ls.as<int32_t>(), key);
+      launch_check("task_cost");
+      for (int k = 0; k < n_batches; ++k) {
+        const int64_t t0 = hpos[k], nt = hpos[k + 1] - t0;
+        if (nt < 2) continue;
+        sort_pairs_i32(key + t0, key2 + t0, tk + t0, tks + t0, nt, kTaskKeyBits, s, s_tmp);
+      }
+    }
     tasks_ready = true;
   }
 
@@ -1063,13 +1086,15 @@ template <typename T, int N> struct Engine : EngineBase {
     else
       k_xscatter<T, Sh, WX><<<grid, NTX, 0, s>>>(tk, nt, ps, fa, fb, out, twp, fsc);
   }
+  // (CIC: the four per-line shares of each point to acc[q qs + p], written
+  // once each; TSC: added to acc[p] with atomics)
   void xgather(int grid, const int32_t* tk, int nt, const PointSet<T>& ps, const int32_t* fa,
-               const int32_t* fb, const C<T>* in, T scale, float* acc, const C<T>* twp,
+               const int32_t* fb, const C<T>* in, T scale, float* acc, int64_t qs, const C<T>* twp,
                const float* fsc, hipStream_t s) {
     if (cfg.assignment == 1)
-      k_xgather<T, Sh, WX, true><<<grid, NTX, 0, s>>>(tk, nt, ps, fa, fb, in, scale, acc, twp, fsc);
+      k_xgather<T, Sh, WX, true><<<grid, NTX, 0, s>>>(tk, nt, ps, fa, fb, in, scale, acc, 0, twp, fsc);
     else
-      k_xgather<T, Sh, WX><<<grid, NTX, 0, s>>>(tk, nt, ps, fa, fb, in, scale, acc, twp, fsc);
+      k_xgather<T, Sh, WX><<<grid, NTX, 0, s>>>(tk, nt, ps, fa, fb, in, scale, acc, qs, twp, fsc);
   }
 
   PointSet<T> gal_set() const {
@@ -1237,8 +1262,11 @@ template <typename T, int N> struct Engine : EngineBase {
     C<T>* x = X.get<C<T>>((int64_t)B * NC);
     C<T>* A = Aacc.get<C<T>>(NC);
     const C<T>* fg = Fg.as<C<T>>();
-    float* gb = gbuf.get<float>(std::max<int64_t>(n_pairs, 1));
-    float* gbg = gbuf_g.get<float>(std::max<int64_t>(n_gal, 1));
+    // pair-side values: the dual form writes one per pair; the per-field
+    // gather (CIC) writes one share per footprint line, summed by the reader
+    const int gcomp = !fwd_dual && cfg.assignment == 0 ? 4 : 1;
+    const int64_t gstride = std::max<int64_t>(n_pairs, 1);
+    float* gb = gbuf.get<float>(gcomp * gstride);
     double* gd = grad_d.get<double>(std::max<int64_t>(n_gal, 1));
     AdjointArgs aa;
     aa.F = F;
@@ -1263,8 +1291,8 @@ template <typename T, int N> struct Engine : EngineBase {
     aa.gwg = gwg.get<double>(1);
     k_finalize_adjoint<<<1, 256, 0, s>>>(aa);
     launch_check("finalize_adjoint");
-    k_fill_value<float><<<grid_for(std::max<int64_t>(n_pairs, 1)), 256, 0, s>>>(gb, std::max<int64_t>(n_pairs, 1), 0.f);
-    k_fill_value<float><<<grid_for(std::max<int64_t>(n_gal, 1)), 256, 0, s>>>(gbg, std::max<int64_t>(n_gal, 1), 0.f);
+    if (gcomp == 1)
+      k_fill_value<float><<<grid_for(gstride), 256, 0, s>>>(gb, gstride, 0.f);
     k_fill_value<double><<<grid_for(std::max<int64_t>(n_gal, 1)), 256, 0, s>>>(gd, std::max<int64_t>(n_gal, 1), 0.0);
     launch_check("fill");
     // galaxy kernel field -> A = K^_g G (on the kernel-spectrum path of the
@@ -1322,7 +1350,7 @@ template <typename T, int N> struct Engine : EngineBase {
         } else {
           if (nt > 0) {
             prof.run("bwd_xscatter", s, pts + (double)nt * N * cb, [&] {
-              xscatter((int)((nt + WX - 1) / WX), tasks.as<int32_t>() + t0, (int)nt, pair_set(), fa, fb,
+              xscatter((int)((nt + WX - 1) / WX), tasks_s.as<int32_t>() + t0, (int)nt, pair_set(), fa, fb,
                        x, twp, FSC.as<float>(), s);
               launch_check("xscatter(bwd)");
             });
@@ -1344,24 +1372,35 @@ template <typename T, int N> struct Engine : EngineBase {
           launch_check("yinv(bwd)");
         });
         if (nt > 0) {
-          prof.run("bwd_xgather", s, pts + (double)nt * N * cb, [&] {
-            xgather((int)((nt + WX - 1) / WX), tasks.as<int32_t>() + t0, (int)nt, pair_set(), fa, fb, x,
-                    (T)1, gb, twp, FSC.as<float>(), s);
+          // point records (x0, fractions) read, the per-line shares written
+          const double gpts = (double)batch_points(k) * (4.0 + 3.0 * sizeof(T) + 4.0 * gcomp);
+          prof.run("bwd_xgather", s, gpts + (double)nt * N * cb, [&] {
+            xgather((int)((nt + WX - 1) / WX), (gcomp == 4 ? tasks_s : tasks).as<int32_t>() + t0, (int)nt,
+                    pair_set(), fa, fb, x, (T)1, gb, gstride, twp, FSC.as<float>(), s);
             launch_check("xgather");
           });
         }
       }
     }
-    galaxy_adjoint_tail(s, A, gb, gbg, gd, aa.gws, aa.gwg, grad_w, twp);
+    galaxy_adjoint_tail(s, A, gb, gcomp, gd, aa.gws, aa.gwg, grad_w, twp);
   }
 
   // Galaxy side and weight chain of the adjoint, after A holds the spectral
   // accumulation: dL/drho_g = 2 Re IDFT(A) with A(0) removed, gathered at the
   // galaxies; then the per-galaxy gradient from the pair terms (gb, pair
   // weights w_i w_j, dL/dWsum_f) and the galaxy terms (dL/dW_g).
-  void galaxy_adjoint_tail(hipStream_t s, C<T>* A, const float* gb, float* gbg, double* gd,
+  // gb: the pair-side values, gcomp components of stride max(n_pairs, 1).
+  void galaxy_adjoint_tail(hipStream_t s, C<T>* A, const float* gb, int gcomp, double* gd,
                            const double* gws_d, const double* gwg_d, float* grad_w, const C<T>* twp) {
     const double cb = (double)sizeof(C<T>);
+    // galaxy-side values: one share per footprint line (CIC), or one sum (TSC)
+    const int ggcomp = cfg.assignment == 0 ? 4 : 1;
+    const int64_t ggstride = std::max<int64_t>(n_gal, 1);
+    float* gbg = gbuf_g.get<float>(ggcomp * ggstride);
+    if (ggcomp == 1) {
+      k_fill_value<float><<<grid_for(ggstride), 256, 0, s>>>(gbg, ggstride, 0.f);
+      launch_check("fill");
+    }
     // galaxy side: dL/drho_g = 2 Re IDFT(A) with A(0) removed
     k_zero_dc<T><<<1, 64, 0, s>>>(A);
     prof.run("bwd_gal_zinv", s, 2.0 * NC * cb, [&] {
@@ -1376,17 +1415,18 @@ template <typename T, int N> struct Engine : EngineBase {
     });
     prof.run("bwd_gal_xgather", s, (double)NC * cb + (double)n_gal * (4 + 4 * sizeof(T)), [&] {
       xgather((int)(NN / WX), g_tasks.as<int32_t>(), (int)NN, gal_set(), gslot_fa.as<int32_t>(),
-              gslot_fb.as<int32_t>(), A, (T)2, gbg, twp, nullptr, s);
+              gslot_fb.as<int32_t>(), A, (T)2, gbg, ggstride, twp, nullptr, s);
       launch_check("gal_xgather");
     });
     const float* wl = w_given ? w_last.as<float>() : nullptr;
     if (n_pairs > 0) {
       k_pair_grad<<<grid_for(n_pairs), 256, 0, s>>>(p_key.as<int32_t>(), p_i.as<int32_t>(),
-                                                    p_j.as<int32_t>(), gb, n_pairs, NN, gws_d, wl, gd);
+                                                    p_j.as<int32_t>(), gb, gcomp, std::max<int64_t>(n_pairs, 1),
+                                                    n_pairs, NN, gws_d, wl, gd);
       launch_check("pair_grad");
     }
     if (n_gal > 0) {
-      k_gal_grad<<<grid_for(n_gal), 256, 0, s>>>(g_idx.as<int32_t>(), gbg, n_gal, gwg_d, gd);
+      k_gal_grad<<<grid_for(n_gal), 256, 0, s>>>(g_idx.as<int32_t>(), gbg, ggcomp, ggstride, n_gal, gwg_d, gd);
       k_grad_out<<<grid_for(n_gal), 256, 0, s>>>(gd, n_gal, grad_w);
       launch_check("grad_out");
     }
@@ -1641,7 +1681,6 @@ template <typename T, int N> struct Engine : EngineBase {
       C<T>* A = Aacc.get<C<T>>(NC);
       C<T>* x = X.get<C<T>>((int64_t)B * NC);
       float* gb = gbuf.get<float>(std::max<int64_t>(P, 1));
-      float* gbg = gbuf_g.get<float>(std::max<int64_t>(n_gal, 1));
       double* gd = grad_d.get<double>(std::max<int64_t>(n_gal, 1));
       double* a = MPA.get<double>((int64_t)F * R * nl);
       double* gws_d = gws.get<double>(F);
@@ -1650,7 +1689,6 @@ template <typename T, int N> struct Engine : EngineBase {
                                                wg_d.as<double>(), F, R, nl, a, gws_d, gwg_d);
       launch_check("finalize_adjoint(multipoles)");
       k_fill_value<float><<<grid_for(std::max<int64_t>(P, 1)), 256, 0, s>>>(gb, std::max<int64_t>(P, 1), 0.f);
-      k_fill_value<float><<<grid_for(std::max<int64_t>(n_gal, 1)), 256, 0, s>>>(gbg, std::max<int64_t>(n_gal, 1), 0.f);
       k_fill_value<double><<<grid_for(std::max<int64_t>(n_gal, 1)), 256, 0, s>>>(gd, std::max<int64_t>(n_gal, 1), 0.0);
       // A = 0 (the multipoles have no galaxy auto-correlation term)
       k_fill_value<T><<<std::min(grid_for(2 * NC), 65536), 256, 0, s>>>(reinterpret_cast<T*>(A), 2 * NC, (T)0);
@@ -1691,7 +1729,7 @@ template <typename T, int N> struct Engine : EngineBase {
           launch_check("zacc(multipoles adjoint)");
         }
       }
-      galaxy_adjoint_tail(s, A, gb, gbg, gd, gws_d, gwg_d, grad_w, twp);
+      galaxy_adjoint_tail(s, A, gb, 1, gd, gws_d, gwg_d, grad_w, twp);
     }
   }
 
@@ -1860,7 +1898,7 @@ template <typename T, int N> struct Engine : EngineBase {
       const double pts = (double)batch_points(k) * (4 + 4 * sizeof(T));
       if (nt > 0) {
         prof.run("xscatter", s, pts + (double)nt * N * cb, [&] {
-          xscatter((int)((nt + WX - 1) / WX), tasks.as<int32_t>() + t0, (int)nt, pair_set(), fa, fb, x,
+          xscatter((int)((nt + WX - 1) / WX), tasks_s.as<int32_t>() + t0, (int)nt, pair_set(), fa, fb, x,
                    twp, FSC.as<float>(), s);
           launch_check("xscatter");
         });

@@ -322,6 +322,9 @@ static __global__ void k_plane_flags(const uint8_t* __restrict__ flags, int N, i
 }
 
 // task words for the x pass: slot * N^2 + line, slot = fp % batch
+constexpr int kTaskKeyBits = 30;
+constexpr int32_t kTaskKeyMax = (1 << kTaskKeyBits) - 1;
+
 static __global__ void k_emit_tasks(const uint8_t* __restrict__ flags, const int32_t* __restrict__ pos,
                              int64_t total, int N, int batch, int32_t* __restrict__ tasks) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -329,6 +332,33 @@ static __global__ void k_emit_tasks(const uint8_t* __restrict__ flags, const int
   const int64_t NN = (int64_t)N * N;
   const int64_t fp = i / NN, l = i % NN;
   tasks[pos[i]] = (int32_t)((fp % batch) * NN + l);
+}
+
+// Sort key of each x-pass task: the number of points whose footprint reaches
+// its line (both fields 2 fp, 2 fp + 1 of its field pair, from the field-major
+// line starts), inverted so that an ascending sort puts the most crowded
+// lines first.  rows = 2 (CIC: base lines y - 1 .. y by z - 1 .. z) or 4
+// (TSC: y - 2 .. y + 1 by z - 2 .. z + 1).  key[pos[i]] for every flagged i.
+static __global__ void k_task_cost(const uint8_t* __restrict__ flags, const int32_t* __restrict__ pos,
+                                   int64_t total, int N, int F, int rows,
+                                   const int32_t* __restrict__ line_start, int32_t* __restrict__ key) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total || !flags[i]) return;
+  const int64_t NN = (int64_t)N * N;
+  const int64_t fp = i / NN, l = i % NN;
+  const int y = (int)(l % N), z = (int)(l / N);
+  const int lo = rows == 4 ? -2 : -1;
+  int64_t c = 0;
+  for (int part = 0; part < 2; ++part) {
+    const int64_t f = 2 * fp + part;
+    if (f >= F) continue;
+    for (int dz = 0; dz < rows; ++dz)
+      for (int dy = 0; dy < rows; ++dy) {
+        const int64_t k = f * NN + (int64_t)((z + lo + dz) & (N - 1)) * N + ((y + lo + dy) & (N - 1));
+        c += line_start[k + 1] - line_start[k];
+      }
+  }
+  key[pos[i]] = kTaskKeyMax - (int32_t)(c < kTaskKeyMax ? c : kTaskKeyMax);
 }
 
 static __global__ void k_iota(int32_t* __restrict__ a, int64_t n) {
