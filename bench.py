@@ -315,7 +315,8 @@ def measure(wl, a, steps, warmup, with_extras):
                  f"{by / max(n, 1) / 1e9:8.3f} GB/launch  {by / (ms * 1e-3) / 1e9 if ms > 0 else 0:8.1f} GB/s"
                  f"  share {ms / (ms_prof * steps):.3f}")
     step_bytes = sum(p[3] for p in prof) / steps
-    step_hbm_frac = step_bytes / (ms_prof * 1e-3) / (HBM_PEAK_GBS * 1e9)
+    # against the timed step (the launch-graph replays the value is quoted on)
+    step_hbm_frac = step_bytes / (ms_step * 1e-3) / (HBM_PEAK_GBS * 1e9)
     dom = max(prof, key=lambda p: p[2])
     name, n, ms, by = dom
     achieved = (by / n) / (ms / n * 1e-3) / 1e9

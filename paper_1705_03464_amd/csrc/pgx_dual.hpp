@@ -843,14 +843,26 @@ k_zdual_acc_ks(const C<T>* __restrict__ x, int64_t x_slot, int n_slots,
       }
     }
   };
-  auto load_k = [&](int slot, C<T>* k) {
+  // kernel values of elements m0 .. m0 + M - 1 of this thread's column.
+  // Elements m < E/2 have kz < N/2 (stored row kz), the others kz >= N/2
+  // (mirrored row N - kz); each half is one per-lane base offset plus a
+  // scalar offset per element, so no per-element address stays live
+  constexpr uint32_t KS = (uint32_t)((H + 1) * N);
+  const uint32_t kb0 = (uint32_t)(((int64_t)t * KS + (int64_t)kyr * N + xx) * CB);
+  const uint32_t kb1 = (uint32_t)(((int64_t)(TPL - t) * KS + (int64_t)kyr * N + xx) * CB);
+  auto load_k = [&](int slot, int m0, auto& k) {
+    constexpr int M = sizeof(k) / sizeof(k[0]);
     if constexpr (BUFK) {
       const Buf<T> bk(ks + slot * ks_slot);
 #pragma unroll
-      for (int m = 0; m < E; ++m) k[m] = bk.load((uint32_t)(ks_index<N>(t + TPL * m, kyr, xx) * CB), 0u);
+      for (int m = 0; m < M; ++m) {
+        const int mm = m0 + m;
+        k[m] = 2 * mm < E ? bk.load(kb0, (uint32_t)mm * TPL * KS * CB)
+                          : bk.load(kb1, (uint32_t)(E - 1 - mm) * TPL * KS * CB);
+      }
     } else {
 #pragma unroll
-      for (int m = 0; m < E; ++m) k[m] = ks[slot * ks_slot + ks_index<N>(t + TPL * m, kyr, xx)];
+      for (int m = 0; m < M; ++m) k[m] = ks[slot * ks_slot + ks_index<N>(t + TPL * (m0 + m), kyr, xx)];
     }
   };
   C<T> acc[E];
@@ -861,23 +873,32 @@ k_zdual_acc_ks(const C<T>* __restrict__ x, int64_t x_slot, int n_slots,
     if constexpr (LEAN) kg[m] = (T)0;
     else kgs[c][t + TPL * m] = (T)0;
   }
+  // lean shapes take the kernel values in two halves, so that at most half
+  // of them are live beside the transformed column and the accumulators
+  constexpr int EH = LEAN && E % 2 == 0 ? E / 2 : E;
   for (int slot = 0; slot < n_slots; ++slot) {
-    C<T> v[E], k[E];
+    C<T> v[E];
     load_pi(slot, true, v);
     block_sync();
     twa.template fft<-1>(v, t, lines[c]);
     // the kernel values are loaded after the transform, so that they are not
     // held in registers during it
-    load_k(slot, k);
     const float2 q = gc[slot];
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const C<T> pk = cmulc(v[m], k[m]);
-      acc[m].x += (T)0.5 * pk.x;
-      acc[m].y += (T)0.5 * pk.y;
-      const T kv = (T)q.x * k[m].x + (T)q.y * k[m].y;
-      if constexpr (LEAN) kg[m] += kv;
-      else kgs[c][t + TPL * m] += kv;
+    for (int h = 0; h < E; h += EH) {
+      C<T> k[EH];
+      load_k(slot, h, k);
+#pragma unroll
+      for (int mm = 0; mm < EH; ++mm) {
+        const int m = h + mm;
+        const C<T> pk = cmulc(v[m], k[mm]);
+        acc[m].x += (T)0.5 * pk.x;
+        acc[m].y += (T)0.5 * pk.y;
+        const T kv = (T)q.x * k[mm].x + (T)q.y * k[mm].y;
+        if constexpr (LEAN) kg[m] += kv;
+        else kgs[c][t + TPL * m] += kv;
+      }
+      if constexpr (EH < E) __builtin_amdgcn_sched_barrier(0);
     }
   }
 #pragma unroll
