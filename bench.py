@@ -260,8 +260,12 @@ def measure(wl, a, steps, warmup, with_extras):
         P0, _ = plan.pairs_build(x, y, z)
         plan.keep_spectra(a.mode == "fwdbwd")
         nb = plan.workspace_bytes(cat.n, P0)
-        plan.set_workspace(nb)
-        workspace = {"bytes": nb}
+        # the bound counts the optional stores (kept spectra, kernel stores),
+        # which the plan makes only when they fit: cap it at what the device has
+        free = torch.cuda.mem_get_info()[0]
+        cap = int(free * 0.92)
+        workspace = {"bytes": min(nb, cap), "bound": nb}
+        plan.set_workspace(min(nb, cap))
     schedule = plan.schedule() if a.no_autotune else None
     if not a.no_autotune:
         plan.pairs_build(x, y, z)
