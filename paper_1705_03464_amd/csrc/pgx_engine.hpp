@@ -767,25 +767,33 @@ template <typename T, int N> struct Engine : EngineBase {
       int best[4] = {b0, 0, 0, 0};
       algo = 0;  // the per-field trials, whatever the schedule in use
       for (int b : cands) {
-        schedule(b, s);
         double t[2][3] = {{0, 0, 0}, {0, 0, 0}}, other = 0;
-        for (int v = 0; v < 2; ++v) {
-          v_ypass = v_yinv = v_zpass = v;
-          prof.reset();
-          prof.on = false;
-          weights(wl, s);
-          forward_batched(s, nullptr, wl);
-          prof.on = true;
-          weights(wl, s);
-          forward_batched(s, nullptr, wl);
-          prof.collect();
-          prof.on = false;
-          for (const auto& c : prof.cats) {
-            if (c.name == "ypass") t[v][0] = c.ms;
-            else if (c.name == "yinv") t[v][1] = c.ms;
-            else if (c.name == "zpass_cross") t[v][2] = c.ms;
-            else if (v == 0) other += c.ms;
+        try {
+          schedule(b, s);
+          for (int v = 0; v < 2; ++v) {
+            v_ypass = v_yinv = v_zpass = v;
+            prof.reset();
+            prof.on = false;
+            weights(wl, s);
+            forward_batched(s, nullptr, wl);
+            prof.on = true;
+            weights(wl, s);
+            forward_batched(s, nullptr, wl);
+            prof.collect();
+            prof.on = false;
+            for (const auto& c : prof.cats) {
+              if (c.name == "ypass") t[v][0] = c.ms;
+              else if (c.name == "yinv") t[v][1] = c.ms;
+              else if (c.name == "zpass_cross") t[v][2] = c.ms;
+              else if (v == 0) other += c.ms;
+            }
           }
+        } catch (const Error& e) {
+          // a larger batch whose slots do not fit in the free runs of a
+          // caller's workspace (its free total can exceed the largest run)
+          prof.on = false;
+          if (e.code != PGX_ENOSPACE || b == b0) throw;
+          continue;
         }
         const int vy = t[1][0] < t[0][0], vi = t[1][1] < t[0][1], vz = t[1][2] < t[0][2];
         const double ms = other + t[vy][0] + t[vi][1] + t[vz][2];
