@@ -35,6 +35,11 @@
  *   - Every call returns a pgx_status; no exception or abort crosses the ABI.
  *     On a non-OK status pgx_last_error(plan) describes the failure.
  *   - A plan is not thread-safe: use one plan per host thread and stream.
+ *   - Fault injection, for tests of the error paths: while the environment
+ *     variable PGX_DEBUG_FAIL_ALLOC holds n >= 1, the n-th allocation from the
+ *     HIP allocator (counted from when the variable took that value) fails as
+ *     an out-of-memory error would: calls needing that buffer return
+ *     PGX_EHIP, optional stores are skipped.  The plan stays usable.
  */
 #ifndef PGX_H
 #define PGX_H

@@ -182,7 +182,7 @@ k_kgen_x(const double* __restrict__ coef, int R, const int32_t* __restrict__ slo
     }
   }
   block_sync();
-  line_fft<Sh, -1>(v, t, lines[l], tw_s, block_sync);
+  line_fft<Sh, -1>(v, t, lines[l], tw_s, wave_sync);
   if (active) {
     C<T>* o = out + slot * out_slot + (int64_t)task * N;
 #pragma unroll
@@ -456,7 +456,7 @@ k_xgather(const int32_t* __restrict__ tasks, int n_tasks, PointSet<T> ps,
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = active ? src[t + TPL * m] : C<T>{0, 0};
   block_sync();
-  line_fft<Sh, 1>(v, t, line, tw_s, block_sync);
+  line_fft<Sh, 1>(v, t, line, tw_s, wave_sync);
   block_sync();
 #pragma unroll
   for (int m = 0; m < E; ++m) line[lpad(t + TPL * m)] = v[m];

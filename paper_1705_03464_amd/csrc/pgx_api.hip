@@ -286,19 +286,19 @@ pgx_status pgx_plan_info(const pgx_plan* plan, int32_t* n_fields, int32_t* n_out
 }
 
 pgx_status pgx_out_counts(const pgx_plan* plan, int64_t* n_b) {
-  if (!plan || !n_b) return fail(PGX_EINVAL, "NULL argument");
+  if (!plan || !n_b) return fail(plan, PGX_EINVAL, "NULL argument");
   for (int b = 0; b < plan->cfg.R; ++b) n_b[b] = plan->cfg.nb[b];
   return PGX_OK;
 }
 
 pgx_status pgx_out_norms(const pgx_plan* plan, double* norm) {
-  if (!plan || !norm) return fail(PGX_EINVAL, "NULL argument");
+  if (!plan || !norm) return fail(plan, PGX_EINVAL, "NULL argument");
   for (int b = 0; b < plan->cfg.R; ++b) norm[b] = plan->cfg.nbw[b];
   return PGX_OK;
 }
 
 pgx_status pgx_field_volumes(const pgx_plan* plan, double* vol) {
-  if (!plan || !vol) return fail(PGX_EINVAL, "NULL argument");
+  if (!plan || !vol) return fail(plan, PGX_EINVAL, "NULL argument");
   for (int f = 0; f < plan->cfg.F; ++f) vol[f] = plan->cfg.vol[f];
   return PGX_OK;
 }
@@ -371,19 +371,19 @@ pgx_status pgx_autotune(pgx_plan* plan, void* stream, int32_t* schedule) {
 
 pgx_status pgx_schedule(pgx_plan* plan, int32_t* schedule) {
   if (!plan) return fail(PGX_EINVAL, "plan is NULL");
-  if (!schedule) return fail(PGX_EINVAL, "schedule is NULL");
+  if (!schedule) return fail(plan, PGX_EINVAL, "schedule is NULL");
   return guarded(plan, [&] { plan->engine().schedule_info(schedule); });
 }
 
 pgx_status pgx_dual_check(pgx_plan* plan, double* disagreement) {
   if (!plan) return fail(PGX_EINVAL, "plan is NULL");
-  if (!disagreement) return fail(PGX_EINVAL, "disagreement is NULL");
+  if (!disagreement) return fail(plan, PGX_EINVAL, "disagreement is NULL");
   return guarded(plan, [&] { *disagreement = plan->eng ? plan->eng->dual_disagreement : -1.0; });
 }
 
 pgx_status pgx_dual_recheck(pgx_plan* plan, void* stream, int32_t fallback, double* disagreement) {
   if (!plan) return fail(PGX_EINVAL, "plan is NULL");
-  if (!disagreement) return fail(PGX_EINVAL, "disagreement is NULL");
+  if (!disagreement) return fail(plan, PGX_EINVAL, "disagreement is NULL");
   return guarded(plan, [&] {
     *disagreement = plan->engine().recheck_dual((hipStream_t)stream, fallback != 0);
   });
@@ -391,7 +391,7 @@ pgx_status pgx_dual_recheck(pgx_plan* plan, void* stream, int32_t fallback, doub
 
 pgx_status pgx_set_schedule(pgx_plan* plan, void* stream, const int32_t* schedule) {
   if (!plan) return fail(PGX_EINVAL, "plan is NULL");
-  if (!schedule) return fail(PGX_EINVAL, "schedule is NULL");
+  if (!schedule) return fail(plan, PGX_EINVAL, "schedule is NULL");
   return guarded(plan, [&] { plan->engine().set_schedule(schedule, (hipStream_t)stream); });
 }
 

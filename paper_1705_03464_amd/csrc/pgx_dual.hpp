@@ -176,8 +176,8 @@ k_xinv_gather_sweep(PointSet<T> ps, const int32_t* __restrict__ perm, int64_t P,
   // inverse transform of v in buffer `buf`, result stored there
   auto transform_into = [&](int buf, C<T>* v) {
     C<T>* line = rows[buf][g];
-    line_fft<Sh, 1>(v, t, line, tw_s, block_sync);
-    block_sync();  // every group has read its last-stage inputs
+    line_fft<Sh, 1>(v, t, line, tw_s, wave_sync);
+    wave_sync();  // this group has read its last-stage inputs
 #pragma unroll
     for (int m = 0; m < E; ++m) line[lpad(t + TPL * m)] = v[m];
   };
@@ -518,7 +518,7 @@ k_xscatter_dual(PointSet<T> ps, const int32_t* __restrict__ lfield, const float2
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = line[lpad(t + TPL * m)];
     block_sync();
-    line_fft<Sh, -1>(v, t, line, tw_s, block_sync);
+    line_fft<Sh, -1>(v, t, line, tw_s, wave_sync);
     C<T>* o = out + (int64_t)slot * out_slot + (int64_t)li * N;
 #pragma unroll
     for (int m = 0; m < E; ++m) o[t + TPL * m] = v[m];

@@ -6,9 +6,11 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <iterator>
 #include <map>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -146,6 +148,28 @@ inline size_t free_device_bytes() {
 // allocated: 4 GiB from the HIP allocator, none inside a caller's workspace.
 inline size_t spare_device_bytes() { return (t_heap || t_session) ? 0 : ((size_t)4 << 30); }
 
+// Fault injection for tests of the error paths: while the environment
+// variable PGX_DEBUG_FAIL_ALLOC holds n >= 1, the n-th device allocation from
+// the HIP allocator (counted from the moment the variable took that value)
+// fails as if the device were out of memory: a required buffer raises
+// PGX_EHIP, an optional store is skipped.  Unset, it costs one getenv per
+// allocation.
+inline bool injected_alloc_failure() {
+  static std::mutex m;
+  static std::string last;
+  static long long count = 0;
+  const char* e = std::getenv("PGX_DEBUG_FAIL_ALLOC");
+  std::lock_guard<std::mutex> g(m);
+  const std::string cur = e ? e : "";
+  if (cur != last) {
+    last = cur;
+    count = 0;
+  }
+  if (cur.empty()) return false;
+  const long long n = std::atoll(cur.c_str());
+  return n > 0 && ++count == n;
+}
+
 // Device allocation that only grows (see Heap for where it lives).
 struct DBuf {
   void* p = nullptr;
@@ -187,6 +211,9 @@ struct DBuf {
         p = t_heap->alloc(n, "workspace");
         owner = t_heap;
       } else {
+        if (injected_alloc_failure())
+          throw Error(PGX_EHIP, "hipMalloc of " + std::to_string(n) +
+                                    " bytes: injected failure (PGX_DEBUG_FAIL_ALLOC)");
         PGX_HIP(hipMalloc(&p, n));
       }
       bytes = n;
@@ -205,7 +232,7 @@ struct DBuf {
       p = t_heap->try_alloc(n);
       if (!p) return false;
       owner = t_heap;
-    } else if (hipMalloc(&p, n) != hipSuccess) {
+    } else if (injected_alloc_failure() || hipMalloc(&p, n) != hipSuccess) {
       (void)hipGetLastError();
       p = nullptr;
       return false;

@@ -37,6 +37,17 @@ template <typename Sh, int W> struct Blk {
 };
 
 __device__ __forceinline__ void block_sync() { __syncthreads(); }
+// Synchronisation of one wavefront around its own LDS accesses.  The
+// x-direction kernels give each line TPL <= 64 consecutive threads, so every
+// line lies within one wavefront and the exchanges between the stages of its
+// transform need no block barrier: the LDS instructions of a wavefront
+// complete in issue order, and the fences keep the compiler from moving LDS
+// accesses across this point.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 template <typename T, typename Sh>
 __device__ __forceinline__ void load_twiddles(C<T>* tw_s, const C<T>* __restrict__ tw_g) {
@@ -272,7 +283,7 @@ k_xscatter(const int32_t* __restrict__ tasks, int n_tasks, PointSet<T> ps,
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = line[lpad(t + TPL * m)];
   block_sync();
-  line_fft<Sh, -1>(v, t, line, tw_s, block_sync);
+  line_fft<Sh, -1>(v, t, line, tw_s, wave_sync);
   if (active) {
     C<T>* o = out + (int64_t)slot * NN * N + ((int64_t)z * N + y) * N;
 #pragma unroll
@@ -665,7 +676,7 @@ k_xinv_bins(const C<T>* __restrict__ in, int64_t in_slot, int pwx, int pwy, int 
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = active ? src[t + TPL * m] : C<T>{0, 0};
   block_sync();
-  line_fft<Sh, 1>(v, t, lines[l], tw_s, block_sync);
+  line_fft<Sh, 1>(v, t, lines[l], tw_s, wave_sync);
   if (active) {
     const int jj = py - pwy, kk = pz - pwz;
 #pragma unroll
@@ -703,7 +714,7 @@ k_xdense(C<T>* data, const C<T>* __restrict__ tw_g) {
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = p[t + TPL * m];
   block_sync();
-  line_fft<Sh, DIR>(v, t, lines[l], tw_s, block_sync);
+  line_fft<Sh, DIR>(v, t, lines[l], tw_s, wave_sync);
 #pragma unroll
   for (int m = 0; m < E; ++m) p[t + TPL * m] = v[m];
 }

@@ -157,3 +157,14 @@ def test_workspace_and_fixed_forward_argument_errors_need_no_device():
     p2 = Plan.from_workload(CONFIGS["cfg4tiny"])
     assert lib.pgx_last_error(p2._h).decode() == ""
     p32.close(); p2.close()
+
+
+def test_dual_recheck_argument_errors_need_no_device():
+    import ctypes as C
+    lib = load_library()
+    d = C.c_double(0.0)
+    assert lib.pgx_dual_recheck(None, None, 1, C.byref(d)) == 1   # EINVAL: no plan
+    p = Plan.from_workload(CONFIGS["cfg4tiny"])
+    assert lib.pgx_dual_recheck(p._h, None, 1, None) == 1         # EINVAL: no output
+    assert "disagreement" in lib.pgx_last_error(p._h).decode()
+    p.close()
