@@ -109,6 +109,8 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="cfg1")
+    ap.add_argument("--assignment", choices=["cic", "tsc"], default=None,
+                    help="override the workload's mass assignment (the paper's TSC or CIC)")
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--mode", choices=["fwd", "fwdbwd"], default="fwdbwd")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default batch schedule")
@@ -151,6 +153,8 @@ def main(argv=None):
     from paper_1705_03464_amd.build import sources_digest
     digest = build_digest()
     wl = get_config(a.config)
+    if a.assignment is not None:
+        wl = wl.scaled(assignment=a.assignment)
     res = measure(wl, a, a.steps, a.warmup, with_extras=True)
     rec = {
         "metric": "pair-field xi_pg cross-correlations/s at 512^3 (fwd, fwd+bwd), % HBM peak",
@@ -324,7 +328,8 @@ def measure(wl, a, steps, warmup, with_extras):
     dom = max(prof, key=lambda p: p[2])
     name, n, ms, by = dom
     achieved = (by / n) / (ms / n * 1e-3) / 1e9
-    traffic = measured_traffic(name, plan.schedule()["batch"]) if wl.name == "cfg1" else None
+    traffic = (measured_traffic(name, plan.schedule()["batch"])
+               if wl.name == "cfg1" and wl.assignment == "cic" else None)
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": name,
@@ -342,7 +347,7 @@ def measure(wl, a, steps, warmup, with_extras):
             "pair_fields": wl.n_fields, "out_bins": wl.n_out, "finite_rows": int(finite.any(1).sum()),
             "step": ("pairs_build + forward + adjoint (autograd)" if a.mode == "fwdbwd"
                      else "pairs_build + forward"),
-            "hod_weights": bool(hod), "parallelism": "single GPU",
+            "hod_weights": bool(hod), "assignment": wl.assignment, "parallelism": "single GPU",
             "schedule": plan.schedule(), "autotuned": not a.no_autotune,
             "dual_form_check": round(plan.dual_check(), 4),
             "launch_graphs": not a.no_graphs,

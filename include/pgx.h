@@ -105,10 +105,10 @@ typedef enum { PGX_ASSIGN_CIC = 0, PGX_ASSIGN_TSC = 1 } pgx_assignment;
  *             neighbours on each axis with weights 3/4 - d^2 and
  *             (1/2 -+ d)^2 / 2, d the offset from that node in cells; ties
  *             at d = 1/2 go to the lower node).  On FP32_BATCHED plans TSC
- *             runs with the per-field transforms (forward and adjoint); the
- *             dual form and the multipoles, whose fused gather holds the CIC
- *             footprint, refuse TSC plans (ENOTSUP), and the autotuner keeps
- *             the per-field transforms for them.
+ *             runs in both evaluations, forward and adjoint (the dual form
+ *             keys its line-major pair catalogue by each midpoint's nearest
+ *             node and gathers over the 3 x 3 lines around it); the
+ *             multipoles refuse TSC plans (ENOTSUP).
  */
 typedef struct {
   double L;

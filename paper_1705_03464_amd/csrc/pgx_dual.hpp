@@ -228,6 +228,117 @@ k_xinv_gather_sweep(PointSet<T> ps, const int32_t* __restrict__ perm, int64_t P,
   }
 }
 
+// TSC weights along one axis of the nodes c - 1, c, c + 1 around the nearest
+// node c of a point with CIC fraction f (c is the CIC corner plus one when
+// f > 1/2; a point half-way takes the lower node).
+template <typename T>
+__device__ __forceinline__ void tsc_weights3(T f, T* w) {
+  const T d = f > (T)0.5 ? f - (T)1 : f;
+  w[0] = (T)0.5 * ((T)0.5 - d) * ((T)0.5 - d);
+  w[1] = (T)0.75 - d * d;
+  w[2] = (T)0.5 * ((T)0.5 + d) * ((T)0.5 + d);
+}
+// nearest node of a point with CIC corner a0 and fraction f
+template <typename T>
+__device__ __forceinline__ int tsc_nearest(int a0, T f, int N) {
+  return (a0 + (f > (T)0.5 ? 1 : 0)) & (N - 1);
+}
+
+// Inverse x pass fused with the TSC gather, as a sweep along z (the TSC form
+// of k_xinv_gather_sweep).  The line-major catalogue of a TSC plan is keyed
+// by each point's nearest-node line, and a point reads the 3 x 3 lines around
+// it.  Block = (tile of YT nearest-node lines in y, segment of z, slot); it
+// keeps three z rows of YT + 2 lines (y_base - 1 .. y_base + YT) inverse
+// transformed in LDS, so every point of a nearest-node line (y0, z0) of the
+// tile finds its nine lines in the block; its value is written once.  Then
+// row z0 + 2 replaces row z0 - 1, its global loads issued before the gather.
+// Bins b1 = b0 + 2 slot, b2 = b1 + 1 (< R).
+template <typename T, typename Sh, int YT>
+static __global__ void __launch_bounds__((YT + 2) * Sh::TPL)
+k_xinv_gather_sweep_tsc(PointSet<T> ps, const int32_t* __restrict__ perm, int64_t P,
+                        const C<T>* __restrict__ U, int64_t u_slot, int zlen, int b0, int R,
+                        float* __restrict__ gv, const C<T>* __restrict__ tw_g) {
+  constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>(), NG = YT + 2;
+  __shared__ C<T> tw_s[Sh::tw_entries()];
+  __shared__ C<T> rows[3][NG][LL];
+  load_twiddles<T, Sh>(tw_s, tw_g);
+  const int g = threadIdx.x / TPL, t = threadIdx.x % TPL;
+  const int y_base = blockIdx.x * YT;
+  const int y = (y_base - 1 + g) & (N - 1);  // the line this group transforms
+  const int z_lo = blockIdx.y * zlen, z_hi = min(z_lo + zlen, N);
+  const int slot = blockIdx.z;
+  const C<T>* us = U + (int64_t)slot * u_slot;
+  const int b1 = b0 + 2 * slot, b2 = b1 + 1;
+  float* g1 = gv + (int64_t)b1 * P;
+  float* g2 = gv + (int64_t)b2 * P;
+  auto load_row = [&](int z, C<T>* v) {
+    const C<T>* src = us + ((int64_t)(z & (N - 1)) * N + y) * N;
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = src[t + TPL * m];
+  };
+  // ring slot of row z: rows z_lo - 1, z_lo, z_lo + 1, ... take slots 0, 1, 2, 0, ...
+  auto ring = [&](int z) { return (z - z_lo + 1) % 3; };
+  auto transform_into = [&](int buf, C<T>* v) {
+    C<T>* line = rows[buf][g];
+    line_fft<Sh, 1>(v, t, line, tw_s, wave_sync);
+    wave_sync();  // this group has read its last-stage inputs
+#pragma unroll
+    for (int m = 0; m < E; ++m) line[lpad(t + TPL * m)] = v[m];
+  };
+  C<T> v[E];
+  load_row(z_lo - 1 + N, v);
+  block_sync();  // twiddles
+  transform_into(ring(z_lo - 1), v);
+  load_row(z_lo, v);
+  transform_into(ring(z_lo), v);
+  load_row(z_lo + 1, v);
+  transform_into(ring(z_lo + 1), v);
+  block_sync();
+  for (int z0 = z_lo; z0 < z_hi; ++z0) {
+    const bool more = z0 + 1 < z_hi;
+    if (more) load_row(z0 + 2, v);  // in flight during the gather
+    // gather: group g in [1, YT] serves nearest-node line (y_base + g - 1, z0)
+    const int y0 = y_base + g - 1;
+    if (g >= 1 && g <= YT && y0 < N) {
+      const int rz[3] = {ring(z0 - 1), ring(z0), ring(z0 + 1)};
+      const int key = z0 * N + y0;
+      const int s = ps.line_start[key], e = ps.line_start[key + 1];
+      for (int k = s + t; k < e; k += TPL) {
+        T wx[3], wy[3], wz[3];
+        int lx;
+        tsc_axis<T>(ps.x0[k], ps.fx[k], lx, wx);
+        tsc_weights3<T>(ps.fy[k], wy);
+        tsc_weights3<T>(ps.fz[k], wz);
+        T sx = (T)0, sy = (T)0;
+#pragma unroll
+        for (int jz = 0; jz < 3; ++jz)
+#pragma unroll
+          for (int jy = 0; jy < 3; ++jy) {
+            const C<T>* a = rows[rz[jz]][g - 1 + jy];
+            T ax = (T)0, ay = (T)0;
+#pragma unroll
+            for (int jx = 0; jx < 3; ++jx) {
+              const C<T> c = a[lpad((lx + jx) & (N - 1))];
+              ax += wx[jx] * c.x;
+              ay += wx[jx] * c.y;
+            }
+            const T w = wz[jz] * wy[jy];
+            sx += w * ax;
+            sy += w * ay;
+          }
+        const int64_t p = perm[k];
+        g1[p] = (float)sx;
+        if (b2 < R) g2[p] = (float)sy;
+      }
+    }
+    block_sync();  // row z0 - 1 is no longer read
+    if (more) {
+      transform_into(ring(z0 + 2), v);  // row z0 + 2 takes row z0 - 1's buffer
+      block_sync();
+    }
+  }
+}
+
 // S[f][b] = sum over the pairs of field f of (w_i w_j) gv[b][p] (FP64 pair
 // weights from k_pair_wts), divided by the bin's kernel scale (the FP32
 // value the kernel generator applied).  Block (f, b, k) of a grid (F, R, K)
@@ -257,6 +368,21 @@ static __global__ void k_line_x_key(const int32_t* __restrict__ key, const int32
                                     int64_t P, int64_t nn, int n, int32_t* __restrict__ out) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p < P) out[p] = (int32_t)((key[p] % nn) * n + x0[p]);
+}
+// TSC plans: the sort key (nearest-node line, nearest x node) of each pair,
+// from its CIC corner and fractions (the same FP32 fractions, and the same
+// rule for a point half-way, as the TSC weights)
+template <typename T>
+static __global__ void k_line_x_key_tsc(const int32_t* __restrict__ key, const int32_t* __restrict__ x0,
+                                        const T* __restrict__ fx, const T* __restrict__ fy,
+                                        const T* __restrict__ fz, int64_t P, int64_t nn, int n,
+                                        int32_t* __restrict__ out) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const int line = (int)(key[p] % nn);
+  const int cy = tsc_nearest(line % n, fy[p], n), cz = tsc_nearest(line / n, fz[p], n);
+  const int cx = tsc_nearest(x0[p], fx[p], n);
+  out[p] = (int32_t)(((int64_t)cz * n + cy) * n + cx);
 }
 // base line of a sorted (line, x0) key
 static __global__ void k_key_line(const int32_t* __restrict__ k, int64_t P, int n,
@@ -635,6 +761,142 @@ k_zdual_acc(const C<T>* __restrict__ x, int64_t x_slot, int n_slots,
     C<T>* p = acc_out + col + (int64_t)(t + TPL * m) * NN;
     const C<T> o = *p;
     *p = C<T>{o.x + acc[m].x, o.y + acc[m].y};
+  }
+}
+
+// The points whose TSC footprint reaches line (y, z) in a TSC plan's
+// line-major catalogue (keyed by nearest-node line): those of the nine lines
+// (y + dy, z + dz), dy, dz in {-1, 0, 1}, taken as one index range (range
+// q = 3 (dz + 1) + dy + 1).
+struct LineRanges9 {
+  int o[9], d[9], n;
+  // UNIFORM: the line is the same on every lane of the wavefront (one line
+  // per wavefront), so the table is taken into scalar registers
+  template <bool UNIFORM, typename T>
+  __device__ __forceinline__ void init(const PointSet<T>& ps, int y, int z, int N) {
+    n = 0;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const int yy = (y + q % 3 - 1) & (N - 1), zz = (z + q / 3 - 1) & (N - 1);
+      const int k = zz * N + yy;
+      int s = ps.line_start[k], e = ps.line_start[k + 1];
+      if constexpr (UNIFORM) {
+        s = __builtin_amdgcn_readfirstlane(s);
+        e = __builtin_amdgcn_readfirstlane(e);
+      }
+      o[q] = n;
+      d[q] = s - n;
+      n += e - s;
+    }
+  }
+  __device__ __forceinline__ int range(int i) const {
+    int q = 0;
+#pragma unroll
+    for (int k = 1; k < 9; ++k) q += i >= o[k] ? 1 : 0;
+    return q;
+  }
+  // (selects, not indexing: the tables stay in registers)
+  __device__ __forceinline__ int point(int i, int q) const {
+    int dq = d[0];
+#pragma unroll
+    for (int k = 1; k < 9; ++k) dq = q == k ? d[k] : dq;
+    return i + dq;
+  }
+};
+template <typename T>
+__device__ __forceinline__ T pick3(const T* w, int j) {
+  return j == 0 ? w[0] : (j == 1 ? w[1] : w[2]);
+}
+
+// Pi scatter of the dual form's adjoint with TSC (the TSC form of
+// k_xscatter_dual): every pair whose footprint reaches line (y, z) adds
+// coef[slot][f] times its weight and its TSC weights along y, z (node offset
+// from its nearest node: the range it came from) and x (three nodes) to the
+// line in LDS; then the line is transformed along x and stored.  One line
+// per wavefront at 512^3: runs of equal (range, nearest x node) are summed
+// across the wavefront first (the catalogue is sorted that way within each
+// line), and only the last lane of a run issues the LDS atomics.
+template <typename T, typename Sh, int W>
+static __global__ void __launch_bounds__(W * Sh::TPL)
+k_xscatter_dual_tsc(PointSet<T> ps, const int32_t* __restrict__ lfield, const float2* __restrict__ coef,
+                    int F, int q0, int nq, C<T>* __restrict__ out, int64_t out_slot,
+                    const C<T>* __restrict__ tw_g) {
+  constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>();
+  constexpr bool RUNS = TPL == 64 && std::is_same<T, float>::value;
+  __shared__ C<T> tw_s[Sh::tw_entries()];
+  __shared__ C<T> lines[W][LL];
+  load_twiddles<T, Sh>(tw_s, tw_g);
+  const int t = threadIdx.x % TPL, l = threadIdx.x / TPL;
+  const int li = blockIdx.x * W + l;  // < N*N by the grid
+  const int y = li % N, z = li / N;
+  C<T>* line = lines[l];
+  LineRanges9 lr;
+  lr.template init<TPL == 64>(ps, y, z, N);
+  for (int slot = 0; slot < nq; ++slot) {
+    if (slot > 0) block_sync();  // the previous slot's transform has left the LDS line
+#pragma unroll
+    for (int m = 0; m < E; ++m) line[lpad(t + TPL * m)] = C<T>{0, 0};
+    block_sync();
+    const float2* cq = coef + (int64_t)(q0 + slot) * F;
+    // every lane of a wavefront takes the same trips (RUNS: one line per wavefront)
+    for (int base = 0; base < lr.n; base += TPL) {
+      const int i = base + t;
+      const bool act = i < lr.n;
+      T w[3] = {(T)0, (T)0, (T)0};
+      int lx = 0, q = 0;
+      float2 c = float2{0.f, 0.f};
+      if (act) {
+        q = lr.range(i);
+        const int p = lr.point(i, q);
+        T wy[3], wz[3];
+        tsc_weights3<T>(ps.fy[p], wy);
+        tsc_weights3<T>(ps.fz[p], wz);
+        // this line is node 1 - (q % 3) from the nearest node in y (range
+        // q % 3 = 0 holds points whose nearest line is y - 1), likewise in z
+        const T wyz = (ps.wt ? ps.wt[p] : (T)1) * pick3(wy, 2 - q % 3) * pick3(wz, 2 - q / 3);
+        T wx[3];
+        tsc_axis<T>(ps.x0[p], ps.fx[p], lx, wx);
+        w[0] = wyz * wx[0];
+        w[1] = wyz * wx[1];
+        w[2] = wyz * wx[2];
+        c = cq[lfield[p]];
+      }
+      T sx[3], sy[3];
+      bool issue = act;
+      if constexpr (RUNS) {
+        WaveRuns r;
+        r.init(act ? q * N + ((lx + 1) & (N - 1)) : 9 * N + t);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          sx[j] = r.add(w[j] * (T)c.x);
+          sy[j] = r.add(w[j] * (T)c.y);
+        }
+        issue = act && r.tail;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          sx[j] = w[j] * (T)c.x;
+          sy[j] = w[j] * (T)c.y;
+        }
+      }
+      if (issue) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          C<T>* a = &line[lpad((lx + j) & (N - 1))];
+          atomicAdd(&a->x, sx[j]);
+          atomicAdd(&a->y, sy[j]);
+        }
+      }
+    }
+    block_sync();
+    C<T> v[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = line[lpad(t + TPL * m)];
+    block_sync();
+    line_fft<Sh, -1>(v, t, line, tw_s, wave_sync);
+    C<T>* o = out + (int64_t)slot * out_slot + (int64_t)li * N;
+#pragma unroll
+    for (int m = 0; m < E; ++m) o[t + TPL * m] = v[m];
   }
 }
 

@@ -674,7 +674,12 @@ template <typename T, int N> struct Engine : EngineBase {
       if (P > 0) {
         k_iota<<<grid_for(P), 256, 0, s>>>(iota, P);
         launch_check("iota");
-        k_line_x_key<<<grid_for(P), 256, 0, s>>>(sk, p_x0.as<int32_t>(), P, NN, N, lk);
+        // CIC: by the corner's line and x node; TSC: by the nearest node's
+        if (cfg.assignment == 1)
+          k_line_x_key_tsc<T><<<grid_for(P), 256, 0, s>>>(sk, p_x0.as<int32_t>(), p_fx.as<T>(), p_fy.as<T>(),
+                                                          p_fz.as<T>(), P, NN, N, lk);
+        else
+          k_line_x_key<<<grid_for(P), 256, 0, s>>>(sk, p_x0.as<int32_t>(), P, NN, N, lk);
         launch_check("line_x_key");
       }
       sort_pairs_i32(lk, lks, iota, lp, P, bits_for(NN * N), s, s_tmp);
@@ -815,9 +820,7 @@ template <typename T, int N> struct Engine : EngineBase {
       int best_algo = 0, best_vz_dual = 0;
       dual_disagreement = -1.0;
       algo = 0;
-      // the dual form's gather and scatter hold the CIC footprint: with TSC
-      // the per-field transforms serve
-      if (cfg.assignment == 0 && dual_fits()) {
+      if (dual_fits()) {
         const int F = cfg.F, R = cfg.R;
         double* sref = S_ref.get<double>((int64_t)F * R);
         PGX_HIP(hipMemcpyAsync(sref, S.as<double>(), (size_t)F * R * sizeof(double),
@@ -889,8 +892,6 @@ template <typename T, int N> struct Engine : EngineBase {
     if constexpr (!std::is_same<T, float>::value) {
       throw Error(PGX_ENOTSUP, "schedules apply to the FP32 batched path");
     } else {
-      PGX_REQUIRE(in[4] == 0 || cfg.assignment == 0, PGX_ENOTSUP,
-                  "the dual form holds the CIC footprint: TSC plans use the per-field transforms");
       schedule(in[0], s);
       v_ypass = in[1];
       v_yinv = in[2];
@@ -1472,8 +1473,12 @@ template <typename T, int N> struct Engine : EngineBase {
       const int nq = std::min(B, Q - q0);
       C<T>* ky = ksp ? nullptr : dual_kernels(s, q0, nq, kc, twp, bm, "bwd_dual_kgen", "bwd_dual_kgen_y");
       prof.run("bwd_dual_xscatter", s, (double)nq * ((double)NC * cb + pts), [&] {
-        k_xscatter_dual<T, Sh, WX><<<(int)(NN / WX), NTX, 0, s>>>(line_set(), l_f.as<int32_t>(), cf, F,
-                                                                 q0, nq, x, NC, twp);
+        if (cfg.assignment == 1)
+          k_xscatter_dual_tsc<T, Sh, WX><<<(int)(NN / WX), NTX, 0, s>>>(line_set(), l_f.as<int32_t>(), cf, F,
+                                                                      q0, nq, x, NC, twp);
+        else
+          k_xscatter_dual<T, Sh, WX><<<(int)(NN / WX), NTX, 0, s>>>(line_set(), l_f.as<int32_t>(), cf, F,
+                                                                   q0, nq, x, NC, twp);
         launch_check("xscatter(dual adjoint)");
       });
       prof.run("bwd_dual_ypass", s, 2.0 * nq * NC * cb, [&] {
@@ -1830,8 +1835,12 @@ template <typename T, int N> struct Engine : EngineBase {
         // the y-transformed grids once, the point records, the gathered values
         const double bytes = (double)nq * NC * cb + (double)n_pairs * (20.0 + 8.0 * nq) + (double)NN * 4.0;
         prof.run("dual_xinv_gather", s, bytes, [&] {
-          k_xinv_gather_sweep<T, Sh, YTS><<<dim3((N + YTS - 1) / YTS, kZSeg, nq), (YTS + 1) * TPL, 0, s>>>(
-              line_set(), l_p.as<int32_t>(), n_pairs, x, NC, zlen, 2 * q0, R, gv, twp);
+          if (cfg.assignment == 1)
+            k_xinv_gather_sweep_tsc<T, Sh, YTS><<<dim3((N + YTS - 1) / YTS, kZSeg, nq), (YTS + 2) * TPL, 0, s>>>(
+                line_set(), l_p.as<int32_t>(), n_pairs, x, NC, zlen, 2 * q0, R, gv, twp);
+          else
+            k_xinv_gather_sweep<T, Sh, YTS><<<dim3((N + YTS - 1) / YTS, kZSeg, nq), (YTS + 1) * TPL, 0, s>>>(
+                line_set(), l_p.as<int32_t>(), n_pairs, x, NC, zlen, 2 * q0, R, gv, twp);
           launch_check("xinv_gather(dual)");
         });
       }

@@ -1,9 +1,10 @@
 """The paper's TSC mass assignment (Implementation section, "Mass assignment
 function") on the batched FP32 path: forward against the oracle at the FP32
 bar and the adjoint against the oracle's adjoint and its finite differences
-at the gradient bar, for galaxies and pair midpoints alike (the per-field
-transforms; the dual form and the multipoles hold the CIC footprint and
-refuse TSC plans)."""
+at the gradient bar, for galaxies and pair midpoints alike, in all three
+evaluations (per-field transforms; the dual form on the window columns and
+on the kernel-spectrum store, whose line-major catalogue is keyed by each
+midpoint's nearest node).  The multipoles refuse TSC plans."""
 import os
 import sys
 
@@ -17,7 +18,7 @@ from oracle.pipeline import forward as oracle_forward  # noqa: E402
 from synth import get_config  # noqa: E402
 from synth.configs import Workload, linbins, logbins  # noqa: E402
 from test_gpu_grad import grad_close, mask_ill_conditioned_q, upstream  # noqa: E402
-from test_gpu_parity import assert_fp32_parity, clustered_catalog  # noqa: E402
+from test_gpu_parity import ALGOS, assert_fp32_parity, clustered_catalog  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -60,15 +61,17 @@ def case(name, seed=21):
     return wl, cat, w
 
 
+@pytest.mark.parametrize("algo", [0, 1, 2])
 @pytest.mark.parametrize("name", list(CASES))
-def test_tsc_forward_against_oracle(name):
+def test_tsc_forward_against_oracle(name, algo):
     from paper_1705_03464_amd import Plan
     wl, cat, w = case(name)
     ref = oracle_forward(cat, wl, w=w)
     plan = Plan.from_workload(wl, precision="fp32", batch=2)
     P, counts = plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
-    _say(f"TSC {name}: n_gal={cat.n} pairs={P}")
+    _say(f"TSC {name}: n_gal={cat.n} pairs={P} evaluation {ALGOS[algo]}")
     assert np.array_equal(counts.cpu().numpy(), ref["counts"])
+    plan.set_schedule(2, 0, 0, *ALGOS[algo])
     out = {k: v.cpu().numpy() for k, v in plan.forward(dev(w, torch.float32)).items()}
     assert_fp32_parity(out, ref)
     # the scheme is applied: CIC gives a different xi_gg
@@ -76,9 +79,9 @@ def test_tsc_forward_against_oracle(name):
     assert np.max(np.abs(ref_c["xi_gg"] - ref["xi_gg"])) > 1e-3 * np.max(np.abs(ref["xi_gg"]))
 
 
-@pytest.mark.parametrize("keep", [False, True])
+@pytest.mark.parametrize("keep,algo", [(False, 0), (True, 0), (False, 1), (False, 2)])
 @pytest.mark.parametrize("name", ["s_mu-64", "rp_pi-64"])
-def test_tsc_adjoint_against_oracle(name, keep):
+def test_tsc_adjoint_against_oracle(name, keep, algo):
     from paper_1705_03464_amd import Plan
     wl, cat, w = case(name, seed=22)
     g = upstream(wl.n_fields, wl.n_out, 5)
@@ -86,13 +89,14 @@ def test_tsc_adjoint_against_oracle(name, keep):
     ref, _ = OG.weight_gradient(cat, wl, w, **g)
     plan = Plan.from_workload(wl, precision="fp32", batch=2)
     plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
+    plan.set_schedule(2, 0, 0, *ALGOS[algo])
     plan.keep_spectra(keep)
     for call in range(2):
         plan.forward(dev(w, torch.float32))
         gw = plan.backward(g_b_pg=dev(g["g_b"]), g_q_eff=dev(g["g_q"]), g_xi_pg=dev(g["g_xipg"]),
                            g_xi_gg=dev(g["g_xigg"]), g_xi_dp=dev(g["g_xidp"]))
         gw = gw.cpu().numpy().astype(np.float64)
-        _say(f"TSC adjoint {name}, kept spectra {keep}, call {call}:")
+        _say(f"TSC adjoint {name}, evaluation {ALGOS[algo]}, kept spectra {keep}, call {call}:")
         assert grad_close(gw, ref)
 
 
@@ -115,16 +119,18 @@ def test_tsc_adjoint_against_finite_differences():
     assert np.all(err <= 1e-3 * np.abs(gw).max())
 
 
-def test_tsc_plans_keep_the_per_field_transforms():
+def test_tsc_plans_tune_both_evaluations_and_refuse_multipoles():
+    """The autotuner measures the TSC dual form against the TSC per-field
+    transforms (its check is reported); the multipoles refuse TSC plans."""
     from paper_1705_03464_amd import PgxError, Plan
     wl, cat, w = case("s_mu-64", seed=24)
     plan = Plan.from_workload(wl, precision="fp32", batch=2)
     plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
-    with pytest.raises(PgxError) as e:
-        plan.set_schedule(2, 0, 0, 0, 1)
-    assert e.value.code == 4
     plan.forward(dev(w, torch.float32))
-    assert plan.autotune()["algorithm"] == 0
+    sched = plan.autotune()
+    _say(f"  TSC autotuned {sched}, dual-form check {plan.dual_check():.3f}")
+    assert plan.dual_check() >= 0.0
+    plan.forward(dev(w, torch.float32))
     with pytest.raises(PgxError) as e:
         plan.multipoles(2)
     assert e.value.code == 4
@@ -151,11 +157,12 @@ def test_tsc_hod_subset_matches_the_fp64_plain_path():
         assert np.all(d <= np.maximum(1e-5 * np.abs(ref[k][fin]), floor)), k
 
 
-def test_tsc_at_512_against_oracle():
-    """512^3 (lines of one wavefront: the scatter's run sums over three x
+@pytest.mark.parametrize("algo", [0, 2])
+def test_tsc_at_512_against_oracle(algo):
+    """512^3 (lines of one wavefront: the scatters' run sums over three x
     nodes are active): the production catalogue with 4 s-bins and 6 shells,
     forward at the FP32 bar and adjoint at the gradient bar against the
-    oracle."""
+    oracle, per-field and in the dual form on the kernel-spectrum store."""
     from paper_1705_03464_amd import Plan
     base = get_config("cfg1")
     wl = base.scaled(name="cfg1-tsc", p1_edges=logbins(0.5, 10.0, 4), p2_edges=linbins(0.0, 1.0, 1),
@@ -170,6 +177,7 @@ def test_tsc_at_512_against_oracle():
     P, counts = plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
     _say(f"TSC 512^3: n_gal={cat.n} pairs={P}")
     assert np.array_equal(counts.cpu().numpy(), rout["counts"])
+    plan.set_schedule(4, 0, 0, *ALGOS[algo])
     plan.keep_spectra(True)
     out = {k: v.cpu().numpy() for k, v in plan.forward(dev(w, torch.float32)).items()}
     assert_fp32_parity(out, rout)
