@@ -1052,12 +1052,10 @@ static __global__ void k_gal_coef(const double* __restrict__ agg, int R,
 
 // z pass of the galaxy-side adjoint on the kernel spectra.  Per slot: forward
 // z transform of the Pi columns, acc += Pi^ conj(K^) / 2, and the galaxy
-// kernel's spectrum kg += gc.x Re K^ + gc.y Im K^ (kept in LDS: each thread
-// owns its planes' entries, so no barrier guards them).  Then
+// kernel's spectrum kg += gc.x Re K^ + gc.y Im K^ (each thread owns its
+// column elements' entries, so no barrier guards them).  Then
 //   A = acc + kg G   (first batch of bin pairs), A += acc + kg G (later ones),
-// which also takes the place of the separate galaxy-kernel pass.  Slot
-// pipeline: the current slot's kernel values and the next slot's Pi columns
-// are issued at the top of each trip.
+// which also takes the place of the separate galaxy-kernel pass.
 template <typename T, typename Sh, int W>
 static __global__ void __launch_bounds__(W * Sh::TPL, Sh::E <= 8 ? 8 : 1)
 k_zdual_acc_ks(const C<T>* __restrict__ x, int64_t x_slot, int n_slots,
@@ -1067,12 +1065,12 @@ k_zdual_acc_ks(const C<T>* __restrict__ x, int64_t x_slot, int n_slots,
   constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>(), H = N / 2;
   constexpr int64_t NN = (int64_t)N * N;
   // Shapes of at most 8 elements per thread run lean: the galaxy-kernel sum
-  // in registers (each thread owns its column elements), stage twiddles from
-  // the LDS table, the kernel values loaded after the transform, no register
-  // prefetch of the next slot; the kernel then fits 64 VGPRs and about 75 KB
-  // of LDS, so two blocks share a compute unit and one block's memory stream
-  // overlaps the other's transforms (5.55 -> 4.78 ms per launch at 512^3 with
-  // 10 bin pairs).  Larger shapes keep the sum in LDS.
+  // in registers, stage twiddles from the LDS table, the kernel values loaded
+  // after the transform and in two halves, no register prefetch of the next
+  // slot; the kernel then fits 64 VGPRs without spills and about 75 KB of
+  // LDS, so two blocks share a compute unit and one block's memory stream
+  // overlaps the other's transforms (5.55 -> 4.14 ms per launch at 512^3
+  // with 10 bin pairs).  Larger shapes keep the sum in LDS.
   constexpr bool LEAN = E <= 8;
   __shared__ C<T> tw_s[LEAN ? Sh::tw_entries() : tw_lds_entries<Sh, kZTwReg>()];
   __shared__ C<T> lines[W][LL];

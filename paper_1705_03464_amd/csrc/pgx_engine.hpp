@@ -215,7 +215,8 @@ template <typename T, int N> struct Engine : EngineBase {
   // dual form, fused inverse x + gather: base lines per y tile and z segments
   // per launch.  Small tiles (two z rows of 4 lines, 35 KB of LDS at 512^3)
   // let several blocks share a compute unit; measured at 512^3: 3.6 ms per
-  // launch against 3.7 ms for 7 and 4.3 ms for 15 base lines per tile.
+  // launch against 3.7 ms for 7 and 4.3 ms for 15 base lines per tile.  The
+  // TSC sweep keeps three z rows of YTS + 2 lines (65 KB).
   static constexpr int YTS = 3;
   static constexpr int kZSeg = 8;
   // dual form, z passes: tile width of the second variant (half the columns,
