@@ -77,7 +77,9 @@ def test_injected_allocation_failures_are_reported_and_recovered():
 
 def test_invalid_inputs_are_rejected_and_the_plan_stays_usable():
     """Non-finite or out-of-box positions and negative or non-finite weights
-    give PGX_EINVAL with a message; the plan then runs a valid catalogue."""
+    give PGX_EINVAL with a message; a rejected pair build leaves the plan
+    without a catalogue (PGX_ESTATE until the next build); the plan then runs
+    a valid catalogue."""
     from paper_1705_03464_amd import Plan, PgxError
     wl = get_config("cfg4tiny")
     cat = wl.catalog()
@@ -100,6 +102,11 @@ def test_invalid_inputs_are_rejected_and_the_plan_stays_usable():
         with pytest.raises(PgxError) as e:
             plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z), w=dev(w, torch.float32), with_wsum=True)
         assert e.value.code == 1, (bad, str(e.value))
+        # a rejected build leaves no catalogue behind: a forward now asks for one
+        with pytest.raises(PgxError) as e:
+            plan.forward()
+        assert e.value.code == 5, str(e.value)
+        plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
     plan.pairs_build(dev(cat.x), dev(cat.y), dev(cat.z))
     out = plan.forward()
     assert np.isfinite(out["xi_gg"].cpu().numpy()).all()
