@@ -159,10 +159,12 @@ k_xinv_gather_sweep(PointSet<T> ps, const int32_t* __restrict__ perm, int64_t P,
   __shared__ C<T> rows[2][NG][LL];
   load_twiddles<T, Sh>(tw_s, tw_g);
   const int g = threadIdx.x / TPL, t = threadIdx.x % TPL;
-  const int y_base = blockIdx.x * YT;
+  // neighbouring y tiles share lines of every z row: they run on one XCD
+  int ytile, zseg, slot;
+  xcd_block3(ytile, zseg, slot);
+  const int y_base = ytile * YT;
   const int y = (y_base + g) & (N - 1);  // the line this group transforms
-  const int z_lo = blockIdx.y * zlen, z_hi = min(z_lo + zlen, N);
-  const int slot = blockIdx.z;
+  const int z_lo = zseg * zlen, z_hi = min(z_lo + zlen, N);
   const C<T>* us = U + (int64_t)slot * u_slot;
   const int b1 = b0 + 2 * slot, b2 = b1 + 1;
   float* g1 = gv + (int64_t)b1 * P;
@@ -263,10 +265,12 @@ k_xinv_gather_sweep_tsc(PointSet<T> ps, const int32_t* __restrict__ perm, int64_
   __shared__ C<T> rows[3][NG][LL];
   load_twiddles<T, Sh>(tw_s, tw_g);
   const int g = threadIdx.x / TPL, t = threadIdx.x % TPL;
-  const int y_base = blockIdx.x * YT;
+  // neighbouring y tiles share lines of every z row: they run on one XCD
+  int ytile, zseg, slot;
+  xcd_block3(ytile, zseg, slot);
+  const int y_base = ytile * YT;
   const int y = (y_base - 1 + g) & (N - 1);  // the line this group transforms
-  const int z_lo = blockIdx.y * zlen, z_hi = min(z_lo + zlen, N);
-  const int slot = blockIdx.z;
+  const int z_lo = zseg * zlen, z_hi = min(z_lo + zlen, N);
   const C<T>* us = U + (int64_t)slot * u_slot;
   const int b1 = b0 + 2 * slot, b2 = b1 + 1;
   float* g1 = gv + (int64_t)b1 * P;

@@ -101,6 +101,22 @@ __device__ __forceinline__ void xcd_tile(int& xt, int& ky) {
   ky = lt / (int)gridDim.x;
 }
 
+// XCD-aware order of a three-dimensional grid (blockIdx.x fastest in the
+// logical order): XCD k takes the contiguous logical range [k nb/8,
+// (k+1) nb/8), so blocks with neighbouring x indices run on one XCD at the
+// same time and data they share is fetched from HBM once, into that XCD's
+// L2.  A grid whose block count is not a multiple of 8 keeps the hardware
+// order.
+__device__ __forceinline__ void xcd_block3(int& bx, int& by, int& bz) {
+  const int nx = (int)gridDim.x, ny = (int)gridDim.y;
+  const int nb = nx * ny * (int)gridDim.z;
+  const int bid = ((int)blockIdx.z * ny + (int)blockIdx.y) * nx + (int)blockIdx.x;
+  const int lt = (nb & 7) == 0 ? (bid & 7) * (nb >> 3) + (bid >> 3) : bid;
+  bx = lt % nx;
+  by = (lt / nx) % ny;
+  bz = lt / (nx * ny);
+}
+
 // z passes: default twiddle source (registers when they fit; the autotuner
 // also tries the LDS table), and the most slots one launch may carry (their
 // plane masks are staged in LDS)
