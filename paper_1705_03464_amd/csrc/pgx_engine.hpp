@@ -1885,8 +1885,8 @@ template <typename T, int N> struct Engine : EngineBase {
       launch_check("ypass(gal)");
     });
     prof.run("gal_zpass", s, 2.0 * NC * cb + (double)p1_slot * cb, [&] {
-      k_zcross<T, Sh, W, true><<<dim3(N / W, N, 1), NT, 0, s>>>(x, 0, nullptr, nullptr, 1, nullptr,
-                                                                 fg, p1, 0, pwz(), twp);
+      k_zcross<T, Sh, W, true, false, false><<<dim3(N / W, N, 1), NT, 0, s>>>(x, 0, nullptr, nullptr, 1, nullptr,
+                                                                               fg, p1, 0, pwz(), twp);
       launch_check("zcross(gal)");
     });
     prof.run("gal_yinv", s, (double)(p1_slot + p2_slot) * cb, [&] {

@@ -456,7 +456,7 @@ k_strided(const C<T>* in, C<T>* out, int64_t in_slot, int64_t out_slot,
 // transform) to `spec` at its field-pair index, for the adjoint.
 // ----------------------------------------------------------------------------
 template <typename T, typename Sh, int W, bool GAL, bool STORE = false, bool TWREG = kZTwReg>
-static __global__ void __launch_bounds__(W * Sh::TPL)
+static __global__ void __launch_bounds__(W * Sh::TPL, GAL && !TWREG && Sh::E <= 8 ? 8 : 1)
 k_zcross(const C<T>* in, int64_t in_slot, const uint8_t* __restrict__ pflag,
          const int32_t* __restrict__ slot_fp, int n_slots, const C<T>* __restrict__ fg,
          C<T>* __restrict__ fg_out, C<T>* __restrict__ out, int64_t out_slot, int pw,
@@ -498,7 +498,11 @@ k_zcross(const C<T>* in, int64_t in_slot, const uint8_t* __restrict__ pflag,
   // offset; pointer path: the tile's first element is read and zeroed when
   // the columns are taken)
   auto load_cols = [&](int slot, bool take, C<T>* dst) {
-    if constexpr (GAL) {
+    if constexpr (GAL && BUF) {
+      const Buf<T> bi(in + slot * in_slot + tile);
+#pragma unroll
+      for (int m = 0; m < E; ++m) dst[m] = bi.load(vo, (uint32_t)m * ZST);
+    } else if constexpr (GAL) {
       const C<T>* src = in + slot * in_slot + col;
 #pragma unroll
       for (int m = 0; m < E; ++m) dst[m] = src[(int64_t)(t + TPL * m) * NN];
@@ -549,11 +553,16 @@ k_zcross(const C<T>* in, int64_t in_slot, const uint8_t* __restrict__ pflag,
     twa.template fft<-1>(v, t, lines[c]);
     if constexpr (GAL) {
       if (col == 0 && t == 0) v[0] = C<T>{0, 0};  // kz = 0 of the (0,0) column
+      if constexpr (BUF) {
+        const Buf<T> bs(fg_out + tile);
 #pragma unroll
-      for (int m = 0; m < E; ++m) {
-        fg_out[col + (int64_t)(t + TPL * m) * NN] = v[m];
-        v[m] = C<T>{v[m].x * v[m].x + v[m].y * v[m].y, (T)0};
+        for (int m = 0; m < E; ++m) bs.store(v[m], vo, (uint32_t)m * ZST);
+      } else {
+#pragma unroll
+        for (int m = 0; m < E; ++m) fg_out[col + (int64_t)(t + TPL * m) * NN] = v[m];
       }
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = C<T>{v[m].x * v[m].x + v[m].y * v[m].y, (T)0};
     } else {
       if constexpr (STORE) {
         // keep the pair-field spectrum (field pair slot_fp[slot], dense N^3)
