@@ -567,15 +567,15 @@ template <typename T, int N> struct Engine : EngineBase {
     int32_t* pp = s_v1.get<int32_t>(P);
     const int64_t nkeys = (int64_t)F * NN;
     sort_pairs_i32(uk, sk, iota, pp, P, bits_for(nkeys), s, s_tmp);
-    gather(pp, ui, p_i.get<int32_t>(P), P, s);
-    gather(pp, uj, p_j.get<int32_t>(P), P, s);
+    int32_t* ppi = p_i.get<int32_t>(P);
+    int32_t* ppj = p_j.get<int32_t>(P);
     int32_t* px0 = p_x0.get<int32_t>(P);
     T* pfx = p_fx.get<T>(P);
     T* pfy = p_fy.get<T>(P);
     T* pfz = p_fz.get<T>(P);
     if (P > 0) {
-      k_pair_cic<T><<<grid_for(P), 256, 0, s>>>(pc, x, y, z, p_i.as<int32_t>(), p_j.as<int32_t>(), P, px0,
-                                                pfx, pfy, pfz);
+      // galaxy indices in sorted order and the midpoints' CIC data, one pass
+      k_pair_cic<T><<<grid_for(P), 256, 0, s>>>(pc, x, y, z, pp, ui, uj, P, ppi, ppj, px0, pfx, pfy, pfz);
       launch_check("pair_cic");
     }
     p_wt.get<T>(P);

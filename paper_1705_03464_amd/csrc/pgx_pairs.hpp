@@ -229,19 +229,27 @@ k_pairs(PairCfg c, const double* __restrict__ px, const double* __restrict__ py,
   }
 }
 
-// CIC corner and fractions of each pair's midpoint, in sorted order, from the
-// catalogue positions of its members (i < j): the same FP64 operations as the
-// pair search (d = x_j - x_i folded once into [-L/2, L/2), m = x_i + d / 2
-// wrapped into [0, L)), so the result matches the key the search gave.
+// Each pair in sorted order: its members (i < j), gathered from the emission
+// order through the sort's permutation and stored, and the CIC corner and
+// fractions of its midpoint from their catalogue positions: the same FP64
+// operations as the pair search (d = x_j - x_i folded once into [-L/2, L/2),
+// m = x_i + d / 2 wrapped into [0, L)), so the result matches the key the
+// search gave.
 template <typename T>
 static __global__ void k_pair_cic(PairCfg c, const double* __restrict__ x, const double* __restrict__ y,
-                                  const double* __restrict__ z, const int32_t* __restrict__ pi,
-                                  const int32_t* __restrict__ pj, int64_t P, int32_t* __restrict__ ox0,
-                                  T* __restrict__ ofx, T* __restrict__ ofy, T* __restrict__ ofz) {
+                                  const double* __restrict__ z, const int32_t* __restrict__ perm,
+                                  const int32_t* __restrict__ ui, const int32_t* __restrict__ uj, int64_t P,
+                                  int32_t* __restrict__ opi, int32_t* __restrict__ opj,
+                                  int32_t* __restrict__ ox0, T* __restrict__ ofx, T* __restrict__ ofy,
+                                  T* __restrict__ ofz) {
 #pragma clang fp contract(off)
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P) return;
-  const int i = pi[p], j = pj[p];
+  // the pair's galaxies from the emission order (perm: sorted -> emitted)
+  const int e = perm[p];
+  const int i = ui[e], j = uj[e];
+  opi[p] = i;
+  opj[p] = j;
   const double xi = x[i], yi = y[i], zi = z[i];
   const double dx = fold(x[j] - xi, c.L, c.halfL);
   const double dy = fold(y[j] - yi, c.L, c.halfL);
