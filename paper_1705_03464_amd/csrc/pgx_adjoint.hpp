@@ -228,7 +228,8 @@ k_zback(C<T>* x, int64_t x_slot, const uint8_t* __restrict__ pflag,
   __shared__ C<T> accs[ACC_LDS ? W : 1][ACC_LDS ? N + 1 : 1];
   C<T> accr[ACC_LDS ? 1 : E];
   load_twiddles<T, Sh>(tw_s, tw_g);
-  const int xt = blockIdx.x, ky = blockIdx.y;
+  int xt = blockIdx.x, ky = blockIdx.y;
+  if constexpr (narrow_tile<T, W>()) xcd_tile(xt, ky);
   const int c = threadIdx.x % W, t = threadIdx.x / W;
   for (int i = threadIdx.x; i < n_slots * TPL; i += W * TPL) {
     const int s = i / TPL, tt = i - s * TPL;
@@ -393,7 +394,8 @@ k_zinit(const C<T>* __restrict__ ky_in, int pwz, const C<T>* __restrict__ fg,
   __shared__ C<T> tw_s[Sh::tw_entries()];
   __shared__ C<T> lines[W][LL];
   load_twiddles<T, Sh>(tw_s, tw_g);
-  const int xt = blockIdx.x, ky = blockIdx.y;
+  int xt = blockIdx.x, ky = blockIdx.y;
+  if constexpr (narrow_tile<T, W>()) xcd_tile(xt, ky);
   const int c = threadIdx.x % W, t = threadIdx.x / W;
   const int64_t col = (int64_t)ky * N + xt * W + c;
   C<T> k[E];

@@ -117,6 +117,11 @@ __device__ __forceinline__ void xcd_block3(int& bx, int& by, int& bz) {
   bz = lt / (nx * ny);
 }
 
+// Tiles of the strided and z passes narrower than one 128-byte row (the
+// eight-column tiles of 1024^3 grids): two neighbouring tiles share every row's
+// 128-byte lines, so they run in XCD order, on one XCD at the same time.
+template <typename T, int W> constexpr bool narrow_tile() { return W * (int)sizeof(C<T>) < 128; }
+
 // z passes: default twiddle source (registers when they fit; the autotuner
 // also tries the LDS table), and the most slots one launch may carry (their
 // plane masks are staged in LDS)
@@ -337,8 +342,8 @@ k_strided(const C<T>* in, C<T>* out, int64_t in_slot, int64_t out_slot,
   constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>();
   __shared__ C<T> tw_s[tw_lds_entries<Sh, false>()];
   __shared__ C<T> lines[W][LL];
-  const int slot = blockIdx.z;
-  const int xt = blockIdx.x, a = blockIdx.y;
+  int xt = blockIdx.x, a = blockIdx.y, slot = blockIdx.z;
+  if constexpr (narrow_tile<T, W>()) xcd_block3(xt, a, slot);
   const uint8_t* lf = nullptr;
   if constexpr (IN == IN_FLAGS || OUT == OUT_FLAGS) {
     const int64_t fp = slot_fp[slot];
@@ -468,7 +473,8 @@ k_zcross(const C<T>* in, int64_t in_slot, const uint8_t* __restrict__ pflag,
   __shared__ C<T> tw_s[tw_lds_entries<Sh, TWREG>()];
   __shared__ C<T> lines[W][LL];
   __shared__ uint32_t pmask[GAL ? 1 : kMaxSlots][TPL];
-  const int xt = blockIdx.x, ky = blockIdx.y;
+  int xt = blockIdx.x, ky = blockIdx.y;
+  if constexpr (narrow_tile<T, W>()) xcd_tile(xt, ky);
   const int c = threadIdx.x % W, t = threadIdx.x / W;
   TwAuto<Sh, T, TWREG> twa;
   twa.init(tw_s, tw_g, t);
