@@ -216,8 +216,11 @@ template <typename T, int N> struct Engine : EngineBase {
   // per launch.  Small tiles (two z rows of 4 lines, 35 KB of LDS at 512^3)
   // let several blocks share a compute unit; measured at 512^3: 3.6 ms per
   // launch against 3.7 ms for 7 and 4.3 ms for 15 base lines per tile.  The
-  // TSC sweep keeps three z rows of YTS + 2 lines (65 KB).
+  // TSC sweep keeps three z rows of YTT + 2 lines: 52 KB with 2 base lines per
+  // tile, three blocks per compute unit (7.7 ms per launch at 512^3, against
+  // 10.2 ms for 3 base lines, 65 KB and two blocks).
   static constexpr int YTS = 3;
+  static constexpr int YTT = 2;
   static constexpr int kZSeg = 8;
   // dual form, z passes: tile width of the second variant (half the columns,
   // so that two blocks share a compute unit)
@@ -1837,7 +1840,7 @@ template <typename T, int N> struct Engine : EngineBase {
         const double bytes = (double)nq * NC * cb + (double)n_pairs * (20.0 + 8.0 * nq) + (double)NN * 4.0;
         prof.run("dual_xinv_gather", s, bytes, [&] {
           if (cfg.assignment == 1)
-            k_xinv_gather_sweep_tsc<T, Sh, YTS><<<dim3((N + YTS - 1) / YTS, kZSeg, nq), (YTS + 2) * TPL, 0, s>>>(
+            k_xinv_gather_sweep_tsc<T, Sh, YTT><<<dim3((N + YTT - 1) / YTT, kZSeg, nq), (YTT + 2) * TPL, 0, s>>>(
                 line_set(), l_p.as<int32_t>(), n_pairs, x, NC, zlen, 2 * q0, R, gv, twp);
           else
             k_xinv_gather_sweep<T, Sh, YTS><<<dim3((N + YTS - 1) / YTS, kZSeg, nq), (YTS + 1) * TPL, 0, s>>>(
