@@ -261,10 +261,11 @@ k_xinv_gather_sweep_tsc(PointSet<T> ps, const int32_t* __restrict__ perm, int64_
                         const C<T>* __restrict__ U, int64_t u_slot, int zlen, int b0, int R,
                         float* __restrict__ gv, const C<T>* __restrict__ tw_g) {
   constexpr int N = Sh::n, E = Sh::E, TPL = Sh::TPL, LL = lds_line_elems<N>(), NG = YT + 2;
-  __shared__ C<T> tw_s[Sh::tw_entries()];
+  // stage twiddles in registers: the LDS holds only the three rows of lines
   __shared__ C<T> rows[3][NG][LL];
-  load_twiddles<T, Sh>(tw_s, tw_g);
   const int g = threadIdx.x / TPL, t = threadIdx.x % TPL;
+  TwReg<Sh, T> twr;
+  twr.load(tw_g, t);
   // neighbouring y tiles share lines of every z row: they run on one XCD
   int ytile, zseg, slot;
   xcd_block3(ytile, zseg, slot);
@@ -284,14 +285,13 @@ k_xinv_gather_sweep_tsc(PointSet<T> ps, const int32_t* __restrict__ perm, int64_
   auto ring = [&](int z) { return (z - z_lo + 1) % 3; };
   auto transform_into = [&](int buf, C<T>* v) {
     C<T>* line = rows[buf][g];
-    line_fft<Sh, 1>(v, t, line, tw_s, wave_sync);
+    line_fft_tw<Sh, 1, T>(v, t, line, twr, wave_sync);
     wave_sync();  // this group has read its last-stage inputs
 #pragma unroll
     for (int m = 0; m < E; ++m) line[lpad(t + TPL * m)] = v[m];
   };
   C<T> v[E];
   load_row(z_lo - 1 + N, v);
-  block_sync();  // twiddles
   transform_into(ring(z_lo - 1), v);
   load_row(z_lo, v);
   transform_into(ring(z_lo), v);

@@ -216,9 +216,10 @@ template <typename T, int N> struct Engine : EngineBase {
   // per launch.  Small tiles (two z rows of 4 lines, 35 KB of LDS at 512^3)
   // let several blocks share a compute unit; measured at 512^3: 3.6 ms per
   // launch against 3.7 ms for 7 and 4.3 ms for 15 base lines per tile.  The
-  // TSC sweep keeps three z rows of YTT + 2 lines: 52 KB with 2 base lines per
-  // tile, three blocks per compute unit (7.7 ms per launch at 512^3, against
-  // 10.2 ms for 3 base lines, 65 KB and two blocks).
+  // TSC sweep keeps three z rows of YTT + 2 lines and its stage twiddles in
+  // registers: 52 KB with 2 base lines per tile, three blocks per compute unit
+  // (5.6 ms per launch at 512^3, against 7.7 ms with the LDS twiddle table and
+  // two blocks, and 10.2 ms for 3 base lines per tile).
   static constexpr int YTS = 3;
   static constexpr int YTT = 2;
   static constexpr int kZSeg = 8;
