@@ -836,6 +836,63 @@ k_xscatter_dual_tsc(PointSet<T> ps, const int32_t* __restrict__ lfield, const fl
   C<T>* line = lines[l];
   LineRanges9 lr;
   lr.template init<TPL == 64>(ps, y, z, N);
+  // point i of the line's nine ranges: TSC weights of this line (its weight
+  // times the y and z weights of the node offset its range stands for, times
+  // the three x weights), first x node and field
+  auto point_data = [&](int i, T* w, int& lx, int& q, int& f) {
+    q = lr.range(i);
+    const int p = lr.point(i, q);
+    T wy[3], wz[3];
+    tsc_weights3<T>(ps.fy[p], wy);
+    tsc_weights3<T>(ps.fz[p], wz);
+    // this line is node 1 - (q % 3) from the nearest node in y (range
+    // q % 3 = 0 holds points whose nearest line is y - 1), likewise in z
+    const T wyz = (ps.wt ? ps.wt[p] : (T)1) * pick3(wy, 2 - q % 3) * pick3(wz, 2 - q / 3);
+    T wx[3];
+    tsc_axis<T>(ps.x0[p], ps.fx[p], lx, wx);
+    w[0] = wyz * wx[0];
+    w[1] = wyz * wx[1];
+    w[2] = wyz * wx[2];
+    f = lfield[p];
+  };
+  // one trip of TPL points into the line: wavefront run sums over equal
+  // (range, nearest x node), then the run's last lane adds to LDS
+  auto add_trip = [&](bool act, const T* w, int lx, int q, float2 c) {
+    T sx[3], sy[3];
+    bool issue = act;
+    if constexpr (RUNS) {
+      WaveRuns r;
+      r.init(act ? q * N + ((lx + 1) & (N - 1)) : 9 * N + t);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        sx[j] = r.add(w[j] * (T)c.x);
+        sy[j] = r.add(w[j] * (T)c.y);
+      }
+      issue = act && r.tail;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        sx[j] = w[j] * (T)c.x;
+        sy[j] = w[j] * (T)c.y;
+      }
+    }
+    if (issue) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        C<T>* a = &line[lpad((lx + j) & (N - 1))];
+        atomicAdd(&a->x, sx[j]);
+        atomicAdd(&a->y, sy[j]);
+      }
+    }
+  };
+  // the first two trips' point data stay in registers across the slots (most
+  // lines have at most 2 TPL points in their nine ranges); only the field's
+  // coefficients are read per slot
+  T w0[3] = {(T)0, (T)0, (T)0}, w1[3] = {(T)0, (T)0, (T)0};
+  int lx0 = 0, q0r = 0, f0 = 0, lx1 = 0, q1r = 0, f1 = 0;
+  const bool a0 = t < lr.n, a1 = TPL + t < lr.n;
+  if (a0) point_data(t, w0, lx0, q0r, f0);
+  if (a1) point_data(TPL + t, w1, lx1, q1r, f1);
   for (int slot = 0; slot < nq; ++slot) {
     if (slot > 0) block_sync();  // the previous slot's transform has left the LDS line
 #pragma unroll
@@ -843,54 +900,15 @@ k_xscatter_dual_tsc(PointSet<T> ps, const int32_t* __restrict__ lfield, const fl
     block_sync();
     const float2* cq = coef + (int64_t)(q0 + slot) * F;
     // every lane of a wavefront takes the same trips (RUNS: one line per wavefront)
-    for (int base = 0; base < lr.n; base += TPL) {
+    if (lr.n > 0) add_trip(a0, w0, lx0, q0r, a0 ? cq[f0] : float2{0.f, 0.f});
+    if (lr.n > TPL) add_trip(a1, w1, lx1, q1r, a1 ? cq[f1] : float2{0.f, 0.f});
+    for (int base = 2 * TPL; base < lr.n; base += TPL) {
       const int i = base + t;
       const bool act = i < lr.n;
       T w[3] = {(T)0, (T)0, (T)0};
-      int lx = 0, q = 0;
-      float2 c = float2{0.f, 0.f};
-      if (act) {
-        q = lr.range(i);
-        const int p = lr.point(i, q);
-        T wy[3], wz[3];
-        tsc_weights3<T>(ps.fy[p], wy);
-        tsc_weights3<T>(ps.fz[p], wz);
-        // this line is node 1 - (q % 3) from the nearest node in y (range
-        // q % 3 = 0 holds points whose nearest line is y - 1), likewise in z
-        const T wyz = (ps.wt ? ps.wt[p] : (T)1) * pick3(wy, 2 - q % 3) * pick3(wz, 2 - q / 3);
-        T wx[3];
-        tsc_axis<T>(ps.x0[p], ps.fx[p], lx, wx);
-        w[0] = wyz * wx[0];
-        w[1] = wyz * wx[1];
-        w[2] = wyz * wx[2];
-        c = cq[lfield[p]];
-      }
-      T sx[3], sy[3];
-      bool issue = act;
-      if constexpr (RUNS) {
-        WaveRuns r;
-        r.init(act ? q * N + ((lx + 1) & (N - 1)) : 9 * N + t);
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          sx[j] = r.add(w[j] * (T)c.x);
-          sy[j] = r.add(w[j] * (T)c.y);
-        }
-        issue = act && r.tail;
-      } else {
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          sx[j] = w[j] * (T)c.x;
-          sy[j] = w[j] * (T)c.y;
-        }
-      }
-      if (issue) {
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          C<T>* a = &line[lpad((lx + j) & (N - 1))];
-          atomicAdd(&a->x, sx[j]);
-          atomicAdd(&a->y, sy[j]);
-        }
-      }
+      int lx = 0, q = 0, f = 0;
+      if (act) point_data(i, w, lx, q, f);
+      add_trip(act, w, lx, q, act ? cq[f] : float2{0.f, 0.f});
     }
     block_sync();
     C<T> v[E];
